@@ -1,0 +1,899 @@
+/*
+ * Plain FP64 CPU oracle for the positivity-preserving fifth-order
+ * finite-volume compact-WENO (FVCW) scheme for the Euler equations
+ * (Guo, Xiong & Shi, arXiv 1402.5618).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the independent checker that the
+ * HIP path is compared against.  It shares no code, header, table or helper
+ * with the product library; only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load it.
+ *
+ * Written for clarity, not speed: every step follows the paper in its order
+ * (Sec. 2.1-2.5), component-wise on the conserved variables, in IEEE double
+ * with no fast-math and no FMA contraction.  Readings of passages the paper
+ * leaves open are marked "reading:" and are listed in the design notes.
+ *
+ * Layout: a line is [ncomp][n] contiguous; a 2D state is [4][ny][nx];
+ * ncomp = 3 (rho, rho u, E) in 1D and 4 (rho, rho u, rho v, E) in 2D.
+ * Boundary codes: 0 periodic, 1 transmissive, 2 reflective.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NG 3 /* ghost cells per side for non-periodic lines */
+
+typedef struct {
+    double gamma;     /* ratio of specific heats (Sec. 1) */
+    double weno_eps;  /* epsilon in the WENO-Z weights, eq. (weight) */
+    double eps_cap;   /* cap of the positivity epsilon, limiter step 1 */
+    double gl_w1;     /* Gauss-Lobatto end weight w^_1 (= w^_M), Sec. 2.4 */
+    int linear;       /* 1: weights forced to (c0,c1,c2): linear scheme, eqs (5th-order1/2) */
+    int first_order;  /* 1: no reconstruction, U+- = cell average: scheme (1DEulerFV-First) */
+    int limiter;      /* 1: apply the positivity-preserving limiter */
+} orc_params;
+
+/* Optional per-line intermediate results for tests (any pointer may be NULL). */
+typedef struct {
+    double *um, *up;       /* [ncomp][n] reconstructed U-_{i+1/2}, U+_{i-1/2} before limiting */
+    double *um_l, *up_l;   /* [ncomp][n] after the limiter */
+    double *flux;          /* [ncomp][n+1] face fluxes, face f between cells f-1 and f */
+} orc_line_dbg;
+
+/* |u_n| + a of a state (normal velocity u_n = U[nrm] / rho).  A pressure
+ * that is negative only by roundoff (E almost all kinetic) counts as 0. */
+static double wave_speed(double g, int ncomp, int nrm, const double *U)
+{
+    double m2 = 0.0;
+    for (int k = 1; k < ncomp - 1; ++k) m2 += U[k] * U[k];
+    double p = (g - 1.0) * (U[ncomp - 1] - 0.5 * m2 / U[0]);
+    return fabs(U[nrm] / U[0]) + sqrt(g * fmax(p, 0.0) / U[0]);
+}
+
+/* running maximum in which a NaN is sticky */
+static void max_into(double *acc, double v)
+{
+    if (v > *acc || v != v) *acc = v;
+}
+
+static double sq(double x) { return x * x; }
+
+/* ------------------------------------------------------------------ Sec 2.2
+ * Smoothness indicators of the three candidate stencils of the value at node
+ * j+1/2 seen from cell j (the "-" side), from v[0..4] = ubar_{j-2..j+2}.
+ * These are the classical indicators printed after eq. (weight). */
+static void beta_minus(const double v[5], double b[3])
+{
+    b[0] = 13.0 / 12.0 * sq(v[0] - 2.0 * v[1] + v[2]) + 0.25 * sq(v[0] - 4.0 * v[1] + 3.0 * v[2]);
+    b[1] = 13.0 / 12.0 * sq(v[1] - 2.0 * v[2] + v[3]) + 0.25 * sq(v[1] - v[3]);
+    b[2] = 13.0 / 12.0 * sq(v[2] - 2.0 * v[3] + v[4]) + 0.25 * sq(3.0 * v[2] - 4.0 * v[3] + v[4]);
+}
+
+/* The "+" side at node j+1/2 (seen from cell j+1) is the mirror image of the
+ * "-" side about the node: cell j+m <-> cell j+1-m.  v[0..4] = ubar_{j-1..j+3};
+ * candidate k is the mirror of candidate k of the "-" side. */
+static void beta_plus(const double v[5], double b[3])
+{
+    b[0] = 13.0 / 12.0 * sq(v[4] - 2.0 * v[3] + v[2]) + 0.25 * sq(v[4] - 4.0 * v[3] + 3.0 * v[2]);
+    b[1] = 13.0 / 12.0 * sq(v[3] - 2.0 * v[2] + v[1]) + 0.25 * sq(v[3] - v[1]);
+    b[2] = 13.0 / 12.0 * sq(v[2] - 2.0 * v[1] + v[0]) + 0.25 * sq(3.0 * v[2] - 4.0 * v[1] + v[0]);
+}
+
+/* eq. (weight): WENO-Z weights with tau5 = |beta2 - beta0| and power 2. */
+static void wenoz(const double b[3], const double c[3], double eps, double w[3])
+{
+    double tau = fabs(b[2] - b[0]);
+    double al[3], s = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        al[k] = c[k] * (1.0 + sq(tau / (b[k] + eps)));
+        s += al[k];
+    }
+    for (int k = 0; k < 3; ++k) w[k] = al[k] / s;
+}
+
+static const double C_LIN[3] = {0.2, 0.5, 0.3}; /* optimal linear weights, Sec 2.2 */
+
+/* Test hook: weights of both sides at node j+1/2 from v[0..5] = ubar_{j-2..j+3}:
+ * w[0..2] for the "-" side (cells j-2..j+2), w[3..5] for the "+" side (cells j-1..j+3). */
+void orc_weights(const double *v, double eps, double *w)
+{
+    double b[3];
+    beta_minus(v, b);
+    wenoz(b, C_LIN, eps, w);
+    beta_plus(v + 1, b);
+    wenoz(b, C_LIN, eps, w + 3);
+}
+
+/* Weights of one side, honouring the "linear" switch. */
+static void side_weights(const double b[3], const orc_params *P, double w[3])
+{
+    if (P->linear) {
+        w[0] = C_LIN[0]; w[1] = C_LIN[1]; w[2] = C_LIN[2];
+    } else {
+        wenoz(b, C_LIN, P->weno_eps, w);
+    }
+}
+
+/* eq. (CWENO-FV): row at node j+1/2 of the "-" system, coupling
+ * u~_{j-1/2}, u~_{j+1/2}, u~_{j+3/2}; right side from ubar_{j-1}, ubar_j, ubar_{j+1}. */
+static void row_minus(const double w[3], double um1, double u0, double up1,
+                      double *a, double *b, double *c, double *r)
+{
+    *a = (2.0 * w[0] + w[1]) / 3.0;
+    *b = (w[0] + 2.0 * (w[1] + w[2])) / 3.0;
+    *c = w[2] / 3.0;
+    *r = w[0] / 6.0 * um1 + (5.0 * (w[0] + w[1]) + w[2]) / 6.0 * u0 + (w[1] + 5.0 * w[2]) / 6.0 * up1;
+}
+
+/* Mirror of eq. (CWENO-FV) for the "+" system at node j+1/2 (Sec 2.2, last
+ * paragraph): coupling u~+_{j-1/2} (a), u~+_{j+1/2} (b), u~+_{j+3/2} (c);
+ * right side from ubar_j, ubar_{j+1}, ubar_{j+2}.  With w = c this is eq. (5th-order2). */
+static void row_plus(const double w[3], double u0, double up1, double up2,
+                     double *a, double *b, double *c, double *r)
+{
+    *a = w[2] / 3.0;
+    *b = (w[0] + 2.0 * (w[1] + w[2])) / 3.0;
+    *c = (2.0 * w[0] + w[1]) / 3.0;
+    *r = (w[1] + 5.0 * w[2]) / 6.0 * u0 + (5.0 * (w[0] + w[1]) + w[2]) / 6.0 * up1 + w[0] / 6.0 * up2;
+}
+
+/* Reading (boundary closure): the nodal value just outside a non-periodic
+ * line comes from the classical explicit fifth-order WENO-Z reconstruction on
+ * the ghost-extended averages, v[0..4] = ubar_{j-2..j+2}, "-" side of node j+1/2. */
+static double weno5z_minus(const double v[5], const orc_params *P)
+{
+    static const double D5[3] = {0.1, 0.6, 0.3};
+    double q0 = (2.0 * v[0] - 7.0 * v[1] + 11.0 * v[2]) / 6.0;
+    double q1 = (-v[1] + 5.0 * v[2] + 2.0 * v[3]) / 6.0;
+    double q2 = (2.0 * v[2] + 5.0 * v[3] - v[4]) / 6.0;
+    double b[3], w[3];
+    beta_minus(v, b);
+    if (P->linear) { w[0] = D5[0]; w[1] = D5[1]; w[2] = D5[2]; }
+    else wenoz(b, D5, P->weno_eps, w);
+    return w[0] * q0 + w[1] * q1 + w[2] * q2;
+}
+
+/* ------------------------------------------------------- tridiagonal solves
+ * Chasing (Thomas) elimination, no pivoting: a_i x_{i-1} + b_i x_i + c_i x_{i+1} = r_i,
+ * i = 0..n-1, a_0 and c_{n-1} ignored.  Returns 0, or -1 on a zero pivot. */
+int orc_thomas(int n, const double *a, const double *b, const double *c, const double *r, double *x)
+{
+    double *cp = (double *)malloc(sizeof(double) * (size_t)n);
+    double *dp = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!cp || !dp) { free(cp); free(dp); return -2; }
+    int rc = 0;
+    if (b[0] == 0.0) { rc = -1; goto done; }
+    cp[0] = c[0] / b[0];
+    dp[0] = r[0] / b[0];
+    for (int i = 1; i < n; ++i) {
+        double m = b[i] - a[i] * cp[i - 1];
+        if (m == 0.0) { rc = -1; goto done; }
+        cp[i] = c[i] / m;
+        dp[i] = (r[i] - a[i] * dp[i - 1]) / m;
+    }
+    x[n - 1] = dp[n - 1];
+    for (int i = n - 2; i >= 0; --i) x[i] = dp[i] - cp[i] * x[i + 1];
+done:
+    free(cp);
+    free(dp);
+    return rc;
+}
+
+/* Cyclic tridiagonal system (indices mod n, n >= 3): the last unknown is
+ * kept as a parameter, x_i = p_i + q_i x_{n-1} from two chasing solves of the
+ * leading (n-1)x(n-1) block, then the last row gives x_{n-1}. */
+int orc_cyclic(int n, const double *a, const double *b, const double *c, const double *r, double *x)
+{
+    if (n < 3) return -3;
+    int m = n - 1;
+    double *v = (double *)calloc((size_t)m, sizeof(double));
+    double *p = (double *)malloc(sizeof(double) * (size_t)m);
+    double *q = (double *)malloc(sizeof(double) * (size_t)m);
+    if (!v || !p || !q) { free(v); free(p); free(q); return -2; }
+    v[0] = -a[0];
+    v[m - 1] += -c[m - 1];
+    int rc = orc_thomas(m, a, b, c, r, p);
+    if (rc == 0) rc = orc_thomas(m, a, b, c, v, q);
+    if (rc == 0) {
+        double den = b[n - 1] + a[n - 1] * q[m - 1] + c[n - 1] * q[0];
+        if (den == 0.0) rc = -1;
+        else {
+            double xl = (r[n - 1] - a[n - 1] * p[m - 1] - c[n - 1] * p[0]) / den;
+            for (int i = 0; i < m; ++i) x[i] = p[i] + q[i] * xl;
+            x[n - 1] = xl;
+        }
+    }
+    free(v); free(p); free(q);
+    return rc;
+}
+
+/* Dense Gaussian elimination with partial pivoting on an n x n row-major
+ * matrix (test support for small lines).  Returns 0 or -1 if singular. */
+int orc_dense_solve(int n, const double *A, const double *r, double *x)
+{
+    double *M = (double *)malloc(sizeof(double) * (size_t)n * (size_t)(n + 1));
+    if (!M) return -2;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) M[i * (n + 1) + j] = A[i * n + j];
+        M[i * (n + 1) + n] = r[i];
+    }
+    int rc = 0;
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < n; ++i)
+            if (fabs(M[i * (n + 1) + k]) > fabs(M[piv * (n + 1) + k])) piv = i;
+        if (M[piv * (n + 1) + k] == 0.0) { rc = -1; break; }
+        if (piv != k)
+            for (int j = 0; j <= n; ++j) {
+                double t = M[k * (n + 1) + j];
+                M[k * (n + 1) + j] = M[piv * (n + 1) + j];
+                M[piv * (n + 1) + j] = t;
+            }
+        for (int i = k + 1; i < n; ++i) {
+            double f = M[i * (n + 1) + k] / M[k * (n + 1) + k];
+            for (int j = k; j <= n; ++j) M[i * (n + 1) + j] -= f * M[k * (n + 1) + j];
+        }
+    }
+    if (rc == 0)
+        for (int i = n - 1; i >= 0; --i) {
+            double s = M[i * (n + 1) + n];
+            for (int j = i + 1; j < n; ++j) s -= M[i * (n + 1) + j] * x[j];
+            x[i] = s / M[i * (n + 1) + i];
+        }
+    free(M);
+    return rc;
+}
+
+/* Reading: the "+" system is chased from its right end, the mirror of the
+ * "-" sweep: solve on the reversed system (a and c exchange roles). */
+static int solve_reversed(int n, int cyclic, const double *a, const double *b, const double *c,
+                          const double *r, double *x, double *work /* 5n */)
+{
+    double *ra = work, *rb = work + n, *rc = work + 2 * n, *rr = work + 3 * n, *rx = work + 4 * n;
+    for (int i = 0; i < n; ++i) {
+        ra[i] = c[n - 1 - i];
+        rb[i] = b[n - 1 - i];
+        rc[i] = a[n - 1 - i];
+        rr[i] = r[n - 1 - i];
+    }
+    int s = cyclic ? orc_cyclic(n, ra, rb, rc, rr, rx) : orc_thomas(n, ra, rb, rc, rr, rx);
+    for (int i = 0; i < n; ++i) x[i] = rx[n - 1 - i];
+    return s;
+}
+
+/* -------------------------------------------------------------- Sec 2.2-2.3
+ * Component-wise reconstruction of one scalar line.  ue[0..n+5] holds the
+ * averages of cells -3..n+2 (cell i at ue[i+3]); for a periodic line the
+ * ghosts are the wrapped cells.  Outputs: um[i] = u-_{i+1/2} (right face of
+ * cell i, "-" system) and up[i] = u+_{i-1/2} (left face of cell i, "+" system). */
+static int recon_scalar(int n, int cyclic, const double *ue, const orc_params *P,
+                        double *um, double *up, double *work /* >= 9n */)
+{
+    double *a = work, *b = work + n, *c = work + 2 * n, *r = work + 3 * n;
+    double *w5 = work + 4 * n;
+    double v[5], beta[3], w[3];
+    /* "-" system: row i sits at node i+1/2; stencil cells i-2..i+2. */
+    for (int i = 0; i < n; ++i) {
+        for (int k = 0; k < 5; ++k) v[k] = ue[i + 1 + k];
+        beta_minus(v, beta);
+        side_weights(beta, P, w);
+        row_minus(w, v[1], v[2], v[3], &a[i], &b[i], &c[i], &r[i]);
+    }
+    int s;
+    if (cyclic) {
+        s = orc_cyclic(n, a, b, c, r, um);
+    } else {
+        /* closure values u-_{-1/2} (cell -1) and u-_{n+1/2} (cell n) */
+        double xl = weno5z_minus(&ue[0], P);
+        double xr = weno5z_minus(&ue[n + 1], P);
+        r[0] -= a[0] * xl;
+        r[n - 1] -= c[n - 1] * xr;
+        s = orc_thomas(n, a, b, c, r, um);
+    }
+    if (s) return s;
+    /* "+" system: unknown i is u+ at node i-1/2; its row is the mirrored row at
+     * that node, with stencil cells i-2..i+2 (right side from i-1, i, i+1). */
+    for (int i = 0; i < n; ++i) {
+        for (int k = 0; k < 5; ++k) v[k] = ue[i + 1 + k];
+        beta_plus(v, beta);
+        side_weights(beta, P, w);
+        row_plus(w, v[1], v[2], v[3], &a[i], &b[i], &c[i], &r[i]);
+    }
+    if (cyclic) {
+        s = solve_reversed(n, 1, a, b, c, r, up, w5);
+    } else {
+        /* closure values u+ at the left faces of cells -1 and n: mirrored
+         * explicit reconstruction on the reversed stencils */
+        double mv[5];
+        for (int k = 0; k < 5; ++k) mv[k] = ue[4 - k];     /* cells 1..-3 */
+        double xl = weno5z_minus(mv, P);
+        for (int k = 0; k < 5; ++k) mv[k] = ue[n + 5 - k]; /* cells n+2..n-2 */
+        double xr = weno5z_minus(mv, P);
+        r[0] -= a[0] * xl;
+        r[n - 1] -= c[n - 1] * xr;
+        s = solve_reversed(n, 0, a, b, c, r, up, w5);
+    }
+    return s;
+}
+
+/* ----------------------------------------------------------------- Sec 2.4
+ * HLLC flux (eqs. (HLLC), (contact-v), (star-l), (acoustic ws)) across a
+ * face whose normal momentum is component `nrm` (1: x, 2: y).
+ * Readings: the contact speed denominator uses rho_r for the right state and
+ * S_R takes the max of its two candidates (the printed formulas repeat
+ * rho_l and write min).  In 2D the tangential momentum of a star state is
+ * rho* times the tangential velocity of its side.  Sound speeds use
+ * max(p, 0): the limiter leaves interface states with e = eps, whose
+ * pressure computed from (rho, m, E) is pure roundoff and may come out
+ * slightly negative; the Roe sound-speed argument is clipped likewise. */
+static void hllc(double g, int ncomp, int nrm, const double *Ul, const double *Ur, double *F)
+{
+    int ie = ncomp - 1, tg = (ncomp == 4) ? 3 - nrm : -1;
+    double rl = Ul[0], ul = Ul[nrm] / rl, vl = tg > 0 ? Ul[tg] / rl : 0.0, El = Ul[ie];
+    double rr = Ur[0], ur = Ur[nrm] / rr, vr = tg > 0 ? Ur[tg] / rr : 0.0, Er = Ur[ie];
+    double pl = (g - 1.0) * (El - 0.5 * rl * (ul * ul + vl * vl));
+    double pr = (g - 1.0) * (Er - 0.5 * rr * (ur * ur + vr * vr));
+    double al = sqrt(g * fmax(pl, 0.0) / rl), ar = sqrt(g * fmax(pr, 0.0) / rr);
+    double Hl = (El + pl) / rl, Hr = (Er + pr) / rr;
+    double R = sqrt(rr / rl);
+    double ut = (ul + ur * R) / (1.0 + R);
+    double vt = (vl + vr * R) / (1.0 + R);
+    double Ht = (Hl + Hr * R) / (1.0 + R);
+    double at = sqrt(fmax((g - 1.0) * (Ht - 0.5 * (ut * ut + vt * vt)), 0.0));
+    double SL = fmin(ul - al, ut - at);
+    double SR = fmax(ur + ar, ut + at);
+    /* reading: the denominator is >= 0; it vanishes only when two states
+     * with zero computed sound speed separate, and then the midpoint makes
+     * both star states vacuum (zero flux), the limit of a -> 0+ */
+    double den = rr * (SR - ur) - rl * (SL - ul);
+    double SM = den > 0.0 ? (rr * ur * (SR - ur) - rl * ul * (SL - ul) + pl - pr) / den
+                          : 0.5 * (SL + SR);
+    double Fl[4], Fr[4];
+    Fl[0] = rl * ul; Fl[nrm] = rl * ul * ul + pl; Fl[ie] = ul * (El + pl);
+    Fr[0] = rr * ur; Fr[nrm] = rr * ur * ur + pr; Fr[ie] = ur * (Er + pr);
+    if (tg > 0) { Fl[tg] = rl * ul * vl; Fr[tg] = rr * ur * vr; }
+    if (SL > 0.0) {
+        for (int k = 0; k < ncomp; ++k) F[k] = Fl[k];
+    } else if (SM > 0.0) {
+        double d = SL - SM, ps = rl * (ul - SL) * (ul - SM) + pl, Us[4];
+        Us[0] = rl * (SL - ul) / d;
+        Us[nrm] = ((SL - ul) * rl * ul + (ps - pl)) / d;
+        Us[ie] = ((SL - ul) * El - pl * ul + ps * SM) / d;
+        if (tg > 0) Us[tg] = Us[0] * vl;
+        for (int k = 0; k < ncomp; ++k) F[k] = Fl[k] + SL * (Us[k] - Ul[k]);
+    } else if (SR >= 0.0 && SR > SM) {
+        double d = SR - SM, ps = rr * (ur - SR) * (ur - SM) + pr, Us[4];
+        Us[0] = rr * (SR - ur) / d;
+        Us[nrm] = ((SR - ur) * rr * ur + (ps - pr)) / d;
+        Us[ie] = ((SR - ur) * Er - pr * ur + ps * SM) / d;
+        if (tg > 0) Us[tg] = Us[0] * vr;
+        for (int k = 0; k < ncomp; ++k) F[k] = Fr[k] + SR * (Us[k] - Ur[k]);
+    } else {
+        for (int k = 0; k < ncomp; ++k) F[k] = Fr[k];
+    }
+}
+
+/* Exported for unit tests. */
+void orc_hllc(double gamma, int ncomp, int nrm, const double *Ul, const double *Ur, double *F)
+{
+    hllc(gamma, ncomp, nrm, Ul, Ur, F);
+}
+
+/* HLLC wave-speed estimates and contact speed, for tests of eq. (inequ-v). */
+void orc_hllc_speeds(double g, int ncomp, int nrm, const double *Ul, const double *Ur, double *S)
+{
+    int ie = ncomp - 1, tg = (ncomp == 4) ? 3 - nrm : -1;
+    double rl = Ul[0], ul = Ul[nrm] / rl, vl = tg > 0 ? Ul[tg] / rl : 0.0, El = Ul[ie];
+    double rr = Ur[0], ur = Ur[nrm] / rr, vr = tg > 0 ? Ur[tg] / rr : 0.0, Er = Ur[ie];
+    double pl = (g - 1.0) * (El - 0.5 * rl * (ul * ul + vl * vl));
+    double pr = (g - 1.0) * (Er - 0.5 * rr * (ur * ur + vr * vr));
+    double al = sqrt(g * fmax(pl, 0.0) / rl), ar = sqrt(g * fmax(pr, 0.0) / rr);
+    double Hl = (El + pl) / rl, Hr = (Er + pr) / rr;
+    double R = sqrt(rr / rl);
+    double ut = (ul + ur * R) / (1.0 + R), vt = (vl + vr * R) / (1.0 + R);
+    double Ht = (Hl + Hr * R) / (1.0 + R);
+    double at = sqrt(fmax((g - 1.0) * (Ht - 0.5 * (ut * ut + vt * vt)), 0.0));
+    S[0] = fmin(ul - al, ut - at);
+    S[2] = fmax(ur + ar, ut + at);
+    double den = rr * (S[2] - ur) - rl * (S[0] - ul);
+    S[1] = den > 0.0 ? (rr * ur * (S[2] - ur) - rl * ul * (S[0] - ul) + pl - pr) / den
+                     : 0.5 * (S[0] + S[2]);
+}
+
+/* Specific internal energy e = E/rho - |m|^2/(2 rho^2) (definition of G). */
+static double spec_e(int ncomp, const double *U)
+{
+    double m2 = 0.0;
+    for (int k = 1; k < ncomp - 1; ++k) m2 += U[k] * U[k];
+    return U[ncomp - 1] / U[0] - 0.5 * m2 / (U[0] * U[0]);
+}
+
+/* Limiter step 4: t in [0,1] with e((1-t) Ubar + t W) = eps.  Along
+ * U(t) = Ubar + t (W - Ubar), rho(t) e(U(t)) - eps rho(t)^2 =
+ * rho E - |m|^2/2 - eps rho^2 is the quadratic A t^2 + B t + C with C >= 0 and
+ * a negative value at t = 1; its root in [0,1] is 2C / (-B + sqrt(B^2 - 4AC)). */
+static double pp_root(int ncomp, double eps, const double *Ub, const double *W)
+{
+    int ie = ncomp - 1;
+    double D[4];
+    for (int k = 0; k < ncomp; ++k) D[k] = W[k] - Ub[k];
+    double dm2 = 0.0, mdm = 0.0, m2 = 0.0;
+    for (int k = 1; k < ie; ++k) {
+        dm2 += D[k] * D[k];
+        mdm += Ub[k] * D[k];
+        m2 += Ub[k] * Ub[k];
+    }
+    double A = D[0] * D[ie] - 0.5 * dm2 - eps * D[0] * D[0];
+    double B = Ub[0] * D[ie] + Ub[ie] * D[0] - mdm - 2.0 * eps * Ub[0] * D[0];
+    double C = Ub[0] * Ub[ie] - 0.5 * m2 - eps * Ub[0] * Ub[0];
+    if (C <= 0.0) return 0.0;
+    double disc = B * B - 4.0 * A * C;
+    if (disc < 0.0) disc = 0.0;
+    double t = 2.0 * C / (-B + sqrt(disc));
+    if (!(t >= 0.0)) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    return t;
+}
+
+/* Positivity-preserving limiter of one cell (Sec 2.4, steps 1-4).
+ * Um = U-_{j+1/2}, Up = U+_{j-1/2}, modified in place.  Returns 1 if the
+ * limiter changed anything.  Readings: rho_min is the minimum of the three
+ * densities and theta1 = 1 whenever rho_min >= eps_rho; eps_e is the
+ * internal-energy threshold (min(cap, min e(Ubar)) over the grid). */
+static int pp_limit(int ncomp, double w1, double eps_rho, double eps_e, const double *Ub,
+                    double *Um, double *Up)
+{
+    int active = 0;
+    /* step 2 */
+    double rmid = (Ub[0] - w1 * Up[0] - w1 * Um[0]) / (1.0 - 2.0 * w1);
+    double rmin = fmin(fmin(Um[0], Up[0]), rmid);
+    double th1 = 1.0;
+    if (rmin < eps_rho) th1 = fmin((Ub[0] - eps_rho) / (Ub[0] - rmin), 1.0);
+    /* step 3 */
+    if (th1 < 1.0) {
+        Um[0] = th1 * (Um[0] - Ub[0]) + Ub[0];
+        Up[0] = th1 * (Up[0] - Ub[0]) + Ub[0];
+        active = 1;
+    }
+    double W[3][4];
+    for (int k = 0; k < ncomp; ++k) {
+        W[0][k] = Um[k];
+        W[1][k] = Up[k];
+        W[2][k] = (Ub[k] - w1 * Up[k] - w1 * Um[k]) / (1.0 - 2.0 * w1);
+    }
+    /* step 4 */
+    double th2 = 1.0;
+    for (int al = 0; al < 3; ++al) {
+        if (!(W[al][0] > 0.0) || spec_e(ncomp, W[al]) < eps_e) {
+            double t = pp_root(ncomp, eps_e, Ub, W[al]);
+            if (t < th2) th2 = t;
+        }
+    }
+    if (th2 < 1.0) {
+        for (int k = 0; k < ncomp; ++k) {
+            Um[k] = th2 * (Um[k] - Ub[k]) + Ub[k];
+            Up[k] = th2 * (Up[k] - Ub[k]) + Ub[k];
+        }
+        active = 1;
+    }
+    return active;
+}
+
+/* Exported single-cell limiter for unit tests (in-place on Um, Up). */
+int orc_limit_cell(int ncomp, double w1, double eps_rho, double eps_e, const double *Ub,
+                   double *Um, double *Up)
+{
+    return pp_limit(ncomp, w1, eps_rho, eps_e, Ub, Um, Up);
+}
+
+/* Limiter step 1 over a set of cells ([ncomp][ncell]): eps_rho = min(cap, min rho);
+ * reading: eps_e = min(cap, min e(Ubar)). */
+void orc_eps(long ncell, int ncomp, const double *U, double cap, double *eps_rho, double *eps_e)
+{
+    double er = cap, ee = cap, cell[4];
+    for (long i = 0; i < ncell; ++i) {
+        for (int k = 0; k < ncomp; ++k) cell[k] = U[(long)k * ncell + i];
+        if (cell[0] < er) er = cell[0];
+        double e = spec_e(ncomp, cell);
+        if (e < ee) ee = e;
+    }
+    *eps_rho = er;
+    *eps_e = ee;
+}
+
+/* ------------------------------------------------------------ Sec 2.1, 2.4
+ * Spatial operator of one line: L_i = -(F_{i+1/2} - F_{i-1/2}) / h, with the
+ * compact-WENO reconstruction, the limiter and the HLLC flux.  u and L are
+ * [ncomp][n]; nrm is the component index of the normal momentum.
+ * Returns the number of limited cells, or a negative error code. */
+long orc_line_op(int n, int ncomp, int nrm, const double *u, int bc_lo, int bc_hi, double h,
+                 const orc_params *P, double eps_rho, double eps_e, double *L, orc_line_dbg *dbg,
+                 double *smax)
+{
+    int cyclic = (bc_lo == 0);
+    int ne = n + 2 * NG;
+    size_t need = (size_t)ncomp * (size_t)ne + 4u * (size_t)ncomp * (size_t)n +
+                  (size_t)ncomp * (size_t)(n + 1) + 9u * (size_t)n;
+    double *mem = (double *)malloc(sizeof(double) * need);
+    if (!mem) return -2;
+    double *ue = mem;                            /* [ncomp][ne] */
+    double *um = ue + (size_t)ncomp * ne;        /* [ncomp][n] */
+    double *up = um + (size_t)ncomp * n;
+    double *uml = up + (size_t)ncomp * n;
+    double *upl = uml + (size_t)ncomp * n;
+    double *F = upl + (size_t)ncomp * n;         /* [ncomp][n+1] */
+    double *work = F + (size_t)ncomp * (n + 1);  /* 9n */
+
+    /* ghost fill (reading: transmissive = copy of the edge cell, reflective =
+     * mirror image with the normal momentum negated; periodic = wrap) */
+    for (int k = 0; k < ncomp; ++k) {
+        double *e = ue + (size_t)k * ne;
+        const double *x = u + (size_t)k * n;
+        for (int i = 0; i < n; ++i) e[i + NG] = x[i];
+        for (int g = 1; g <= NG; ++g) {
+            double lo, hi;
+            if (bc_lo == 0) lo = x[((-g) % n + n) % n];
+            else if (bc_lo == 1) lo = x[0];
+            else lo = (k == nrm ? -1.0 : 1.0) * x[g - 1 < n ? g - 1 : n - 1];
+            if (bc_hi == 0) hi = x[(n - 1 + g) % n];
+            else if (bc_hi == 1) hi = x[n - 1];
+            else hi = (k == nrm ? -1.0 : 1.0) * x[n - g >= 0 ? n - g : 0];
+            e[NG - g] = lo;
+            e[n - 1 + NG + g] = hi;
+        }
+    }
+
+    /* reconstruction, component by component (conservative variables) */
+    for (int k = 0; k < ncomp; ++k) {
+        double *mk = um + (size_t)k * n, *pk = up + (size_t)k * n;
+        if (P->first_order) {
+            for (int i = 0; i < n; ++i) mk[i] = pk[i] = u[(size_t)k * n + i];
+        } else {
+            int s = recon_scalar(n, cyclic, ue + (size_t)k * ne, P, mk, pk, work);
+            if (s) { free(mem); return -10 + s; }
+        }
+    }
+
+    /* limiter, cell by cell */
+    long nlim = 0;
+    for (int i = 0; i < n; ++i) {
+        double Ub[4], Um[4], Up[4];
+        for (int k = 0; k < ncomp; ++k) {
+            Ub[k] = u[(size_t)k * n + i];
+            Um[k] = um[(size_t)k * n + i];
+            Up[k] = up[(size_t)k * n + i];
+        }
+        if (P->limiter) nlim += pp_limit(ncomp, P->gl_w1, eps_rho, eps_e, Ub, Um, Up);
+        for (int k = 0; k < ncomp; ++k) {
+            uml[(size_t)k * n + i] = Um[k];
+            upl[(size_t)k * n + i] = Up[k];
+        }
+        if (smax) {
+            /* reading of (CFL-CD): the sup-norm of |u|+a runs over the cell
+             * averages and the limited interface states */
+            if (*smax == *smax) {
+                max_into(smax, wave_speed(P->gamma, ncomp, nrm, Ub));
+                max_into(smax, wave_speed(P->gamma, ncomp, nrm, Um));
+                max_into(smax, wave_speed(P->gamma, ncomp, nrm, Up));
+            }
+        }
+    }
+
+    /* fluxes at faces 0..n; face f lies between cells f-1 and f */
+    for (int f = 0; f <= n; ++f) {
+        double Ul[4], Ur[4], Ff[4];
+        if (f > 0 && f < n) {
+            for (int k = 0; k < ncomp; ++k) {
+                Ul[k] = uml[(size_t)k * n + f - 1];
+                Ur[k] = upl[(size_t)k * n + f];
+            }
+        } else if (cyclic) {
+            for (int k = 0; k < ncomp; ++k) {
+                Ul[k] = uml[(size_t)k * n + n - 1];
+                Ur[k] = upl[(size_t)k * n + 0];
+            }
+        } else if (f == 0) {
+            /* reading: image state outside the left boundary */
+            for (int k = 0; k < ncomp; ++k) {
+                Ur[k] = upl[(size_t)k * n + 0];
+                Ul[k] = (bc_lo == 2 && k == nrm) ? -Ur[k] : Ur[k];
+            }
+        } else {
+            for (int k = 0; k < ncomp; ++k) {
+                Ul[k] = uml[(size_t)k * n + n - 1];
+                Ur[k] = (bc_hi == 2 && k == nrm) ? -Ul[k] : Ul[k];
+            }
+        }
+        hllc(P->gamma, ncomp, nrm, Ul, Ur, Ff);
+        for (int k = 0; k < ncomp; ++k) F[(size_t)k * (n + 1) + f] = Ff[k];
+    }
+
+    /* eq. (1DEulerFV-b) */
+    for (int k = 0; k < ncomp; ++k)
+        for (int i = 0; i < n; ++i)
+            L[(size_t)k * n + i] = -(F[(size_t)k * (n + 1) + i + 1] - F[(size_t)k * (n + 1) + i]) / h;
+
+    if (dbg) {
+        size_t cn = (size_t)ncomp * n;
+        if (dbg->um) memcpy(dbg->um, um, sizeof(double) * cn);
+        if (dbg->up) memcpy(dbg->up, up, sizeof(double) * cn);
+        if (dbg->um_l) memcpy(dbg->um_l, uml, sizeof(double) * cn);
+        if (dbg->up_l) memcpy(dbg->up_l, upl, sizeof(double) * cn);
+        if (dbg->flux) memcpy(dbg->flux, F, sizeof(double) * (size_t)ncomp * (n + 1));
+    }
+    free(mem);
+    return nlim;
+}
+
+/* Scalar reconstruction hook for tests: ue[0..n+5] ghost-extended averages
+ * (cells -3..n+2), cyclic = 1 for a periodic line.  Returns 0 on success. */
+int orc_recon_scalar(int n, int cyclic, const double *ue, const orc_params *P, double *um, double *up)
+{
+    double *work = (double *)malloc(sizeof(double) * 9u * (size_t)n);
+    if (!work) return -2;
+    int s = recon_scalar(n, cyclic, ue, P, um, up, work);
+    free(work);
+    return s;
+}
+
+/* ------------------------------------------------------------------- 1D */
+long orc_rhs_1d(int n, const double *U, int bc_lo, int bc_hi, double h, const orc_params *P,
+                double *L)
+{
+    double er, ee;
+    orc_eps(n, 3, U, P->eps_cap, &er, &ee);
+    return orc_line_op(n, 3, 1, U, bc_lo, bc_hi, h, P, er, ee, L, NULL, NULL);
+}
+
+/* eq. (RK3): stage s (1, 2, 3) of the SSP Runge-Kutta method, written as printed. */
+static void rk3_combine(long m, int stage, double dt, const double *U0, const double *Us,
+                        const double *L, double *Uo)
+{
+    for (long i = 0; i < m; ++i) {
+        if (stage == 1) Uo[i] = U0[i] + dt * L[i];
+        else if (stage == 2) Uo[i] = 0.75 * U0[i] + 0.25 * Us[i] + 0.25 * dt * L[i];
+        else Uo[i] = U0[i] / 3.0 + 2.0 / 3.0 * Us[i] + 2.0 / 3.0 * dt * L[i];
+    }
+}
+
+void orc_rk3_combine(long m, int stage, double dt, const double *U0, const double *Us,
+                     const double *L, double *Uo)
+{
+    rk3_combine(m, stage, dt, U0, Us, L, Uo);
+}
+
+long orc_stage_1d(int n, const double *U0, const double *Us, double *Uo, int stage, double dt,
+                  int bc_lo, int bc_hi, double h, const orc_params *P)
+{
+    double *L = (double *)malloc(sizeof(double) * 3u * (size_t)n);
+    if (!L) return -2;
+    long r = orc_rhs_1d(n, Us, bc_lo, bc_hi, h, P, L);
+    if (r >= 0) rk3_combine(3L * n, stage, dt, U0, Us, L, Uo);
+    free(L);
+    return r;
+}
+
+/* max over cells of |u| + a of the cell averages. */
+double orc_max_speed_1d(int n, const double *U, double gamma)
+{
+    double s = 0.0, cell[3];
+    for (int i = 0; i < n && s == s; ++i) {
+        cell[0] = U[i]; cell[1] = U[n + i]; cell[2] = U[2 * n + i];
+        max_into(&s, wave_speed(gamma, 3, 1, cell));
+    }
+    return s;
+}
+
+/* Spatial operator of the first stage together with the wave-speed bound
+ * of the step: max |u|+a over the averages and the limited interface states. */
+long orc_rhs_speed_1d(int n, const double *U, int bc_lo, int bc_hi, double h, const orc_params *P,
+                      double *L, double *smax)
+{
+    double er, ee;
+    orc_eps(n, 3, U, P->eps_cap, &er, &ee);
+    *smax = 0.0;
+    return orc_line_op(n, 3, 1, U, bc_lo, bc_hi, h, P, er, ee, L, NULL, smax);
+}
+
+/* Time-step rules: 0 -> dt = cfl h / S        (condition (CFL-CD));
+ *                  1 -> dt = cfl h^(5/3) / S  (Example 3.1, Table 1),
+ * reading: S = max(|u|+a) over the cell averages at the start of the step;
+ * the last step is shortened to land on t_end. */
+static double dt_rule_1d(int rule, double cfl, double h, double smax)
+{
+    return rule == 1 ? cfl * pow(h, 5.0 / 3.0) / smax : cfl * h / smax;
+}
+
+/* Advance U ([3][n], in place) to t_end (or max_steps).  out[0] = t reached,
+ * out[1] = steps, out[2] = total limited cells, out[3] = min rho, out[4] = min p
+ * over all step outputs.  Returns 0 or a negative code (-4: no valid dt). */
+int orc_run_1d(int n, double *U, int bc_lo, int bc_hi, double h, const orc_params *P,
+               double t_end, double cfl, int rule, long max_steps, double *out)
+{
+    size_t m = 3u * (size_t)n;
+    double *U1 = (double *)malloc(sizeof(double) * m), *U2 = (double *)malloc(sizeof(double) * m);
+    if (!U1 || !U2) { free(U1); free(U2); return -2; }
+    double t = 0.0, minr = INFINITY, minp = INFINITY;
+    long steps = 0, lim = 0;
+    int rc = 0;
+    while (t < t_end && steps < max_steps) {
+        double dt = dt_rule_1d(rule, cfl, h, orc_max_speed_1d(n, U, P->gamma));
+        if (!(dt > 0.0) || dt == INFINITY) { rc = -4; break; }
+        if (t + dt > t_end) dt = t_end - t;
+        long r1 = orc_stage_1d(n, U, U, U1, 1, dt, bc_lo, bc_hi, h, P);
+        long r2 = r1 >= 0 ? orc_stage_1d(n, U, U1, U2, 2, dt, bc_lo, bc_hi, h, P) : r1;
+        long r3 = r2 >= 0 ? orc_stage_1d(n, U, U2, U1, 3, dt, bc_lo, bc_hi, h, P) : r2;
+        if (r3 < 0) { rc = (int)r3; break; }
+        lim += r1 + r2 + r3;
+        memcpy(U, U1, sizeof(double) * m);
+        for (int i = 0; i < n; ++i) {
+            double r = U[i], u = U[n + i] / r;
+            double p = (P->gamma - 1.0) * (U[2 * n + i] - 0.5 * r * u * u);
+            if (!(r >= minr)) minr = r;
+            if (!(p >= minp)) minp = p;
+        }
+        t += dt;
+        ++steps;
+    }
+    out[0] = t; out[1] = (double)steps; out[2] = (double)lim; out[3] = minr; out[4] = minp;
+    free(U1); free(U2);
+    return rc;
+}
+
+/* ------------------------------------------------------------------- 2D
+ * Reading (the paper is one-dimensional): dimension by dimension.  Each x-line
+ * (row) and y-line (column) is treated as a 1D line of 2D cell averages with
+ * the normal momentum rho u (x) or rho v (y); L = L_x + L_y from the same
+ * stage input, and the limiter of each direction uses the same averages. */
+long orc_rhs_2d_speed(int nx, int ny, const double *U, const int *bc, double dx, double dy,
+                      const orc_params *P, double *L, double *smax /* [2] or NULL */)
+{
+    long ncell = (long)nx * ny;
+    double er, ee;
+    orc_eps(ncell, 4, U, P->eps_cap, &er, &ee);
+    long nlim = 0;
+    int err = 0;
+    for (long i = 0; i < 4 * ncell; ++i) L[i] = 0.0;
+    double *Lx = (double *)calloc((size_t)(4 * ncell), sizeof(double));
+    if (!Lx) return -2;
+
+    double sx = 0.0, sy = 0.0;
+#pragma omp parallel reduction(+ : nlim) reduction(max : sx, sy)
+    {
+        int mx = nx > ny ? nx : ny;
+        double *line = (double *)malloc(sizeof(double) * 4u * (size_t)mx);
+        double *lo = (double *)malloc(sizeof(double) * 4u * (size_t)mx);
+#pragma omp for schedule(static)
+        for (int y = 0; y < ny; ++y) {
+            for (int k = 0; k < 4; ++k)
+                for (int x = 0; x < nx; ++x) line[(size_t)k * nx + x] = U[k * ncell + (long)y * nx + x];
+            double s = 0.0;
+            long r = orc_line_op(nx, 4, 1, line, bc[0], bc[1], dx, P, er, ee, lo, NULL, &s);
+            if (s > sx || s != s) sx = s != s ? INFINITY : s;
+            if (r < 0) err = (int)r; else nlim += r;
+            for (int k = 0; k < 4; ++k)
+                for (int x = 0; x < nx; ++x) Lx[k * ncell + (long)y * nx + x] = lo[(size_t)k * nx + x];
+        }
+#pragma omp for schedule(static)
+        for (int x = 0; x < nx; ++x) {
+            for (int k = 0; k < 4; ++k)
+                for (int y = 0; y < ny; ++y) line[(size_t)k * ny + y] = U[k * ncell + (long)y * nx + x];
+            double s = 0.0;
+            long r = orc_line_op(ny, 4, 2, line, bc[2], bc[3], dy, P, er, ee, lo, NULL, &s);
+            if (s > sy || s != s) sy = s != s ? INFINITY : s;
+            if (r < 0) err = (int)r; else nlim += r;
+            for (int k = 0; k < 4; ++k)
+                for (int y = 0; y < ny; ++y) L[k * ncell + (long)y * nx + x] = lo[(size_t)k * ny + y];
+        }
+        free(line);
+        free(lo);
+    }
+    for (long i = 0; i < 4 * ncell; ++i) L[i] = Lx[i] + L[i];
+    free(Lx);
+    if (smax) { smax[0] = sx; smax[1] = sy; }
+    return err ? err : nlim;
+}
+
+long orc_rhs_2d(int nx, int ny, const double *U, const int *bc, double dx, double dy,
+                const orc_params *P, double *L)
+{
+    return orc_rhs_2d_speed(nx, ny, U, bc, dx, dy, P, L, NULL);
+}
+
+long orc_stage_2d(int nx, int ny, const double *U0, const double *Us, double *Uo, int stage,
+                  double dt, const int *bc, double dx, double dy, const orc_params *P)
+{
+    long m = 4L * nx * ny;
+    double *L = (double *)malloc(sizeof(double) * (size_t)m);
+    if (!L) return -2;
+    long r = orc_rhs_2d(nx, ny, Us, bc, dx, dy, P, L);
+    if (r >= 0) rk3_combine(m, stage, dt, U0, Us, L, Uo);
+    free(L);
+    return r;
+}
+
+/* out[0] = max(|u| + a), out[1] = max(|v| + a) over cells. */
+void orc_max_speed_2d(int nx, int ny, const double *U, double gamma, double *out)
+{
+    long nc = (long)nx * ny;
+    double sx = 0.0, sy = 0.0, cell[4];
+    for (long i = 0; i < nc; ++i) {
+        for (int k = 0; k < 4; ++k) cell[k] = U[k * nc + i];
+        max_into(&sx, wave_speed(gamma, 4, 1, cell));
+        max_into(&sy, wave_speed(gamma, 4, 2, cell));
+    }
+    out[0] = sx;
+    out[1] = sy;
+}
+
+/* Reading: dt = cfl / (Sx/dx + Sy/dy) with Sx = max(|u|+a), Sy = max(|v|+a)
+ * over the cell averages at the start of the step; last step clipped. */
+int orc_run_2d(int nx, int ny, double *U, const int *bc, double dx, double dy,
+               const orc_params *P, double t_end, double cfl, long max_steps, double *out)
+{
+    size_t m = 4u * (size_t)nx * (size_t)ny;
+    double *U1 = (double *)malloc(sizeof(double) * m), *U2 = (double *)malloc(sizeof(double) * m);
+    if (!U1 || !U2) { free(U1); free(U2); return -2; }
+    double t = 0.0, minr = INFINITY, minp = INFINITY, s[2];
+    long steps = 0, lim = 0;
+    int rc = 0;
+    while (t < t_end && steps < max_steps) {
+        orc_max_speed_2d(nx, ny, U, P->gamma, s);
+        double dt = cfl / (s[0] / dx + s[1] / dy);
+        if (!(dt > 0.0) || dt == INFINITY) { rc = -4; break; }
+        if (t + dt > t_end) dt = t_end - t;
+        long r1 = orc_stage_2d(nx, ny, U, U, U1, 1, dt, bc, dx, dy, P);
+        long r2 = r1 >= 0 ? orc_stage_2d(nx, ny, U, U1, U2, 2, dt, bc, dx, dy, P) : r1;
+        long r3 = r2 >= 0 ? orc_stage_2d(nx, ny, U, U2, U1, 3, dt, bc, dx, dy, P) : r2;
+        if (r3 < 0) { rc = (int)r3; break; }
+        lim += r1 + r2 + r3;
+        memcpy(U, U1, sizeof(double) * m);
+        long nc = (long)nx * ny;
+        for (long i = 0; i < nc; ++i) {
+            double r = U[i], u = U[nc + i] / r, v = U[2 * nc + i] / r;
+            double p = (P->gamma - 1.0) * (U[3 * nc + i] - 0.5 * r * (u * u + v * v));
+            if (!(r >= minr)) minr = r;
+            if (!(p >= minp)) minp = p;
+        }
+        t += dt;
+        ++steps;
+    }
+    out[0] = t; out[1] = (double)steps; out[2] = (double)lim; out[3] = minr; out[4] = minp;
+    free(U1); free(U2);
+    return rc;
+}
+
+/* ------------------------------------------------------- batched 1D ensemble
+ * Independent problems packed [3][sum n_i]; each advances with its own dt
+ * (rule 0) to t_end.  OpenMP over problems. Returns 0 or the first error. */
+int orc_run_batch(int nprob, const long *offsets, double *U, const int *bc, const double *dxs,
+                  const orc_params *P, double t_end, double cfl, long total, double *steps_out)
+{
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < nprob; ++i) {
+        int n = (int)(offsets[i + 1] - offsets[i]);
+        double *line = (double *)malloc(sizeof(double) * 3u * (size_t)n), out[5];
+        for (int k = 0; k < 3; ++k)
+            memcpy(line + (size_t)k * n, U + (size_t)k * total + offsets[i], sizeof(double) * n);
+        int r = orc_run_1d(n, line, bc[2 * i], bc[2 * i + 1], dxs[i], P, t_end, cfl, 0, 1L << 40, out);
+        if (r) err = r;
+        for (int k = 0; k < 3; ++k)
+            memcpy(U + (size_t)k * total + offsets[i], line + (size_t)k * n, sizeof(double) * n);
+        if (steps_out) steps_out[i] = out[1];
+        free(line);
+    }
+    return err;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
