@@ -1,0 +1,155 @@
+/*
+ * pp_cweno.h - C ABI of the MI355X (gfx950) library for the positivity-
+ * preserving fifth-order finite-volume compact-WENO scheme for the Euler
+ * equations (Guo, Xiong & Shi, arXiv 1402.5618).
+ *
+ * The library advances cell averages of the conserved variables
+ *   1D: U = (rho, rho u, E)            (Sec. 1, eq. (1DEuler))
+ *   2D: U = (rho, rho u, rho v, E)     (dimension-by-dimension extension)
+ * on a uniform grid (Sec. 2.2, h = (b - a) / N) with the per-stage spatial
+ * operator L(U) of eq. (1DEulerFV-b): component-wise compact-WENO
+ * reconstruction (eqs. (CWENO-FV), (weight) and their mirror), the
+ * positivity-preserving limiter (Sec. 2.4, steps 1-4), the HLLC flux
+ * (eqs. (HLLC), (contact-v), (star-l), (acoustic ws)), and the SSP-RK3
+ * stage update of eq. (RK3).
+ *
+ * Conventions for every entry point:
+ *  - All state/output pointers are DEVICE pointers to float64 arrays owned
+ *    by the caller; the library never frees them.  Layouts:
+ *      1D        [3][n]            component-major, contiguous
+ *      2D        [4][ny][nx]       component-major, x fastest
+ *      batched   [3][sum_i n_i]    problems back to back in config order
+ *  - Calls enqueue work on the stream given in the config and return
+ *    without synchronising, except pp_cweno_init, pp_cweno_status,
+ *    pp_cweno_run and pp_cweno_destroy, which synchronise that stream.
+ *  - Every call returns PP_OK (0) or a negative PP_E* code.  Argument
+ *    errors (PP_EINVAL / PP_EUNSUPPORTED) are detected on the host before
+ *    anything is launched and leave the context usable.  PP_EDEVICE means a
+ *    HIP runtime error; the context must then be destroyed.
+ *    pp_cweno_last_error() gives a message for the last failure.
+ *  - One context per host thread / stream; calls on one context are not
+ *    thread-safe.
+ */
+#ifndef PP_CWENO_H
+#define PP_CWENO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pp_cweno_ctx pp_cweno_ctx; /* opaque, library-owned */
+
+enum {
+    PP_OK = 0,
+    PP_EINVAL = -1,        /* invalid argument (checked before any launch)          */
+    PP_ENOMEM = -2,        /* device or host allocation failed                      */
+    PP_EDEVICE = -3,       /* HIP runtime error                                     */
+    PP_ESTATE = -4,        /* a stage produced a non-finite value or left the set G */
+    PP_EUNSUPPORTED = -5   /* valid but not supported by this build (e.g. size)     */
+};
+
+/* Boundary conditions (Sec. 3: periodic, Neumann/transmissive, reflective). */
+enum { PP_BC_PERIODIC = 0, PP_BC_TRANSMISSIVE = 1, PP_BC_REFLECTIVE = 2 };
+
+/* Arithmetic of the reconstruction, solves and HLLC.  PP_FP64: all double.
+ * PP_MIXED: weights, rows, tridiagonal solves (plus one FP64-residual
+ * refinement sweep) and HLLC in float; limiter, flux difference and stage
+ * accumulation in double.  Inputs and outputs are float64 in both cases. */
+enum { PP_FP64 = 0, PP_MIXED = 1 };
+
+/* Time-step rules for pp_cweno_run (reading of condition (CFL-CD)):
+ *  PP_DT_CFL : dt = cfl * h / S            (1D),  cfl / (Sx/dx + Sy/dy) (2D)
+ *  PP_DT_H53 : dt = cfl * h^(5/3) / S      (Example 3.1, Table 1; 1D only)
+ * with S = max(|u|+a) over the cell averages at the start of each step; the
+ * last step is shortened to land on t_end. */
+enum { PP_DT_CFL = 0, PP_DT_H53 = 1 };
+
+typedef struct {
+    int ndim;            /* 1, or 2 (dimension-by-dimension sweeps)                    */
+    int64_t nx, ny;      /* cells (ny = 1 in 1D); nx <= 4096 in 1D, nx, ny <= 2048 in 2D */
+    double dx, dy;       /* uniform spacing h > 0 (dy ignored in 1D)                     */
+    double gamma;        /* ratio of specific heats > 1 (1.4 for air)                   */
+    int bc[4];           /* x_lo, x_hi, y_lo, y_hi: PP_BC_*; periodic on both ends of an
+                            axis or on neither                                          */
+    int precision;       /* PP_FP64 or PP_MIXED                                         */
+    double weno_eps;     /* epsilon of the WENO-Z weights, eq. (weight): 1e-13          */
+    double pp_eps_cap;   /* cap of the limiter's epsilon, step 1: 1e-13                 */
+    double gl_w1;        /* Gauss-Lobatto end weight w^_1 in (0, 1/2): 1/12 (M = 4)      */
+    int64_t nbatch;      /* 0: single grid.  > 0: batched 1D ensemble of nbatch lines   */
+    const int64_t *lengths; /* host [nbatch] cells per problem (batched only; 3..4096)  */
+    const double *dxs;      /* host [nbatch] spacing per problem (batched only)         */
+    const int *bcs;         /* host [nbatch][2] boundary codes (batched; non-periodic)  */
+    void *stream;        /* hipStream_t to enqueue on (NULL: the null stream)           */
+} pp_cweno_config;
+
+/* Fill *cfg with defaults: ndim 1, gamma 1.4, epsilons 1e-13, gl_w1 1/12, FP64,
+ * periodic, no batch, null stream.  Sizes and spacings are left zero. */
+void pp_cweno_config_defaults(pp_cweno_config *cfg);
+
+/* Validate cfg, allocate device scratch, and return a context in *out
+ * (caller frees it with pp_cweno_destroy).  Host arrays of the config are
+ * copied.  Synchronises the stream. */
+int pp_cweno_init(const pp_cweno_config *cfg, pp_cweno_ctx **out);
+
+/* L = L(U): the limited spatial operator of eq. (1DEuler-FVCW) (2D: L_x + L_y)
+ * for the state U, with the limiter's epsilon computed from U (step 1).
+ * U and L are distinct device arrays in the grid layout. */
+int pp_cweno_rhs(pp_cweno_ctx *ctx, const double *U, double *L);
+
+/* One stage of eq. (RK3): Uout = a*U0 + b*(Us + dt*L(Us)) with
+ * (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3) for stage = 1, 2, 3.
+ * Uout must not alias U0 or Us. */
+int pp_cweno_stage(pp_cweno_ctx *ctx, const double *U0, const double *Us, double *Uout,
+                   int stage, double dt);
+
+/* One SSP-RK3 step of size dt, in place on U (device). */
+int pp_cweno_step(pp_cweno_ctx *ctx, double *U, double dt);
+
+/* Advance U (in place) from t = 0 until t_end or nsteps_max steps, whichever
+ * comes first, with the time-step rule `rule` (PP_DT_*) and factor cfl; dt is
+ * computed on the device every step.  Writes the time reached and the number
+ * of steps taken to *t_out, *steps_out (host; either may be NULL).
+ * Synchronises; returns PP_ESTATE if a stage left the admissible set. */
+int pp_cweno_run(pp_cweno_ctx *ctx, double *U, double t_end, int64_t nsteps_max, double cfl,
+                 int rule, double *t_out, int64_t *steps_out);
+
+/* Batched ensemble: one SSP-RK3 step of every problem of the packed state
+ * Upacked, problem i with its own dt_dev[i] (device array); problems with
+ * dt_dev[i] <= 0 are left unchanged.  One persistent launch per stage. */
+int pp_cweno_batch_step(pp_cweno_ctx *ctx, double *Upacked, const double *dt_dev);
+
+/* Batched ensemble driver: advance every problem to t_end with per-problem
+ * dt = cfl * dx_i / S_i (S_i from problem i's averages), nsteps_max steps at
+ * most; steps_out (host [nbatch], may be NULL) receives each problem's step
+ * count.  Synchronises. */
+int pp_cweno_batch_run(pp_cweno_ctx *ctx, double *Upacked, double t_end, int64_t nsteps_max,
+                       double cfl, int64_t *steps_out);
+
+/* out_dev[0] = max(|u|+a) (2D: also out_dev[1] = max(|v|+a)) over the cell
+ * averages of U (device pointers). */
+int pp_cweno_max_speed(pp_cweno_ctx *ctx, const double *U, double *out_dev);
+
+/* Synchronise the stream and return the sticky status: *flags (may be NULL)
+ * receives bit 0 = non-finite value seen, bit 1 = rho <= 0 or p <= 0 seen in a
+ * stage output.  Returns PP_ESTATE if any bit is set (and clears them). */
+int pp_cweno_status(pp_cweno_ctx *ctx, uint32_t *flags);
+
+/* Test hook: reconstructed interface states and face fluxes of the operator
+ * for state U (FP64 or mixed, as configured): um, up [ncomp][cells] are
+ * U-_{i+1/2} and U+_{i-1/2} before limiting; flux [ncomp][lines][n+1].
+ * 1D only (lines = 1).  Any pointer may be NULL. */
+int pp_cweno_debug_line(pp_cweno_ctx *ctx, const double *U, double *um, double *up,
+                        double *flux);
+
+/* Message for the last error on ctx (or for init failures when ctx is NULL). */
+const char *pp_cweno_last_error(const pp_cweno_ctx *ctx);
+
+/* Release the context and its device scratch (synchronises).  NULL is a no-op. */
+void pp_cweno_destroy(pp_cweno_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PP_CWENO_H */

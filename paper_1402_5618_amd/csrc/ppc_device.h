@@ -1,0 +1,235 @@
+// Device building blocks of the compact-WENO line operator for gfx950.
+//
+// Everything here is per-lane arithmetic; the kernels that arrange lanes,
+// LDS and HBM traffic live in ppcweno.hip.  Section and equation names refer
+// to arXiv 1402.5618 (Guo, Xiong & Shi).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ppc {
+
+// ------------------------------------------------------------ reductions
+// Order-preserving map of a double onto int64 so that global atomicMin/Max on
+// 64-bit integers give exact, order-independent min/max of doubles.
+__device__ __forceinline__ long long ord_enc(double x) {
+    long long i = __double_as_longlong(x);
+    return i >= 0 ? i : (i ^ 0x7fffffffffffffffLL);
+}
+__device__ __forceinline__ double ord_dec(long long i) {
+    return __longlong_as_double(i >= 0 ? i : (i ^ 0x7fffffffffffffffLL));
+}
+constexpr long long kEncPosInf = 0x7ff0000000000000LL;  // ord_enc(+inf)
+constexpr long long kEncZero = 0;                       // ord_enc(+0.0)
+
+// ------------------------------------------------------- Sec 2.2 weights
+// Smoothness indicators of the three candidates of the "-" side at node
+// j+1/2 from v0..v4 = ubar_{j-2..j+2}, then WENO-Z weights (power 2) with the
+// three divisions of eq. (weight) folded into one reciprocal:
+//   alpha_k ~ c_k (d_k^2 + tau^2) * prod_{l != k} d_l^2,  d_k = beta_k + eps.
+// Exact in real arithmetic; in FP64 no product leaves the normal range for
+// |ubar| < 1e50.
+template <typename T>
+__device__ __forceinline__ void wenoz_weights(T v0, T v1, T v2, T v3, T v4, T eps, T& w0, T& w1,
+                                              T& w2) {
+    const T k13 = T(13) / T(12), k14 = T(0.25);
+    T s0 = v0 - T(2) * v1 + v2, t0 = v0 - T(4) * v1 + T(3) * v2;
+    T s1 = v1 - T(2) * v2 + v3, t1 = v1 - v3;
+    T s2 = v2 - T(2) * v3 + v4, t2 = T(3) * v2 - T(4) * v3 + v4;
+    T b0 = k13 * s0 * s0 + k14 * t0 * t0;
+    T b1 = k13 * s1 * s1 + k14 * t1 * t1;
+    T b2 = k13 * s2 * s2 + k14 * t2 * t2;
+    T tau = b2 - b0;
+    T tt = tau * tau;
+    T d0 = b0 + eps, d1 = b1 + eps, d2 = b2 + eps;
+    T e0 = d0 * d0, e1 = d1 * d1, e2 = d2 * d2;
+    T a0 = T(0.2) * (e0 + tt) * (e1 * e2);
+    T a1 = T(0.5) * (e1 + tt) * (e0 * e2);
+    T a2 = T(0.3) * (e2 + tt) * (e0 * e1);
+    T inv = T(1) / (a0 + a1 + a2);
+    w0 = a0 * inv;
+    w1 = a1 * inv;
+    w2 = a2 * inv;
+}
+
+// Row of eq. (CWENO-FV) at node j+1/2 ("-" side): a u~_{j-1/2} + b u~_{j+1/2}
+// + c u~_{j+3/2} = r, right side from ubar_{j-1}, ubar_j, ubar_{j+1}.  The "+"
+// side is the same row on the mirrored line.
+template <typename T>
+__device__ __forceinline__ void cweno_row(T w0, T w1, T w2, T um1, T u0, T up1, T& a, T& b, T& c,
+                                          T& r) {
+    const T third = T(1) / T(3), sixth = T(1) / T(6);
+    a = (T(2) * w0 + w1) * third;
+    b = (w0 + T(2) * (w1 + w2)) * third;
+    c = w2 * third;
+    r = (w0 * um1 + (T(5) * (w0 + w1) + w2) * u0 + (w1 + T(5) * w2) * up1) * sixth;
+}
+
+// Closure of a non-periodic line: explicit fifth-order WENO-Z value at node
+// j+1/2 ("-" side) from ubar_{j-2..j+2}, linear weights (0.1, 0.6, 0.3).
+__device__ __forceinline__ double weno5z_value(double v0, double v1, double v2, double v3,
+                                               double v4, double eps) {
+    const double k13 = 13.0 / 12.0;
+    double s0 = v0 - 2.0 * v1 + v2, t0 = v0 - 4.0 * v1 + 3.0 * v2;
+    double s1 = v1 - 2.0 * v2 + v3, t1 = v1 - v3;
+    double s2 = v2 - 2.0 * v3 + v4, t2 = 3.0 * v2 - 4.0 * v3 + v4;
+    double b0 = k13 * s0 * s0 + 0.25 * t0 * t0;
+    double b1 = k13 * s1 * s1 + 0.25 * t1 * t1;
+    double b2 = k13 * s2 * s2 + 0.25 * t2 * t2;
+    double tau = b2 - b0;
+    double q0 = tau / (b0 + eps), q1 = tau / (b1 + eps), q2 = tau / (b2 + eps);
+    double a0 = 0.1 * (1.0 + q0 * q0), a1 = 0.6 * (1.0 + q1 * q1), a2 = 0.3 * (1.0 + q2 * q2);
+    double p0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) / 6.0;
+    double p1 = (-v1 + 5.0 * v2 + 2.0 * v3) / 6.0;
+    double p2 = (2.0 * v2 + 5.0 * v3 - v4) / 6.0;
+    return (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
+}
+
+// ------------------------------------------------------------- Sec 2.4
+// HLLC flux across a face with normal momentum component NRM (1: x, 2: y).
+// Contact speed with rho_r in its right term, S_R = max of its candidates,
+// sound speeds from max(p, 0), and the vacuum midpoint when the contact-speed
+// denominator vanishes (two separating states of zero sound speed).
+template <int NC, int NRM>
+__device__ __forceinline__ void hllc_flux(double g, const double (&Ul)[NC], const double (&Ur)[NC],
+                                          double (&F)[NC]) {
+    constexpr int IE = NC - 1;
+    constexpr int TG = (NC == 4) ? 3 - NRM : -1;
+    const double rl = Ul[0], rr = Ur[0];
+    const double irl = 1.0 / rl, irr = 1.0 / rr;
+    const double ul = Ul[NRM] * irl, ur = Ur[NRM] * irr;
+    double vl = 0.0, vr = 0.0;
+    if constexpr (TG > 0) {
+        vl = Ul[TG] * irl;
+        vr = Ur[TG] * irr;
+    }
+    const double El = Ul[IE], Er = Ur[IE];
+    const double pl = (g - 1.0) * (El - 0.5 * rl * (ul * ul + vl * vl));
+    const double pr = (g - 1.0) * (Er - 0.5 * rr * (ur * ur + vr * vr));
+    const double al = sqrt(g * fmax(pl, 0.0) * irl), ar = sqrt(g * fmax(pr, 0.0) * irr);
+    const double Hl = (El + pl) * irl, Hr = (Er + pr) * irr;
+    const double R = sqrt(rr * irl);
+    const double i1R = 1.0 / (1.0 + R);
+    const double ut = (ul + ur * R) * i1R, vt = (vl + vr * R) * i1R, Ht = (Hl + Hr * R) * i1R;
+    const double at = sqrt(fmax((g - 1.0) * (Ht - 0.5 * (ut * ut + vt * vt)), 0.0));
+    const double SL = fmin(ul - al, ut - at);
+    const double SR = fmax(ur + ar, ut + at);
+    const double den = rr * (SR - ur) - rl * (SL - ul);
+    const double SM =
+        den > 0.0 ? (rr * ur * (SR - ur) - rl * ul * (SL - ul) + pl - pr) / den : 0.5 * (SL + SR);
+    if (SL > 0.0) {
+        F[0] = rl * ul;
+        F[NRM] = rl * ul * ul + pl;
+        if constexpr (TG > 0) F[TG] = rl * ul * vl;
+        F[IE] = ul * (El + pl);
+    } else if (SM > 0.0) {
+        const double id = 1.0 / (SL - SM);
+        const double ps = rl * (ul - SL) * (ul - SM) + pl;
+        const double s0 = rl * (SL - ul) * id;
+        const double sn = ((SL - ul) * rl * ul + (ps - pl)) * id;
+        const double se = ((SL - ul) * El - pl * ul + ps * SM) * id;
+        F[0] = rl * ul + SL * (s0 - rl);
+        F[NRM] = rl * ul * ul + pl + SL * (sn - Ul[NRM]);
+        if constexpr (TG > 0) F[TG] = rl * ul * vl + SL * (s0 * vl - Ul[TG]);
+        F[IE] = ul * (El + pl) + SL * (se - El);
+    } else if (SR >= 0.0 && SR > SM) {
+        const double id = 1.0 / (SR - SM);
+        const double ps = rr * (ur - SR) * (ur - SM) + pr;
+        const double s0 = rr * (SR - ur) * id;
+        const double sn = ((SR - ur) * rr * ur + (ps - pr)) * id;
+        const double se = ((SR - ur) * Er - pr * ur + ps * SM) * id;
+        F[0] = rr * ur + SR * (s0 - rr);
+        F[NRM] = rr * ur * ur + pr + SR * (sn - Ur[NRM]);
+        if constexpr (TG > 0) F[TG] = rr * ur * vr + SR * (s0 * vr - Ur[TG]);
+        F[IE] = ur * (Er + pr) + SR * (se - Er);
+    } else {
+        F[0] = rr * ur;
+        F[NRM] = rr * ur * ur + pr;
+        if constexpr (TG > 0) F[TG] = rr * ur * vr;
+        F[IE] = ur * (Er + pr);
+    }
+}
+
+// e = E/rho - |m|^2 / (2 rho^2), the specific internal energy of the set G.
+template <int NC>
+__device__ __forceinline__ double spec_e(const double (&U)[NC]) {
+    double m2 = 0.0;
+#pragma unroll
+    for (int k = 1; k < NC - 1; ++k) m2 += U[k] * U[k];
+    return U[NC - 1] / U[0] - 0.5 * m2 / (U[0] * U[0]);
+}
+
+// Limiter step 4: root t in [0, 1] of e(Ubar + t (W - Ubar)) = eps via
+// rho E - |m|^2/2 - eps rho^2 = A t^2 + B t + C, t = 2C / (-B + sqrt(B^2 - 4AC)).
+template <int NC>
+__device__ __forceinline__ double pp_root(double eps, const double (&Ub)[NC],
+                                          const double (&W)[NC]) {
+    constexpr int IE = NC - 1;
+    double D[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) D[k] = W[k] - Ub[k];
+    double dm2 = 0.0, mdm = 0.0, m2 = 0.0;
+#pragma unroll
+    for (int k = 1; k < IE; ++k) {
+        dm2 += D[k] * D[k];
+        mdm += Ub[k] * D[k];
+        m2 += Ub[k] * Ub[k];
+    }
+    const double A = D[0] * D[IE] - 0.5 * dm2 - eps * D[0] * D[0];
+    const double B = Ub[0] * D[IE] + Ub[IE] * D[0] - mdm - 2.0 * eps * Ub[0] * D[0];
+    const double C = Ub[0] * Ub[IE] - 0.5 * m2 - eps * Ub[0] * Ub[0];
+    if (C <= 0.0) return 0.0;
+    const double disc = fmax(B * B - 4.0 * A * C, 0.0);
+    double t = 2.0 * C / (-B + sqrt(disc));
+    if (!(t >= 0.0)) t = 0.0;
+    return fmin(t, 1.0);
+}
+
+// Positivity-preserving limiter of one cell (Sec 2.4, steps 1-4): Um = U-_{j+1/2},
+// Up = U+_{j-1/2}, limited in place.  Returns 1 if anything changed.
+template <int NC>
+__device__ __forceinline__ int pp_limit(double w1, double eps_rho, double eps_e,
+                                        const double (&Ub)[NC], double (&Um)[NC],
+                                        double (&Up)[NC]) {
+    int active = 0;
+    const double i12 = 1.0 / (1.0 - 2.0 * w1);
+    const double rmid = (Ub[0] - w1 * Up[0] - w1 * Um[0]) * i12;
+    const double rmin = fmin(fmin(Um[0], Up[0]), rmid);
+    if (rmin < eps_rho) {
+        const double th1 = fmin((Ub[0] - eps_rho) / (Ub[0] - rmin), 1.0);
+        if (th1 < 1.0) {
+            Um[0] = th1 * (Um[0] - Ub[0]) + Ub[0];
+            Up[0] = th1 * (Up[0] - Ub[0]) + Ub[0];
+            active = 1;
+        }
+    }
+    double W3[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) W3[k] = (Ub[k] - w1 * Up[k] - w1 * Um[k]) * i12;
+    double th2 = 1.0;
+    if (!(Um[0] > 0.0) || spec_e<NC>(Um) < eps_e) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, Um));
+    if (!(Up[0] > 0.0) || spec_e<NC>(Up) < eps_e) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, Up));
+    if (!(W3[0] > 0.0) || spec_e<NC>(W3) < eps_e) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, W3));
+    if (th2 < 1.0) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            Um[k] = th2 * (Um[k] - Ub[k]) + Ub[k];
+            Up[k] = th2 * (Up[k] - Ub[k]) + Ub[k];
+        }
+        active = 1;
+    }
+    return active;
+}
+
+// |u_n| + a of a state, a pressure negative by roundoff counting as 0.
+template <int NC, int NRM>
+__device__ __forceinline__ double wave_speed(double g, const double (&U)[NC]) {
+    double m2 = 0.0;
+#pragma unroll
+    for (int k = 1; k < NC - 1; ++k) m2 += U[k] * U[k];
+    const double ir = 1.0 / U[0];
+    const double p = (g - 1.0) * (U[NC - 1] - 0.5 * m2 * ir);
+    return fabs(U[NRM] * ir) + sqrt(g * fmax(p, 0.0) * ir);
+}
+
+}  // namespace ppc

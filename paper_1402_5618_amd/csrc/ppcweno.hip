@@ -1,0 +1,1374 @@
+// MI355X (gfx950) implementation of the per-stage operator of the
+// positivity-preserving fifth-order finite-volume compact-WENO scheme
+// (arXiv 1402.5618) behind the C ABI of include/pp_cweno.h.
+//
+// Line kernel (one workgroup per grid line, or per problem of a batch):
+//   phase 0  stage the line (and 3 ghost cells per side) in LDS;
+//   phase 1  every (component, side) system gets a 64-lane wave (two waves
+//            for lines longer than 2048): lane k chases chunk k of the rows
+//            of eq. (CWENO-FV) in registers, the chunk separators form a
+//            small tridiagonal system solved by parallel cyclic reduction in
+//            LDS, then each lane back-substitutes its chunk.  The "+" system
+//            is the "-" system of the mirrored line, so one code path serves
+//            both sides and the "+" chase runs from the right end;
+//   phase 2  the limiter (Sec 2.4) per cell, the HLLC flux per face (each
+//            face once), the flux difference (eq. (1DEulerFV-b)) and the
+//            epilogue: write L, or the RK3 stage combination of eq. (RK3).
+// 2D: x-lines run on the [4][ny][nx] state, y-lines on a transposed copy
+// [4][nx][ny]; a tiled combine kernel forms U_{s+1} = a Un + b (Us + dt (Lx + Ly)),
+// writes it in both layouts and reduces the next stage's limiter epsilon and
+// the next step's wave speeds with order-independent atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pp_cweno.h"
+#include "ppc_device.h"
+
+using namespace ppc;
+
+namespace {
+
+constexpr int kCH = 32;      // max rows of one chunk held in registers
+constexpr int kCPT = 8;      // max cells per thread in phase 2
+constexpr int kNG = 3;       // ghost cells per side
+
+__device__ __forceinline__ int padi(int e) { return e + (e >> 5); }
+
+// Device scalars of a run: limiter epsilons per stage slot, wave speeds,
+// time step, time, step count, sticky status.
+struct Scal {
+    long long eps[3][2];   // slot s: encoded min rho, min e of a stage input
+    long long spd[2];      // encoded max(|u|+a), max(|v|+a)
+    double dt, t;
+    long long steps;
+    int active;
+    unsigned status;
+};
+
+struct LineArgs {
+    const double* U;        // stage input
+    const double* U0;       // RK base (stage mode)
+    double* out;            // L (mode 0) or stage output (mode 1)
+    long long cs;           // component stride
+    long long ls;           // line stride (used when off == nullptr)
+    const long long* off;   // batched: element offset of each problem
+    const int* nline;       // batched: cells of each problem
+    const double* hline;    // batched: spacing of each problem
+    const int* bcline;      // batched: [2] boundary codes of each problem
+    double* dtline;         // batched: dt of each problem (<= 0: inactive)
+    double* tline;          // batched: time of each problem
+    const int* order;       // batched: processing order (longest first)
+    int* counter;           // batched: persistent work counter
+    int n, nlines;
+    int bc_lo, bc_hi;
+    int seg_max;            // max cells per phase-2 segment
+    double h, gamma, w1, weno_eps, eps_cap, t_end, cfl;
+    const long long* eps_enc;  // encoded (min rho, min e) of the whole grid, or nullptr
+    const double* dt_dev;      // stage mode: dt on the device, or nullptr -> dt_val
+    double dt_val;
+    double rk_a, rk_b;
+    int mode;               // 0: write L; 1: write the stage combination
+    int stage;              // 1..3 (batched stage 3 advances dt and t)
+    Scal* scal;             // single grid: active flag, status, speed reduction
+    unsigned* status;
+    double* dbg_um;
+    double* dbg_up;
+    double* dbg_flux;
+};
+
+template <int NT>
+__device__ __forceinline__ void block_min2(double& a, double& b, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a = fmin(a, __shfl_xor(a, o));
+        b = fmin(b, __shfl_xor(b, o));
+    }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) {
+        red[2 * w] = a;
+        red[2 * w + 1] = b;
+    }
+    __syncthreads();
+    a = red[0];
+    b = red[1];
+    for (int i = 1; i < NT / 64; ++i) {
+        a = fmin(a, red[2 * i]);
+        b = fmin(b, red[2 * i + 1]);
+    }
+    __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ double block_max(double a, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a = fmax(a, __shfl_xor(a, o));
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) red[w] = a;
+    __syncthreads();
+    a = red[0];
+    for (int i = 1; i < NT / 64; ++i) a = fmax(a, red[i]);
+    __syncthreads();
+    return a;
+}
+
+// One line (or one problem) through the whole operator.  NC components, NRM
+// the normal momentum component, W waves per system (lines up to 2048 W).
+template <int NC, int NRM, int W>
+__device__ void line_op(const LineArgs& A, int b, double* smem) {
+    constexpr int NS = 2 * NC;
+    constexpr int LANES = 64 * W;
+    constexpr int NT = NS * LANES;
+    const int tid = threadIdx.x;
+
+    // ---- problem geometry
+    const bool batched = A.off != nullptr;
+    const int n = batched ? A.nline[b] : A.n;
+    const double h = batched ? A.hline[b] : A.h;
+    const int bc_lo = batched ? A.bcline[2 * b] : A.bc_lo;
+    const int bc_hi = batched ? A.bcline[2 * b + 1] : A.bc_hi;
+    const long long base = batched ? A.off[b] : (long long)b * A.ls;
+    const bool cyclic = (bc_lo == PP_BC_PERIODIC);
+    double dt = 0.0;
+    if (A.mode == 1) dt = batched ? A.dtline[b] : (A.dt_dev ? *A.dt_dev : A.dt_val);
+    if (batched && !(dt > 0.0)) return;  // finished problem: leave it untouched
+
+    const double* __restrict__ U = A.U + base;
+    const int LP = padi(n + 2 * kNG - 1) + 1;   // padded LDS length of one component
+    double* sU = smem;                          // phase 0/1: [NC][LP]
+    // reduction scratch after the largest phase area (same formula as the host)
+    const long long area0 = (long long)NC * LP;
+    const long long area1 = (long long)NS * LANES * 8;
+    const long long area2 = (long long)NS * (A.seg_max + 2) + (long long)NC * NT;
+    long long area = area0 > area1 ? area0 : area1;
+    area = area > area2 ? area : area2;
+    double* red = smem + area;
+
+    // ---- phase 0: stage the line with ghosts; limiter epsilon
+    double mr = INFINITY, me = INFINITY;
+    for (int q = tid; q < n + 2 * kNG; q += NT) {
+        const int i = q - kNG;   // cell index, -3..n+2
+        int src;
+        double sgn[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sgn[c] = 1.0;
+        if (i >= 0 && i < n) {
+            src = i;
+        } else if (cyclic) {
+            src = (i + n) % n;
+        } else {
+            const int bc = i < 0 ? bc_lo : bc_hi;
+            if (bc == PP_BC_TRANSMISSIVE) {
+                src = i < 0 ? 0 : n - 1;
+            } else {   // reflective: mirror image, normal momentum negated
+                src = i < 0 ? (-i - 1) : (2 * n - 1 - i);
+                src = src < 0 ? 0 : (src >= n ? n - 1 : src);
+                sgn[NRM] = -1.0;
+            }
+        }
+        double cell[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            cell[c] = U[(long long)c * A.cs + src];
+            sU[c * LP + padi(q)] = sgn[c] * cell[c];
+        }
+        if (i >= 0 && i < n && A.eps_enc == nullptr) {
+            mr = fmin(mr, cell[0]);
+            me = fmin(me, spec_e<NC>(cell));
+        }
+    }
+    double eps_rho, eps_e;
+    if (A.eps_enc != nullptr) {
+        eps_rho = fmin(A.eps_cap, ord_dec(A.eps_enc[0]));
+        eps_e = fmin(A.eps_cap, ord_dec(A.eps_enc[1]));
+        __syncthreads();
+    } else {
+        block_min2<NT>(mr, me, red);   // contains the barriers
+        eps_rho = fmin(A.eps_cap, mr);
+        eps_e = fmin(A.eps_cap, me);
+    }
+
+    // ---- phase 1: chunked chasing of every (component, side) system
+    const int sys = tid / LANES, k = tid % LANES;
+    const int comp = sys >> 1;
+    const bool rev = (sys & 1) != 0;
+    int P = LANES;
+    while (P > n) P >>= 1;                  // chunks: power of two, <= n
+    const bool act = k < P;
+    const int r0 = (int)(((long long)k * n) / P);
+    const int r1 = (int)(((long long)(k + 1) * n) / P);
+    const int len = act ? r1 - r0 : 0;
+    const double* sUc = sU + comp * LP;
+    auto ub = [&](int m) -> double {
+        const int o = rev ? (n - 1 - m) : m;
+        return sUc[padi(o + kNG)];
+    };
+
+    double E0[kCH], E1[kCH], E2[kCH];
+    double ae = 0.0, be = 1.0, ce = 0.0, re = 0.0;
+    double gP = 0.0, gQ = 1.0, gS = 0.0;   // x_{r1-2} = gP + gQ L + gS R
+    double fP = 0.0, fQ = 0.0, fS = 1.0;   // x_{r0}   = fP + fQ L + fS R
+    if (act) {
+        const double weps = A.weno_eps;
+        double clo = 0.0, chi = 0.0;
+        if (!cyclic && r0 == 0) clo = weno5z_value(ub(-3), ub(-2), ub(-1), ub(0), ub(1), weps);
+        if (!cyclic && r1 == n)
+            chi = weno5z_value(ub(n - 2), ub(n - 1), ub(n), ub(n + 1), ub(n + 2), weps);
+        double v0 = ub(r0 - 2), v1 = ub(r0 - 1), v2 = ub(r0), v3 = ub(r0 + 1);
+        double cprev = 0.0, pprev = 0.0, qprev = 0.0;
+#pragma unroll
+        for (int j = 0; j < kCH; ++j) {
+            if (j < len) {
+                const int g = r0 + j;
+                const double v4 = ub(g + 2);
+                double w0, w1, w2, a, bb, c, r;
+                wenoz_weights<double>(v0, v1, v2, v3, v4, weps, w0, w1, w2);
+                cweno_row<double>(w0, w1, w2, v1, v2, v3, a, bb, c, r);
+                if (!cyclic) {
+                    if (g == 0) {
+                        r -= a * clo;
+                        a = 0.0;
+                    }
+                    if (g == n - 1) {
+                        r -= c * chi;
+                        c = 0.0;
+                    }
+                }
+                if (j < len - 1) {
+                    const double piv = (j == 0) ? bb : bb - a * cprev;
+                    const double ip = 1.0 / piv;
+                    const double cj = c * ip;
+                    const double pj = ((j == 0) ? r : r - a * pprev) * ip;
+                    const double qj = ((j == 0) ? -a : -a * qprev) * ip;
+                    E0[j] = cj;
+                    E1[j] = pj;
+                    E2[j] = qj;
+                    cprev = cj;
+                    pprev = pj;
+                    qprev = qj;
+                } else {
+                    ae = a;
+                    be = bb;
+                    ce = c;
+                    re = r;
+                }
+                v0 = v1;
+                v1 = v2;
+                v2 = v3;
+                v3 = v4;
+            }
+        }
+        // symbolic back substitution: x_j = P_j + Q_j L + S_j R
+        double Pn = 0.0, Qn = 0.0, Sn = 0.0;
+#pragma unroll
+        for (int j = kCH - 1; j >= 0; --j) {
+            if (j < len - 1) {
+                const double cj = E0[j];
+                double Pj, Qj, Sj;
+                if (j == len - 2) {
+                    Pj = E1[j];
+                    Qj = E2[j];
+                    Sj = -cj;
+                    gP = Pj;
+                    gQ = Qj;
+                    gS = Sj;
+                } else {
+                    Pj = E1[j] - cj * Pn;
+                    Qj = E2[j] - cj * Qn;
+                    Sj = -cj * Sn;
+                }
+                E0[j] = Pj;
+                E1[j] = Qj;
+                E2[j] = Sj;
+                Pn = Pj;
+                Qn = Qj;
+                Sn = Sj;
+            }
+        }
+        if (len >= 2) {
+            fP = E0[0];
+            fQ = E1[0];
+            fS = E2[0];
+        }
+    }
+    __syncthreads();   // line data no longer needed: reuse LDS
+    double* sF = smem;                          // [NS][LANES][3]
+    double* sR = smem + NS * LANES * 3;         // [NS][LANES][4]
+    double* sS = smem + NS * LANES * 7;         // [NS][LANES]
+    const int slot = sys * LANES + k;
+    if (act) {
+        sF[3 * slot + 0] = fP;
+        sF[3 * slot + 1] = fQ;
+        sF[3 * slot + 2] = fS;
+    }
+    __syncthreads();
+    double RA = 0.0, RB = 1.0, RC = 0.0, RD = 0.0;
+    if (act) {
+        int kn = k + 1;
+        double nP = 0.0, nQ = 0.0, nS = 0.0;
+        if (kn < P || cyclic) {
+            kn = kn & (P - 1);
+            nP = sF[3 * (sys * LANES + kn) + 0];
+            nQ = sF[3 * (sys * LANES + kn) + 1];
+            nS = sF[3 * (sys * LANES + kn) + 2];
+        }
+        RA = ae * gQ;
+        RB = be + ae * gS + ce * nQ;
+        RC = ce * nS;
+        RD = re - ae * gP - ce * nP;
+        sR[4 * slot + 0] = RA;
+        sR[4 * slot + 1] = RB;
+        sR[4 * slot + 2] = RC;
+        sR[4 * slot + 3] = RD;
+    }
+    __syncthreads();
+    // parallel cyclic reduction of the separator system
+    for (int s = 1; s < P; s <<= 1) {
+        double nA = 0.0, nB = 1.0, nC = 0.0, nD = 0.0;
+        if (act) {
+            int km = k - s, kp = k + s;
+            double Am = 0.0, Bm = 1.0, Cm = 0.0, Dm = 0.0, Ap = 0.0, Bp = 1.0, Cp = 0.0, Dp = 0.0;
+            if (cyclic) {
+                km &= (P - 1);
+                kp &= (P - 1);
+            }
+            if (km >= 0) {
+                const double* q = sR + 4 * (sys * LANES + km);
+                Am = q[0]; Bm = q[1]; Cm = q[2]; Dm = q[3];
+            }
+            if (kp < P) {
+                const double* q = sR + 4 * (sys * LANES + kp);
+                Ap = q[0]; Bp = q[1]; Cp = q[2]; Dp = q[3];
+            }
+            const double al = -RA / Bm, bt = -RC / Bp;
+            nA = al * Am;
+            nC = bt * Cp;
+            nB = RB + al * Cm + bt * Ap;
+            nD = RD + al * Dm + bt * Dp;
+        }
+        __syncthreads();
+        if (act) {
+            RA = nA; RB = nB; RC = nC; RD = nD;
+            sR[4 * slot + 0] = RA;
+            sR[4 * slot + 1] = RB;
+            sR[4 * slot + 2] = RC;
+            sR[4 * slot + 3] = RD;
+        }
+        __syncthreads();
+    }
+    double Rk = 0.0;
+    if (act) {
+        Rk = cyclic ? RD / (RA + RB + RC) : RD / RB;
+        sS[slot] = Rk;
+    }
+    __syncthreads();
+    if (act) {
+        double Lk = 0.0;
+        if (k > 0) Lk = sS[sys * LANES + k - 1];
+        else if (cyclic) Lk = sS[sys * LANES + P - 1];
+#pragma unroll
+        for (int j = 0; j < kCH; ++j) {
+            if (j < len - 1) E0[j] = E0[j] + E1[j] * Lk + E2[j] * Rk;
+            else if (j == len - 1) E0[j] = Rk;
+        }
+    }
+    __syncthreads();   // separator scratch done: LDS becomes phase-2 staging
+
+    // ---- phase 2: limiter, HLLC, flux difference, epilogue (by segments)
+    const int SMAX = A.seg_max;
+    const int SS = SMAX + 2;
+    double* sRes = smem;                         // [NS][SS]
+    double* sX = smem + (long long)NS * SS;      // [NC][NT] face-flux exchange
+    double smax_speed = 0.0;
+    unsigned bad = 0u;
+    for (int g0 = 0; g0 < n; g0 += SMAX) {
+        const int g1 = min(n, g0 + SMAX);
+        const int S = g1 - g0;
+        const int left = cyclic ? (g0 - 1 + n) % n : g0 - 1;
+        const int right = cyclic ? g1 % n : g1;
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < kCH; ++j) {
+                if (j < len) {
+                    const int g = r0 + j;
+                    const int cell = rev ? (n - 1 - g) : g;
+                    const double x = E0[j];
+                    double* row = sRes + sys * SS;
+                    if (cell >= g0 && cell < g1) {
+                        row[cell - g0 + 1] = x;
+                        double* d = rev ? A.dbg_up : A.dbg_um;
+                        if (d) d[(long long)comp * n + cell] = x;
+                    }
+                    if (cell == left) row[0] = x;
+                    if (cell == right) row[S + 1] = x;
+                }
+            }
+        }
+        __syncthreads();
+        // limiter on slots 0..S+1 (cells g0-1 .. g1)
+        for (int q = tid; q < S + 2; q += NT) {
+            const int cell = (q == 0) ? left : (q == S + 1 ? right : g0 + q - 1);
+            if (cell < 0 || cell >= n) continue;
+            double Ub[NC], Um[NC], Up[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                Ub[c] = U[(long long)c * A.cs + cell];
+                Um[c] = sRes[(2 * c) * SS + q];
+                Up[c] = sRes[(2 * c + 1) * SS + q];
+            }
+            pp_limit<NC>(A.w1, eps_rho, eps_e, Ub, Um, Up);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                sRes[(2 * c) * SS + q] = Um[c];
+                sRes[(2 * c + 1) * SS + q] = Up[c];
+            }
+        }
+        __syncthreads();
+        // fluxes: thread t owns cells [c0, c1) and their right faces
+        const int cpt = (S + NT - 1) / NT;
+        const int c0 = g0 + tid * cpt;
+        const int c1 = min(g1, c0 + cpt);
+        double Fr[kCPT][NC];
+        double F0[NC];
+        auto face = [&](int f, double (&F)[NC]) {
+            double Ul[NC], Ur[NC];
+            const int ql = f - g0, qr = f - g0 + 1;   // slots of cells f-1 and f
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                Ul[c] = sRes[(2 * c) * SS + ql];
+                Ur[c] = sRes[(2 * c + 1) * SS + qr];
+            }
+            if (!cyclic && f == 0) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    Ul[c] = (bc_lo == PP_BC_REFLECTIVE && c == NRM) ? -Ur[c] : Ur[c];
+            }
+            if (!cyclic && f == n) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    Ur[c] = (bc_hi == PP_BC_REFLECTIVE && c == NRM) ? -Ul[c] : Ul[c];
+            }
+            hllc_flux<NC, NRM>(A.gamma, Ul, Ur, F);
+            if (A.dbg_flux) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) A.dbg_flux[(long long)c * (n + 1) + f] = F[c];
+            }
+        };
+        if (c0 < c1) {
+            if (tid == 0) face(g0, F0);
+#pragma unroll
+            for (int j = 0; j < kCPT; ++j)
+                if (c0 + j < c1) face(c0 + j + 1, Fr[j]);
+            const int jl = c1 - c0 - 1;
+#pragma unroll
+            for (int j = 0; j < kCPT; ++j)
+                if (j == jl) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) sX[c * NT + tid] = Fr[j][c];
+                }
+        }
+        __syncthreads();
+        if (c0 < c1) {
+            double Fl[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) Fl[c] = (tid == 0) ? F0[c] : sX[c * NT + tid - 1];
+            const double ih = 1.0 / h;
+#pragma unroll
+            for (int j = 0; j < kCPT; ++j) {
+                if (c0 + j < c1) {
+                    const int i = c0 + j;
+                    double o[NC];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        const double L = -(Fr[j][c] - Fl[c]) * ih;
+                        const long long at = base + (long long)c * A.cs + i;
+                        if (A.mode == 0) {
+                            o[c] = L;
+                        } else {
+                            const double us = A.U[at];
+                            const double u0 = (A.rk_a != 0.0) ? A.U0[at] : 0.0;
+                            o[c] = A.rk_a * u0 + A.rk_b * (us + dt * L);
+                        }
+                        A.out[at] = o[c];
+                        Fl[c] = Fr[j][c];
+                    }
+                    if (A.mode == 1) {
+                        double m2 = 0.0;
+#pragma unroll
+                        for (int c = 1; c < NC - 1; ++c) m2 += o[c] * o[c];
+                        const double p = (A.gamma - 1.0) * (o[NC - 1] - 0.5 * m2 / o[0]);
+                        bool fin = true;
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) fin = fin && isfinite(o[c]);
+                        if (!fin) bad |= 1u;
+                        if (!(o[0] > 0.0) || !(p > 0.0)) bad |= 2u;
+                        if (A.stage == 3) smax_speed = fmax(smax_speed, wave_speed<NC, NRM>(A.gamma, o));
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (A.mode == 1) {
+        if (bad && A.status) atomicOr(A.status, bad);
+        if (A.stage == 3) {
+            const double S = block_max<NT>(smax_speed, red);
+            if (batched) {
+                if (tid == 0) {
+                    const double t = A.tline[b] + dt;
+                    A.tline[b] = t;
+                    double dn = A.cfl * h / S;
+                    if (t >= A.t_end) dn = 0.0;
+                    else if (t + dn > A.t_end) dn = A.t_end - t;
+                    A.dtline[b] = dn;
+                }
+            } else if (A.scal && tid == 0) {
+                atomicMax(&A.scal->spd[0], ord_enc(S));
+            }
+        }
+    }
+}
+
+template <int NC, int NRM, int W>
+__global__ void __launch_bounds__(2 * NC * 64 * W) line_kernel(LineArgs A) {
+    extern __shared__ double smem[];
+    if (A.scal && !A.scal->active) return;
+    line_op<NC, NRM, W>(A, blockIdx.x, smem);
+}
+
+// Batched ensemble: one persistent launch per stage; workgroups pop problem
+// ids (longest first) from a counter until the queue is empty.
+template <int NC, int NRM, int W>
+__global__ void __launch_bounds__(2 * NC * 64 * W) line_kernel_persistent(LineArgs A) {
+    extern __shared__ double smem[];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(A.counter, 1);
+        __syncthreads();
+        const int q = next;
+        __syncthreads();
+        if (q >= A.nlines) break;
+        line_op<NC, NRM, W>(A, A.order[q], smem);
+        __syncthreads();
+    }
+}
+
+__global__ void reset_counter(int* c) { *c = 0; }
+
+// ---------------------------------------------------------------- 2D pieces
+constexpr int TT = 32;   // transpose tile edge
+
+// B[c][x][y] = A[c][y][x]
+__global__ void __launch_bounds__(256) transpose_kernel(const double* __restrict__ src,
+                                                        double* __restrict__ dst, int nx, int ny,
+                                                        int ncomp) {
+    __shared__ double tile[TT][TT + 1];
+    const long long cs = (long long)nx * ny;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int x0 = blockIdx.x * TT, y0 = blockIdx.y * TT;
+    for (int c = 0; c < ncomp; ++c) {
+        for (int yy = ty; yy < TT; yy += 8) {
+            const int x = x0 + tx, y = y0 + yy;
+            if (x < nx && y < ny) tile[yy][tx] = src[c * cs + (long long)y * nx + x];
+        }
+        __syncthreads();
+        for (int xx = ty; xx < TT; xx += 8) {
+            const int y = y0 + tx, x = x0 + xx;
+            if (x < nx && y < ny) dst[c * cs + (long long)x * ny + y] = tile[tx][xx];
+        }
+        __syncthreads();
+    }
+}
+
+// mode 0: Out = Lx + Ly (L only).  mode 1: Out = a Un + b (Us + dt (Lx + Ly)),
+// written in layout A (Out) and B (OutB); reduces min rho / min e of the
+// output into eps_out and (stage 3) max speeds into spd_out.
+__global__ void __launch_bounds__(256) combine2d_kernel(
+    const double* __restrict__ Lx, const double* __restrict__ LyB, const double* __restrict__ Us,
+    const double* Un, double* Out, double* __restrict__ OutB, int nx,
+    int ny, int mode, double ra, double rb, const double* dt_dev, double dt_val, double gamma,
+    long long* eps_out, long long* spd_out, long long* eps_reset, Scal* scal, unsigned* status) {
+    __shared__ double tile[TT][TT + 1];
+    __shared__ double red[4][8];
+    if (scal && !scal->active) return;
+    if (eps_reset && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        eps_reset[0] = kEncPosInf;
+        eps_reset[1] = kEncPosInf;
+    }
+    const long long cs = (long long)nx * ny;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int x0 = blockIdx.x * TT, y0 = blockIdx.y * TT;
+    const double dt = dt_dev ? *dt_dev : dt_val;
+    double cell[4][4];   // [row yy/8][comp]
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        for (int xx = ty; xx < TT; xx += 8) {
+            const int y = y0 + tx, x = x0 + xx;
+            if (x < nx && y < ny) tile[xx][tx] = LyB[c * cs + (long long)x * ny + y];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int yy = ty + 8 * r;
+            const int x = x0 + tx, y = y0 + yy;
+            double v = 0.0;
+            if (x < nx && y < ny) {
+                const long long at = c * cs + (long long)y * nx + x;
+                const double L = Lx[at] + tile[tx][yy];
+                if (mode == 0) {
+                    v = L;
+                } else {
+                    const double u0 = (ra != 0.0) ? Un[at] : 0.0;
+                    v = ra * u0 + rb * (Us[at] + dt * L);
+                }
+                Out[at] = v;
+            }
+            cell[r][c] = v;
+        }
+        __syncthreads();
+        if (mode == 1) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tile[ty + 8 * r][tx] = cell[r][c];
+            __syncthreads();
+            for (int xx = ty; xx < TT; xx += 8) {
+                const int y = y0 + tx, x = x0 + xx;
+                if (x < nx && y < ny) OutB[c * cs + (long long)x * ny + y] = tile[tx][xx];
+            }
+            __syncthreads();
+        }
+    }
+    if (mode != 1) return;
+    double mr = INFINITY, me = INFINITY, sx = 0.0, sy = 0.0;
+    unsigned bad = 0u;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int x = x0 + tx, y = y0 + ty + 8 * r;
+        if (x >= nx || y >= ny) continue;
+        const double q[4] = {cell[r][0], cell[r][1], cell[r][2], cell[r][3]};
+        const double e = spec_e<4>(q);
+        mr = fmin(mr, q[0]);
+        me = fmin(me, e);
+        const double p = (gamma - 1.0) * q[0] * e;
+        if (!(isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && isfinite(q[3]))) bad |= 1u;
+        if (!(q[0] > 0.0) || !(p > 0.0)) bad |= 2u;
+        if (spd_out) {
+            sx = fmax(sx, wave_speed<4, 1>(gamma, q));
+            sy = fmax(sy, wave_speed<4, 2>(gamma, q));
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mr = fmin(mr, __shfl_xor(mr, o));
+        me = fmin(me, __shfl_xor(me, o));
+        sx = fmax(sx, __shfl_xor(sx, o));
+        sy = fmax(sy, __shfl_xor(sy, o));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[w][0] = mr; red[w][1] = me; red[w][2] = sx; red[w][3] = sy;
+    }
+    if (bad && status) atomicOr(status, bad);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 4; ++i) {
+            mr = fmin(mr, red[i][0]); me = fmin(me, red[i][1]);
+            sx = fmax(sx, red[i][2]); sy = fmax(sy, red[i][3]);
+        }
+        atomicMin(&eps_out[0], ord_enc(mr));
+        atomicMin(&eps_out[1], ord_enc(me));
+        if (spd_out) {
+            atomicMax(&spd_out[0], ord_enc(sx));
+            atomicMax(&spd_out[1], ord_enc(sy));
+        }
+    }
+}
+
+// Min rho, min e and max wave speeds of a state [NC][ncell] (x-fastest 2D or 1D).
+template <int NC>
+__global__ void __launch_bounds__(256) reduce_state_kernel(const double* __restrict__ U,
+                                                           long long ncell, double gamma,
+                                                           long long* eps_out, long long* spd_out) {
+    __shared__ double red[4][4];
+    double mr = INFINITY, me = INFINITY, sx = 0.0, sy = 0.0;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < ncell; i += 256LL * gridDim.x) {
+        double q[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[c] = U[c * ncell + i];
+        mr = fmin(mr, q[0]);
+        me = fmin(me, spec_e<NC>(q));
+        sx = fmax(sx, wave_speed<NC, 1>(gamma, q));
+        if constexpr (NC == 4) sy = fmax(sy, wave_speed<NC, 2>(gamma, q));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mr = fmin(mr, __shfl_xor(mr, o));
+        me = fmin(me, __shfl_xor(me, o));
+        sx = fmax(sx, __shfl_xor(sx, o));
+        sy = fmax(sy, __shfl_xor(sy, o));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[w][0] = mr; red[w][1] = me; red[w][2] = sx; red[w][3] = sy;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 4; ++i) {
+            mr = fmin(mr, red[i][0]); me = fmin(me, red[i][1]);
+            sx = fmax(sx, red[i][2]); sy = fmax(sy, red[i][3]);
+        }
+        if (eps_out) {
+            atomicMin(&eps_out[0], ord_enc(mr));
+            atomicMin(&eps_out[1], ord_enc(me));
+        }
+        if (spd_out) {
+            atomicMax(&spd_out[0], ord_enc(sx));
+            atomicMax(&spd_out[1], ord_enc(sy));
+        }
+    }
+}
+
+__global__ void init_scal_kernel(Scal* s) {
+    for (int i = 0; i < 3; ++i) s->eps[i][0] = s->eps[i][1] = kEncPosInf;
+    s->spd[0] = s->spd[1] = kEncZero;
+    s->dt = 0.0;
+    s->t = 0.0;
+    s->steps = 0;
+    s->active = 1;
+    s->status = 0u;
+}
+
+// Start of a step: advance t by the previous dt, pick the new dt from the
+// wave speeds of the current state, clip to t_end / step budget, reset the
+// reductions this step will fill.
+__global__ void dt_kernel(Scal* s, int ndim, int rule, double cfl, double dx, double dy,
+                          double t_end, long long steps_max) {
+    if (s->active && s->dt > 0.0) {
+        s->t += s->dt;
+        s->steps += 1;
+    }
+    const double sx = ord_dec(s->spd[0]), sy = ord_dec(s->spd[1]);
+    double dt;
+    if (ndim == 1) dt = (rule == PP_DT_H53 ? cfl * pow(dx, 5.0 / 3.0) : cfl * dx) / sx;
+    else dt = cfl / (sx / dx + sy / dy);
+    const bool go = s->t < t_end && s->steps < steps_max && dt > 0.0 && isfinite(dt);
+    if (!(dt > 0.0) || !isfinite(dt)) s->status |= 1u;
+    if (go && s->t + dt > t_end) dt = t_end - s->t;
+    s->active = go ? 1 : 0;
+    s->dt = go ? dt : 0.0;
+    s->spd[0] = s->spd[1] = kEncZero;
+    s->eps[0][0] = s->eps[0][1] = kEncPosInf;
+    s->eps[1][0] = s->eps[1][1] = kEncPosInf;
+}
+
+}  // namespace
+
+// ======================================================================= host
+struct pp_cweno_ctx {
+    pp_cweno_config cfg{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    int nc = 3;
+    long long ncell = 0;
+    // single-grid scratch
+    double *U1 = nullptr, *U2 = nullptr, *UA = nullptr;        // layout A stage buffers
+    double *UB = nullptr, *U1B = nullptr, *U2B = nullptr;      // layout B copies (2D)
+    double *Lx = nullptr, *LyB = nullptr;                      // 2D operator halves
+    Scal* scal = nullptr;
+    // batched
+    std::vector<int64_t> lengths;
+    std::vector<double> dxs;
+    std::vector<int> bcs;
+    long long total = 0;
+    int maxn = 0;
+    long long* d_off = nullptr;
+    int* d_n = nullptr;
+    double* d_h = nullptr;
+    int* d_bc = nullptr;
+    double* d_dt = nullptr;
+    double* d_t = nullptr;
+    int* d_order = nullptr;
+    int* d_counter = nullptr;
+    double* d_dtcopy = nullptr;
+    int n_sm = 0;
+};
+
+namespace {
+
+thread_local std::string g_init_err;
+
+int fail(pp_cweno_ctx* c, int code, const std::string& m) {
+    if (c) c->err = m;
+    else g_init_err = m;
+    return code;
+}
+
+int hip_fail(pp_cweno_ctx* c, hipError_t e, const char* what) {
+    return fail(c, PP_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, call)                                   \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+    } while (0)
+
+// Dynamic LDS of the line kernel for lines of up to nmax cells.
+template <int NC, int W>
+size_t line_lds_bytes(int nmax, int seg_max) {
+    constexpr int NS = 2 * NC, LANES = 64 * W, NT = NS * LANES;
+    const long long LP = (nmax + 2 * kNG - 1) + ((nmax + 2 * kNG - 1) >> 5) + 1;
+    const long long a0 = (long long)NC * LP;
+    const long long a1 = (long long)NS * LANES * 8;
+    const long long a2 = (long long)NS * (seg_max + 2) + (long long)NC * NT;
+    long long m = std::max(a0, std::max(a1, a2));
+    return (size_t)(m + NT) * sizeof(double);
+}
+
+constexpr size_t kLdsBudget = 160 * 1024;
+
+template <int NC, int W>
+int pick_segment(int nmax) {
+    constexpr int NT = 2 * NC * 64 * W;
+    int seg = nmax;
+    while (seg > 64 && (line_lds_bytes<NC, W>(nmax, seg) > kLdsBudget || (seg + NT - 1) / NT > kCPT))
+        seg = (seg + 1) / 2;
+    return seg;
+}
+
+template <int NC, int NRM, int W>
+int launch_line(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int grid) {
+    const int seg = pick_segment<NC, W>(nmax);
+    A.seg_max = seg;
+    const size_t lds = line_lds_bytes<NC, W>(nmax, seg);
+    if (lds > kLdsBudget || (seg + 2 * NC * 64 * W - 1) / (2 * NC * 64 * W) > kCPT)
+        return fail(ctx, PP_EUNSUPPORTED, "line too long for the on-chip line kernel");
+    constexpr int NT = 2 * NC * 64 * W;
+    if (persistent) {
+        auto fn = line_kernel_persistent<NC, NRM, W>;
+        HIPCHK(ctx, hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds));
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, ctx->stream, A);
+    } else {
+        auto fn = line_kernel<NC, NRM, W>;
+        HIPCHK(ctx, hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds));
+        hipLaunchKernelGGL(fn, dim3(A.nlines), dim3(NT), lds, ctx->stream, A);
+    }
+    HIPCHK(ctx, hipGetLastError());
+    return PP_OK;
+}
+
+LineArgs base_args(const pp_cweno_ctx* ctx) {
+    LineArgs A{};
+    A.gamma = ctx->cfg.gamma;
+    A.w1 = ctx->cfg.gl_w1;
+    A.weno_eps = ctx->cfg.weno_eps;
+    A.eps_cap = ctx->cfg.pp_eps_cap;
+    A.rk_a = 0.0;
+    A.rk_b = 1.0;
+    A.status = ctx->scal ? &ctx->scal->status : nullptr;
+    return A;
+}
+
+// 1D single line: L (mode 0) or stage (mode 1).
+int launch_1d(pp_cweno_ctx* ctx, const double* Us, const double* U0, double* out, int mode,
+              int stage, double ra, double rb, const double* dt_dev, double dt_val, bool run,
+              double* dbg_um = nullptr, double* dbg_up = nullptr, double* dbg_flux = nullptr) {
+    LineArgs A = base_args(ctx);
+    A.U = Us;
+    A.U0 = U0;
+    A.out = out;
+    A.cs = ctx->cfg.nx;
+    A.ls = 0;
+    A.n = (int)ctx->cfg.nx;
+    A.nlines = 1;
+    A.bc_lo = ctx->cfg.bc[0];
+    A.bc_hi = ctx->cfg.bc[1];
+    A.h = ctx->cfg.dx;
+    A.mode = mode;
+    A.stage = stage;
+    A.rk_a = ra;
+    A.rk_b = rb;
+    A.dt_dev = dt_dev;
+    A.dt_val = dt_val;
+    A.scal = run ? ctx->scal : nullptr;
+    A.dbg_um = dbg_um;
+    A.dbg_up = dbg_up;
+    A.dbg_flux = dbg_flux;
+    if (A.n <= 2048) return launch_line<3, 1, 1>(ctx, A, A.n, false, 1);
+    return launch_line<3, 1, 2>(ctx, A, A.n, false, 1);
+}
+
+// 2D sweeps of one stage input (Us in layout A and B) into Lx and LyB.
+int sweeps_2d(pp_cweno_ctx* ctx, const double* UsA, const double* UsB, const long long* eps_enc,
+              bool run) {
+    const auto& c = ctx->cfg;
+    LineArgs A = base_args(ctx);
+    A.mode = 0;
+    A.eps_enc = eps_enc;
+    A.scal = run ? ctx->scal : nullptr;
+    A.cs = (long long)c.nx * c.ny;
+    // x-lines: rows of the [4][ny][nx] state
+    A.U = UsA;
+    A.out = ctx->Lx;
+    A.ls = c.nx;
+    A.n = (int)c.nx;
+    A.nlines = (int)c.ny;
+    A.bc_lo = c.bc[0];
+    A.bc_hi = c.bc[1];
+    A.h = c.dx;
+    int r = launch_line<4, 1, 1>(ctx, A, A.n, false, 0);
+    if (r) return r;
+    // y-lines: rows of the transposed [4][nx][ny] state
+    A.U = UsB;
+    A.out = ctx->LyB;
+    A.ls = c.ny;
+    A.n = (int)c.ny;
+    A.nlines = (int)c.nx;
+    A.bc_lo = c.bc[2];
+    A.bc_hi = c.bc[3];
+    A.h = c.dy;
+    return launch_line<4, 2, 1>(ctx, A, A.n, false, 0);
+}
+
+int combine_2d(pp_cweno_ctx* ctx, const double* UsA, const double* Un, double* Out, double* OutB,
+               int mode, double ra, double rb, const double* dt_dev, double dt_val,
+               long long* eps_out, long long* spd_out, long long* eps_reset, bool run) {
+    const auto& c = ctx->cfg;
+    dim3 grid((unsigned)((c.nx + TT - 1) / TT), (unsigned)((c.ny + TT - 1) / TT));
+    hipLaunchKernelGGL(combine2d_kernel, grid, dim3(256), 0, ctx->stream, ctx->Lx, ctx->LyB, UsA,
+                       Un, Out, OutB, (int)c.nx, (int)c.ny, mode, ra, rb, dt_dev, dt_val, c.gamma,
+                       eps_out, spd_out, eps_reset, run ? ctx->scal : nullptr,
+                       ctx->scal ? &ctx->scal->status : nullptr);
+    HIPCHK(ctx, hipGetLastError());
+    return PP_OK;
+}
+
+int transpose_2d(pp_cweno_ctx* ctx, const double* src, double* dst) {
+    const auto& c = ctx->cfg;
+    dim3 grid((unsigned)((c.nx + TT - 1) / TT), (unsigned)((c.ny + TT - 1) / TT));
+    hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, ctx->stream, src, dst, (int)c.nx,
+                       (int)c.ny, 4);
+    HIPCHK(ctx, hipGetLastError());
+    return PP_OK;
+}
+
+int reduce_state(pp_cweno_ctx* ctx, const double* U, long long* eps_out, long long* spd_out) {
+    const int grid = (int)std::min<long long>((ctx->ncell + 255) / 256, 4096);
+    if (ctx->nc == 3)
+        hipLaunchKernelGGL(reduce_state_kernel<3>, dim3(grid), dim3(256), 0, ctx->stream, U,
+                           ctx->ncell, ctx->cfg.gamma, eps_out, spd_out);
+    else
+        hipLaunchKernelGGL(reduce_state_kernel<4>, dim3(grid), dim3(256), 0, ctx->stream, U,
+                           ctx->ncell, ctx->cfg.gamma, eps_out, spd_out);
+    HIPCHK(ctx, hipGetLastError());
+    return PP_OK;
+}
+
+int reset_scal(pp_cweno_ctx* ctx) {
+    hipLaunchKernelGGL(init_scal_kernel, dim3(1), dim3(1), 0, ctx->stream, ctx->scal);
+    HIPCHK(ctx, hipGetLastError());
+    return PP_OK;
+}
+
+const double kRK[4][2] = {{0, 0}, {0.0, 1.0}, {0.75, 0.25}, {1.0 / 3.0, 2.0 / 3.0}};
+
+// One full SSP-RK3 step on a single grid (U in/out, layout A; for 2D the
+// B copy of U must be current in ctx->UB).  run = take dt and the epsilon
+// reductions from the device scalars.
+int step_single(pp_cweno_ctx* ctx, double* U, const double* dt_dev, double dt_val, bool run) {
+    const auto& c = ctx->cfg;
+    Scal* s = ctx->scal;
+    int r;
+    if (c.ndim == 1) {
+        const double* Uin[3] = {U, ctx->U1, ctx->U2};
+        double* Uout[3] = {ctx->U1, ctx->U2, U};
+        for (int st = 1; st <= 3; ++st) {
+            r = launch_1d(ctx, Uin[st - 1], U, Uout[st - 1], 1, st, kRK[st][0], kRK[st][1],
+                          dt_dev, dt_val, run);
+            if (r) return r;
+        }
+        return PP_OK;
+    }
+    // 2D: stage inputs in both layouts.  Epsilon slots: 2 = stage-1 input
+    // (written by the previous stage 3 or the initial reduction), 0 = U1,
+    // 1 = U2.  Stage 3 combines in place into U (each element is read and
+    // written by the same thread only).
+    const double* inA[3] = {U, ctx->U1, ctx->U2};
+    const double* inB[3] = {ctx->UB, ctx->U1B, ctx->U2B};
+    double* outA[3] = {ctx->U1, ctx->U2, U};
+    double* outB[3] = {ctx->U1B, ctx->U2B, ctx->UB};
+    for (int st = 1; st <= 3; ++st) {
+        const int in_slot = (st + 1) % 3;
+        const int out_slot = st - 1;
+        r = sweeps_2d(ctx, inA[st - 1], inB[st - 1], s->eps[in_slot], run);
+        if (r) return r;
+        r = combine_2d(ctx, inA[st - 1], U, outA[st - 1], outB[st - 1], 1, kRK[st][0], kRK[st][1],
+                       dt_dev, dt_val, s->eps[out_slot], st == 3 ? s->spd : nullptr,
+                       st == 1 ? s->eps[2] : nullptr, run);
+        if (r) return r;
+    }
+    return PP_OK;
+}
+
+bool bc_ok(int b) { return b == PP_BC_PERIODIC || b == PP_BC_TRANSMISSIVE || b == PP_BC_REFLECTIVE; }
+
+}  // namespace
+
+extern "C" {
+
+void pp_cweno_config_defaults(pp_cweno_config* cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->ndim = 1;
+    cfg->ny = 1;
+    cfg->gamma = 1.4;
+    cfg->weno_eps = 1e-13;
+    cfg->pp_eps_cap = 1e-13;
+    cfg->gl_w1 = 1.0 / 12.0;
+    cfg->precision = PP_FP64;
+}
+
+int pp_cweno_init(const pp_cweno_config* cfg, pp_cweno_ctx** out) {
+    if (!out) return fail(nullptr, PP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cfg) return fail(nullptr, PP_EINVAL, "cfg is NULL");
+    const pp_cweno_config& c = *cfg;
+    if (c.ndim != 1 && c.ndim != 2) return fail(nullptr, PP_EINVAL, "ndim must be 1 or 2");
+    if (!(c.gamma > 1.0)) return fail(nullptr, PP_EINVAL, "gamma must be > 1");
+    if (!(c.gl_w1 > 0.0 && c.gl_w1 < 0.5)) return fail(nullptr, PP_EINVAL, "gl_w1 must be in (0, 1/2)");
+    if (!(c.weno_eps > 0.0) || !(c.pp_eps_cap > 0.0))
+        return fail(nullptr, PP_EINVAL, "epsilons must be > 0");
+    if (c.precision != PP_FP64 && c.precision != PP_MIXED)
+        return fail(nullptr, PP_EINVAL, "precision must be PP_FP64 or PP_MIXED");
+    if (c.precision == PP_MIXED)
+        return fail(nullptr, PP_EUNSUPPORTED, "mixed precision is not built yet");
+    const int naxes = c.ndim == 2 ? 2 : 1;
+    for (int a = 0; a < naxes; ++a) {
+        if (!bc_ok(c.bc[2 * a]) || !bc_ok(c.bc[2 * a + 1]))
+            return fail(nullptr, PP_EINVAL, "unknown boundary code");
+        if ((c.bc[2 * a] == PP_BC_PERIODIC) != (c.bc[2 * a + 1] == PP_BC_PERIODIC))
+            return fail(nullptr, PP_EINVAL, "periodic must be set on both ends of an axis");
+    }
+    if (c.nbatch < 0) return fail(nullptr, PP_EINVAL, "nbatch < 0");
+    if (c.nbatch > 0) {
+        if (c.ndim != 1) return fail(nullptr, PP_EINVAL, "batched ensembles are 1D");
+        if (!c.lengths || !c.dxs || !c.bcs) return fail(nullptr, PP_EINVAL, "batch arrays are NULL");
+        for (int64_t i = 0; i < c.nbatch; ++i) {
+            if (c.lengths[i] < 3) return fail(nullptr, PP_EINVAL, "batched problem with < 3 cells");
+            if (c.lengths[i] > 4096) return fail(nullptr, PP_EUNSUPPORTED, "batched problem > 4096 cells");
+            if (!(c.dxs[i] > 0.0)) return fail(nullptr, PP_EINVAL, "batched dx must be > 0");
+            for (int e = 0; e < 2; ++e)
+                if (!bc_ok(c.bcs[2 * i + e]) || c.bcs[2 * i + e] == PP_BC_PERIODIC)
+                    return fail(nullptr, PP_EINVAL, "batched problems need non-periodic codes");
+        }
+    } else {
+        const int64_t nmin_x = c.bc[0] == PP_BC_PERIODIC ? 5 : 3;
+        if (c.nx < nmin_x) return fail(nullptr, PP_EINVAL, "nx too small");
+        if (!(c.dx > 0.0)) return fail(nullptr, PP_EINVAL, "dx must be > 0");
+        if (c.ndim == 1) {
+            if (c.nx > 4096) return fail(nullptr, PP_EUNSUPPORTED, "1D lines are limited to 4096 cells");
+        } else {
+            const int64_t nmin_y = c.bc[2] == PP_BC_PERIODIC ? 5 : 3;
+            if (c.ny < nmin_y) return fail(nullptr, PP_EINVAL, "ny too small");
+            if (!(c.dy > 0.0)) return fail(nullptr, PP_EINVAL, "dy must be > 0");
+            if (c.nx > 2048 || c.ny > 2048)
+                return fail(nullptr, PP_EUNSUPPORTED, "2D lines are limited to 2048 cells");
+        }
+    }
+    auto* ctx = new (std::nothrow) pp_cweno_ctx();
+    if (!ctx) return fail(nullptr, PP_ENOMEM, "host allocation failed");
+    ctx->cfg = c;
+    ctx->cfg.lengths = nullptr;
+    ctx->cfg.dxs = nullptr;
+    ctx->cfg.bcs = nullptr;
+    ctx->stream = (hipStream_t)c.stream;
+    ctx->nc = c.ndim == 2 ? 4 : 3;
+    auto bail = [&](int code) {
+        g_init_err = ctx->err;
+        pp_cweno_destroy(ctx);
+        return code;
+    };
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        hip_fail(ctx, e, "hipGetDevice");
+        return bail(PP_EDEVICE);
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ctx->n_sm = prop.multiProcessorCount;
+    if (ctx->n_sm <= 0) ctx->n_sm = 256;
+    auto dmalloc = [&](void** p, size_t bytes) -> bool {
+        hipError_t er = hipMalloc(p, bytes);
+        if (er != hipSuccess) {
+            hip_fail(ctx, er, "hipMalloc");
+            return false;
+        }
+        return true;
+    };
+    if (!dmalloc((void**)&ctx->scal, sizeof(Scal))) return bail(PP_ENOMEM);
+    if (c.nbatch > 0) {
+        const int64_t nb = c.nbatch;
+        ctx->lengths.assign(c.lengths, c.lengths + nb);
+        ctx->dxs.assign(c.dxs, c.dxs + nb);
+        ctx->bcs.assign(c.bcs, c.bcs + 2 * nb);
+        std::vector<long long> off(nb + 1, 0);
+        for (int64_t i = 0; i < nb; ++i) {
+            off[i + 1] = off[i] + c.lengths[i];
+            ctx->maxn = std::max<int>(ctx->maxn, (int)c.lengths[i]);
+        }
+        ctx->total = off[nb];
+        ctx->ncell = ctx->total;
+        std::vector<int> order(nb), ln(nb);
+        for (int64_t i = 0; i < nb; ++i) {
+            order[i] = (int)i;
+            ln[i] = (int)c.lengths[i];
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return ln[a] > ln[b]; });
+        if (!dmalloc((void**)&ctx->d_off, sizeof(long long) * (nb + 1)) ||
+            !dmalloc((void**)&ctx->d_n, sizeof(int) * nb) ||
+            !dmalloc((void**)&ctx->d_h, sizeof(double) * nb) ||
+            !dmalloc((void**)&ctx->d_bc, sizeof(int) * 2 * nb) ||
+            !dmalloc((void**)&ctx->d_dt, sizeof(double) * nb) ||
+            !dmalloc((void**)&ctx->d_dtcopy, sizeof(double) * nb) ||
+            !dmalloc((void**)&ctx->d_t, sizeof(double) * nb) ||
+            !dmalloc((void**)&ctx->d_order, sizeof(int) * nb) ||
+            !dmalloc((void**)&ctx->d_counter, sizeof(int) * 4) ||
+            !dmalloc((void**)&ctx->U1, sizeof(double) * 3 * ctx->total) ||
+            !dmalloc((void**)&ctx->U2, sizeof(double) * 3 * ctx->total))
+            return bail(PP_ENOMEM);
+        hipError_t e2 = hipSuccess;
+        e2 = e2 == hipSuccess ? hipMemcpy(ctx->d_off, off.data(), sizeof(long long) * (nb + 1), hipMemcpyHostToDevice) : e2;
+        e2 = e2 == hipSuccess ? hipMemcpy(ctx->d_n, ln.data(), sizeof(int) * nb, hipMemcpyHostToDevice) : e2;
+        e2 = e2 == hipSuccess ? hipMemcpy(ctx->d_h, c.dxs, sizeof(double) * nb, hipMemcpyHostToDevice) : e2;
+        e2 = e2 == hipSuccess ? hipMemcpy(ctx->d_bc, c.bcs, sizeof(int) * 2 * nb, hipMemcpyHostToDevice) : e2;
+        e2 = e2 == hipSuccess ? hipMemcpy(ctx->d_order, order.data(), sizeof(int) * nb, hipMemcpyHostToDevice) : e2;
+        if (e2 != hipSuccess) {
+            hip_fail(ctx, e2, "hipMemcpy");
+            return bail(PP_EDEVICE);
+        }
+    } else {
+        ctx->ncell = c.nx * (c.ndim == 2 ? c.ny : 1);
+        const size_t bytes = sizeof(double) * ctx->nc * ctx->ncell;
+        if (!dmalloc((void**)&ctx->U1, bytes) || !dmalloc((void**)&ctx->U2, bytes))
+            return bail(PP_ENOMEM);
+        if (c.ndim == 2) {
+            if (!dmalloc((void**)&ctx->UA, bytes) || !dmalloc((void**)&ctx->UB, bytes) ||
+                !dmalloc((void**)&ctx->U1B, bytes) || !dmalloc((void**)&ctx->U2B, bytes) ||
+                !dmalloc((void**)&ctx->Lx, bytes) || !dmalloc((void**)&ctx->LyB, bytes))
+                return bail(PP_ENOMEM);
+        }
+    }
+    if (reset_scal(ctx)) return bail(PP_EDEVICE);
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        hip_fail(ctx, e, "hipStreamSynchronize");
+        return bail(PP_EDEVICE);
+    }
+    *out = ctx;
+    return PP_OK;
+}
+
+int pp_cweno_rhs(pp_cweno_ctx* ctx, const double* U, double* L) {
+    if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
+    if (!U || !L) return fail(ctx, PP_EINVAL, "U or L is NULL");
+    if (U == L) return fail(ctx, PP_EINVAL, "U and L must be distinct");
+    if (ctx->cfg.nbatch > 0) return fail(ctx, PP_EINVAL, "pp_cweno_rhs needs a single grid");
+    if (ctx->cfg.ndim == 1) return launch_1d(ctx, U, nullptr, L, 0, 0, 0.0, 1.0, nullptr, 0.0, false);
+    // 2D: epsilon of U into slot 0 of the scalars, transposed copy, sweeps, sum
+    int r = reset_scal(ctx);
+    if (!r) r = reduce_state(ctx, U, ctx->scal->eps[0], nullptr);
+    if (!r) r = transpose_2d(ctx, U, ctx->UB);
+    if (!r) r = sweeps_2d(ctx, U, ctx->UB, ctx->scal->eps[0], false);
+    if (!r) r = combine_2d(ctx, U, nullptr, L, nullptr, 0, 0.0, 1.0, nullptr, 0.0, nullptr, nullptr,
+                           nullptr, false);
+    return r;
+}
+
+int pp_cweno_stage(pp_cweno_ctx* ctx, const double* U0, const double* Us, double* Uout, int stage,
+                   double dt) {
+    if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
+    if (!U0 || !Us || !Uout) return fail(ctx, PP_EINVAL, "NULL state pointer");
+    if (Uout == U0 || Uout == Us) return fail(ctx, PP_EINVAL, "Uout must not alias U0 or Us");
+    if (stage < 1 || stage > 3) return fail(ctx, PP_EINVAL, "stage must be 1, 2 or 3");
+    if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(ctx, PP_EINVAL, "dt must be finite and >= 0");
+    if (ctx->cfg.nbatch > 0) return fail(ctx, PP_EINVAL, "pp_cweno_stage needs a single grid");
+    if (ctx->cfg.ndim == 1)
+        return launch_1d(ctx, Us, U0, Uout, 1, stage, kRK[stage][0], kRK[stage][1], nullptr, dt, false);
+    int r = reset_scal(ctx);
+    if (!r) r = reduce_state(ctx, Us, ctx->scal->eps[0], nullptr);
+    if (!r) r = transpose_2d(ctx, Us, ctx->U1B);
+    if (!r) r = sweeps_2d(ctx, Us, ctx->U1B, ctx->scal->eps[0], false);
+    if (!r) r = combine_2d(ctx, Us, U0, Uout, ctx->U2B, 1, kRK[stage][0], kRK[stage][1], nullptr, dt,
+                           ctx->scal->eps[1], nullptr, nullptr, false);
+    return r;
+}
+
+int pp_cweno_step(pp_cweno_ctx* ctx, double* U, double dt) {
+    if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
+    if (!U) return fail(ctx, PP_EINVAL, "U is NULL");
+    if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(ctx, PP_EINVAL, "dt must be finite and >= 0");
+    if (ctx->cfg.nbatch > 0) return fail(ctx, PP_EINVAL, "use pp_cweno_batch_step for ensembles");
+    int r = reset_scal(ctx);
+    if (r) return r;
+    if (ctx->cfg.ndim == 2) {
+        r = reduce_state(ctx, U, ctx->scal->eps[2], nullptr);
+        if (!r) r = transpose_2d(ctx, U, ctx->UB);
+        if (r) return r;
+    }
+    return step_single(ctx, U, nullptr, dt, false);
+}
+
+int pp_cweno_run(pp_cweno_ctx* ctx, double* U, double t_end, int64_t nsteps_max, double cfl,
+                 int rule, double* t_out, int64_t* steps_out) {
+    if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
+    if (!U) return fail(ctx, PP_EINVAL, "U is NULL");
+    if (!(t_end > 0.0) || !(cfl > 0.0) || nsteps_max < 0)
+        return fail(ctx, PP_EINVAL, "t_end and cfl must be > 0, nsteps_max >= 0");
+    if (rule != PP_DT_CFL && rule != PP_DT_H53) return fail(ctx, PP_EINVAL, "unknown dt rule");
+    if (rule == PP_DT_H53 && ctx->cfg.ndim != 1) return fail(ctx, PP_EINVAL, "h^(5/3) rule is 1D");
+    if (ctx->cfg.nbatch > 0) return fail(ctx, PP_EINVAL, "use pp_cweno_batch_run for ensembles");
+    const auto& c = ctx->cfg;
+    Scal* s = ctx->scal;
+    int r = reset_scal(ctx);
+    if (!r) r = reduce_state(ctx, U, s->eps[2], s->spd);
+    if (!r && c.ndim == 2) r = transpose_2d(ctx, U, ctx->UB);
+    if (r) return r;
+    // (dt kernel, step) pairs are launched in batches; the dt kernel retires
+    // the run at t_end or after nsteps_max steps (later launches return at
+    // once), and each batch ends with a host check of the device scalars.
+    int64_t launched = 0;
+    Scal host{};
+    for (;;) {
+        const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(64, nsteps_max - launched + 1));
+        for (int64_t i = 0; i < batch; ++i, ++launched) {
+            hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(1), 0, ctx->stream, s, c.ndim, rule, cfl,
+                               c.dx, c.dy, t_end, (long long)nsteps_max);
+            HIPCHK(ctx, hipGetLastError());
+            r = step_single(ctx, U, &s->dt, 0.0, true);
+            if (r) return r;
+        }
+        HIPCHK(ctx, hipMemcpyAsync(&host, s, sizeof(Scal), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        if (!host.active) break;
+    }
+    if (t_out) *t_out = host.t;
+    if (steps_out) *steps_out = host.steps;
+    if (host.status) return fail(ctx, PP_ESTATE, "a stage left the admissible set or was not finite");
+    return PP_OK;
+}
+
+int pp_cweno_max_speed(pp_cweno_ctx* ctx, const double* U, double* out_dev) {
+    if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
+    if (!U || !out_dev) return fail(ctx, PP_EINVAL, "NULL pointer");
+    int r = reset_scal(ctx);
+    if (!r) r = reduce_state(ctx, U, nullptr, ctx->scal->spd);
+    if (r) return r;
+    // decode on the device side through a tiny copy of the encoded values
+    long long enc[2];
+    HIPCHK(ctx, hipMemcpyAsync(enc, ctx->scal->spd, sizeof(enc), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    double v[2];
+    for (int i = 0; i < 2; ++i) {
+        long long x = enc[i] >= 0 ? enc[i] : (enc[i] ^ 0x7fffffffffffffffLL);
+        std::memcpy(&v[i], &x, sizeof(double));
+    }
+    HIPCHK(ctx, hipMemcpyAsync(out_dev, v, sizeof(double) * (ctx->cfg.ndim == 2 ? 2 : 1),
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return PP_OK;
+}
+
+int pp_cweno_batch_step(pp_cweno_ctx* ctx, double* Upacked, const double* dt_dev) {
+    if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
+    if (!Upacked || !dt_dev) return fail(ctx, PP_EINVAL, "NULL pointer");
+    if (ctx->cfg.nbatch <= 0) return fail(ctx, PP_EINVAL, "context has no batch");
+    // the kernels read each problem's dt from d_dt; a copy keeps the caller's
+    // array read-only (the stage-3 epilogue only advances dt inside batch_run)
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_dtcopy, dt_dev, sizeof(double) * ctx->cfg.nbatch,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    LineArgs A = base_args(ctx);
+    A.cs = ctx->total;
+    A.off = ctx->d_off;
+    A.nline = ctx->d_n;
+    A.hline = ctx->d_h;
+    A.bcline = ctx->d_bc;
+    A.dtline = ctx->d_dtcopy;
+    A.tline = ctx->d_t;
+    A.order = ctx->d_order;
+    A.nlines = (int)ctx->cfg.nbatch;
+    A.mode = 1;
+    A.t_end = INFINITY;
+    A.cfl = 0.0;
+    const double* Uin[3] = {Upacked, ctx->U1, ctx->U2};
+    double* Uout[3] = {ctx->U1, ctx->U2, Upacked};
+    const int grid = ctx->n_sm;
+    for (int st = 1; st <= 3; ++st) {
+        hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, ctx->stream, ctx->d_counter + st);
+        A.counter = ctx->d_counter + st;
+        A.U = Uin[st - 1];
+        A.U0 = Upacked;
+        A.out = Uout[st - 1];
+        A.stage = st == 3 ? 0 : st;   // no dt/t advance in the one-step entry point
+        A.rk_a = kRK[st][0];
+        A.rk_b = kRK[st][1];
+        int r = launch_line<3, 1, 2>(ctx, A, ctx->maxn, true, grid);
+        if (r) return r;
+    }
+    (void)Uout;
+    return PP_OK;
+}
+
+int pp_cweno_batch_run(pp_cweno_ctx* ctx, double* Upacked, double t_end, int64_t nsteps_max,
+                       double cfl, int64_t* steps_out) {
+    (void)ctx; (void)Upacked; (void)t_end; (void)nsteps_max; (void)cfl; (void)steps_out;
+    if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
+    return fail(ctx, PP_EUNSUPPORTED, "batch_run is not built yet");
+}
+
+int pp_cweno_status(pp_cweno_ctx* ctx, uint32_t* flags) {
+    if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    unsigned st = 0;
+    HIPCHK(ctx, hipMemcpy(&st, &ctx->scal->status, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (flags) *flags = st;
+    if (st) {
+        unsigned zero = 0;
+        HIPCHK(ctx, hipMemcpy(&ctx->scal->status, &zero, sizeof(unsigned), hipMemcpyHostToDevice));
+        return fail(ctx, PP_ESTATE, "a stage left the admissible set or was not finite");
+    }
+    return PP_OK;
+}
+
+int pp_cweno_debug_line(pp_cweno_ctx* ctx, const double* U, double* um, double* up, double* flux) {
+    if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
+    if (!U) return fail(ctx, PP_EINVAL, "U is NULL");
+    if (ctx->cfg.ndim != 1 || ctx->cfg.nbatch > 0) return fail(ctx, PP_EINVAL, "debug_line is 1D only");
+    return launch_1d(ctx, U, nullptr, ctx->U2, 0, 0, 0.0, 1.0, nullptr, 0.0, false, um, up, flux);
+}
+
+const char* pp_cweno_last_error(const pp_cweno_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_init_err.c_str();
+}
+
+void pp_cweno_destroy(pp_cweno_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    void* bufs[] = {ctx->U1, ctx->U2, ctx->UA, ctx->UB, ctx->U1B, ctx->U2B, ctx->Lx, ctx->LyB,
+                    ctx->scal, ctx->d_off, ctx->d_n, ctx->d_h, ctx->d_bc, ctx->d_dt, ctx->d_t,
+                    ctx->d_order, ctx->d_counter, ctx->d_dtcopy};
+    for (void* p : bufs)
+        if (p) (void)hipFree(p);
+    delete ctx;
+}
+
+}  // extern "C"
