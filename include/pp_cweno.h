@@ -143,6 +143,15 @@ int pp_cweno_status(pp_cweno_ctx *ctx, uint32_t *flags);
 int pp_cweno_debug_line(pp_cweno_ctx *ctx, const double *U, double *um, double *up,
                         double *flux);
 
+/* Kernel timing for measurement: with on != 0, every later launch of the
+ * line kernel (x and y lines) and of the 2D combine kernel is bracketed by
+ * HIP events on the context's stream.  pp_cweno_get_timing synchronises and
+ * writes out[0..5] = {x-line ms total, x-line launches, y-line ms total,
+ * y-line launches, combine ms total, combine launches} since the last
+ * pp_cweno_set_timing call.  At most 4096 launches per class are timed. */
+int pp_cweno_set_timing(pp_cweno_ctx *ctx, int on);
+int pp_cweno_get_timing(pp_cweno_ctx *ctx, double *out);
+
 /* Message for the last error on ctx (or for init failures when ctx is NULL). */
 const char *pp_cweno_last_error(const pp_cweno_ctx *ctx);
 

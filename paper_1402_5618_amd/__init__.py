@@ -22,8 +22,8 @@ PP_DT_CFL, PP_DT_H53 = 0, 1
 EXPORTED = [
     "pp_cweno_config_defaults", "pp_cweno_init", "pp_cweno_rhs", "pp_cweno_stage",
     "pp_cweno_step", "pp_cweno_run", "pp_cweno_batch_step", "pp_cweno_batch_run",
-    "pp_cweno_max_speed", "pp_cweno_status", "pp_cweno_debug_line", "pp_cweno_last_error",
-    "pp_cweno_destroy",
+    "pp_cweno_max_speed", "pp_cweno_status", "pp_cweno_debug_line", "pp_cweno_set_timing",
+    "pp_cweno_get_timing", "pp_cweno_last_error", "pp_cweno_destroy",
 ]
 
 
@@ -72,6 +72,8 @@ def lib():
             "pp_cweno_max_speed": (ctypes.c_int, [_VP, _VP, _VP]),
             "pp_cweno_status": (ctypes.c_int, [_VP, P(ctypes.c_uint32)]),
             "pp_cweno_debug_line": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+            "pp_cweno_set_timing": (ctypes.c_int, [_VP, ctypes.c_int]),
+            "pp_cweno_get_timing": (ctypes.c_int, [_VP, P(ctypes.c_double)]),
             "pp_cweno_last_error": (ctypes.c_char_p, [_VP]),
             "pp_cweno_destroy": (None, [_VP]),
         }
@@ -174,6 +176,16 @@ class Solver:
     def debug_line(self, U, um=None, up=None, flux=None):
         return self._check(lib().pp_cweno_debug_line(self._ctx, _ptr(U), _ptr(um), _ptr(up),
                                                      _ptr(flux)))
+
+    def set_timing(self, on=True):
+        return self._check(lib().pp_cweno_set_timing(self._ctx, int(bool(on))))
+
+    def get_timing(self):
+        """{class: (total ms, launches)} for 'x', 'y', 'combine'."""
+        out = (ctypes.c_double * 6)()
+        self._check(lib().pp_cweno_get_timing(self._ctx, out))
+        return {"x": (out[0], int(out[1])), "y": (out[2], int(out[3])),
+                "combine": (out[4], int(out[5]))}
 
     def close(self):
         if self._ctx:

@@ -798,6 +798,10 @@ struct pp_cweno_ctx {
     int* d_counter = nullptr;
     double* d_dtcopy = nullptr;
     int n_sm = 0;
+    // measurement: event pairs around kernel launches, per class
+    bool timing = false;
+    std::vector<hipEvent_t> ev[3];
+    int nev[3] = {0, 0, 0};
 };
 
 namespace {
@@ -819,6 +823,26 @@ int hip_fail(pp_cweno_ctx* c, hipError_t e, const char* what) {
         hipError_t e_ = (call);                             \
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
     } while (0)
+
+constexpr int kMaxTimed = 4096;
+
+// Record the start event of a timed launch of class k (0 x-lines, 1 y-lines,
+// 2 combine); returns the slot or -1.
+int timed_begin(pp_cweno_ctx* ctx, int k) {
+    if (!ctx->timing || ctx->nev[k] >= kMaxTimed) return -1;
+    const int i = ctx->nev[k]++;
+    while ((int)ctx->ev[k].size() < 2 * (i + 1)) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        ctx->ev[k].push_back(e);
+    }
+    (void)hipEventRecord(ctx->ev[k][2 * i], ctx->stream);
+    return i;
+}
+
+void timed_end(pp_cweno_ctx* ctx, int k, int i) {
+    if (i >= 0) (void)hipEventRecord(ctx->ev[k][2 * i + 1], ctx->stream);
+}
 
 // Dynamic LDS of the line kernel for lines of up to nmax cells.
 template <int NC, int W>
@@ -925,7 +949,9 @@ int sweeps_2d(pp_cweno_ctx* ctx, const double* UsA, const double* UsB, const lon
     A.bc_lo = c.bc[0];
     A.bc_hi = c.bc[1];
     A.h = c.dx;
+    int slot = timed_begin(ctx, 0);
     int r = launch_line<4, 1, 1>(ctx, A, A.n, false, 0);
+    timed_end(ctx, 0, slot);
     if (r) return r;
     // y-lines: rows of the transposed [4][nx][ny] state
     A.U = UsB;
@@ -936,7 +962,10 @@ int sweeps_2d(pp_cweno_ctx* ctx, const double* UsA, const double* UsB, const lon
     A.bc_lo = c.bc[2];
     A.bc_hi = c.bc[3];
     A.h = c.dy;
-    return launch_line<4, 2, 1>(ctx, A, A.n, false, 0);
+    slot = timed_begin(ctx, 1);
+    r = launch_line<4, 2, 1>(ctx, A, A.n, false, 0);
+    timed_end(ctx, 1, slot);
+    return r;
 }
 
 int combine_2d(pp_cweno_ctx* ctx, const double* UsA, const double* Un, double* Out, double* OutB,
@@ -944,10 +973,12 @@ int combine_2d(pp_cweno_ctx* ctx, const double* UsA, const double* Un, double* O
                long long* eps_out, long long* spd_out, long long* eps_reset, bool run) {
     const auto& c = ctx->cfg;
     dim3 grid((unsigned)((c.nx + TT - 1) / TT), (unsigned)((c.ny + TT - 1) / TT));
+    const int slot = timed_begin(ctx, 2);
     hipLaunchKernelGGL(combine2d_kernel, grid, dim3(256), 0, ctx->stream, ctx->Lx, ctx->LyB, UsA,
                        Un, Out, OutB, (int)c.nx, (int)c.ny, mode, ra, rb, dt_dev, dt_val, c.gamma,
                        eps_out, spd_out, eps_reset, run ? ctx->scal : nullptr,
                        ctx->scal ? &ctx->scal->status : nullptr);
+    timed_end(ctx, 2, slot);
     HIPCHK(ctx, hipGetLastError());
     return PP_OK;
 }
@@ -1356,6 +1387,31 @@ int pp_cweno_debug_line(pp_cweno_ctx* ctx, const double* U, double* um, double* 
     return launch_1d(ctx, U, nullptr, ctx->U2, 0, 0, 0.0, 1.0, nullptr, 0.0, false, um, up, flux);
 }
 
+int pp_cweno_set_timing(pp_cweno_ctx* ctx, int on) {
+    if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->timing = on != 0;
+    for (int k = 0; k < 3; ++k) ctx->nev[k] = 0;
+    return PP_OK;
+}
+
+int pp_cweno_get_timing(pp_cweno_ctx* ctx, double* out) {
+    if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
+    if (!out) return fail(ctx, PP_EINVAL, "out is NULL");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < 3; ++k) {
+        double tot = 0.0;
+        for (int i = 0; i < ctx->nev[k]; ++i) {
+            float ms = 0.0f;
+            HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[k][2 * i], ctx->ev[k][2 * i + 1]));
+            tot += ms;
+        }
+        out[2 * k] = tot;
+        out[2 * k + 1] = ctx->nev[k];
+    }
+    return PP_OK;
+}
+
 const char* pp_cweno_last_error(const pp_cweno_ctx* ctx) {
     return ctx ? ctx->err.c_str() : g_init_err.c_str();
 }
@@ -1368,6 +1424,8 @@ void pp_cweno_destroy(pp_cweno_ctx* ctx) {
                     ctx->d_order, ctx->d_counter, ctx->d_dtcopy};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
+    for (int k = 0; k < 3; ++k)
+        for (hipEvent_t e : ctx->ev[k]) (void)hipEventDestroy(e);
     delete ctx;
 }
 
