@@ -159,11 +159,17 @@ class Solver:
         return self._check(lib().pp_cweno_batch_step(self._ctx, _ptr(U), _ptr(dt_dev)))
 
     def batch_run(self, U, t_end, nsteps_max=1 << 62, cfl=1.0 / 12.0):
+        """Per-problem step counts; raises PPError(PP_ESTATE) after the run if
+        a stage left the admissible set (counts then via last_batch_steps)."""
         nb = self.cfg.nbatch
         steps = (ctypes.c_int64 * nb)()
+        self._last_steps = steps
         self._check(lib().pp_cweno_batch_run(self._ctx, _ptr(U), float(t_end), int(nsteps_max),
                                              float(cfl), steps))
         return list(steps)
+
+    def last_batch_steps(self):
+        return list(self._last_steps)
 
     def max_speed(self, U, out):
         return self._check(lib().pp_cweno_max_speed(self._ctx, _ptr(U), _ptr(out)))

@@ -22,6 +22,22 @@ __device__ __forceinline__ double ord_dec(long long i) {
 constexpr long long kEncPosInf = 0x7ff0000000000000LL;  // ord_enc(+inf)
 constexpr long long kEncZero = 0;                       // ord_enc(+0.0)
 
+// Reciprocal: hardware estimate refined by Newton steps (two in double,
+// one in float) to within an ulp or two; shorter dependency chains than
+// the IEEE division sequence.
+__device__ __forceinline__ double rcp_t(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_t(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    const float e = fmaf(-x, r, 1.0f);
+    return fmaf(r, e, r);
+}
+
 // ------------------------------------------------------- Sec 2.2 weights
 // Smoothness indicators of the three candidates of the "-" side at node
 // j+1/2 from v0..v4 = ubar_{j-2..j+2}, then WENO-Z weights (power 2) with the
@@ -46,7 +62,7 @@ __device__ __forceinline__ void wenoz_weights(T v0, T v1, T v2, T v3, T v4, T ep
     T a0 = T(0.2) * (e0 + tt) * (e1 * e2);
     T a1 = T(0.5) * (e1 + tt) * (e0 * e2);
     T a2 = T(0.3) * (e2 + tt) * (e0 * e1);
-    T inv = T(1) / (a0 + a1 + a2);
+    T inv = rcp_t(a0 + a1 + a2);
     w0 = a0 * inv;
     w1 = a1 * inv;
     w2 = a2 * inv;
@@ -96,7 +112,7 @@ __device__ __forceinline__ void hllc_flux(double g, const double (&Ul)[NC], cons
     constexpr int IE = NC - 1;
     constexpr int TG = (NC == 4) ? 3 - NRM : -1;
     const double rl = Ul[0], rr = Ur[0];
-    const double irl = 1.0 / rl, irr = 1.0 / rr;
+    const double irl = rcp_t(rl), irr = rcp_t(rr);
     const double ul = Ul[NRM] * irl, ur = Ur[NRM] * irr;
     double vl = 0.0, vr = 0.0;
     if constexpr (TG > 0) {
@@ -109,21 +125,22 @@ __device__ __forceinline__ void hllc_flux(double g, const double (&Ul)[NC], cons
     const double al = sqrt(g * fmax(pl, 0.0) * irl), ar = sqrt(g * fmax(pr, 0.0) * irr);
     const double Hl = (El + pl) * irl, Hr = (Er + pr) * irr;
     const double R = sqrt(rr * irl);
-    const double i1R = 1.0 / (1.0 + R);
+    const double i1R = rcp_t(1.0 + R);
     const double ut = (ul + ur * R) * i1R, vt = (vl + vr * R) * i1R, Ht = (Hl + Hr * R) * i1R;
     const double at = sqrt(fmax((g - 1.0) * (Ht - 0.5 * (ut * ut + vt * vt)), 0.0));
     const double SL = fmin(ul - al, ut - at);
     const double SR = fmax(ur + ar, ut + at);
     const double den = rr * (SR - ur) - rl * (SL - ul);
     const double SM =
-        den > 0.0 ? (rr * ur * (SR - ur) - rl * ul * (SL - ul) + pl - pr) / den : 0.5 * (SL + SR);
+        den > 0.0 ? (rr * ur * (SR - ur) - rl * ul * (SL - ul) + pl - pr) * rcp_t(den)
+                  : 0.5 * (SL + SR);
     if (SL > 0.0) {
         F[0] = rl * ul;
         F[NRM] = rl * ul * ul + pl;
         if constexpr (TG > 0) F[TG] = rl * ul * vl;
         F[IE] = ul * (El + pl);
     } else if (SM > 0.0) {
-        const double id = 1.0 / (SL - SM);
+        const double id = rcp_t(SL - SM);
         const double ps = rl * (ul - SL) * (ul - SM) + pl;
         const double s0 = rl * (SL - ul) * id;
         const double sn = ((SL - ul) * rl * ul + (ps - pl)) * id;
@@ -133,7 +150,7 @@ __device__ __forceinline__ void hllc_flux(double g, const double (&Ul)[NC], cons
         if constexpr (TG > 0) F[TG] = rl * ul * vl + SL * (s0 * vl - Ul[TG]);
         F[IE] = ul * (El + pl) + SL * (se - El);
     } else if (SR >= 0.0 && SR > SM) {
-        const double id = 1.0 / (SR - SM);
+        const double id = rcp_t(SR - SM);
         const double ps = rr * (ur - SR) * (ur - SM) + pr;
         const double s0 = rr * (SR - ur) * id;
         const double sn = ((SR - ur) * rr * ur + (ps - pr)) * id;
@@ -157,6 +174,16 @@ __device__ __forceinline__ double spec_e(const double (&U)[NC]) {
 #pragma unroll
     for (int k = 1; k < NC - 1; ++k) m2 += U[k] * U[k];
     return U[NC - 1] / U[0] - 0.5 * m2 / (U[0] * U[0]);
+}
+
+// Limiter step 4 test "rho <= 0 or e(W) < eps" without divisions:
+// for rho > 0, e < eps  <=>  rho E - |m|^2/2 < eps rho^2.
+template <int NC>
+__device__ __forceinline__ bool below_eps(double eps, const double (&U)[NC]) {
+    double m2 = 0.0;
+#pragma unroll
+    for (int k = 1; k < NC - 1; ++k) m2 += U[k] * U[k];
+    return !(U[0] > 0.0) || (U[0] * U[NC - 1] - 0.5 * m2 < eps * U[0] * U[0]);
 }
 
 // Limiter step 4: root t in [0, 1] of e(Ubar + t (W - Ubar)) = eps via
@@ -188,11 +215,10 @@ __device__ __forceinline__ double pp_root(double eps, const double (&Ub)[NC],
 // Positivity-preserving limiter of one cell (Sec 2.4, steps 1-4): Um = U-_{j+1/2},
 // Up = U+_{j-1/2}, limited in place.  Returns 1 if anything changed.
 template <int NC>
-__device__ __forceinline__ int pp_limit(double w1, double eps_rho, double eps_e,
+__device__ __forceinline__ int pp_limit(double w1, double i12, double eps_rho, double eps_e,
                                         const double (&Ub)[NC], double (&Um)[NC],
                                         double (&Up)[NC]) {
-    int active = 0;
-    const double i12 = 1.0 / (1.0 - 2.0 * w1);
+    int active = 0;   // i12 = 1 / (1 - 2 w1)
     const double rmid = (Ub[0] - w1 * Up[0] - w1 * Um[0]) * i12;
     const double rmin = fmin(fmin(Um[0], Up[0]), rmid);
     if (rmin < eps_rho) {
@@ -207,9 +233,9 @@ __device__ __forceinline__ int pp_limit(double w1, double eps_rho, double eps_e,
 #pragma unroll
     for (int k = 0; k < NC; ++k) W3[k] = (Ub[k] - w1 * Up[k] - w1 * Um[k]) * i12;
     double th2 = 1.0;
-    if (!(Um[0] > 0.0) || spec_e<NC>(Um) < eps_e) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, Um));
-    if (!(Up[0] > 0.0) || spec_e<NC>(Up) < eps_e) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, Up));
-    if (!(W3[0] > 0.0) || spec_e<NC>(W3) < eps_e) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, W3));
+    if (below_eps<NC>(eps_e, Um)) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, Um));
+    if (below_eps<NC>(eps_e, Up)) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, Up));
+    if (below_eps<NC>(eps_e, W3)) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, W3));
     if (th2 < 1.0) {
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
@@ -227,7 +253,7 @@ __device__ __forceinline__ double wave_speed(double g, const double (&U)[NC]) {
     double m2 = 0.0;
 #pragma unroll
     for (int k = 1; k < NC - 1; ++k) m2 += U[k] * U[k];
-    const double ir = 1.0 / U[0];
+    const double ir = rcp_t(U[0]);
     const double p = (g - 1.0) * (U[NC - 1] - 0.5 * m2 * ir);
     return fabs(U[NRM] * ir) + sqrt(g * fmax(p, 0.0) * ir);
 }

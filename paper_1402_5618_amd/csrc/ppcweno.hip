@@ -36,7 +36,6 @@ using namespace ppc;
 namespace {
 
 constexpr int kCH = 32;      // max rows of one chunk held in registers
-constexpr int kCPT = 8;      // max cells per thread in phase 2
 constexpr int kNG = 3;       // ghost cells per side
 
 __device__ __forceinline__ int padi(int e) { return e + (e >> 5); }
@@ -64,12 +63,14 @@ struct LineArgs {
     const int* bcline;      // batched: [2] boundary codes of each problem
     double* dtline;         // batched: dt of each problem (<= 0: inactive)
     double* tline;          // batched: time of each problem
+    long long* stepline;    // batched: steps taken by each problem (stage-3 advance)
+    long long steps_max;    // batched: step budget per problem
     const int* order;       // batched: processing order (longest first)
     int* counter;           // batched: persistent work counter
     int n, nlines;
     int bc_lo, bc_hi;
     int seg_max;            // max cells per phase-2 segment
-    double h, gamma, w1, weno_eps, eps_cap, t_end, cfl;
+    double h, gamma, w1, i12, weno_eps, eps_cap, t_end, cfl;
     const long long* eps_enc;  // encoded (min rho, min e) of the whole grid, or nullptr
     const double* dt_dev;      // stage mode: dt on the device, or nullptr -> dt_val
     double dt_val;
@@ -122,7 +123,7 @@ __device__ __forceinline__ double block_max(double a, double* red) {
 
 // One line (or one problem) through the whole operator.  NC components, NRM
 // the normal momentum component, W waves per system (lines up to 2048 W).
-template <int NC, int NRM, int W>
+template <int NC, int NRM, int W, int CPT, bool SEG1>
 __device__ void line_op(const LineArgs& A, int b, double* smem) {
     constexpr int NS = 2 * NC;
     constexpr int LANES = 64 * W;
@@ -244,7 +245,7 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
                 }
                 if (j < len - 1) {
                     const double piv = (j == 0) ? bb : bb - a * cprev;
-                    const double ip = 1.0 / piv;
+                    const double ip = rcp_t(piv);
                     const double cj = c * ip;
                     const double pj = ((j == 0) ? r : r - a * pprev) * ip;
                     const double qj = ((j == 0) ? -a : -a * qprev) * ip;
@@ -299,81 +300,107 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
             fS = E2[0];
         }
     }
-    __syncthreads();   // line data no longer needed: reuse LDS
-    double* sF = smem;                          // [NS][LANES][3]
-    double* sR = smem + NS * LANES * 3;         // [NS][LANES][4]
-    double* sS = smem + NS * LANES * 7;         // [NS][LANES]
-    const int slot = sys * LANES + k;
-    if (act) {
-        sF[3 * slot + 0] = fP;
-        sF[3 * slot + 1] = fQ;
-        sF[3 * slot + 2] = fS;
-    }
-    __syncthreads();
-    double RA = 0.0, RB = 1.0, RC = 0.0, RD = 0.0;
-    if (act) {
-        int kn = k + 1;
-        double nP = 0.0, nQ = 0.0, nS = 0.0;
-        if (kn < P || cyclic) {
-            kn = kn & (P - 1);
-            nP = sF[3 * (sys * LANES + kn) + 0];
-            nQ = sF[3 * (sys * LANES + kn) + 1];
-            nS = sF[3 * (sys * LANES + kn) + 2];
+    double Rk = 0.0, Lk = 0.0;
+    if constexpr (W == 1) {
+        // one wave holds all chunks of a system: exchange through lane shuffles
+        const int kn = (k + 1) & (P - 1);
+        double nP = __shfl(fP, kn), nQ = __shfl(fQ, kn), nS = __shfl(fS, kn);
+        if (!cyclic && k + 1 >= P) nP = nQ = nS = 0.0;
+        double RA = ae * gQ, RB = be + ae * gS + ce * nQ, RC = ce * nS;
+        double RD = re - ae * gP - ce * nP;
+        for (int s = 1; s < P; s <<= 1) {
+            const int km = (k - s) & (P - 1), kp = (k + s) & (P - 1);
+            double Am = __shfl(RA, km), Bm = __shfl(RB, km), Cm = __shfl(RC, km), Dm = __shfl(RD, km);
+            double Ap = __shfl(RA, kp), Bp = __shfl(RB, kp), Cp = __shfl(RC, kp), Dp = __shfl(RD, kp);
+            if (!cyclic) {
+                if (k - s < 0) { Am = 0.0; Bm = 1.0; Cm = 0.0; Dm = 0.0; }
+                if (k + s >= P) { Ap = 0.0; Bp = 1.0; Cp = 0.0; Dp = 0.0; }
+            }
+            const double al = -RA * rcp_t(Bm), bt = -RC * rcp_t(Bp);
+            const double nA = al * Am, nC = bt * Cp;
+            const double nB = RB + al * Cm + bt * Ap, nD = RD + al * Dm + bt * Dp;
+            RA = nA; RB = nB; RC = nC; RD = nD;
         }
-        RA = ae * gQ;
-        RB = be + ae * gS + ce * nQ;
-        RC = ce * nS;
-        RD = re - ae * gP - ce * nP;
-        sR[4 * slot + 0] = RA;
-        sR[4 * slot + 1] = RB;
-        sR[4 * slot + 2] = RC;
-        sR[4 * slot + 3] = RD;
-    }
-    __syncthreads();
-    // parallel cyclic reduction of the separator system
-    for (int s = 1; s < P; s <<= 1) {
-        double nA = 0.0, nB = 1.0, nC = 0.0, nD = 0.0;
+        Rk = cyclic ? RD / (RA + RB + RC) : RD / RB;
+        Lk = __shfl(Rk, (k - 1) & (P - 1));
+        if (!cyclic && k == 0) Lk = 0.0;
+    } else {
+        __syncthreads();   // line data no longer needed: reuse LDS
+        double* sF = smem;                          // [NS][LANES][3]
+        double* sR = smem + NS * LANES * 3;         // [NS][LANES][4]
+        double* sS = smem + NS * LANES * 7;         // [NS][LANES]
+        const int slot = sys * LANES + k;
         if (act) {
-            int km = k - s, kp = k + s;
-            double Am = 0.0, Bm = 1.0, Cm = 0.0, Dm = 0.0, Ap = 0.0, Bp = 1.0, Cp = 0.0, Dp = 0.0;
-            if (cyclic) {
-                km &= (P - 1);
-                kp &= (P - 1);
-            }
-            if (km >= 0) {
-                const double* q = sR + 4 * (sys * LANES + km);
-                Am = q[0]; Bm = q[1]; Cm = q[2]; Dm = q[3];
-            }
-            if (kp < P) {
-                const double* q = sR + 4 * (sys * LANES + kp);
-                Ap = q[0]; Bp = q[1]; Cp = q[2]; Dp = q[3];
-            }
-            const double al = -RA / Bm, bt = -RC / Bp;
-            nA = al * Am;
-            nC = bt * Cp;
-            nB = RB + al * Cm + bt * Ap;
-            nD = RD + al * Dm + bt * Dp;
+            sF[3 * slot + 0] = fP;
+            sF[3 * slot + 1] = fQ;
+            sF[3 * slot + 2] = fS;
         }
         __syncthreads();
+        double RA = 0.0, RB = 1.0, RC = 0.0, RD = 0.0;
         if (act) {
-            RA = nA; RB = nB; RC = nC; RD = nD;
+            int kn = k + 1;
+            double nP = 0.0, nQ = 0.0, nS = 0.0;
+            if (kn < P || cyclic) {
+                kn = kn & (P - 1);
+                nP = sF[3 * (sys * LANES + kn) + 0];
+                nQ = sF[3 * (sys * LANES + kn) + 1];
+                nS = sF[3 * (sys * LANES + kn) + 2];
+            }
+            RA = ae * gQ;
+            RB = be + ae * gS + ce * nQ;
+            RC = ce * nS;
+            RD = re - ae * gP - ce * nP;
             sR[4 * slot + 0] = RA;
             sR[4 * slot + 1] = RB;
             sR[4 * slot + 2] = RC;
             sR[4 * slot + 3] = RD;
         }
         __syncthreads();
+        // parallel cyclic reduction of the separator system
+        for (int s = 1; s < P; s <<= 1) {
+            double nA = 0.0, nB = 1.0, nC = 0.0, nD = 0.0;
+            if (act) {
+                int km = k - s, kp = k + s;
+                double Am = 0.0, Bm = 1.0, Cm = 0.0, Dm = 0.0, Ap = 0.0, Bp = 1.0, Cp = 0.0, Dp = 0.0;
+                if (cyclic) {
+                    km &= (P - 1);
+                    kp &= (P - 1);
+                }
+                if (km >= 0) {
+                    const double* q = sR + 4 * (sys * LANES + km);
+                    Am = q[0]; Bm = q[1]; Cm = q[2]; Dm = q[3];
+                }
+                if (kp < P) {
+                    const double* q = sR + 4 * (sys * LANES + kp);
+                    Ap = q[0]; Bp = q[1]; Cp = q[2]; Dp = q[3];
+                }
+                const double al = -RA * rcp_t(Bm), bt = -RC * rcp_t(Bp);
+                nA = al * Am;
+                nC = bt * Cp;
+                nB = RB + al * Cm + bt * Ap;
+                nD = RD + al * Dm + bt * Dp;
+            }
+            __syncthreads();
+            if (act) {
+                RA = nA; RB = nB; RC = nC; RD = nD;
+                sR[4 * slot + 0] = RA;
+                sR[4 * slot + 1] = RB;
+                sR[4 * slot + 2] = RC;
+                sR[4 * slot + 3] = RD;
+            }
+            __syncthreads();
+        }
+        if (act) {
+            Rk = cyclic ? RD / (RA + RB + RC) : RD / RB;
+            sS[slot] = Rk;
+        }
+        __syncthreads();
+        if (act) {
+            if (k > 0) Lk = sS[sys * LANES + k - 1];
+            else if (cyclic) Lk = sS[sys * LANES + P - 1];
+        }
     }
-    double Rk = 0.0;
     if (act) {
-        Rk = cyclic ? RD / (RA + RB + RC) : RD / RB;
-        sS[slot] = Rk;
-    }
-    __syncthreads();
-    if (act) {
-        double Lk = 0.0;
-        if (k > 0) Lk = sS[sys * LANES + k - 1];
-        else if (cyclic) Lk = sS[sys * LANES + P - 1];
 #pragma unroll
         for (int j = 0; j < kCH; ++j) {
             if (j < len - 1) E0[j] = E0[j] + E1[j] * Lk + E2[j] * Rk;
@@ -389,7 +416,10 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
     double* sX = smem + (long long)NS * SS;      // [NC][NT] face-flux exchange
     double smax_speed = 0.0;
     unsigned bad = 0u;
-    for (int g0 = 0; g0 < n; g0 += SMAX) {
+    // SEG1: the whole line is one segment (the loop disappears at compile time)
+    const int nseg = SEG1 ? 1 : (n + SMAX - 1) / SMAX;
+    for (int sg = 0; sg < nseg; ++sg) {
+        const int g0 = sg * SMAX;
         const int g1 = min(n, g0 + SMAX);
         const int S = g1 - g0;
         const int left = cyclic ? (g0 - 1 + n) % n : g0 - 1;
@@ -424,7 +454,7 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
                 Um[c] = sRes[(2 * c) * SS + q];
                 Up[c] = sRes[(2 * c + 1) * SS + q];
             }
-            pp_limit<NC>(A.w1, eps_rho, eps_e, Ub, Um, Up);
+            pp_limit<NC>(A.w1, A.i12, eps_rho, eps_e, Ub, Um, Up);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 sRes[(2 * c) * SS + q] = Um[c];
@@ -436,7 +466,7 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
         const int cpt = (S + NT - 1) / NT;
         const int c0 = g0 + tid * cpt;
         const int c1 = min(g1, c0 + cpt);
-        double Fr[kCPT][NC];
+        double Fr[CPT][NC];
         double F0[NC];
         auto face = [&](int f, double (&F)[NC]) {
             double Ul[NC], Ur[NC];
@@ -465,11 +495,11 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
         if (c0 < c1) {
             if (tid == 0) face(g0, F0);
 #pragma unroll
-            for (int j = 0; j < kCPT; ++j)
+            for (int j = 0; j < CPT; ++j)
                 if (c0 + j < c1) face(c0 + j + 1, Fr[j]);
             const int jl = c1 - c0 - 1;
 #pragma unroll
-            for (int j = 0; j < kCPT; ++j)
+            for (int j = 0; j < CPT; ++j)
                 if (j == jl) {
 #pragma unroll
                     for (int c = 0; c < NC; ++c) sX[c * NT + tid] = Fr[j][c];
@@ -482,7 +512,7 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
             for (int c = 0; c < NC; ++c) Fl[c] = (tid == 0) ? F0[c] : sX[c * NT + tid - 1];
             const double ih = 1.0 / h;
 #pragma unroll
-            for (int j = 0; j < kCPT; ++j) {
+            for (int j = 0; j < CPT; ++j) {
                 if (c0 + j < c1) {
                     const int i = c0 + j;
                     double o[NC];
@@ -523,10 +553,18 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
             const double S = block_max<NT>(smax_speed, red);
             if (batched) {
                 if (tid == 0) {
+                    // next step of this problem: dt = cfl h / max(|u|+a) of the
+                    // new averages, clipped to t_end; 0 retires the problem
                     const double t = A.tline[b] + dt;
+                    const long long st = A.stepline[b] + 1;
                     A.tline[b] = t;
+                    A.stepline[b] = st;
                     double dn = A.cfl * h / S;
-                    if (t >= A.t_end) dn = 0.0;
+                    if (!(dn > 0.0) || !isfinite(dn)) {
+                        dn = 0.0;
+                        if (A.status) atomicOr(A.status, 1u);
+                    }
+                    if (t >= A.t_end || st >= A.steps_max) dn = 0.0;
                     else if (t + dn > A.t_end) dn = A.t_end - t;
                     A.dtline[b] = dn;
                 }
@@ -537,16 +575,16 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
     }
 }
 
-template <int NC, int NRM, int W>
+template <int NC, int NRM, int W, int CPT, bool SEG1>
 __global__ void __launch_bounds__(2 * NC * 64 * W) line_kernel(LineArgs A) {
     extern __shared__ double smem[];
     if (A.scal && !A.scal->active) return;
-    line_op<NC, NRM, W>(A, blockIdx.x, smem);
+    line_op<NC, NRM, W, CPT, SEG1>(A, blockIdx.x, smem);
 }
 
 // Batched ensemble: one persistent launch per stage; workgroups pop problem
 // ids (longest first) from a counter until the queue is empty.
-template <int NC, int NRM, int W>
+template <int NC, int NRM, int W, int CPT, bool SEG1>
 __global__ void __launch_bounds__(2 * NC * 64 * W) line_kernel_persistent(LineArgs A) {
     extern __shared__ double smem[];
     __shared__ int next;
@@ -556,12 +594,42 @@ __global__ void __launch_bounds__(2 * NC * 64 * W) line_kernel_persistent(LineAr
         const int q = next;
         __syncthreads();
         if (q >= A.nlines) break;
-        line_op<NC, NRM, W>(A, A.order[q], smem);
+        line_op<NC, NRM, W, CPT, SEG1>(A, A.order[q], smem);
         __syncthreads();
     }
 }
 
 __global__ void reset_counter(int* c) { *c = 0; }
+
+// Batched run start: per problem t = 0, steps = 0 and the first dt from the
+// wave speeds of its initial averages.
+__global__ void __launch_bounds__(256) batch_init_kernel(const double* __restrict__ U,
+                                                         long long total, const long long* off,
+                                                         const int* nl, const double* hl,
+                                                         double* dtl, double* tl, long long* sl,
+                                                         double gamma, double cfl, double t_end) {
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    const long long o = off[b];
+    double S = 0.0;
+    for (int i = threadIdx.x; i < nl[b]; i += 256) {
+        const double q[3] = {U[o + i], U[total + o + i], U[2 * total + o + i]};
+        S = fmax(S, wave_speed<3, 1>(gamma, q));
+    }
+#pragma unroll
+    for (int k = 32; k > 0; k >>= 1) S = fmax(S, __shfl_xor(S, k));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = S;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        S = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        double dt = cfl * hl[b] / S;
+        if (!(dt > 0.0) || !isfinite(dt)) dt = 0.0;
+        if (dt > t_end) dt = t_end;
+        dtl[b] = dt;
+        tl[b] = 0.0;
+        sl[b] = 0;
+    }
+}
 
 // ---------------------------------------------------------------- 2D pieces
 constexpr int TT = 32;   // transpose tile edge
@@ -750,7 +818,8 @@ __global__ void init_scal_kernel(Scal* s) {
 // reductions this step will fill.
 __global__ void dt_kernel(Scal* s, int ndim, int rule, double cfl, double dx, double dy,
                           double t_end, long long steps_max) {
-    if (s->active && s->dt > 0.0) {
+    if (!s->active) return;   // retired run: later launches change nothing
+    if (s->dt > 0.0) {
         s->t += s->dt;
         s->steps += 1;
     }
@@ -758,8 +827,11 @@ __global__ void dt_kernel(Scal* s, int ndim, int rule, double cfl, double dx, do
     double dt;
     if (ndim == 1) dt = (rule == PP_DT_H53 ? cfl * pow(dx, 5.0 / 3.0) : cfl * dx) / sx;
     else dt = cfl / (sx / dx + sy / dy);
-    const bool go = s->t < t_end && s->steps < steps_max && dt > 0.0 && isfinite(dt);
-    if (!(dt > 0.0) || !isfinite(dt)) s->status |= 1u;
+    bool go = s->t < t_end && s->steps < steps_max;
+    if (go && !(dt > 0.0 && isfinite(dt))) {
+        s->status |= 1u;   // no usable wave speed: stop the run
+        go = false;
+    }
     if (go && s->t + dt > t_end) dt = t_end - s->t;
     s->active = go ? 1 : 0;
     s->dt = go ? dt : 0.0;
@@ -794,6 +866,7 @@ struct pp_cweno_ctx {
     int* d_bc = nullptr;
     double* d_dt = nullptr;
     double* d_t = nullptr;
+    long long* d_steps = nullptr;
     int* d_order = nullptr;
     int* d_counter = nullptr;
     double* d_dtcopy = nullptr;
@@ -858,35 +931,36 @@ size_t line_lds_bytes(int nmax, int seg_max) {
 
 constexpr size_t kLdsBudget = 160 * 1024;
 
-template <int NC, int W>
+template <int NC, int W, int CPT>
 int pick_segment(int nmax) {
     constexpr int NT = 2 * NC * 64 * W;
     int seg = nmax;
-    while (seg > 64 && (line_lds_bytes<NC, W>(nmax, seg) > kLdsBudget || (seg + NT - 1) / NT > kCPT))
+    while (seg > 64 && (line_lds_bytes<NC, W>(nmax, seg) > kLdsBudget || (seg + NT - 1) / NT > CPT))
         seg = (seg + 1) / 2;
     return seg;
 }
 
-template <int NC, int NRM, int W>
+// Launch the line kernel for lines of at most nmax cells; picks the
+// single-segment variant when the whole line fits the phase-2 staging.
+template <int NC, int NRM, int W, int CPT>
 int launch_line(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int grid) {
-    const int seg = pick_segment<NC, W>(nmax);
+    constexpr int NT = 2 * NC * 64 * W;
+    const int seg = pick_segment<NC, W, CPT>(nmax);
     A.seg_max = seg;
     const size_t lds = line_lds_bytes<NC, W>(nmax, seg);
-    if (lds > kLdsBudget || (seg + 2 * NC * 64 * W - 1) / (2 * NC * 64 * W) > kCPT)
+    if (lds > kLdsBudget || (seg + NT - 1) / NT > CPT)
         return fail(ctx, PP_EUNSUPPORTED, "line too long for the on-chip line kernel");
-    constexpr int NT = 2 * NC * 64 * W;
-    if (persistent) {
-        auto fn = line_kernel_persistent<NC, NRM, W>;
-        HIPCHK(ctx, hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)lds));
-        hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, ctx->stream, A);
-    } else {
-        auto fn = line_kernel<NC, NRM, W>;
-        HIPCHK(ctx, hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)lds));
-        hipLaunchKernelGGL(fn, dim3(A.nlines), dim3(NT), lds, ctx->stream, A);
-    }
-    HIPCHK(ctx, hipGetLastError());
+    const void* fn;
+    if (seg >= nmax)
+        fn = persistent ? (const void*)line_kernel_persistent<NC, NRM, W, CPT, true>
+                        : (const void*)line_kernel<NC, NRM, W, CPT, true>;
+    else
+        fn = persistent ? (const void*)line_kernel_persistent<NC, NRM, W, CPT, false>
+                        : (const void*)line_kernel<NC, NRM, W, CPT, false>;
+    HIPCHK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    void* args[] = {&A};
+    HIPCHK(ctx, hipLaunchKernel(fn, dim3(persistent ? grid : A.nlines), dim3(NT), args, lds,
+                                ctx->stream));
     return PP_OK;
 }
 
@@ -894,6 +968,7 @@ LineArgs base_args(const pp_cweno_ctx* ctx) {
     LineArgs A{};
     A.gamma = ctx->cfg.gamma;
     A.w1 = ctx->cfg.gl_w1;
+    A.i12 = 1.0 / (1.0 - 2.0 * ctx->cfg.gl_w1);
     A.weno_eps = ctx->cfg.weno_eps;
     A.eps_cap = ctx->cfg.pp_eps_cap;
     A.rk_a = 0.0;
@@ -927,8 +1002,8 @@ int launch_1d(pp_cweno_ctx* ctx, const double* Us, const double* U0, double* out
     A.dbg_um = dbg_um;
     A.dbg_up = dbg_up;
     A.dbg_flux = dbg_flux;
-    if (A.n <= 2048) return launch_line<3, 1, 1>(ctx, A, A.n, false, 1);
-    return launch_line<3, 1, 2>(ctx, A, A.n, false, 1);
+    if (A.n <= 2048) return launch_line<3, 1, 1, 6>(ctx, A, A.n, false, 1);
+    return launch_line<3, 1, 2, 3>(ctx, A, A.n, false, 1);
 }
 
 // 2D sweeps of one stage input (Us in layout A and B) into Lx and LyB.
@@ -950,7 +1025,7 @@ int sweeps_2d(pp_cweno_ctx* ctx, const double* UsA, const double* UsB, const lon
     A.bc_hi = c.bc[1];
     A.h = c.dx;
     int slot = timed_begin(ctx, 0);
-    int r = launch_line<4, 1, 1>(ctx, A, A.n, false, 0);
+    int r = launch_line<4, 1, 1, 4>(ctx, A, A.n, false, 0);
     timed_end(ctx, 0, slot);
     if (r) return r;
     // y-lines: rows of the transposed [4][nx][ny] state
@@ -963,7 +1038,7 @@ int sweeps_2d(pp_cweno_ctx* ctx, const double* UsA, const double* UsB, const lon
     A.bc_hi = c.bc[3];
     A.h = c.dy;
     slot = timed_begin(ctx, 1);
-    r = launch_line<4, 2, 1>(ctx, A, A.n, false, 0);
+    r = launch_line<4, 2, 1, 4>(ctx, A, A.n, false, 0);
     timed_end(ctx, 1, slot);
     return r;
 }
@@ -1045,6 +1120,45 @@ int step_single(pp_cweno_ctx* ctx, double* U, const double* dt_dev, double dt_va
         r = combine_2d(ctx, inA[st - 1], U, outA[st - 1], outB[st - 1], 1, kRK[st][0], kRK[st][1],
                        dt_dev, dt_val, s->eps[out_slot], st == 3 ? s->spd : nullptr,
                        st == 1 ? s->eps[2] : nullptr, run);
+        if (r) return r;
+    }
+    return PP_OK;
+}
+
+// One SSP-RK3 step of every active problem of a batch: 3 persistent launches.
+// advance: the stage-3 epilogue advances t, step count and dt per problem.
+int batch_step_launch(pp_cweno_ctx* ctx, double* Upacked, double* dtl, bool advance, double cfl,
+                      double t_end, long long steps_max) {
+    LineArgs A = base_args(ctx);
+    A.cs = ctx->total;
+    A.off = ctx->d_off;
+    A.nline = ctx->d_n;
+    A.hline = ctx->d_h;
+    A.bcline = ctx->d_bc;
+    A.dtline = dtl;
+    A.tline = ctx->d_t;
+    A.stepline = ctx->d_steps;
+    A.steps_max = steps_max;
+    A.order = ctx->d_order;
+    A.nlines = (int)ctx->cfg.nbatch;
+    A.mode = 1;
+    A.t_end = t_end;
+    A.cfl = cfl;
+    const double* Uin[3] = {Upacked, ctx->U1, ctx->U2};
+    double* Uout[3] = {ctx->U1, ctx->U2, Upacked};
+    const int grid = ctx->n_sm;
+    for (int st = 1; st <= 3; ++st) {
+        hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, ctx->stream, ctx->d_counter + st);
+        HIPCHK(ctx, hipGetLastError());
+        A.counter = ctx->d_counter + st;
+        A.U = Uin[st - 1];
+        A.U0 = Upacked;
+        A.out = Uout[st - 1];
+        A.stage = (st == 3 && !advance) ? 0 : st;
+        A.rk_a = kRK[st][0];
+        A.rk_b = kRK[st][1];
+        int r = ctx->maxn <= 2048 ? launch_line<3, 1, 1, 6>(ctx, A, ctx->maxn, true, grid)
+                                  : launch_line<3, 1, 2, 3>(ctx, A, ctx->maxn, true, grid);
         if (r) return r;
     }
     return PP_OK;
@@ -1172,6 +1286,7 @@ int pp_cweno_init(const pp_cweno_config* cfg, pp_cweno_ctx** out) {
             !dmalloc((void**)&ctx->d_dt, sizeof(double) * nb) ||
             !dmalloc((void**)&ctx->d_dtcopy, sizeof(double) * nb) ||
             !dmalloc((void**)&ctx->d_t, sizeof(double) * nb) ||
+            !dmalloc((void**)&ctx->d_steps, sizeof(long long) * nb) ||
             !dmalloc((void**)&ctx->d_order, sizeof(int) * nb) ||
             !dmalloc((void**)&ctx->d_counter, sizeof(int) * 4) ||
             !dmalloc((void**)&ctx->U1, sizeof(double) * 3 * ctx->total) ||
@@ -1323,47 +1438,87 @@ int pp_cweno_batch_step(pp_cweno_ctx* ctx, double* Upacked, const double* dt_dev
     if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
     if (!Upacked || !dt_dev) return fail(ctx, PP_EINVAL, "NULL pointer");
     if (ctx->cfg.nbatch <= 0) return fail(ctx, PP_EINVAL, "context has no batch");
-    // the kernels read each problem's dt from d_dt; a copy keeps the caller's
-    // array read-only (the stage-3 epilogue only advances dt inside batch_run)
+    // the kernels read each problem's dt from a private copy so the caller's
+    // array stays read-only
     HIPCHK(ctx, hipMemcpyAsync(ctx->d_dtcopy, dt_dev, sizeof(double) * ctx->cfg.nbatch,
                                hipMemcpyDeviceToDevice, ctx->stream));
-    LineArgs A = base_args(ctx);
-    A.cs = ctx->total;
-    A.off = ctx->d_off;
-    A.nline = ctx->d_n;
-    A.hline = ctx->d_h;
-    A.bcline = ctx->d_bc;
-    A.dtline = ctx->d_dtcopy;
-    A.tline = ctx->d_t;
-    A.order = ctx->d_order;
-    A.nlines = (int)ctx->cfg.nbatch;
-    A.mode = 1;
-    A.t_end = INFINITY;
-    A.cfl = 0.0;
-    const double* Uin[3] = {Upacked, ctx->U1, ctx->U2};
-    double* Uout[3] = {ctx->U1, ctx->U2, Upacked};
-    const int grid = ctx->n_sm;
-    for (int st = 1; st <= 3; ++st) {
-        hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, ctx->stream, ctx->d_counter + st);
-        A.counter = ctx->d_counter + st;
-        A.U = Uin[st - 1];
-        A.U0 = Upacked;
-        A.out = Uout[st - 1];
-        A.stage = st == 3 ? 0 : st;   // no dt/t advance in the one-step entry point
-        A.rk_a = kRK[st][0];
-        A.rk_b = kRK[st][1];
-        int r = launch_line<3, 1, 2>(ctx, A, ctx->maxn, true, grid);
-        if (r) return r;
-    }
-    (void)Uout;
-    return PP_OK;
+    return batch_step_launch(ctx, Upacked, ctx->d_dtcopy, false, 0.0, 0.0, 0);
 }
 
 int pp_cweno_batch_run(pp_cweno_ctx* ctx, double* Upacked, double t_end, int64_t nsteps_max,
                        double cfl, int64_t* steps_out) {
-    (void)ctx; (void)Upacked; (void)t_end; (void)nsteps_max; (void)cfl; (void)steps_out;
     if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
-    return fail(ctx, PP_EUNSUPPORTED, "batch_run is not built yet");
+    if (!Upacked) return fail(ctx, PP_EINVAL, "Upacked is NULL");
+    if (ctx->cfg.nbatch <= 0) return fail(ctx, PP_EINVAL, "context has no batch");
+    if (!(t_end > 0.0) || !(cfl > 0.0) || nsteps_max < 1)
+        return fail(ctx, PP_EINVAL, "t_end and cfl must be > 0, nsteps_max >= 1");
+    const int nb = (int)ctx->cfg.nbatch;
+    int r = reset_scal(ctx);
+    if (r) return r;
+    hipLaunchKernelGGL(batch_init_kernel, dim3(nb), dim3(256), 0, ctx->stream, Upacked, ctx->total,
+                       ctx->d_off, ctx->d_n, ctx->d_h, ctx->d_dt, ctx->d_t, ctx->d_steps,
+                       ctx->cfg.gamma, cfl, t_end);
+    HIPCHK(ctx, hipGetLastError());
+    // K steps (3 persistent launches each) captured once in a graph on a
+    // private stream, replayed until every problem has retired
+    const int K = 8;
+    hipStream_t user = ctx->stream, gs = nullptr;
+    hipEvent_t ev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    auto cleanup = [&]() {
+        ctx->stream = user;
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev) (void)hipEventDestroy(ev);
+        if (gs) (void)hipStreamDestroy(gs);
+    };
+    hipError_t e = hipStreamCreateWithFlags(&gs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, user);
+    if (e == hipSuccess) e = hipStreamWaitEvent(gs, ev, 0);
+    if (e == hipSuccess) e = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(ctx, e, "graph capture setup");
+    }
+    ctx->stream = gs;
+    for (int k = 0; k < K && r == 0; ++k) r = batch_step_launch(ctx, Upacked, ctx->d_dt, true, cfl, t_end, nsteps_max);
+    e = hipStreamEndCapture(gs, &graph);
+    if (r || e != hipSuccess) {
+        cleanup();
+        return r ? r : hip_fail(ctx, e, "hipStreamEndCapture");
+    }
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(ctx, e, "hipGraphInstantiate");
+    }
+    std::vector<double> dts(nb);
+    const int64_t max_replays = nsteps_max / K + 2;
+    for (int64_t rep = 0; rep < max_replays; ++rep) {
+        e = hipGraphLaunch(exec, gs);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dts.data(), ctx->d_dt, sizeof(double) * nb, hipMemcpyDeviceToHost, gs);
+        if (e == hipSuccess) e = hipStreamSynchronize(gs);
+        if (e != hipSuccess) {
+            cleanup();
+            return hip_fail(ctx, e, "graph replay");
+        }
+        bool any = false;
+        for (double d : dts) any = any || d > 0.0;
+        if (!any) break;
+    }
+    cleanup();
+    if (steps_out) {
+        std::vector<long long> st(nb);
+        HIPCHK(ctx, hipMemcpy(st.data(), ctx->d_steps, sizeof(long long) * nb, hipMemcpyDeviceToHost));
+        for (int i = 0; i < nb; ++i) steps_out[i] = st[i];
+    }
+    unsigned status = 0;
+    HIPCHK(ctx, hipMemcpy(&status, &ctx->scal->status, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (status) return fail(ctx, PP_ESTATE, "a stage left the admissible set or was not finite");
+    return PP_OK;
 }
 
 int pp_cweno_status(pp_cweno_ctx* ctx, uint32_t* flags) {
@@ -1421,6 +1576,7 @@ void pp_cweno_destroy(pp_cweno_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     void* bufs[] = {ctx->U1, ctx->U2, ctx->UA, ctx->UB, ctx->U1B, ctx->U2B, ctx->Lx, ctx->LyB,
                     ctx->scal, ctx->d_off, ctx->d_n, ctx->d_h, ctx->d_bc, ctx->d_dt, ctx->d_t,
+                    ctx->d_steps,
                     ctx->d_order, ctx->d_counter, ctx->d_dtcopy};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
