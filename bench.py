@@ -64,27 +64,41 @@ def main():
     n = args.n
     dx = 2.0 / n
     U0 = torch.tensor(W.density_wave_2d(n, n), device="cuda")
-    solver = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=(0, 0, 0, 0), precision=pp.PP_FP64)
     cfl = 1.0 / 12.0
-
-    U = U0.clone()
-    if args.warmup > 0:
-        solver.run(U, 1e30, args.warmup, cfl)
-    U.copy_(U0)
-    torch.cuda.synchronize()
-    solver.set_timing(True)
-    t0 = time.perf_counter()
-    t_reached, steps = solver.run(U, 1e30, args.steps, cfl)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    timing = solver.get_timing()
-    solver.set_timing(False)
-    assert steps == args.steps, (steps, args.steps)
-    code, flags = solver.status()
-
     cells = n * n
-    value = cells * steps / wall
-    ms_step = 1e3 * wall / steps
+
+    def measure(precision):
+        solver = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=(0, 0, 0, 0), precision=precision)
+        U = U0.clone()
+        if args.warmup > 0:
+            solver.run(U, 1e30, args.warmup, cfl)
+        U.copy_(U0)
+        torch.cuda.synchronize()
+        solver.set_timing(True)
+        t0 = time.perf_counter()
+        t_reached, steps = solver.run(U, 1e30, args.steps, cfl)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        timing = solver.get_timing()
+        solver.set_timing(False)
+        assert steps == args.steps, (steps, args.steps)
+        code, flags = solver.status()
+        solver.close()
+        ex = W.density_wave_2d(n, n, t=t_reached)
+        Uh = U.cpu().numpy()
+        return dict(wall=wall, steps=steps, t=t_reached, timing=timing, flags=flags, U=Uh,
+                    l1=W.error_norms(Uh[0], ex[0], dx * dx)[0])
+
+    r64 = measure(pp.PP_FP64)
+    rmx = measure(pp.PP_MIXED)
+    steps = r64["steps"]
+    value = cells * steps / r64["wall"]
+    ms_step = 1e3 * r64["wall"] / steps
+    timing = r64["timing"]
+    value_mx = cells * steps / rmx["wall"]
+    l1_mx_vs_fp64 = float(np.abs(rmx["U"][0] - r64["U"][0]).sum() / np.abs(r64["U"][0]).sum())
+    mass_drift = float(abs(rmx["U"][0].sum() - W.density_wave_2d(n, n)[0].sum())
+                       / W.density_wave_2d(n, n)[0].sum())
 
     # dominant kernel of the step and its roofline (algorithmic bytes / launch)
     dom = max(timing, key=lambda k: timing[k][0])
@@ -95,10 +109,6 @@ def main():
     else:
         bytes_launch = cells * BYTES_PER_SWEEP_CELL
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-
-    # accuracy at the end of the timed run vs the exact cell averages
-    ex = W.density_wave_2d(n, n, t=t_reached)
-    l1 = W.error_norms(U[0].cpu().numpy(), ex[0], dx * dx)[0]
 
     line = {
         "metric": "cell-updates/s, 2D 2048^2 FP64 vs mixed-FP32 at fixed L1 error; % HBM BW",
@@ -114,14 +124,25 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"2D Euler smooth density wave, periodic {n}x{n}, FP64, SSP-RK3, "
-                        f"CFL-rule dt (w1=1/12)",
+            "workload": f"2D Euler smooth density wave, periodic {n}x{n}, SSP-RK3, "
+                        f"CFL-rule dt (w1=1/12), {steps} steps; value = FP64 form",
             "nx": n, "ny": n, "precision": "fp64",
             "pct_hbm_algorithmic": 100.0 * value * BYTES_PER_CELL_UPDATE / (HBM_PEAK_GBS * 1e9),
-            "l1_rho_vs_exact": l1,
-            "t_reached": t_reached,
-            "status_flags": flags,
+            "l1_rho_vs_exact": r64["l1"],
+            "t_reached": r64["t"],
+            "status_flags": r64["flags"],
             "kernel_ms_per_launch": {k: (v[0] / max(v[1], 1)) for k, v in timing.items()},
+            "mixed": {
+                "value": value_mx,
+                "ms_per_step": 1e3 * rmx["wall"] / steps,
+                "speedup_vs_fp64": value_mx / value,
+                "pct_hbm_algorithmic": 100.0 * value_mx * BYTES_PER_CELL_UPDATE / (HBM_PEAK_GBS * 1e9),
+                "l1_rho_vs_exact": rmx["l1"],
+                "l1_rho_rel_vs_fp64": l1_mx_vs_fp64,
+                "mass_drift_rel": mass_drift,
+                "status_flags": rmx["flags"],
+                "kernel_ms_per_launch": {k: (v[0] / max(v[1], 1)) for k, v in rmx["timing"].items()},
+            },
         },
         "roofline": {
             "bound": "hbm",
@@ -135,7 +156,6 @@ def main():
         },
         "cpu_baseline": None,
     }
-    solver.close()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
     print(json.dumps(line), flush=True)

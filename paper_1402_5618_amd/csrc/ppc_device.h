@@ -68,6 +68,33 @@ __device__ __forceinline__ void wenoz_weights(T v0, T v1, T v2, T v3, T v4, T ep
     w2 = a2 * inv;
 }
 
+// Float WENO-Z weights: the product form above under/overflows in float
+// (d^6 spans far more than the float range), so evaluate q_k = tau/(beta_k+eps),
+// scale by m = max(1, q_0, q_1, q_2) and use alpha_k ~ c_k (1/m^2 + (q_k/m)^2):
+// every term stays in [0, 1] and the normalised weights are unchanged.
+template <>
+__device__ __forceinline__ void wenoz_weights<float>(float v0, float v1, float v2, float v3,
+                                                     float v4, float eps, float& w0, float& w1,
+                                                     float& w2) {
+    const float k13 = 13.0f / 12.0f, k14 = 0.25f;
+    const float s0 = v0 - 2.0f * v1 + v2, t0 = v0 - 4.0f * v1 + 3.0f * v2;
+    const float s1 = v1 - 2.0f * v2 + v3, t1 = v1 - v3;
+    const float s2 = v2 - 2.0f * v3 + v4, t2 = 3.0f * v2 - 4.0f * v3 + v4;
+    const float b0 = k13 * s0 * s0 + k14 * t0 * t0;
+    const float b1 = k13 * s1 * s1 + k14 * t1 * t1;
+    const float b2 = k13 * s2 * s2 + k14 * t2 * t2;
+    const float tau = fabsf(b2 - b0);
+    const float q0 = tau * rcp_t(b0 + eps), q1 = tau * rcp_t(b1 + eps), q2 = tau * rcp_t(b2 + eps);
+    const float m = fmaxf(fmaxf(q0, q1), fmaxf(q2, 1.0f));
+    const float is = rcp_t(m);
+    const float r0 = q0 * is, r1 = q1 * is, r2 = q2 * is, s2m = is * is;
+    const float a0 = 0.2f * (s2m + r0 * r0), a1 = 0.5f * (s2m + r1 * r1), a2 = 0.3f * (s2m + r2 * r2);
+    const float inv = rcp_t(a0 + a1 + a2);
+    w0 = a0 * inv;
+    w1 = a1 * inv;
+    w2 = a2 * inv;
+}
+
 // Row of eq. (CWENO-FV) at node j+1/2 ("-" side): a u~_{j-1/2} + b u~_{j+1/2}
 // + c u~_{j+3/2} = r, right side from ubar_{j-1}, ubar_j, ubar_{j+1}.  The "+"
 // side is the same row on the mirrored line.
@@ -165,6 +192,77 @@ __device__ __forceinline__ void hllc_flux(double g, const double (&Ul)[NC], cons
         if constexpr (TG > 0) F[TG] = rr * ur * vr;
         F[IE] = ur * (Er + pr);
     }
+}
+
+// Mixed precision HLLC: primitives (rho, u_n, u_t, p) and E are formed in
+// double from the limited conserved states (so p never suffers float
+// cancellation near vacuum), then the wave speeds, contact, star states and
+// flux are evaluated in float; the flux is returned in double.
+template <int NC, int NRM>
+__device__ __forceinline__ void hllc_flux_f32(double gd, const double (&Uld)[NC],
+                                              const double (&Urd)[NC], double (&Fd)[NC]) {
+    constexpr int IE = NC - 1;
+    constexpr int TG = (NC == 4) ? 3 - NRM : -1;
+    const double irld = 1.0 / Uld[0], irrd = 1.0 / Urd[0];
+    const double uld = Uld[NRM] * irld, urd = Urd[NRM] * irrd;
+    double vld = 0.0, vrd = 0.0;
+    if constexpr (TG > 0) {
+        vld = Uld[TG] * irld;
+        vrd = Urd[TG] * irrd;
+    }
+    const double pld = (gd - 1.0) * (Uld[IE] - 0.5 * Uld[0] * (uld * uld + vld * vld));
+    const double prd = (gd - 1.0) * (Urd[IE] - 0.5 * Urd[0] * (urd * urd + vrd * vrd));
+    const float g = (float)gd;
+    const float rl = (float)Uld[0], rr = (float)Urd[0];
+    const float ul = (float)uld, ur = (float)urd, vl = (float)vld, vr = (float)vrd;
+    const float pl = (float)pld, pr = (float)prd, El = (float)Uld[IE], Er = (float)Urd[IE];
+    const float irl = rcp_t(rl), irr = rcp_t(rr);
+    const float al = sqrtf(g * fmaxf(pl, 0.0f) * irl), ar = sqrtf(g * fmaxf(pr, 0.0f) * irr);
+    const float Hl = (El + pl) * irl, Hr = (Er + pr) * irr;
+    const float R = sqrtf(rr * irl);
+    const float i1R = rcp_t(1.0f + R);
+    const float ut = (ul + ur * R) * i1R, vt = (vl + vr * R) * i1R, Ht = (Hl + Hr * R) * i1R;
+    const float at = sqrtf(fmaxf((g - 1.0f) * (Ht - 0.5f * (ut * ut + vt * vt)), 0.0f));
+    const float SL = fminf(ul - al, ut - at);
+    const float SR = fmaxf(ur + ar, ut + at);
+    const float den = rr * (SR - ur) - rl * (SL - ul);
+    const float SM = den > 0.0f ? (rr * ur * (SR - ur) - rl * ul * (SL - ul) + pl - pr) * rcp_t(den)
+                                : 0.5f * (SL + SR);
+    float F[NC];
+    const float mnl = rl * ul, mnr = rr * ur;
+    if (SL > 0.0f) {
+        F[0] = mnl;
+        F[NRM] = mnl * ul + pl;
+        if constexpr (TG > 0) F[TG] = mnl * vl;
+        F[IE] = ul * (El + pl);
+    } else if (SM > 0.0f) {
+        const float id = rcp_t(SL - SM);
+        const float ps = rl * (ul - SL) * (ul - SM) + pl;
+        const float s0 = rl * (SL - ul) * id;
+        const float sn = ((SL - ul) * mnl + (ps - pl)) * id;
+        const float se = ((SL - ul) * El - pl * ul + ps * SM) * id;
+        F[0] = mnl + SL * (s0 - rl);
+        F[NRM] = mnl * ul + pl + SL * (sn - mnl);
+        if constexpr (TG > 0) F[TG] = mnl * vl + SL * (s0 * vl - rl * vl);
+        F[IE] = ul * (El + pl) + SL * (se - El);
+    } else if (SR >= 0.0f && SR > SM) {
+        const float id = rcp_t(SR - SM);
+        const float ps = rr * (ur - SR) * (ur - SM) + pr;
+        const float s0 = rr * (SR - ur) * id;
+        const float sn = ((SR - ur) * mnr + (ps - pr)) * id;
+        const float se = ((SR - ur) * Er - pr * ur + ps * SM) * id;
+        F[0] = mnr + SR * (s0 - rr);
+        F[NRM] = mnr * ur + pr + SR * (sn - mnr);
+        if constexpr (TG > 0) F[TG] = mnr * vr + SR * (s0 * vr - rr * vr);
+        F[IE] = ur * (Er + pr) + SR * (se - Er);
+    } else {
+        F[0] = mnr;
+        F[NRM] = mnr * ur + pr;
+        if constexpr (TG > 0) F[TG] = mnr * vr;
+        F[IE] = ur * (Er + pr);
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) Fd[k] = (double)F[k];
 }
 
 // e = E/rho - |m|^2 / (2 rho^2), the specific internal energy of the set G.

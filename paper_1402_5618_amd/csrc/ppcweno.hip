@@ -121,9 +121,71 @@ __device__ __forceinline__ double block_max(double a, double* red) {
     return a;
 }
 
+// Values of lane src of this system (src in [0, P)): lane shuffles when one
+// wave holds the system, else an LDS round trip (all threads must call).
+template <int W, int NV>
+__device__ __forceinline__ void xch(double (&v)[NV], int src, double* sx, int sys, int k) {
+    constexpr int LANES = 64 * W;
+    if constexpr (W == 1) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = __shfl(v[i], src);
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sx[(sys * LANES + k) * 4 + i] = v[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = sx[(sys * LANES + src) * 4 + i];
+    }
+}
+
+// Parallel cyclic reduction of the separator system of one (component,
+// side): row k is A R_{k-1} + B R_k + C R_{k+1} = D over P lanes (indices mod P
+// when cyclic).  Returns R_k.  Arithmetic in T.
+template <int W, typename T>
+__device__ __forceinline__ T pcr_solve(T A, T B, T C, T D, int k, int P, bool cyclic, double* sx,
+                                       int sys) {
+    for (int s = 1; s < P; s <<= 1) {
+        const int km = (k - s) & (P - 1), kp = (k + s) & (P - 1);
+        double m[4] = {(double)A, (double)B, (double)C, (double)D};
+        double p[4] = {(double)A, (double)B, (double)C, (double)D};
+        xch<W, 4>(m, km, sx, sys, k);
+        xch<W, 4>(p, kp, sx, sys, k);
+        T Am = (T)m[0], Bm = (T)m[1], Cm = (T)m[2], Dm = (T)m[3];
+        T Ap = (T)p[0], Bp = (T)p[1], Cp = (T)p[2], Dp = (T)p[3];
+        if (!cyclic) {
+            if (k - s < 0) { Am = T(0); Bm = T(1); Cm = T(0); Dm = T(0); }
+            if (k + s >= P) { Ap = T(0); Bp = T(1); Cp = T(0); Dp = T(0); }
+        }
+        const T al = -A * rcp_t(Bm), bt = -C * rcp_t(Bp);
+        const T nA = al * Am, nC = bt * Cp;
+        const T nB = B + al * Cm + bt * Ap, nD = D + al * Dm + bt * Dp;
+        A = nA; B = nB; C = nC; D = nD;
+    }
+    return cyclic ? D / (A + B + C) : D / B;
+}
+
+// Rows of the mixed system from the stored weights (w1 := 1 - w0 - w2 in
+// float, so both passes see identical coefficients): eq. (CWENO-FV) matrix
+// (a, b, c) and right-side weights (e0, e1, e2).
+__device__ __forceinline__ void rows_from_w(float w0, float w2, float& a, float& b, float& c,
+                                            float& e0, float& e1, float& e2) {
+    const float w1 = 1.0f - w0 - w2;
+    const float third = 1.0f / 3.0f, sixth = 1.0f / 6.0f;
+    a = (2.0f * w0 + w1) * third;
+    b = (w0 + 2.0f * (w1 + w2)) * third;
+    c = w2 * third;
+    e0 = w0 * sixth;
+    e1 = (5.0f * (w0 + w1) + w2) * sixth;
+    e2 = (w1 + 5.0f * w2) * sixth;
+}
+
 // One line (or one problem) through the whole operator.  NC components, NRM
-// the normal momentum component, W waves per system (lines up to 2048 W).
-template <int NC, int NRM, int W, int CPT, bool SEG1>
+// the normal momentum component, W waves per system (lines up to 2048 W),
+// CPT cells per thread in phase 2, SEG1 = the line is one phase-2 segment,
+// MIXED = float reconstruction/solve with one FP64-residual refinement
+// sweep and a float HLLC (limiter and accumulation stay double).
+template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED>
 __device__ void line_op(const LineArgs& A, int b, double* smem) {
     constexpr int NS = 2 * NC;
     constexpr int LANES = 64 * W;
@@ -145,12 +207,14 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
     const double* __restrict__ U = A.U + base;
     const int LP = padi(n + 2 * kNG - 1) + 1;   // padded LDS length of one component
     double* sU = smem;                          // phase 0/1: [NC][LP]
-    // reduction scratch after the largest phase area (same formula as the host)
+    // layout (same formula as the host): line data, then (W > 1) the
+    // exchange scratch, and the reduction scratch after the largest area
     const long long area0 = (long long)NC * LP;
-    const long long area1 = (long long)NS * LANES * 8;
+    const long long area1 = (W > 1) ? (long long)NS * LANES * 4 : 0;
     const long long area2 = (long long)NS * (A.seg_max + 2) + (long long)NC * NT;
-    long long area = area0 > area1 ? area0 : area1;
+    long long area = area0 + area1;
     area = area > area2 ? area : area2;
+    double* sx = smem + area0;
     double* red = smem + area;
 
     // ---- phase 0: stage the line with ghosts; limiter epsilon
@@ -204,210 +268,249 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
     int P = LANES;
     while (P > n) P >>= 1;                  // chunks: power of two, <= n
     const bool act = k < P;
-    const int r0 = (int)(((long long)k * n) / P);
-    const int r1 = (int)(((long long)(k + 1) * n) / P);
-    const int len = act ? r1 - r0 : 0;
+    const int r0 = act ? (int)(((long long)k * n) / P) : 0;
+    const int r1 = act ? (int)(((long long)(k + 1) * n) / P) : 0;
+    const int len = r1 - r0;
+    const int knext = (k + 1) & (P - 1), kprev = (k - 1) & (P - 1);
     const double* sUc = sU + comp * LP;
     auto ub = [&](int m) -> double {
         const int o = rev ? (n - 1 - m) : m;
         return sUc[padi(o + kNG)];
     };
+    double clo = 0.0, chi = 0.0;
+    if (act && !cyclic && r0 == 0)
+        clo = weno5z_value(ub(-3), ub(-2), ub(-1), ub(0), ub(1), A.weno_eps);
+    if (act && !cyclic && r1 == n)
+        chi = weno5z_value(ub(n - 2), ub(n - 1), ub(n), ub(n + 1), ub(n + 2), A.weno_eps);
 
-    double E0[kCH], E1[kCH], E2[kCH];
-    double ae = 0.0, be = 1.0, ce = 0.0, re = 0.0;
-    double gP = 0.0, gQ = 1.0, gS = 0.0;   // x_{r1-2} = gP + gQ L + gS R
-    double fP = 0.0, fQ = 0.0, fS = 1.0;   // x_{r0}   = fP + fQ L + fS R
-    if (act) {
-        const double weps = A.weno_eps;
-        double clo = 0.0, chi = 0.0;
-        if (!cyclic && r0 == 0) clo = weno5z_value(ub(-3), ub(-2), ub(-1), ub(0), ub(1), weps);
-        if (!cyclic && r1 == n)
-            chi = weno5z_value(ub(n - 2), ub(n - 1), ub(n), ub(n + 1), ub(n + 2), weps);
-        double v0 = ub(r0 - 2), v1 = ub(r0 - 1), v2 = ub(r0), v3 = ub(r0 + 1);
-        double cprev = 0.0, pprev = 0.0, qprev = 0.0;
+    // per-lane results: x_j (double) = res(j)
+    double E0[MIXED ? 1 : kCH], E1[MIXED ? 1 : kCH], E2[MIXED ? 1 : kCH];
+    float X0[MIXED ? kCH : 1], Qf[MIXED ? kCH : 1], Sf[MIXED ? kCH : 1];
+    float W0[MIXED ? kCH : 1], W2[MIXED ? kCH : 1];
+    double Lk = 0.0, Rk = 0.0;
+    float Ld = 0.0f, Rd = 0.0f;   // mixed: separators of the correction solve
+
+    if constexpr (!MIXED) {
+        double ae = 0.0, be = 1.0, ce = 0.0, re = 0.0;
+        double gP = 0.0, gQ = 1.0, gS = 0.0;   // x_{r1-2} = gP + gQ L + gS R
+        double fP = 0.0, fQ = 0.0, fS = 1.0;   // x_{r0}   = fP + fQ L + fS R
+        if (act) {
+            const double weps = A.weno_eps;
+            double v0 = ub(r0 - 2), v1 = ub(r0 - 1), v2 = ub(r0), v3 = ub(r0 + 1);
+            double cprev = 0.0, pprev = 0.0, qprev = 0.0;
 #pragma unroll
-        for (int j = 0; j < kCH; ++j) {
-            if (j < len) {
-                const int g = r0 + j;
-                const double v4 = ub(g + 2);
-                double w0, w1, w2, a, bb, c, r;
-                wenoz_weights<double>(v0, v1, v2, v3, v4, weps, w0, w1, w2);
-                cweno_row<double>(w0, w1, w2, v1, v2, v3, a, bb, c, r);
-                if (!cyclic) {
-                    if (g == 0) {
-                        r -= a * clo;
-                        a = 0.0;
+            for (int j = 0; j < kCH; ++j) {
+                if (j < len) {
+                    const int g = r0 + j;
+                    const double v4 = ub(g + 2);
+                    double w0, w1, w2, a, bb, c, r;
+                    wenoz_weights<double>(v0, v1, v2, v3, v4, weps, w0, w1, w2);
+                    cweno_row<double>(w0, w1, w2, v1, v2, v3, a, bb, c, r);
+                    if (!cyclic) {
+                        if (g == 0) { r -= a * clo; a = 0.0; }
+                        if (g == n - 1) { r -= c * chi; c = 0.0; }
                     }
-                    if (g == n - 1) {
-                        r -= c * chi;
-                        c = 0.0;
+                    if (j < len - 1) {
+                        const double piv = (j == 0) ? bb : bb - a * cprev;
+                        const double ip = rcp_t(piv);
+                        const double cj = c * ip;
+                        const double pj = ((j == 0) ? r : r - a * pprev) * ip;
+                        const double qj = ((j == 0) ? -a : -a * qprev) * ip;
+                        E0[j] = cj; E1[j] = pj; E2[j] = qj;
+                        cprev = cj; pprev = pj; qprev = qj;
+                    } else {
+                        ae = a; be = bb; ce = c; re = r;
                     }
+                    v0 = v1; v1 = v2; v2 = v3; v3 = v4;
                 }
+            }
+            // symbolic back substitution: x_j = P_j + Q_j L + S_j R
+            double Pn = 0.0, Qn = 0.0, Sn = 0.0;
+#pragma unroll
+            for (int j = kCH - 1; j >= 0; --j) {
                 if (j < len - 1) {
-                    const double piv = (j == 0) ? bb : bb - a * cprev;
-                    const double ip = rcp_t(piv);
-                    const double cj = c * ip;
-                    const double pj = ((j == 0) ? r : r - a * pprev) * ip;
-                    const double qj = ((j == 0) ? -a : -a * qprev) * ip;
-                    E0[j] = cj;
-                    E1[j] = pj;
-                    E2[j] = qj;
-                    cprev = cj;
-                    pprev = pj;
-                    qprev = qj;
-                } else {
-                    ae = a;
-                    be = bb;
-                    ce = c;
-                    re = r;
+                    const double cj = E0[j];
+                    double Pj, Qj, Sj;
+                    if (j == len - 2) {
+                        Pj = E1[j]; Qj = E2[j]; Sj = -cj;
+                        gP = Pj; gQ = Qj; gS = Sj;
+                    } else {
+                        Pj = E1[j] - cj * Pn; Qj = E2[j] - cj * Qn; Sj = -cj * Sn;
+                    }
+                    E0[j] = Pj; E1[j] = Qj; E2[j] = Sj;
+                    Pn = Pj; Qn = Qj; Sn = Sj;
                 }
-                v0 = v1;
-                v1 = v2;
-                v2 = v3;
-                v3 = v4;
             }
+            if (len >= 2) { fP = E0[0]; fQ = E1[0]; fS = E2[0]; }
         }
-        // symbolic back substitution: x_j = P_j + Q_j L + S_j R
-        double Pn = 0.0, Qn = 0.0, Sn = 0.0;
+        double nf[3] = {fP, fQ, fS};
+        xch<W, 3>(nf, knext, sx, sys, k);
+        if (!cyclic && k + 1 >= P) nf[0] = nf[1] = nf[2] = 0.0;
+        Rk = pcr_solve<W, double>(ae * gQ, be + ae * gS + ce * nf[1], ce * nf[2],
+                                  re - ae * gP - ce * nf[0], k, P, cyclic, sx, sys);
+        double lv[1] = {Rk};
+        xch<W, 1>(lv, kprev, sx, sys, k);
+        Lk = (!cyclic && k == 0) ? 0.0 : lv[0];
+        if (act) {
 #pragma unroll
-        for (int j = kCH - 1; j >= 0; --j) {
-            if (j < len - 1) {
-                const double cj = E0[j];
-                double Pj, Qj, Sj;
-                if (j == len - 2) {
-                    Pj = E1[j];
-                    Qj = E2[j];
-                    Sj = -cj;
-                    gP = Pj;
-                    gQ = Qj;
-                    gS = Sj;
-                } else {
-                    Pj = E1[j] - cj * Pn;
-                    Qj = E2[j] - cj * Qn;
-                    Sj = -cj * Sn;
-                }
-                E0[j] = Pj;
-                E1[j] = Qj;
-                E2[j] = Sj;
-                Pn = Pj;
-                Qn = Qj;
-                Sn = Sj;
+            for (int j = 0; j < kCH; ++j) {
+                if (j < len - 1) E0[j] = E0[j] + E1[j] * Lk + E2[j] * Rk;
+                else if (j == len - 1) E0[j] = Rk;
             }
         }
-        if (len >= 2) {
-            fP = E0[0];
-            fQ = E1[0];
-            fS = E2[0];
-        }
-    }
-    double Rk = 0.0, Lk = 0.0;
-    if constexpr (W == 1) {
-        // one wave holds all chunks of a system: exchange through lane shuffles
-        const int kn = (k + 1) & (P - 1);
-        double nP = __shfl(fP, kn), nQ = __shfl(fQ, kn), nS = __shfl(fS, kn);
-        if (!cyclic && k + 1 >= P) nP = nQ = nS = 0.0;
-        double RA = ae * gQ, RB = be + ae * gS + ce * nQ, RC = ce * nS;
-        double RD = re - ae * gP - ce * nP;
-        for (int s = 1; s < P; s <<= 1) {
-            const int km = (k - s) & (P - 1), kp = (k + s) & (P - 1);
-            double Am = __shfl(RA, km), Bm = __shfl(RB, km), Cm = __shfl(RC, km), Dm = __shfl(RD, km);
-            double Ap = __shfl(RA, kp), Bp = __shfl(RB, kp), Cp = __shfl(RC, kp), Dp = __shfl(RD, kp);
-            if (!cyclic) {
-                if (k - s < 0) { Am = 0.0; Bm = 1.0; Cm = 0.0; Dm = 0.0; }
-                if (k + s >= P) { Ap = 0.0; Bp = 1.0; Cp = 0.0; Dp = 0.0; }
-            }
-            const double al = -RA * rcp_t(Bm), bt = -RC * rcp_t(Bp);
-            const double nA = al * Am, nC = bt * Cp;
-            const double nB = RB + al * Cm + bt * Ap, nD = RD + al * Dm + bt * Dp;
-            RA = nA; RB = nB; RC = nC; RD = nD;
-        }
-        Rk = cyclic ? RD / (RA + RB + RC) : RD / RB;
-        Lk = __shfl(Rk, (k - 1) & (P - 1));
-        if (!cyclic && k == 0) Lk = 0.0;
     } else {
-        __syncthreads();   // line data no longer needed: reuse LDS
-        double* sF = smem;                          // [NS][LANES][3]
-        double* sR = smem + NS * LANES * 3;         // [NS][LANES][4]
-        double* sS = smem + NS * LANES * 7;         // [NS][LANES]
-        const int slot = sys * LANES + k;
+        // ---------------- pass A: float weights, rows and chasing
+        float ae = 0.0f, be = 1.0f, ce = 0.0f, re = 0.0f;
+        float gP = 0.0f, gQ = 1.0f, gS = 0.0f, fP = 0.0f, fQ = 0.0f, fS = 1.0f;
+        const float weps = (float)A.weno_eps;
         if (act) {
-            sF[3 * slot + 0] = fP;
-            sF[3 * slot + 1] = fQ;
-            sF[3 * slot + 2] = fS;
-        }
-        __syncthreads();
-        double RA = 0.0, RB = 1.0, RC = 0.0, RD = 0.0;
-        if (act) {
-            int kn = k + 1;
-            double nP = 0.0, nQ = 0.0, nS = 0.0;
-            if (kn < P || cyclic) {
-                kn = kn & (P - 1);
-                nP = sF[3 * (sys * LANES + kn) + 0];
-                nQ = sF[3 * (sys * LANES + kn) + 1];
-                nS = sF[3 * (sys * LANES + kn) + 2];
-            }
-            RA = ae * gQ;
-            RB = be + ae * gS + ce * nQ;
-            RC = ce * nS;
-            RD = re - ae * gP - ce * nP;
-            sR[4 * slot + 0] = RA;
-            sR[4 * slot + 1] = RB;
-            sR[4 * slot + 2] = RC;
-            sR[4 * slot + 3] = RD;
-        }
-        __syncthreads();
-        // parallel cyclic reduction of the separator system
-        for (int s = 1; s < P; s <<= 1) {
-            double nA = 0.0, nB = 1.0, nC = 0.0, nD = 0.0;
-            if (act) {
-                int km = k - s, kp = k + s;
-                double Am = 0.0, Bm = 1.0, Cm = 0.0, Dm = 0.0, Ap = 0.0, Bp = 1.0, Cp = 0.0, Dp = 0.0;
-                if (cyclic) {
-                    km &= (P - 1);
-                    kp &= (P - 1);
-                }
-                if (km >= 0) {
-                    const double* q = sR + 4 * (sys * LANES + km);
-                    Am = q[0]; Bm = q[1]; Cm = q[2]; Dm = q[3];
-                }
-                if (kp < P) {
-                    const double* q = sR + 4 * (sys * LANES + kp);
-                    Ap = q[0]; Bp = q[1]; Cp = q[2]; Dp = q[3];
-                }
-                const double al = -RA * rcp_t(Bm), bt = -RC * rcp_t(Bp);
-                nA = al * Am;
-                nC = bt * Cp;
-                nB = RB + al * Cm + bt * Ap;
-                nD = RD + al * Dm + bt * Dp;
-            }
-            __syncthreads();
-            if (act) {
-                RA = nA; RB = nB; RC = nC; RD = nD;
-                sR[4 * slot + 0] = RA;
-                sR[4 * slot + 1] = RB;
-                sR[4 * slot + 2] = RC;
-                sR[4 * slot + 3] = RD;
-            }
-            __syncthreads();
-        }
-        if (act) {
-            Rk = cyclic ? RD / (RA + RB + RC) : RD / RB;
-            sS[slot] = Rk;
-        }
-        __syncthreads();
-        if (act) {
-            if (k > 0) Lk = sS[sys * LANES + k - 1];
-            else if (cyclic) Lk = sS[sys * LANES + P - 1];
-        }
-    }
-    if (act) {
+            float v0 = (float)ub(r0 - 2), v1 = (float)ub(r0 - 1), v2 = (float)ub(r0),
+                  v3 = (float)ub(r0 + 1);
+            float cprev = 0.0f, pprev = 0.0f, qprev = 0.0f;
 #pragma unroll
-        for (int j = 0; j < kCH; ++j) {
-            if (j < len - 1) E0[j] = E0[j] + E1[j] * Lk + E2[j] * Rk;
-            else if (j == len - 1) E0[j] = Rk;
+            for (int j = 0; j < kCH; ++j) {
+                if (j < len) {
+                    const int g = r0 + j;
+                    const float v4 = (float)ub(g + 2);
+                    float w0, w1, w2, a, bb, c, e0, e1, e2;
+                    wenoz_weights<float>(v0, v1, v2, v3, v4, weps, w0, w1, w2);
+                    W0[j] = w0;
+                    W2[j] = w2;
+                    rows_from_w(w0, w2, a, bb, c, e0, e1, e2);
+                    float r = e0 * v1 + e1 * v2 + e2 * v3;
+                    if (!cyclic) {
+                        if (g == 0) { r -= a * (float)clo; a = 0.0f; }
+                        if (g == n - 1) { r -= c * (float)chi; c = 0.0f; }
+                    }
+                    if (j < len - 1) {
+                        const float piv = (j == 0) ? bb : bb - a * cprev;
+                        const float ip = rcp_t(piv);
+                        const float cj = c * ip;
+                        const float pj = ((j == 0) ? r : r - a * pprev) * ip;
+                        const float qj = ((j == 0) ? -a : -a * qprev) * ip;
+                        X0[j] = cj; Qf[j] = pj; Sf[j] = qj;
+                        cprev = cj; pprev = pj; qprev = qj;
+                    } else {
+                        ae = a; be = bb; ce = c; re = r;
+                    }
+                    v0 = v1; v1 = v2; v2 = v3; v3 = v4;
+                }
+            }
+            float Pn = 0.0f, Qn = 0.0f, Sn = 0.0f;
+#pragma unroll
+            for (int j = kCH - 1; j >= 0; --j) {
+                if (j < len - 1) {
+                    const float cj = X0[j];
+                    float Pj, Qj, Sj;
+                    if (j == len - 2) {
+                        Pj = Qf[j]; Qj = Sf[j]; Sj = -cj;
+                        gP = Pj; gQ = Qj; gS = Sj;
+                    } else {
+                        Pj = Qf[j] - cj * Pn; Qj = Sf[j] - cj * Qn; Sj = -cj * Sn;
+                    }
+                    X0[j] = Pj; Qf[j] = Qj; Sf[j] = Sj;
+                    Pn = Pj; Qn = Qj; Sn = Sj;
+                }
+            }
+            if (len >= 2) { fP = X0[0]; fQ = Qf[0]; fS = Sf[0]; }
         }
+        double nf[3] = {fP, fQ, fS};
+        xch<W, 3>(nf, knext, sx, sys, k);
+        if (!cyclic && k + 1 >= P) nf[0] = nf[1] = nf[2] = 0.0;
+        const float RA = ae * gQ, RB = be + ae * gS + ce * (float)nf[1], RC = ce * (float)nf[2];
+        const float R0 = pcr_solve<W, float>(RA, RB, RC, re - ae * gP - ce * (float)nf[0], k, P,
+                                             cyclic, sx, sys);
+        double lv[1] = {(double)R0};
+        xch<W, 1>(lv, kprev, sx, sys, k);
+        const float L0 = (!cyclic && k == 0) ? 0.0f : (float)lv[0];
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < kCH; ++j) {
+                if (j < len - 1) X0[j] = X0[j] + Qf[j] * L0 + Sf[j] * R0;
+                else if (j == len - 1) X0[j] = R0;
+            }
+        }
+        // ---------------- refinement sweep: FP64 residual of the float
+        // system, float correction through the same chunk factorisation
+        double xn[1] = {act && len >= 1 ? (double)X0[0] : 0.0};   // next chunk's x_{r0}
+        xch<W, 1>(xn, knext, sx, sys, k);
+        float ge = 0.0f, fe = 0.0f;     // P parts of x_{r1-2} and x_{r0}
+        float res_e = 0.0f;             // residual of the separator row
+        if (act) {
+            double v1 = ub(r0 - 1), v2 = ub(r0), v3 = ub(r0 + 1);
+            float cprev = 0.0f, pprev = 0.0f;
+            double xm = (double)L0;     // x_{g-1}
+#pragma unroll
+            for (int j = 0; j < kCH; ++j) {
+                if (j < len) {
+                    const int g = r0 + j;
+                    // float rows: the factorisation of pass A; double rows
+                    // (same float weights): the system whose residual is taken
+                    float a, bb, c, e0, e1, e2;
+                    rows_from_w(W0[j], W2[j], a, bb, c, e0, e1, e2);
+                    const double dw0 = (double)W0[j], dw2 = (double)W2[j];
+                    const double dw1 = 1.0 - dw0 - dw2;
+                    double da = (2.0 * dw0 + dw1) / 3.0, db = (dw0 + 2.0 * (dw1 + dw2)) / 3.0;
+                    double dc = dw2 / 3.0;
+                    double r = (dw0 * v1 + (5.0 * (dw0 + dw1) + dw2) * v2 + (dw1 + 5.0 * dw2) * v3) / 6.0;
+                    if (!cyclic) {
+                        if (g == 0) { r -= da * clo; da = 0.0; a = 0.0f; }
+                        if (g == n - 1) { r -= dc * chi; dc = 0.0; c = 0.0f; }
+                    }
+                    const double x0 = (double)X0[j];
+                    const double xp = (j + 1 < len) ? (double)X0[j + 1 < kCH ? j + 1 : kCH - 1]
+                                                    : xn[0];
+                    const double res = r - (da * xm + db * x0 + dc * xp);
+                    const float rf = (float)res;
+                    if (j < len - 1) {
+                        const float piv = (j == 0) ? bb : bb - a * cprev;
+                        const float ip = rcp_t(piv);
+                        const float cj = c * ip;
+                        const float pj = ((j == 0) ? rf : rf - a * pprev) * ip;
+                        W0[j] = cj;
+                        W2[j] = pj;
+                        cprev = cj;
+                        pprev = pj;
+                    } else {
+                        res_e = rf;
+                    }
+                    xm = x0;
+                    v1 = v2;
+                    v2 = v3;
+                    v3 = ub(g + 2);
+                }
+            }
+            float Pn = 0.0f;
+#pragma unroll
+            for (int j = kCH - 1; j >= 0; --j) {
+                if (j < len - 1) {
+                    const float Pj = (j == len - 2) ? W2[j] : W2[j] - W0[j] * Pn;
+                    W2[j] = Pj;
+                    Pn = Pj;
+                    if (j == len - 2) ge = Pj;
+                }
+            }
+            if (len >= 2) fe = W2[0];
+        }
+        double nfe[1] = {(double)fe};
+        xch<W, 1>(nfe, knext, sx, sys, k);
+        if (!cyclic && k + 1 >= P) nfe[0] = 0.0;
+        Rd = pcr_solve<W, float>(RA, RB, RC, res_e - ae * ge - ce * (float)nfe[0], k, P, cyclic,
+                                 sx, sys);
+        double ld[1] = {(double)Rd};
+        xch<W, 1>(ld, kprev, sx, sys, k);
+        Ld = (!cyclic && k == 0) ? 0.0f : (float)ld[0];
     }
-    __syncthreads();   // separator scratch done: LDS becomes phase-2 staging
+    // x_j of this lane's chunk, in double
+    auto xval = [&](int j) -> double {
+        if constexpr (MIXED) {
+            const float d = (j < len - 1) ? W2[j] + Qf[j] * Ld + Sf[j] * Rd : Rd;
+            return (double)X0[j] + (double)d;
+        } else {
+            return E0[j];
+        }
+    };
+    __syncthreads();   // line data and exchange scratch done: LDS becomes staging
 
     // ---- phase 2: limiter, HLLC, flux difference, epilogue (by segments)
     const int SMAX = A.seg_max;
@@ -430,7 +533,7 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
                 if (j < len) {
                     const int g = r0 + j;
                     const int cell = rev ? (n - 1 - g) : g;
-                    const double x = E0[j];
+                    const double x = xval(j);
                     double* row = sRes + sys * SS;
                     if (cell >= g0 && cell < g1) {
                         row[cell - g0 + 1] = x;
@@ -486,7 +589,11 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
                 for (int c = 0; c < NC; ++c)
                     Ur[c] = (bc_hi == PP_BC_REFLECTIVE && c == NRM) ? -Ul[c] : Ul[c];
             }
-            hllc_flux<NC, NRM>(A.gamma, Ul, Ur, F);
+            if constexpr (MIXED) {
+                hllc_flux_f32<NC, NRM>(A.gamma, Ul, Ur, F);
+            } else {
+                hllc_flux<NC, NRM>(A.gamma, Ul, Ur, F);
+            }
             if (A.dbg_flux) {
 #pragma unroll
                 for (int c = 0; c < NC; ++c) A.dbg_flux[(long long)c * (n + 1) + f] = F[c];
@@ -575,16 +682,16 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
     }
 }
 
-template <int NC, int NRM, int W, int CPT, bool SEG1>
+template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED>
 __global__ void __launch_bounds__(2 * NC * 64 * W) line_kernel(LineArgs A) {
     extern __shared__ double smem[];
     if (A.scal && !A.scal->active) return;
-    line_op<NC, NRM, W, CPT, SEG1>(A, blockIdx.x, smem);
+    line_op<NC, NRM, W, CPT, SEG1, MIXED>(A, blockIdx.x, smem);
 }
 
 // Batched ensemble: one persistent launch per stage; workgroups pop problem
 // ids (longest first) from a counter until the queue is empty.
-template <int NC, int NRM, int W, int CPT, bool SEG1>
+template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED>
 __global__ void __launch_bounds__(2 * NC * 64 * W) line_kernel_persistent(LineArgs A) {
     extern __shared__ double smem[];
     __shared__ int next;
@@ -594,7 +701,7 @@ __global__ void __launch_bounds__(2 * NC * 64 * W) line_kernel_persistent(LineAr
         const int q = next;
         __syncthreads();
         if (q >= A.nlines) break;
-        line_op<NC, NRM, W, CPT, SEG1>(A, A.order[q], smem);
+        line_op<NC, NRM, W, CPT, SEG1, MIXED>(A, A.order[q], smem);
         __syncthreads();
     }
 }
@@ -923,9 +1030,9 @@ size_t line_lds_bytes(int nmax, int seg_max) {
     constexpr int NS = 2 * NC, LANES = 64 * W, NT = NS * LANES;
     const long long LP = (nmax + 2 * kNG - 1) + ((nmax + 2 * kNG - 1) >> 5) + 1;
     const long long a0 = (long long)NC * LP;
-    const long long a1 = (long long)NS * LANES * 8;
+    const long long a1 = W > 1 ? (long long)NS * LANES * 4 : 0;
     const long long a2 = (long long)NS * (seg_max + 2) + (long long)NC * NT;
-    long long m = std::max(a0, std::max(a1, a2));
+    long long m = std::max(a0 + a1, a2);
     return (size_t)(m + NT) * sizeof(double);
 }
 
@@ -942,8 +1049,8 @@ int pick_segment(int nmax) {
 
 // Launch the line kernel for lines of at most nmax cells; picks the
 // single-segment variant when the whole line fits the phase-2 staging.
-template <int NC, int NRM, int W, int CPT>
-int launch_line(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int grid) {
+template <int NC, int NRM, int W, int CPT, bool MIXED>
+int launch_line_p(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int grid) {
     constexpr int NT = 2 * NC * 64 * W;
     const int seg = pick_segment<NC, W, CPT>(nmax);
     A.seg_max = seg;
@@ -951,17 +1058,24 @@ int launch_line(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int gr
     if (lds > kLdsBudget || (seg + NT - 1) / NT > CPT)
         return fail(ctx, PP_EUNSUPPORTED, "line too long for the on-chip line kernel");
     const void* fn;
-    if (seg >= nmax)
-        fn = persistent ? (const void*)line_kernel_persistent<NC, NRM, W, CPT, true>
-                        : (const void*)line_kernel<NC, NRM, W, CPT, true>;
+    if (persistent)
+        fn = seg >= nmax ? (const void*)line_kernel_persistent<NC, NRM, W, CPT, true, MIXED>
+                         : (const void*)line_kernel_persistent<NC, NRM, W, CPT, false, MIXED>;
     else
-        fn = persistent ? (const void*)line_kernel_persistent<NC, NRM, W, CPT, false>
-                        : (const void*)line_kernel<NC, NRM, W, CPT, false>;
+        fn = seg >= nmax ? (const void*)line_kernel<NC, NRM, W, CPT, true, MIXED>
+                         : (const void*)line_kernel<NC, NRM, W, CPT, false, MIXED>;
     HIPCHK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     void* args[] = {&A};
     HIPCHK(ctx, hipLaunchKernel(fn, dim3(persistent ? grid : A.nlines), dim3(NT), args, lds,
                                 ctx->stream));
     return PP_OK;
+}
+
+template <int NC, int NRM, int W, int CPT>
+int launch_line(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int grid) {
+    if (ctx->cfg.precision == PP_MIXED)
+        return launch_line_p<NC, NRM, W, CPT, true>(ctx, A, nmax, persistent, grid);
+    return launch_line_p<NC, NRM, W, CPT, false>(ctx, A, nmax, persistent, grid);
 }
 
 LineArgs base_args(const pp_cweno_ctx* ctx) {
@@ -1194,8 +1308,6 @@ int pp_cweno_init(const pp_cweno_config* cfg, pp_cweno_ctx** out) {
         return fail(nullptr, PP_EINVAL, "epsilons must be > 0");
     if (c.precision != PP_FP64 && c.precision != PP_MIXED)
         return fail(nullptr, PP_EINVAL, "precision must be PP_FP64 or PP_MIXED");
-    if (c.precision == PP_MIXED)
-        return fail(nullptr, PP_EUNSUPPORTED, "mixed precision is not built yet");
     const int naxes = c.ndim == 2 ? 2 : 1;
     for (int a = 0; a < naxes; ++a) {
         if (!bc_ok(c.bc[2 * a]) || !bc_ok(c.bc[2 * a + 1]))
