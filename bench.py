@@ -6,7 +6,17 @@ seeded-free closed form), CFL-rule dt (w1 = 1/12) computed on the device every
 step.  One bench step = one SSP-RK3 step: 3 stages x (x-lines, y-lines,
 combine) over the whole grid.  Prints one JSON line.
 
-Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--no-cpu]
+Other workloads (one JSON line each, bounded runs):
+  --workload sedov2d      quarter-plane near-vacuum blast, 1024^2, reflective
+                          x=0 / y=0, transmissive far sides, mixed precision
+  --workload ensemble     4096 seeded 1D Riemann problems, N in [256, 4096],
+                          mixed precision, one persistent launch per stage,
+                          hipGraph replay, per-problem dt
+  --workload wave1d       Example 3.1 at N = 200, dt = w1 h^(5/3)/S, to t = 2
+  --workload rarefaction1d / blast1d   the 1D positivity configurations, N = 4000
+  --workload copy         plain device copy of a known size (counter calibration)
+
+Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--no-cpu] [--workload W]
 """
 import argparse
 import json
@@ -31,7 +41,119 @@ def parse():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--workload", default="density2d",
+                    choices=["density2d", "sedov2d", "ensemble", "wave1d", "rarefaction1d",
+                             "blast1d", "copy"])
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     return ap.parse_args()
+
+
+def other_workload(args):
+    """Bounded throughput runs of the other configurations (one JSON line)."""
+    import numpy as np
+    import torch
+
+    import paper_1402_5618_amd as pp
+    import workloads as W
+    prec_name = args.precision or ("mixed" if args.workload in ("sedov2d", "ensemble") else "fp64")
+    prec = pp.PP_MIXED if prec_name == "mixed" else pp.PP_FP64
+    out = {"unit": "cell-updates/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if prec_name == "fp64" else "f32+f64",
+           "data": "synthetic", "warmup": 0}
+    if args.workload == "copy":
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out.update(metric="device copy GB/s (read + write)", unit="GB/s",
+                   value=2 * nbytes * args.steps / dt / 1e9, steps=args.steps,
+                   config={"workload": f"copy of {nbytes} bytes x {args.steps}"})
+    elif args.workload == "sedov2d":
+        n = 1024
+        dx = 1.1 / n
+        U = torch.tensor(W.sedov_corner_2d(n), device="cuda")
+        s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=(2, 1, 2, 1), precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            t, steps = s.run(U, 1.0, args.steps, 1.0 / 12.0)
+            flags = 0
+        except pp.PPError as e:
+            t, steps, flags = float("nan"), args.steps, e.code
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        Uh = U.cpu().numpy()
+        out.update(metric="cell-updates/s, 2D Sedov-type blast 1024^2", value=n * n * steps / wall,
+                   steps=steps, ms_per_step=1e3 * wall / steps,
+                   config={"workload": f"quarter-plane blast 1024^2 on [0,1.1]^2, {prec_name}, "
+                                       f"{steps} steps (t = {t:.3e} of 1.0)",
+                           "min_rho": float(Uh[0].min()),
+                           "min_p": float(W.pressure(Uh).min()), "status": flags,
+                           "symmetry_rel": float(np.abs(Uh[0] - Uh[0].T).max() / Uh[0].max())})
+        s.close()
+    elif args.workload == "ensemble":
+        ens = W.riemann_ensemble()
+        nb = len(ens.lengths)
+        U = torch.tensor(ens.U, device="cuda")
+        s = pp.Solver(ndim=1, lengths=ens.lengths, dxs=ens.dx, bcs=[1] * (2 * nb), precision=prec)
+        s.batch_run(U.clone(), ens.t_end, 2, 1.0 / 12.0)   # warm-up (graph, kernels)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            steps = s.batch_run(U, ens.t_end, args.steps, 1.0 / 12.0)
+            flags = 0
+        except pp.PPError as e:
+            steps, flags = s.last_batch_steps(), e.code
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        cu = float(np.dot(np.asarray(steps, dtype=np.float64), ens.lengths))
+        Uh = U.cpu().numpy()
+        p = W.pressure(Uh)
+        out.update(metric="cell-updates/s, 4096-problem 1D Riemann ensemble",
+                   value=cu / wall, steps=int(max(steps)), ms_per_step=1e3 * wall / max(steps),
+                   config={"workload": f"{nb} Riemann problems, N in [256,4096] (sum "
+                                       f"{int(ens.lengths.sum())} cells), {prec_name}, "
+                                       f"{args.steps} steps per problem (bounded; t_end 0.2 not reached)",
+                           "problems_out_of_G": int(sum(1 for i in range(nb) if
+                                                        p[ens.offsets[i]:ens.offsets[i + 1]].min() <= 0
+                                                        or Uh[0, ens.offsets[i]:ens.offsets[i + 1]].min() <= 0)),
+                           "status": flags})
+        s.close()
+    else:
+        if args.workload == "wave1d":
+            n, h, U0, bc, T, rule = 200, 0.01, W.density_wave_1d(200), (0, 0), 2.0, pp.PP_DT_H53
+        elif args.workload == "rarefaction1d":
+            n, h, U0, bc, T, rule = 4000, 2.0 / 4000, W.double_rarefaction_1d(4000), (1, 1), 0.6, pp.PP_DT_CFL
+        else:
+            n, h, U0, bc, T, rule = 4000, 2.0 / 4000, W.vacuum_blast_1d(4000), (1, 1), 1e-3, pp.PP_DT_CFL
+        U = torch.tensor(U0, device="cuda")
+        s = pp.Solver(ndim=1, nx=n, dx=h, bc=(*bc, 0, 0), precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            t, steps = s.run(U, T, 10 ** 8, 1.0 / 12.0, rule)
+            flags = 0
+        except pp.PPError as e:
+            t, steps, flags = T, -1, e.code
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        Uh = U.cpu().numpy()
+        extra = {}
+        if args.workload == "wave1d":
+            extra["l1_rho_vs_exact"] = W.error_norms(Uh[0], W.density_wave_1d(n, t=t)[0], h)[0]
+        out.update(metric=f"cell-updates/s, 1D {args.workload} N={n}",
+                   value=(n * steps / wall) if steps > 0 else None, steps=steps,
+                   ms_per_step=(1e3 * wall / steps) if steps > 0 else None,
+                   config=dict(workload=f"1D {args.workload}, N={n}, to t={T}, {prec_name}",
+                               min_rho=float(Uh[0].min()), min_p=float(W.pressure(Uh).min()),
+                               status=flags, wall_s=wall, **extra))
+        s.close()
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(n, steps):
@@ -55,6 +177,9 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is design-only here)", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "density2d":
+        other_workload(args)
+        return
     import numpy as np
     import torch
 

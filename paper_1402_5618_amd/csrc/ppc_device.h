@@ -25,17 +25,21 @@ constexpr long long kEncZero = 0;                       // ord_enc(+0.0)
 // Reciprocal: hardware estimate refined by Newton steps (two in double,
 // one in float) to within an ulp or two; shorter dependency chains than
 // the IEEE division sequence.
+// A zero or infinite estimate (x = +-0, +-inf) is returned as is, like the
+// IEEE quotient, instead of letting the Newton step turn it into NaN.
 __device__ __forceinline__ double rcp_t(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
+    const double r0 = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r0, 1.0);
+    double r = fma(r0, e, r0);
     e = fma(-x, r, 1.0);
-    return fma(r, e, r);
+    r = fma(r, e, r);
+    return (r0 == 0.0 || isinf(r0)) ? r0 : r;
 }
 __device__ __forceinline__ float rcp_t(float x) {
-    float r = __builtin_amdgcn_rcpf(x);
-    const float e = fmaf(-x, r, 1.0f);
-    return fmaf(r, e, r);
+    const float r0 = __builtin_amdgcn_rcpf(x);
+    const float e = fmaf(-x, r0, 1.0f);
+    const float r = fmaf(r0, e, r0);
+    return (r0 == 0.0f || isinf(r0)) ? r0 : r;
 }
 
 // ------------------------------------------------------- Sec 2.2 weights

@@ -186,7 +186,7 @@ __device__ __forceinline__ void rows_from_w(float w0, float w2, float& a, float&
 // MIXED = float reconstruction/solve with one FP64-residual refinement
 // sweep and a float HLLC (limiter and accumulation stay double).
 template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED>
-__device__ void line_op(const LineArgs& A, int b, double* smem) {
+__device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) {
     constexpr int NS = 2 * NC;
     constexpr int LANES = 64 * W;
     constexpr int NT = NS * LANES;
@@ -450,9 +450,10 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
                     rows_from_w(W0[j], W2[j], a, bb, c, e0, e1, e2);
                     const double dw0 = (double)W0[j], dw2 = (double)W2[j];
                     const double dw1 = 1.0 - dw0 - dw2;
-                    double da = (2.0 * dw0 + dw1) / 3.0, db = (dw0 + 2.0 * (dw1 + dw2)) / 3.0;
-                    double dc = dw2 / 3.0;
-                    double r = (dw0 * v1 + (5.0 * (dw0 + dw1) + dw2) * v2 + (dw1 + 5.0 * dw2) * v3) / 6.0;
+                    // the row times 6 (exact scalings only), residual scaled back
+                    double da = 2.0 * (2.0 * dw0 + dw1), db = 2.0 * (dw0 + 2.0 * (dw1 + dw2));
+                    double dc = 2.0 * dw2;
+                    double r = dw0 * v1 + (5.0 * (dw0 + dw1) + dw2) * v2 + (dw1 + 5.0 * dw2) * v3;
                     if (!cyclic) {
                         if (g == 0) { r -= da * clo; da = 0.0; a = 0.0f; }
                         if (g == n - 1) { r -= dc * chi; dc = 0.0; c = 0.0f; }
@@ -460,7 +461,7 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
                     const double x0 = (double)X0[j];
                     const double xp = (j + 1 < len) ? (double)X0[j + 1 < kCH ? j + 1 : kCH - 1]
                                                     : xn[0];
-                    const double res = r - (da * xm + db * x0 + dc * xp);
+                    const double res = (r - (da * xm + db * x0 + dc * xp)) * (1.0 / 6.0);
                     const float rf = (float)res;
                     if (j < len - 1) {
                         const float piv = (j == 0) ? bb : bb - a * cprev;
@@ -501,15 +502,6 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
         xch<W, 1>(ld, kprev, sx, sys, k);
         Ld = (!cyclic && k == 0) ? 0.0f : (float)ld[0];
     }
-    // x_j of this lane's chunk, in double
-    auto xval = [&](int j) -> double {
-        if constexpr (MIXED) {
-            const float d = (j < len - 1) ? W2[j] + Qf[j] * Ld + Sf[j] * Rd : Rd;
-            return (double)X0[j] + (double)d;
-        } else {
-            return E0[j];
-        }
-    };
     __syncthreads();   // line data and exchange scratch done: LDS becomes staging
 
     // ---- phase 2: limiter, HLLC, flux difference, epilogue (by segments)
@@ -533,7 +525,14 @@ __device__ void line_op(const LineArgs& A, int b, double* smem) {
                 if (j < len) {
                     const int g = r0 + j;
                     const int cell = rev ? (n - 1 - g) : g;
-                    const double x = xval(j);
+                    // x_j of this lane's chunk, in double
+                    double x;
+                    if constexpr (MIXED) {
+                        const float d = (j < len - 1) ? W2[j] + Qf[j] * Ld + Sf[j] * Rd : Rd;
+                        x = (double)X0[j] + (double)d;
+                    } else {
+                        x = E0[j];
+                    }
                     double* row = sRes + sys * SS;
                     if (cell >= g0 && cell < g1) {
                         row[cell - g0 + 1] = x;
