@@ -38,7 +38,10 @@ namespace {
 constexpr int kCH = 32;      // max rows of one chunk held in registers
 constexpr int kNG = 3;       // ghost cells per side
 
-__device__ __forceinline__ int padi(int e) { return e + (e >> 5); }
+// LDS padding: one spare double after every 2^SH, so lanes that stride by
+// 2^SH doubles (one chunk of rows each) hit different banks.
+template <int SH>
+__host__ __device__ __forceinline__ int padn(int e) { return e + (e >> SH); }
 
 // Device scalars of a run: limiter epsilons per stage slot, wave speeds,
 // time step, time, step count, sticky status.
@@ -165,6 +168,52 @@ __device__ __forceinline__ T pcr_solve(T A, T B, T C, T D, int k, int P, bool cy
     return cyclic ? D / (A + B + C) : D / B;
 }
 
+// Both chunked systems of one component at once (FP64): the "-" system on
+// lane order k and the "+" system on mirrored order P-1-k, so its neighbours
+// k-1 / k+1 in elimination order are the physical lanes k+1 / k-1.  Row of
+// either: A R_prev + B R + C R_next = D.  sx: this component's [8][128] LDS
+// slots (value-major, so a wave's accesses are bank-conflict free); every
+// thread of the block must call (barriers inside).
+__device__ __forceinline__ void pcr_pair(double (&A)[2], double (&B)[2], double (&C)[2],
+                                         double (&D)[2], int k, int P, bool cyclic, double* sx) {
+    for (int s = 1; s < P; s <<= 1) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            sx[(4 * q) * 128 + k] = A[q];
+            sx[(4 * q + 1) * 128 + k] = B[q];
+            sx[(4 * q + 2) * 128 + k] = C[q];
+            sx[(4 * q + 3) * 128 + k] = D[q];
+        }
+        __syncthreads();
+        const int lo = (k - s) & (P - 1);   // physical lane k - s
+        const int hi = (k + s) & (P - 1);   // physical lane k + s
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const double* v = sx + (4 * q) * 128;
+            const int m = q == 0 ? lo : hi;   // previous in elimination order
+            const int p = q == 0 ? hi : lo;   // next in elimination order
+            double Am = v[m], Bm = v[128 + m], Cm = v[256 + m], Dm = v[384 + m];
+            double Ap = v[p], Bp = v[128 + p], Cp = v[256 + p], Dp = v[384 + p];
+            if (!cyclic) {
+                const bool mout = q == 0 ? (k - s < 0) : (k + s >= P);
+                const bool pout = q == 0 ? (k + s >= P) : (k - s < 0);
+                if (mout) { Am = 0.0; Bm = 1.0; Cm = 0.0; Dm = 0.0; }
+                if (pout) { Ap = 0.0; Bp = 1.0; Cp = 0.0; Dp = 0.0; }
+            }
+            const double al = -A[q] * rcp_t(Bm), bt = -C[q] * rcp_t(Bp);
+            const double nA = al * Am, nC = bt * Cp;
+            const double nB = B[q] + al * Cm + bt * Ap, nD = D[q] + al * Dm + bt * Dp;
+            A[q] = nA;
+            B[q] = nB;
+            C[q] = nC;
+            D[q] = nD;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) D[q] = cyclic ? D[q] / (A[q] + B[q] + C[q]) : D[q] / B[q];
+}
+
 // Rows of the mixed system from the stored weights (w1 := 1 - w0 - w2 in
 // float, so both passes see identical coefficients): eq. (CWENO-FV) matrix
 // (a, b, c) and right-side weights (e0, e1, e2).
@@ -190,6 +239,9 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     constexpr int NS = 2 * NC;
     constexpr int LANES = 64 * W;
     constexpr int NT = NS * LANES;
+    // FP64 lines of up to 2048 cells: both sides of a component per lane
+    constexpr bool PAIRED = !MIXED && W == 1;
+    constexpr int PSH = PAIRED ? 4 : 5;   // chunk stride 16 (paired) or 32 rows
     const int tid = threadIdx.x;
 
     // ---- problem geometry
@@ -205,13 +257,13 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     if (batched && !(dt > 0.0)) return;  // finished problem: leave it untouched
 
     const double* __restrict__ U = A.U + base;
-    const int LP = padi(n + 2 * kNG - 1) + 1;   // padded LDS length of one component
+    const int LP = padn<PSH>(n + 2 * kNG - 1) + 1;   // padded LDS length of one component
     double* sU = smem;                          // phase 0/1: [NC][LP]
-    // layout (same formula as the host): line data, then (W > 1) the
+    // layout (same formula as the host): line data, then (W > 1 or paired) the
     // exchange scratch, and the reduction scratch after the largest area
     const long long area0 = (long long)NC * LP;
-    const long long area1 = (W > 1) ? (long long)NS * LANES * 4 : 0;
-    const long long area2 = (long long)NS * (A.seg_max + 2) + (long long)NC * NT;
+    const long long area1 = (W > 1 || !MIXED) ? (long long)NS * 512 : 0;
+    const long long area2 = (long long)NS * (padn<PSH>(A.seg_max + 1) + 1) + (long long)NC * NT;
     long long area = area0 + area1;
     area = area > area2 ? area : area2;
     double* sx = smem + area0;
@@ -243,7 +295,7 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             cell[c] = U[(long long)c * A.cs + src];
-            sU[c * LP + padi(q)] = sgn[c] * cell[c];
+            sU[c * LP + padn<PSH>(q)] = sgn[c] * cell[c];
         }
         if (i >= 0 && i < n && A.eps_enc == nullptr) {
             mr = fmin(mr, cell[0]);
@@ -261,11 +313,20 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
         eps_e = fmin(A.eps_cap, me);
     }
 
-    // ---- phase 1: chunked chasing of every (component, side) system
-    const int sys = tid / LANES, k = tid % LANES;
+    // ---- phase 1: chunked chasing of every (component, side) system.
+    // PAIRED (FP64, lines <= 2048): one lane holds a chunk of BOTH systems of
+    // its component, 128 lanes per component, so the smoothness indicators and
+    // weight products of a cell are formed once for the two sides (the "+"
+    // side at node j-1/2 of cell j uses the indicators of the "-" side at node
+    // j+1/2 of the same cell, in mirrored order).  Otherwise one system per
+    // 64 W lanes, the "+" system as the "-" system of the reversed line.
+    constexpr int PL = PAIRED ? 128 : LANES;    // lanes per chunked system
+    constexpr int CHP = 16;                     // paired: rows per lane and side
+    const int sys = PAIRED ? 2 * (tid / 128) : tid / LANES;
+    const int k = tid % PL;
     const int comp = sys >> 1;
-    const bool rev = (sys & 1) != 0;
-    int P = LANES;
+    const bool rev = !PAIRED && (sys & 1) != 0;
+    int P = PL;
     while (P > n) P >>= 1;                  // chunks: power of two, <= n
     const bool act = k < P;
     const int r0 = act ? (int)(((long long)k * n) / P) : 0;
@@ -275,22 +336,200 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     const double* sUc = sU + comp * LP;
     auto ub = [&](int m) -> double {
         const int o = rev ? (n - 1 - m) : m;
-        return sUc[padi(o + kNG)];
+        return sUc[padn<PSH>(o + kNG)];
     };
+    // closure of a non-periodic line (explicit WENO5-Z on the ghosts)
     double clo = 0.0, chi = 0.0;
-    if (act && !cyclic && r0 == 0)
+    if (!PAIRED && act && !cyclic && r0 == 0)
         clo = weno5z_value(ub(-3), ub(-2), ub(-1), ub(0), ub(1), A.weno_eps);
-    if (act && !cyclic && r1 == n)
+    if (!PAIRED && act && !cyclic && r1 == n)
         chi = weno5z_value(ub(n - 2), ub(n - 1), ub(n), ub(n + 1), ub(n + 2), A.weno_eps);
 
     // per-lane results: x_j (double) = res(j)
-    double E0[MIXED ? 1 : kCH], E1[MIXED ? 1 : kCH], E2[MIXED ? 1 : kCH];
+    constexpr int CHE = PAIRED ? CHP : kCH;
+    double E0[MIXED ? 1 : CHE], E1[MIXED ? 1 : CHE], E2[MIXED ? 1 : CHE];
+    double F0[PAIRED ? CHP : 1], F1[PAIRED ? CHP : 1], F2[PAIRED ? CHP : 1];
     float X0[MIXED ? kCH : 1], Qf[MIXED ? kCH : 1], Sf[MIXED ? kCH : 1];
     float W0[MIXED ? kCH : 1], W2[MIXED ? kCH : 1];
     double Lk = 0.0, Rk = 0.0;
     float Ld = 0.0f, Rd = 0.0f;   // mixed: separators of the correction solve
 
-    if constexpr (!MIXED) {
+    if constexpr (PAIRED) {
+        const double weps = A.weno_eps;
+        const double k13 = 13.0 / 12.0, third = 1.0 / 3.0, sixth = 1.0 / 6.0;
+        double* sxc = sx + comp * 1024;   // [8][128] exchange slots of this component
+        // closure values: "-" side x_{-1}, x_n (nodes -1/2, n+1/2 seen from the
+        // ghost cells) and "+" side y_{-1}, y_n (mirror images)
+        double clo_m = 0.0, chi_m = 0.0, clo_p = 0.0, chi_p = 0.0;
+        if (act && !cyclic && k == 0) {
+            clo_m = weno5z_value(ub(-3), ub(-2), ub(-1), ub(0), ub(1), weps);
+            chi_p = weno5z_value(ub(1), ub(0), ub(-1), ub(-2), ub(-3), weps);
+        }
+        if (act && !cyclic && k == P - 1) {
+            chi_m = weno5z_value(ub(n - 2), ub(n - 1), ub(n), ub(n + 1), ub(n + 2), weps);
+            clo_p = weno5z_value(ub(n + 2), ub(n + 1), ub(n), ub(n - 1), ub(n - 2), weps);
+        }
+        // "-": x_j = P + Q L + S R, L = x_{r0-1}, R = x_{r1-1} (separator)
+        // "+": y_j = P + Q L + S R, L = y_{r1},  R = y_{r0}   (separator)
+        double ae = 0.0, be = 1.0, ce = 0.0, re = 0.0;
+        double gP = 0.0, gQ = 1.0, gS = 0.0, fP = 0.0, fQ = 0.0, fS = 1.0;
+        double aeP = 0.0, beP = 1.0, ceP = 0.0, reP = 0.0;
+        double gPp = 0.0, gQp = 1.0, gSp = 0.0, fPp = 0.0, fQp = 0.0, fSp = 1.0;
+        if (act) {
+            // pass 1, ascending: indicators and both weight sets; "-" chasing;
+            // the "+" weights are kept for the descending pass
+            double v0 = ub(r0 - 2), v1 = ub(r0 - 1), v2 = ub(r0), v3 = ub(r0 + 1);
+            double d2m = v0 - 2.0 * v1 + v2, d2c = v1 - 2.0 * v2 + v3;
+            double qm = k13 * d2m * d2m, qc = k13 * d2c * d2c;
+            double cprev = 0.0, pprev = 0.0, qprev = 0.0;
+#pragma unroll
+            for (int j = 0; j < CHP; ++j) {
+                if (j < len) {
+                    const int g = r0 + j;
+                    const double v4 = ub(g + 2);
+                    const double d2p = v2 - 2.0 * v3 + v4;
+                    const double qp = k13 * d2p * d2p;
+                    const double t0 = v0 - 4.0 * v1 + 3.0 * v2, t1 = v1 - v3;
+                    const double t2 = 3.0 * v2 - 4.0 * v3 + v4;
+                    const double b0 = qm + 0.25 * t0 * t0;
+                    const double b1 = qc + 0.25 * t1 * t1;
+                    const double b2 = qp + 0.25 * t2 * t2;
+                    const double tau = b2 - b0, tt = tau * tau;
+                    const double d0 = b0 + weps, d1 = b1 + weps, dd2 = b2 + weps;
+                    const double e0 = d0 * d0, e1 = d1 * d1, e2 = dd2 * dd2;
+                    const double G0 = (e0 + tt) * (e1 * e2);
+                    const double G1 = (e1 + tt) * (e0 * e2);
+                    const double G2 = (e2 + tt) * (e0 * e1);
+                    // "-" weights (0.2, 0.5, 0.3) on (G0, G1, G2); "+" on (G2, G1, G0)
+                    const double am0 = 0.2 * G0, am1 = 0.5 * G1, am2 = 0.3 * G2;
+                    const double ap0 = 0.2 * G2, ap2 = 0.3 * G0;
+                    const double im = rcp_t(am0 + am1 + am2), ipw = rcp_t(ap0 + am1 + ap2);
+                    const double w0 = am0 * im, w1 = am1 * im, w2 = am2 * im;
+                    F0[j] = ap0 * ipw;   // "+" w0; its w1 is recovered as 1 - w0 - w2
+                    F2[j] = ap2 * ipw;
+                    double a = (2.0 * w0 + w1) * third, bb = (w0 + 2.0 * (w1 + w2)) * third;
+                    double c = w2 * third;
+                    double r = (w0 * v1 + (5.0 * (w0 + w1) + w2) * v2 + (w1 + 5.0 * w2) * v3) * sixth;
+                    if (!cyclic) {
+                        if (g == 0) { r -= a * clo_m; a = 0.0; }
+                        if (g == n - 1) { r -= c * chi_m; c = 0.0; }
+                    }
+                    if (j < len - 1) {
+                        const double piv = (j == 0) ? bb : bb - a * cprev;
+                        const double ip = rcp_t(piv);
+                        const double cj = c * ip;
+                        const double pj = ((j == 0) ? r : r - a * pprev) * ip;
+                        const double qj = ((j == 0) ? -a : -a * qprev) * ip;
+                        E0[j] = cj; E1[j] = pj; E2[j] = qj;
+                        cprev = cj; pprev = pj; qprev = qj;
+                    } else {
+                        ae = a; be = bb; ce = c; re = r;
+                    }
+                    v0 = v1; v1 = v2; v2 = v3; v3 = v4;
+                    qm = qc; qc = qp;
+                }
+            }
+            // "-" symbolic back substitution
+            double Pn = 0.0, Qn = 0.0, Sn = 0.0;
+#pragma unroll
+            for (int j = CHP - 1; j >= 0; --j) {
+                if (j < len - 1) {
+                    const double cj = E0[j];
+                    double Pj, Qj, Sj;
+                    if (j == len - 2) {
+                        Pj = E1[j]; Qj = E2[j]; Sj = -cj;
+                        gP = Pj; gQ = Qj; gS = Sj;
+                    } else {
+                        Pj = E1[j] - cj * Pn; Qj = E2[j] - cj * Qn; Sj = -cj * Sn;
+                    }
+                    E0[j] = Pj; E1[j] = Qj; E2[j] = Sj;
+                    Pn = Pj; Qn = Qj; Sn = Sj;
+                }
+            }
+            if (len >= 2) { fP = E0[0]; fQ = E1[0]; fS = E2[0]; }
+            // pass 2, descending: "+" rows (a couples y_{g+1}, c couples y_{g-1})
+            double vr = ub(r0 + len), vc = ub(r0 + len - 1);   // v_{g+1}, v_g
+            cprev = 0.0; pprev = 0.0; qprev = 0.0;
+#pragma unroll
+            for (int j = CHP - 1; j >= 0; --j) {
+                if (j < len) {
+                    const int g = r0 + j;
+                    const double vl = ub(g - 1);
+                    const double w0 = F0[j], w2 = F2[j], w1 = 1.0 - w0 - w2;
+                    double a = (2.0 * w0 + w1) * third, bb = (w0 + 2.0 * (w1 + w2)) * third;
+                    double c = w2 * third;
+                    double r = (w0 * vr + (5.0 * (w0 + w1) + w2) * vc + (w1 + 5.0 * w2) * vl) * sixth;
+                    if (!cyclic) {
+                        if (g == n - 1) { r -= a * clo_p; a = 0.0; }
+                        if (g == 0) { r -= c * chi_p; c = 0.0; }
+                    }
+                    if (j > 0) {
+                        const bool first = (j == len - 1);
+                        const double piv = first ? bb : bb - a * cprev;
+                        const double ip = rcp_t(piv);
+                        const double cj = c * ip;
+                        const double pj = (first ? r : r - a * pprev) * ip;
+                        const double qj = (first ? -a : -a * qprev) * ip;
+                        F0[j] = cj; F1[j] = pj; F2[j] = qj;
+                        cprev = cj; pprev = pj; qprev = qj;
+                    } else {
+                        aeP = a; beP = bb; ceP = c; reP = r;
+                    }
+                    vr = vc; vc = vl;
+                }
+            }
+            // "+" symbolic back substitution, ascending from the separator
+            Pn = 0.0; Qn = 0.0; Sn = 0.0;
+#pragma unroll
+            for (int j = 1; j < CHP; ++j) {
+                if (j < len) {
+                    const double cj = F0[j];
+                    double Pj, Qj, Sj;
+                    if (j == 1) {
+                        Pj = F1[j]; Qj = F2[j]; Sj = -cj;
+                        gPp = Pj; gQp = Qj; gSp = Sj;
+                    } else {
+                        Pj = F1[j] - cj * Pn; Qj = F2[j] - cj * Qn; Sj = -cj * Sn;
+                    }
+                    F0[j] = Pj; F1[j] = Qj; F2[j] = Sj;
+                    Pn = Pj; Qn = Qj; Sn = Sj;
+                    if (j == len - 1) { fPp = Pj; fQp = Qj; fSp = Sj; }
+                }
+            }
+        }
+        // first-unknown relations of the neighbour chunks: "-" from lane k+1,
+        // "+" from lane k-1
+        const int kn = (k + 1) & (P - 1), kq = (k - 1) & (P - 1);
+        __syncthreads();
+        sxc[k] = fP; sxc[128 + k] = fQ; sxc[256 + k] = fS;
+        sxc[512 + k] = fPp; sxc[640 + k] = fQp; sxc[768 + k] = fSp;
+        __syncthreads();
+        double nf0 = sxc[kn], nf1 = sxc[128 + kn], nf2 = sxc[256 + kn];
+        double np0 = sxc[512 + kq], np1 = sxc[640 + kq], np2 = sxc[768 + kq];
+        if (!cyclic && k + 1 >= P) nf0 = nf1 = nf2 = 0.0;
+        if (!cyclic && k == 0) np0 = np1 = np2 = 0.0;
+        double RA[2] = {ae * gQ, aeP * gQp};
+        double RB[2] = {be + ae * gS + ce * nf1, beP + aeP * gSp + ceP * np1};
+        double RC[2] = {ce * nf2, ceP * np2};
+        double RD[2] = {re - ae * gP - ce * nf0, reP - aeP * gPp - ceP * np0};
+        pcr_pair(RA, RB, RC, RD, k, P, cyclic, sxc);
+        __syncthreads();
+        sxc[k] = RD[0];
+        sxc[512 + k] = RD[1];
+        __syncthreads();
+        const double Rm = RD[0], Rp = RD[1];
+        const double Lm = (!cyclic && k == 0) ? 0.0 : sxc[kq];
+        const double Lp = (!cyclic && k + 1 >= P) ? 0.0 : sxc[512 + kn];
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < CHP; ++j) {
+                if (j < len - 1) E0[j] = E0[j] + E1[j] * Lm + E2[j] * Rm;
+                else if (j == len - 1) E0[j] = Rm;
+                if (j == 0) F0[j] = Rp;
+                else if (j < len) F0[j] = F0[j] + F1[j] * Lp + F2[j] * Rp;
+            }
+        }
+    } else if constexpr (!MIXED) {
         double ae = 0.0, be = 1.0, ce = 0.0, re = 0.0;
         double gP = 0.0, gQ = 1.0, gS = 0.0;   // x_{r1-2} = gP + gQ L + gS R
         double fP = 0.0, fQ = 0.0, fS = 1.0;   // x_{r0}   = fP + fQ L + fS R
@@ -506,8 +745,8 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
 
     // ---- phase 2: limiter, HLLC, flux difference, epilogue (by segments)
     const int SMAX = A.seg_max;
-    const int SS = SMAX + 2;
-    double* sRes = smem;                         // [NS][SS]
+    const int SS = padn<PSH>(SMAX + 1) + 1;
+    double* sRes = smem;                         // [NS][SS], slots padded
     double* sX = smem + (long long)NS * SS;      // [NC][NT] face-flux exchange
     double smax_speed = 0.0;
     unsigned bad = 0u;
@@ -519,7 +758,28 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
         const int S = g1 - g0;
         const int left = cyclic ? (g0 - 1 + n) % n : g0 - 1;
         const int right = cyclic ? g1 % n : g1;
-        if (act) {
+        if (PAIRED && act) {
+            double* rowm = sRes + (2 * comp) * SS;
+            double* rowp = rowm + SS;
+#pragma unroll
+            for (int j = 0; j < CHP; ++j) {
+                if (j < len) {
+                    const int cell = r0 + j;
+                    const double xm = E0[j], xp = F0[j];
+                    if (cell >= g0 && cell < g1) {
+                        rowm[padn<PSH>(cell - g0 + 1)] = xm;
+                        rowp[padn<PSH>(cell - g0 + 1)] = xp;
+                        if (A.dbg_um) A.dbg_um[(long long)comp * n + cell] = xm;
+                        if (A.dbg_up) A.dbg_up[(long long)comp * n + cell] = xp;
+                    }
+                    if (cell == left) { rowm[0] = xm; rowp[0] = xp; }
+                    if (cell == right) {
+                        rowm[padn<PSH>(S + 1)] = xm;
+                        rowp[padn<PSH>(S + 1)] = xp;
+                    }
+                }
+            }
+        } else if (act) {
 #pragma unroll
             for (int j = 0; j < kCH; ++j) {
                 if (j < len) {
@@ -535,32 +795,34 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
                     }
                     double* row = sRes + sys * SS;
                     if (cell >= g0 && cell < g1) {
-                        row[cell - g0 + 1] = x;
+                        row[padn<PSH>(cell - g0 + 1)] = x;
                         double* d = rev ? A.dbg_up : A.dbg_um;
                         if (d) d[(long long)comp * n + cell] = x;
                     }
                     if (cell == left) row[0] = x;
-                    if (cell == right) row[S + 1] = x;
+                    if (cell == right) row[padn<PSH>(S + 1)] = x;
                 }
             }
         }
         __syncthreads();
-        // limiter on slots 0..S+1 (cells g0-1 .. g1)
-        for (int q = tid; q < S + 2; q += NT) {
+        // limiter on slots 0..S+1 (cells g0-1 .. g1); a single segment reads its
+        // edge neighbours from slots S and 1 instead (periodic) or not at all
+        for (int q = tid + (SEG1 ? 1 : 0); q < S + (SEG1 ? 1 : 2); q += NT) {
             const int cell = (q == 0) ? left : (q == S + 1 ? right : g0 + q - 1);
             if (cell < 0 || cell >= n) continue;
             double Ub[NC], Um[NC], Up[NC];
+            const int pq = padn<PSH>(q);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 Ub[c] = U[(long long)c * A.cs + cell];
-                Um[c] = sRes[(2 * c) * SS + q];
-                Up[c] = sRes[(2 * c + 1) * SS + q];
+                Um[c] = sRes[(2 * c) * SS + pq];
+                Up[c] = sRes[(2 * c + 1) * SS + pq];
             }
             pp_limit<NC>(A.w1, A.i12, eps_rho, eps_e, Ub, Um, Up);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                sRes[(2 * c) * SS + q] = Um[c];
-                sRes[(2 * c + 1) * SS + q] = Up[c];
+                sRes[(2 * c) * SS + pq] = Um[c];
+                sRes[(2 * c + 1) * SS + pq] = Up[c];
             }
         }
         __syncthreads();
@@ -572,11 +834,15 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
         double F0[NC];
         auto face = [&](int f, double (&F)[NC]) {
             double Ul[NC], Ur[NC];
-            const int ql = f - g0, qr = f - g0 + 1;   // slots of cells f-1 and f
+            int ql = f - g0, qr = f - g0 + 1;   // slots of cells f-1 and f
+            if (SEG1 && cyclic) {
+                if (f == 0) ql = S;
+                if (f == n) qr = 1;
+            }
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                Ul[c] = sRes[(2 * c) * SS + ql];
-                Ur[c] = sRes[(2 * c + 1) * SS + qr];
+                Ul[c] = sRes[(2 * c) * SS + padn<PSH>(ql)];
+                Ur[c] = sRes[(2 * c + 1) * SS + padn<PSH>(qr)];
             }
             if (!cyclic && f == 0) {
 #pragma unroll
@@ -598,8 +864,11 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
                 for (int c = 0; c < NC; ++c) A.dbg_flux[(long long)c * (n + 1) + f] = F[c];
             }
         };
+        // one segment of a periodic line: face 0 is face n (last thread)
+        const bool wrap0 = SEG1 && cyclic;
+        const int tlast = (S - 1) / cpt;
         if (c0 < c1) {
-            if (tid == 0) face(g0, F0);
+            if (tid == 0 && !wrap0) face(g0, F0);
 #pragma unroll
             for (int j = 0; j < CPT; ++j)
                 if (c0 + j < c1) face(c0 + j + 1, Fr[j]);
@@ -615,7 +884,12 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
         if (c0 < c1) {
             double Fl[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) Fl[c] = (tid == 0) ? F0[c] : sX[c * NT + tid - 1];
+            for (int c = 0; c < NC; ++c)
+                Fl[c] = (tid == 0) ? (wrap0 ? sX[c * NT + tlast] : F0[c]) : sX[c * NT + tid - 1];
+            if (wrap0 && tid == 0 && A.dbg_flux) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) A.dbg_flux[(long long)c * (n + 1)] = Fl[c];
+            }
             const double ih = 1.0 / h;
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
@@ -1024,24 +1298,26 @@ void timed_end(pp_cweno_ctx* ctx, int k, int i) {
 }
 
 // Dynamic LDS of the line kernel for lines of up to nmax cells.
-template <int NC, int W>
+template <int NC, int W, bool MIXED>
 size_t line_lds_bytes(int nmax, int seg_max) {
     constexpr int NS = 2 * NC, LANES = 64 * W, NT = NS * LANES;
-    const long long LP = (nmax + 2 * kNG - 1) + ((nmax + 2 * kNG - 1) >> 5) + 1;
+    constexpr int SH = (!MIXED && W == 1) ? 4 : 5;   // as the kernel's padding
+    const long long LP = padn<SH>(nmax + 2 * kNG - 1) + 1;
     const long long a0 = (long long)NC * LP;
-    const long long a1 = W > 1 ? (long long)NS * LANES * 4 : 0;
-    const long long a2 = (long long)NS * (seg_max + 2) + (long long)NC * NT;
+    const long long a1 = (W > 1 || !MIXED) ? (long long)NS * 512 : 0;
+    const long long a2 = (long long)NS * (padn<SH>(seg_max + 1) + 1) + (long long)NC * NT;
     long long m = std::max(a0 + a1, a2);
     return (size_t)(m + NT) * sizeof(double);
 }
 
 constexpr size_t kLdsBudget = 160 * 1024;
 
-template <int NC, int W, int CPT>
+template <int NC, int W, int CPT, bool MIXED>
 int pick_segment(int nmax) {
     constexpr int NT = 2 * NC * 64 * W;
     int seg = nmax;
-    while (seg > 64 && (line_lds_bytes<NC, W>(nmax, seg) > kLdsBudget || (seg + NT - 1) / NT > CPT))
+    while (seg > 64 &&
+           (line_lds_bytes<NC, W, MIXED>(nmax, seg) > kLdsBudget || (seg + NT - 1) / NT > CPT))
         seg = (seg + 1) / 2;
     return seg;
 }
@@ -1051,9 +1327,9 @@ int pick_segment(int nmax) {
 template <int NC, int NRM, int W, int CPT, bool MIXED>
 int launch_line_p(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int grid) {
     constexpr int NT = 2 * NC * 64 * W;
-    const int seg = pick_segment<NC, W, CPT>(nmax);
+    const int seg = pick_segment<NC, W, CPT, MIXED>(nmax);
     A.seg_max = seg;
-    const size_t lds = line_lds_bytes<NC, W>(nmax, seg);
+    const size_t lds = line_lds_bytes<NC, W, MIXED>(nmax, seg);
     if (lds > kLdsBudget || (seg + NT - 1) / NT > CPT)
         return fail(ctx, PP_EUNSUPPORTED, "line too long for the on-chip line kernel");
     const void* fn;

@@ -45,6 +45,22 @@ CASES_1D = [(7, (0, 0)), (13, (1, 1)), (64, (0, 0)), (200, (1, 2)), (777, (2, 2)
             (2048, (0, 0)), (2049, (1, 1)), (4000, (1, 1))]
 
 
+def stage_tolerance(U0, Us, st, dt, bc, h, ref, k=4):
+    """1e-12, or 4x the oracle's own change under k seeded relative input
+    perturbations of 1e-15 when that is larger.  Where the limiter puts an
+    interface state on e = eps (pressure ~1e-14), the sound speed is a square
+    root of a roundoff-sized number and the stage output moves by ~1e-12 under
+    a last-bit change of its input; bit-level agreement is then not defined."""
+    rng = np.random.default_rng(1402 + st)
+    sens = 0.0
+    for _ in range(k):
+        f0 = 1.0 + 1e-15 * rng.standard_normal(U0.shape)
+        fs = 1.0 + 1e-15 * rng.standard_normal(Us.shape)
+        V = oracle.stage_1d(U0 * f0, Us * fs, st, dt, bc, h)
+        sens = max(sens, comp_rel(V, ref))
+    return max(TOL_STAGE, 4.0 * sens)
+
+
 @pytest.mark.parametrize("n,bc", CASES_1D)
 def test_1d_stage_parity(n, bc):
     pp = gpu()
@@ -62,8 +78,12 @@ def test_1d_stage_parity(n, bc):
     s.stage(Ud, dev(U1), o2, 2, dt)
     s.stage(Ud, dev(U2), o3, 3, dt)
     torch.cuda.synchronize()
-    for got, ref in ((o1, U1), (o2, U2), (o3, U3)):
-        assert comp_rel(got.cpu().numpy(), ref) <= TOL_STAGE
+    for st, (got, ref, Us) in enumerate(((o1, U1, U), (o2, U2, U1), (o3, U3, U2)), start=1):
+        err = comp_rel(got.cpu().numpy(), ref)
+        if err > TOL_STAGE:   # only then pay for the conditioning estimate
+            tol = stage_tolerance(U, Us, st, dt, bc, h, ref)
+            print(f"stage {st}: err {err:.2e}, conditioning bound {tol:.2e}", flush=True)
+            assert err <= tol
     s.close()
 
 
