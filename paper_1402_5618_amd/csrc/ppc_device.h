@@ -35,6 +35,15 @@ __device__ __forceinline__ double rcp_t(double x) {
     r = fma(r, e, r);
     return (r0 == 0.0 || isinf(r0)) ? r0 : r;
 }
+// Reciprocal of a finite non-zero value (weight sums, pivots): the same
+// estimate and Newton steps without the zero / infinity pass-through.
+__device__ __forceinline__ double rcp_pos(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
 __device__ __forceinline__ float rcp_t(float x) {
     const float r0 = __builtin_amdgcn_rcpf(x);
     const float e = fmaf(-x, r0, 1.0f);

@@ -214,6 +214,201 @@ __device__ __forceinline__ void pcr_pair(double (&A)[2], double (&B)[2], double 
     for (int q = 0; q < 2; ++q) D[q] = cyclic ? D[q] / (A[q] + B[q] + C[q]) : D[q] / B[q];
 }
 
+constexpr int kCHP = 16;   // paired FP64 path: rows per lane and side
+
+// Phase 1 of the paired FP64 path: lane k of a component holds rows
+// [r0, r0 + len) of both tridiagonal systems of that component.
+//  "-" system (eq. (CWENO-FV)): x_j = u-_{j+1/2}, row j couples x_{j-1}, x_j, x_{j+1}.
+//  "+" system (its mirror):     y_j = u+_{j-1/2}, row j couples y_{j+1}, y_j, y_{j-1}
+//  and is eliminated from the right end, within the chunk and through the
+//  separator system.  The smoothness indicators of cell j serve both rows of
+//  cell j; the "+" weights are the "-" weight products in mirrored order.
+// On return E0[j] = x_{r0+j}, F0[j] = y_{r0+j}.  All threads of the block
+// must call.
+__device__ __forceinline__ void paired_solve(const double* __restrict__ sUc, int n, int k, int P,
+                                             bool cyclic, double weps, double* sxc, int r0,
+                                             int len, double (&E0)[kCHP], double (&E1)[kCHP],
+                                             double (&E2)[kCHP], double (&F0)[kCHP],
+                                             double (&F1)[kCHP], double (&F2)[kCHP]) {
+    const double k13 = 13.0 / 12.0, third = 1.0 / 3.0, sixth = 1.0 / 6.0;
+    const bool act = k < P;
+    const int L = len;
+    // cell average of cell r0 + rel (rel >= -3)
+    auto vrel = [&](int rel) -> double { return sUc[padn<4>(r0 + rel + kNG)]; };
+    auto vabs = [&](int m) -> double { return sUc[padn<4>(m + kNG)]; };
+    // closure values: "-" side x_{-1}, x_n (nodes -1/2, n+1/2 seen from the
+    // ghost cells) and "+" side y_{-1}, y_n (mirror images)
+    double clo_m = 0.0, chi_m = 0.0, clo_p = 0.0, chi_p = 0.0;
+    if (act && !cyclic && k == 0) {
+        clo_m = weno5z_value(vabs(-3), vabs(-2), vabs(-1), vabs(0), vabs(1), weps);
+        chi_p = weno5z_value(vabs(1), vabs(0), vabs(-1), vabs(-2), vabs(-3), weps);
+    }
+    if (act && !cyclic && k == P - 1) {
+        chi_m = weno5z_value(vabs(n - 2), vabs(n - 1), vabs(n), vabs(n + 1), vabs(n + 2), weps);
+        clo_p = weno5z_value(vabs(n + 2), vabs(n + 1), vabs(n), vabs(n - 1), vabs(n - 2), weps);
+    }
+    // "-": x_j = P + Q L + S R, L = x_{r0-1}, R = x_{r1-1} (separator)
+    // "+": y_j = P + Q L + S R, L = y_{r1},  R = y_{r0}   (separator)
+    double ae = 0.0, be = 1.0, ce = 0.0, re = 0.0;
+    double gP = 0.0, gQ = 1.0, gS = 0.0, fP = 0.0, fQ = 0.0, fS = 1.0;
+    double aeP = 0.0, beP = 1.0, ceP = 0.0, reP = 0.0;
+    double gPp = 0.0, gQp = 1.0, gSp = 0.0, fPp = 0.0, fQp = 0.0, fSp = 1.0;
+    if (act) {
+        // pass 1, ascending: indicators and both weight sets; "-" chasing;
+        // the "+" weights (w0, w2) are kept for the descending pass
+        double v0 = vrel(-2), v1 = vrel(-1), v2 = vrel(0), v3 = vrel(1);
+        double d2m = v0 - 2.0 * v1 + v2, d2c = v1 - 2.0 * v2 + v3;
+        double qm = k13 * d2m * d2m, qc = k13 * d2c * d2c;
+        double cprev = 0.0, pprev = 0.0, qprev = 0.0;
+#pragma unroll
+        for (int j = 0; j < kCHP; ++j) {
+            if (j < L) {
+                const int g = r0 + j;
+                const double v4 = vrel(j + 2);
+                const double d2p = v2 - 2.0 * v3 + v4;
+                const double qp = k13 * d2p * d2p;
+                const double t0 = v0 - 4.0 * v1 + 3.0 * v2, t1 = v1 - v3;
+                const double t2 = 3.0 * v2 - 4.0 * v3 + v4;
+                const double b0 = qm + 0.25 * t0 * t0;
+                const double b1 = qc + 0.25 * t1 * t1;
+                const double b2 = qp + 0.25 * t2 * t2;
+                const double tau = b2 - b0, tt = tau * tau;
+                const double d0 = b0 + weps, d1 = b1 + weps, dd2 = b2 + weps;
+                const double e0 = d0 * d0, e1 = d1 * d1, e2 = dd2 * dd2;
+                const double G0 = (e0 + tt) * (e1 * e2);
+                const double G1 = (e1 + tt) * (e0 * e2);
+                const double G2 = (e2 + tt) * (e0 * e1);
+                // "-" weights (0.2, 0.5, 0.3) on (G0, G1, G2); "+" on (G2, G1, G0)
+                const double am0 = 0.2 * G0, am1 = 0.5 * G1, am2 = 0.3 * G2;
+                const double ap0 = 0.2 * G2, ap2 = 0.3 * G0;
+                const double im = rcp_pos(am0 + am1 + am2), ipw = rcp_pos(ap0 + am1 + ap2);
+                const double w0 = am0 * im, w1 = am1 * im, w2 = am2 * im;
+                F0[j] = ap0 * ipw;   // "+" w0; its w1 is recovered as 1 - w0 - w2
+                F2[j] = ap2 * ipw;
+                double a = (2.0 * w0 + w1) * third, bb = (w0 + 2.0 * (w1 + w2)) * third;
+                double c = w2 * third;
+                double r = (w0 * v1 + (5.0 * (w0 + w1) + w2) * v2 + (w1 + 5.0 * w2) * v3) * sixth;
+                if (!cyclic) {
+                    if (g == 0) { r -= a * clo_m; a = 0.0; }
+                    if (g == n - 1) { r -= c * chi_m; c = 0.0; }
+                }
+                if (j < L - 1) {
+                    const double piv = (j == 0) ? bb : bb - a * cprev;
+                    const double ip = rcp_pos(piv);
+                    const double cj = c * ip;
+                    const double pj = ((j == 0) ? r : r - a * pprev) * ip;
+                    const double qj = ((j == 0) ? -a : -a * qprev) * ip;
+                    E0[j] = cj; E1[j] = pj; E2[j] = qj;
+                    cprev = cj; pprev = pj; qprev = qj;
+                } else {
+                    ae = a; be = bb; ce = c; re = r;
+                }
+                v0 = v1; v1 = v2; v2 = v3; v3 = v4;
+                qm = qc; qc = qp;
+            }
+        }
+        // "-" symbolic back substitution
+        double Pn = 0.0, Qn = 0.0, Sn = 0.0;
+#pragma unroll
+        for (int j = kCHP - 1; j >= 0; --j) {
+            if (j < L - 1) {
+                const double cj = E0[j];
+                double Pj, Qj, Sj;
+                if (j == L - 2) {
+                    Pj = E1[j]; Qj = E2[j]; Sj = -cj;
+                    gP = Pj; gQ = Qj; gS = Sj;
+                } else {
+                    Pj = E1[j] - cj * Pn; Qj = E2[j] - cj * Qn; Sj = -cj * Sn;
+                }
+                E0[j] = Pj; E1[j] = Qj; E2[j] = Sj;
+                Pn = Pj; Qn = Qj; Sn = Sj;
+            }
+        }
+        if (L >= 2) { fP = E0[0]; fQ = E1[0]; fS = E2[0]; }
+        // pass 2, descending: "+" rows (a couples y_{g+1}, c couples y_{g-1})
+        double vr = vrel(L), vc = vrel(L - 1);   // v_{g+1}, v_g
+        cprev = 0.0; pprev = 0.0; qprev = 0.0;
+#pragma unroll
+        for (int j = kCHP - 1; j >= 0; --j) {
+            if (j < L) {
+                const int g = r0 + j;
+                const double vl = vrel(j - 1);
+                const double w0 = F0[j], w2 = F2[j], w1 = 1.0 - w0 - w2;
+                double a = (2.0 * w0 + w1) * third, bb = (w0 + 2.0 * (w1 + w2)) * third;
+                double c = w2 * third;
+                double r = (w0 * vr + (5.0 * (w0 + w1) + w2) * vc + (w1 + 5.0 * w2) * vl) * sixth;
+                if (!cyclic) {
+                    if (g == n - 1) { r -= a * clo_p; a = 0.0; }
+                    if (g == 0) { r -= c * chi_p; c = 0.0; }
+                }
+                if (j > 0) {
+                    const bool first = (j == L - 1);
+                    const double piv = first ? bb : bb - a * cprev;
+                    const double ip = rcp_pos(piv);
+                    const double cj = c * ip;
+                    const double pj = (first ? r : r - a * pprev) * ip;
+                    const double qj = (first ? -a : -a * qprev) * ip;
+                    F0[j] = cj; F1[j] = pj; F2[j] = qj;
+                    cprev = cj; pprev = pj; qprev = qj;
+                } else {
+                    aeP = a; beP = bb; ceP = c; reP = r;
+                }
+                vr = vc; vc = vl;
+            }
+        }
+        // "+" symbolic back substitution, ascending from the separator
+        Pn = 0.0; Qn = 0.0; Sn = 0.0;
+#pragma unroll
+        for (int j = 1; j < kCHP; ++j) {
+            if (j < L) {
+                const double cj = F0[j];
+                double Pj, Qj, Sj;
+                if (j == 1) {
+                    Pj = F1[j]; Qj = F2[j]; Sj = -cj;
+                    gPp = Pj; gQp = Qj; gSp = Sj;
+                } else {
+                    Pj = F1[j] - cj * Pn; Qj = F2[j] - cj * Qn; Sj = -cj * Sn;
+                }
+                F0[j] = Pj; F1[j] = Qj; F2[j] = Sj;
+                Pn = Pj; Qn = Qj; Sn = Sj;
+                if (j == L - 1) { fPp = Pj; fQp = Qj; fSp = Sj; }
+            }
+        }
+    }
+    // first-unknown relations of the neighbour chunks: "-" from lane k+1,
+    // "+" from lane k-1
+    const int kn = (k + 1) & (P - 1), kq = (k - 1) & (P - 1);
+    __syncthreads();
+    sxc[k] = fP; sxc[128 + k] = fQ; sxc[256 + k] = fS;
+    sxc[512 + k] = fPp; sxc[640 + k] = fQp; sxc[768 + k] = fSp;
+    __syncthreads();
+    double nf0 = sxc[kn], nf1 = sxc[128 + kn], nf2 = sxc[256 + kn];
+    double np0 = sxc[512 + kq], np1 = sxc[640 + kq], np2 = sxc[768 + kq];
+    if (!cyclic && k + 1 >= P) nf0 = nf1 = nf2 = 0.0;
+    if (!cyclic && k == 0) np0 = np1 = np2 = 0.0;
+    double RA[2] = {ae * gQ, aeP * gQp};
+    double RB[2] = {be + ae * gS + ce * nf1, beP + aeP * gSp + ceP * np1};
+    double RC[2] = {ce * nf2, ceP * np2};
+    double RD[2] = {re - ae * gP - ce * nf0, reP - aeP * gPp - ceP * np0};
+    pcr_pair(RA, RB, RC, RD, k, P, cyclic, sxc);
+    __syncthreads();
+    sxc[k] = RD[0];
+    sxc[512 + k] = RD[1];
+    __syncthreads();
+    const double Rm = RD[0], Rp = RD[1];
+    const double Lm = (!cyclic && k == 0) ? 0.0 : sxc[kq];
+    const double Lp = (!cyclic && k + 1 >= P) ? 0.0 : sxc[512 + kn];
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < kCHP; ++j) {
+            if (j < L - 1) E0[j] = E0[j] + E1[j] * Lm + E2[j] * Rm;
+            else if (j == L - 1) E0[j] = Rm;
+            if (j == 0) F0[j] = Rp;
+            else if (j < L) F0[j] = F0[j] + F1[j] * Lp + F2[j] * Rp;
+        }
+    }
+}
+
 // Rows of the mixed system from the stored weights (w1 := 1 - w0 - w2 in
 // float, so both passes see identical coefficients): eq. (CWENO-FV) matrix
 // (a, b, c) and right-side weights (e0, e1, e2).
@@ -321,7 +516,7 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     // j+1/2 of the same cell, in mirrored order).  Otherwise one system per
     // 64 W lanes, the "+" system as the "-" system of the reversed line.
     constexpr int PL = PAIRED ? 128 : LANES;    // lanes per chunked system
-    constexpr int CHP = 16;                     // paired: rows per lane and side
+    constexpr int CHP = kCHP;                   // paired: rows per lane and side
     const int sys = PAIRED ? 2 * (tid / 128) : tid / LANES;
     const int k = tid % PL;
     const int comp = sys >> 1;
@@ -355,180 +550,8 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     float Ld = 0.0f, Rd = 0.0f;   // mixed: separators of the correction solve
 
     if constexpr (PAIRED) {
-        const double weps = A.weno_eps;
-        const double k13 = 13.0 / 12.0, third = 1.0 / 3.0, sixth = 1.0 / 6.0;
         double* sxc = sx + comp * 1024;   // [8][128] exchange slots of this component
-        // closure values: "-" side x_{-1}, x_n (nodes -1/2, n+1/2 seen from the
-        // ghost cells) and "+" side y_{-1}, y_n (mirror images)
-        double clo_m = 0.0, chi_m = 0.0, clo_p = 0.0, chi_p = 0.0;
-        if (act && !cyclic && k == 0) {
-            clo_m = weno5z_value(ub(-3), ub(-2), ub(-1), ub(0), ub(1), weps);
-            chi_p = weno5z_value(ub(1), ub(0), ub(-1), ub(-2), ub(-3), weps);
-        }
-        if (act && !cyclic && k == P - 1) {
-            chi_m = weno5z_value(ub(n - 2), ub(n - 1), ub(n), ub(n + 1), ub(n + 2), weps);
-            clo_p = weno5z_value(ub(n + 2), ub(n + 1), ub(n), ub(n - 1), ub(n - 2), weps);
-        }
-        // "-": x_j = P + Q L + S R, L = x_{r0-1}, R = x_{r1-1} (separator)
-        // "+": y_j = P + Q L + S R, L = y_{r1},  R = y_{r0}   (separator)
-        double ae = 0.0, be = 1.0, ce = 0.0, re = 0.0;
-        double gP = 0.0, gQ = 1.0, gS = 0.0, fP = 0.0, fQ = 0.0, fS = 1.0;
-        double aeP = 0.0, beP = 1.0, ceP = 0.0, reP = 0.0;
-        double gPp = 0.0, gQp = 1.0, gSp = 0.0, fPp = 0.0, fQp = 0.0, fSp = 1.0;
-        if (act) {
-            // pass 1, ascending: indicators and both weight sets; "-" chasing;
-            // the "+" weights are kept for the descending pass
-            double v0 = ub(r0 - 2), v1 = ub(r0 - 1), v2 = ub(r0), v3 = ub(r0 + 1);
-            double d2m = v0 - 2.0 * v1 + v2, d2c = v1 - 2.0 * v2 + v3;
-            double qm = k13 * d2m * d2m, qc = k13 * d2c * d2c;
-            double cprev = 0.0, pprev = 0.0, qprev = 0.0;
-#pragma unroll
-            for (int j = 0; j < CHP; ++j) {
-                if (j < len) {
-                    const int g = r0 + j;
-                    const double v4 = ub(g + 2);
-                    const double d2p = v2 - 2.0 * v3 + v4;
-                    const double qp = k13 * d2p * d2p;
-                    const double t0 = v0 - 4.0 * v1 + 3.0 * v2, t1 = v1 - v3;
-                    const double t2 = 3.0 * v2 - 4.0 * v3 + v4;
-                    const double b0 = qm + 0.25 * t0 * t0;
-                    const double b1 = qc + 0.25 * t1 * t1;
-                    const double b2 = qp + 0.25 * t2 * t2;
-                    const double tau = b2 - b0, tt = tau * tau;
-                    const double d0 = b0 + weps, d1 = b1 + weps, dd2 = b2 + weps;
-                    const double e0 = d0 * d0, e1 = d1 * d1, e2 = dd2 * dd2;
-                    const double G0 = (e0 + tt) * (e1 * e2);
-                    const double G1 = (e1 + tt) * (e0 * e2);
-                    const double G2 = (e2 + tt) * (e0 * e1);
-                    // "-" weights (0.2, 0.5, 0.3) on (G0, G1, G2); "+" on (G2, G1, G0)
-                    const double am0 = 0.2 * G0, am1 = 0.5 * G1, am2 = 0.3 * G2;
-                    const double ap0 = 0.2 * G2, ap2 = 0.3 * G0;
-                    const double im = rcp_t(am0 + am1 + am2), ipw = rcp_t(ap0 + am1 + ap2);
-                    const double w0 = am0 * im, w1 = am1 * im, w2 = am2 * im;
-                    F0[j] = ap0 * ipw;   // "+" w0; its w1 is recovered as 1 - w0 - w2
-                    F2[j] = ap2 * ipw;
-                    double a = (2.0 * w0 + w1) * third, bb = (w0 + 2.0 * (w1 + w2)) * third;
-                    double c = w2 * third;
-                    double r = (w0 * v1 + (5.0 * (w0 + w1) + w2) * v2 + (w1 + 5.0 * w2) * v3) * sixth;
-                    if (!cyclic) {
-                        if (g == 0) { r -= a * clo_m; a = 0.0; }
-                        if (g == n - 1) { r -= c * chi_m; c = 0.0; }
-                    }
-                    if (j < len - 1) {
-                        const double piv = (j == 0) ? bb : bb - a * cprev;
-                        const double ip = rcp_t(piv);
-                        const double cj = c * ip;
-                        const double pj = ((j == 0) ? r : r - a * pprev) * ip;
-                        const double qj = ((j == 0) ? -a : -a * qprev) * ip;
-                        E0[j] = cj; E1[j] = pj; E2[j] = qj;
-                        cprev = cj; pprev = pj; qprev = qj;
-                    } else {
-                        ae = a; be = bb; ce = c; re = r;
-                    }
-                    v0 = v1; v1 = v2; v2 = v3; v3 = v4;
-                    qm = qc; qc = qp;
-                }
-            }
-            // "-" symbolic back substitution
-            double Pn = 0.0, Qn = 0.0, Sn = 0.0;
-#pragma unroll
-            for (int j = CHP - 1; j >= 0; --j) {
-                if (j < len - 1) {
-                    const double cj = E0[j];
-                    double Pj, Qj, Sj;
-                    if (j == len - 2) {
-                        Pj = E1[j]; Qj = E2[j]; Sj = -cj;
-                        gP = Pj; gQ = Qj; gS = Sj;
-                    } else {
-                        Pj = E1[j] - cj * Pn; Qj = E2[j] - cj * Qn; Sj = -cj * Sn;
-                    }
-                    E0[j] = Pj; E1[j] = Qj; E2[j] = Sj;
-                    Pn = Pj; Qn = Qj; Sn = Sj;
-                }
-            }
-            if (len >= 2) { fP = E0[0]; fQ = E1[0]; fS = E2[0]; }
-            // pass 2, descending: "+" rows (a couples y_{g+1}, c couples y_{g-1})
-            double vr = ub(r0 + len), vc = ub(r0 + len - 1);   // v_{g+1}, v_g
-            cprev = 0.0; pprev = 0.0; qprev = 0.0;
-#pragma unroll
-            for (int j = CHP - 1; j >= 0; --j) {
-                if (j < len) {
-                    const int g = r0 + j;
-                    const double vl = ub(g - 1);
-                    const double w0 = F0[j], w2 = F2[j], w1 = 1.0 - w0 - w2;
-                    double a = (2.0 * w0 + w1) * third, bb = (w0 + 2.0 * (w1 + w2)) * third;
-                    double c = w2 * third;
-                    double r = (w0 * vr + (5.0 * (w0 + w1) + w2) * vc + (w1 + 5.0 * w2) * vl) * sixth;
-                    if (!cyclic) {
-                        if (g == n - 1) { r -= a * clo_p; a = 0.0; }
-                        if (g == 0) { r -= c * chi_p; c = 0.0; }
-                    }
-                    if (j > 0) {
-                        const bool first = (j == len - 1);
-                        const double piv = first ? bb : bb - a * cprev;
-                        const double ip = rcp_t(piv);
-                        const double cj = c * ip;
-                        const double pj = (first ? r : r - a * pprev) * ip;
-                        const double qj = (first ? -a : -a * qprev) * ip;
-                        F0[j] = cj; F1[j] = pj; F2[j] = qj;
-                        cprev = cj; pprev = pj; qprev = qj;
-                    } else {
-                        aeP = a; beP = bb; ceP = c; reP = r;
-                    }
-                    vr = vc; vc = vl;
-                }
-            }
-            // "+" symbolic back substitution, ascending from the separator
-            Pn = 0.0; Qn = 0.0; Sn = 0.0;
-#pragma unroll
-            for (int j = 1; j < CHP; ++j) {
-                if (j < len) {
-                    const double cj = F0[j];
-                    double Pj, Qj, Sj;
-                    if (j == 1) {
-                        Pj = F1[j]; Qj = F2[j]; Sj = -cj;
-                        gPp = Pj; gQp = Qj; gSp = Sj;
-                    } else {
-                        Pj = F1[j] - cj * Pn; Qj = F2[j] - cj * Qn; Sj = -cj * Sn;
-                    }
-                    F0[j] = Pj; F1[j] = Qj; F2[j] = Sj;
-                    Pn = Pj; Qn = Qj; Sn = Sj;
-                    if (j == len - 1) { fPp = Pj; fQp = Qj; fSp = Sj; }
-                }
-            }
-        }
-        // first-unknown relations of the neighbour chunks: "-" from lane k+1,
-        // "+" from lane k-1
-        const int kn = (k + 1) & (P - 1), kq = (k - 1) & (P - 1);
-        __syncthreads();
-        sxc[k] = fP; sxc[128 + k] = fQ; sxc[256 + k] = fS;
-        sxc[512 + k] = fPp; sxc[640 + k] = fQp; sxc[768 + k] = fSp;
-        __syncthreads();
-        double nf0 = sxc[kn], nf1 = sxc[128 + kn], nf2 = sxc[256 + kn];
-        double np0 = sxc[512 + kq], np1 = sxc[640 + kq], np2 = sxc[768 + kq];
-        if (!cyclic && k + 1 >= P) nf0 = nf1 = nf2 = 0.0;
-        if (!cyclic && k == 0) np0 = np1 = np2 = 0.0;
-        double RA[2] = {ae * gQ, aeP * gQp};
-        double RB[2] = {be + ae * gS + ce * nf1, beP + aeP * gSp + ceP * np1};
-        double RC[2] = {ce * nf2, ceP * np2};
-        double RD[2] = {re - ae * gP - ce * nf0, reP - aeP * gPp - ceP * np0};
-        pcr_pair(RA, RB, RC, RD, k, P, cyclic, sxc);
-        __syncthreads();
-        sxc[k] = RD[0];
-        sxc[512 + k] = RD[1];
-        __syncthreads();
-        const double Rm = RD[0], Rp = RD[1];
-        const double Lm = (!cyclic && k == 0) ? 0.0 : sxc[kq];
-        const double Lp = (!cyclic && k + 1 >= P) ? 0.0 : sxc[512 + kn];
-        if (act) {
-#pragma unroll
-            for (int j = 0; j < CHP; ++j) {
-                if (j < len - 1) E0[j] = E0[j] + E1[j] * Lm + E2[j] * Rm;
-                else if (j == len - 1) E0[j] = Rm;
-                if (j == 0) F0[j] = Rp;
-                else if (j < len) F0[j] = F0[j] + F1[j] * Lp + F2[j] * Rp;
-            }
-        }
+        paired_solve(sUc, n, k, P, cyclic, A.weno_eps, sxc, r0, len, E0, E1, E2, F0, F1, F2);
     } else if constexpr (!MIXED) {
         double ae = 0.0, be = 1.0, ce = 0.0, re = 0.0;
         double gP = 0.0, gQ = 1.0, gS = 0.0;   // x_{r1-2} = gP + gQ L + gS R
@@ -1044,7 +1067,7 @@ __global__ void __launch_bounds__(256) combine2d_kernel(
     const double* Un, double* Out, double* __restrict__ OutB, int nx,
     int ny, int mode, double ra, double rb, const double* dt_dev, double dt_val, double gamma,
     long long* eps_out, long long* spd_out, long long* eps_reset, Scal* scal, unsigned* status) {
-    __shared__ double tile[TT][TT + 1];
+    __shared__ double tile[4][TT][TT + 1];
     __shared__ double red[4][8];
     if (scal && !scal->active) return;
     if (eps_reset && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
@@ -1055,42 +1078,63 @@ __global__ void __launch_bounds__(256) combine2d_kernel(
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const int x0 = blockIdx.x * TT, y0 = blockIdx.y * TT;
     const double dt = dt_dev ? *dt_dev : dt_val;
+    const bool rd0 = mode == 1 && ra != 0.0;
+    // every load of the tile is issued before the first barrier: Ly through
+    // LDS (transposed), Lx / Us / Un straight into registers
+    double lx[4][4], us[4][4], un[4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int xx = ty + 8 * r;
+            const int y = y0 + tx, x = x0 + xx;
+            if (x < nx && y < ny) tile[c][xx][tx] = LyB[c * cs + (long long)x * ny + y];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int x = x0 + tx, y = y0 + ty + 8 * r;
+            lx[r][c] = us[r][c] = un[r][c] = 0.0;
+            if (x < nx && y < ny) {
+                const long long at = c * cs + (long long)y * nx + x;
+                lx[r][c] = Lx[at];
+                if (mode == 1) us[r][c] = Us[at];
+                if (rd0) un[r][c] = Un[at];
+            }
+        }
+    }
+    __syncthreads();
     double cell[4][4];   // [row yy/8][comp]
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        for (int xx = ty; xx < TT; xx += 8) {
-            const int y = y0 + tx, x = x0 + xx;
-            if (x < nx && y < ny) tile[xx][tx] = LyB[c * cs + (long long)x * ny + y];
-        }
-        __syncthreads();
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int yy = ty + 8 * r;
             const int x = x0 + tx, y = y0 + yy;
-            double v = 0.0;
-            if (x < nx && y < ny) {
-                const long long at = c * cs + (long long)y * nx + x;
-                const double L = Lx[at] + tile[tx][yy];
-                if (mode == 0) {
-                    v = L;
-                } else {
-                    const double u0 = (ra != 0.0) ? Un[at] : 0.0;
-                    v = ra * u0 + rb * (Us[at] + dt * L);
-                }
-                Out[at] = v;
-            }
+            const double L = lx[r][c] + tile[c][tx][yy];
+            const double v = (mode == 0) ? L : ra * un[r][c] + rb * (us[r][c] + dt * L);
+            if (x < nx && y < ny) Out[c * cs + (long long)y * nx + x] = v;
             cell[r][c] = v;
         }
-        __syncthreads();
-        if (mode == 1) {
+    }
+    if (mode == 1) {
+        __syncthreads();   // Ly reads done: the tiles take the transposed output
 #pragma unroll
-            for (int r = 0; r < 4; ++r) tile[ty + 8 * r][tx] = cell[r][c];
-            __syncthreads();
-            for (int xx = ty; xx < TT; xx += 8) {
+        for (int c = 0; c < 4; ++c) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tile[c][ty + 8 * r][tx] = cell[r][c];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int xx = ty + 8 * r;
                 const int y = y0 + tx, x = x0 + xx;
-                if (x < nx && y < ny) OutB[c * cs + (long long)x * ny + y] = tile[tx][xx];
+                if (x < nx && y < ny) OutB[c * cs + (long long)x * ny + y] = tile[c][tx][xx];
             }
-            __syncthreads();
         }
     }
     if (mode != 1) return;
