@@ -29,8 +29,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6         # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 BYTES_PER_CELL_UPDATE = 544.0   # algorithmic bytes of one 2D SSP-RK3 cell-update
 BYTES_PER_SWEEP_CELL = 64.0     # line kernel: read the stage input, write L
+# Algorithmic FP64 operations of one line sweep per 2D cell (4 components),
+# counted from the scheme's formulas (+ - * / sqrt = 1 each): indicators shared
+# by the two sides 4 x 33, WENO-Z weights 4 x 2 x 23, rows 4 x 2 x 22,
+# Thomas 4 x 2 x 8, limiter test (smooth data) 44, HLLC 108, flux difference 8.
+FLOPS_PER_SWEEP_CELL = 716.0
+
+# HBM traffic of the line kernels from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# (KiB per dispatch, 2048^2 density wave, FP64), scaled by the copy-kernel
+# calibration (FETCH reads 2.0x, WRITE 1.0x the bytes of a 1 GiB copy).  Valid
+# only for the kernel sources whose hash is recorded; otherwise reported null.
+TRAFFIC_RECORD = None
 
 
 def parse():
@@ -45,6 +57,11 @@ def parse():
                     choices=["density2d", "sedov2d", "ensemble", "wave1d", "rarefaction1d",
                              "blast1d", "copy"])
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--full", action="store_true",
+                    help="sedov2d / ensemble: run to the configuration's end time")
+    ap.add_argument("--max-wall", type=float, default=240.0,
+                    help="sedov2d --full: stop after this many seconds (the near-vacuum "
+                         "centre makes t = 1 take ~1e7 steps)")
     return ap.parse_args()
 
 
@@ -79,33 +96,54 @@ def other_workload(args):
         U = torch.tensor(W.sedov_corner_2d(n), device="cuda")
         s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=(2, 1, 2, 1), precision=prec)
         torch.cuda.synchronize()
+        # --full: to t = 1 in chunks of --steps steps (the state advances in
+        # place; each chunk restarts the clock at the chunk's start), with the
+        # minima checked after every chunk; otherwise one chunk
+        t_done, steps, flags, min_rho, min_p = 0.0, 0, 0, math.inf, math.inf
         t0 = time.perf_counter()
-        try:
-            t, steps = s.run(U, 1.0, args.steps, 1.0 / 12.0)
-            flags = 0
-        except pp.PPError as e:
-            t, steps, flags = float("nan"), args.steps, e.code
+        while True:
+            try:
+                t, k = s.run(U, 1.0 - t_done, args.steps, 1.0 / 12.0)
+            except pp.PPError as e:
+                flags = e.code
+                break
+            t_done += t
+            steps += k
+            Uh = U.cpu().numpy()
+            min_rho = min(min_rho, float(Uh[0].min()))
+            min_p = min(min_p, float(W.pressure(Uh).min()))
+            if args.full:
+                print(f"sedov2d: {steps} steps, t = {t_done:.4f}, min rho {min_rho:.3e}, "
+                      f"min p {min_p:.3e}, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                      flush=True)
+            if not args.full or t_done >= 1.0 - 1e-12 or k == 0 or \
+                    time.perf_counter() - t0 > args.max_wall:
+                break
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         Uh = U.cpu().numpy()
-        out.update(metric="cell-updates/s, 2D Sedov-type blast 1024^2", value=n * n * steps / wall,
-                   steps=steps, ms_per_step=1e3 * wall / steps,
+        out.update(metric="cell-updates/s, 2D Sedov-type blast 1024^2",
+                   value=n * n * steps / wall if steps else None,
+                   steps=steps, ms_per_step=1e3 * wall / steps if steps else None,
                    config={"workload": f"quarter-plane blast 1024^2 on [0,1.1]^2, {prec_name}, "
-                                       f"{steps} steps (t = {t:.3e} of 1.0)",
-                           "min_rho": float(Uh[0].min()),
-                           "min_p": float(W.pressure(Uh).min()), "status": flags,
-                           "symmetry_rel": float(np.abs(Uh[0] - Uh[0].T).max() / Uh[0].max())})
+                                       f"{steps} steps (t = {t_done:.4e} of 1.0)",
+                           "min_rho_over_run": min_rho, "min_p_over_run": min_p,
+                           "final_min_rho": float(Uh[0].min()),
+                           "final_min_p": float(W.pressure(Uh).min()), "status": flags,
+                           "symmetry_rel": float(np.abs(Uh[0] - Uh[0].T).max() / Uh[0].max()),
+                           "note": "minima sampled after each chunk of steps"})
         s.close()
     elif args.workload == "ensemble":
         ens = W.riemann_ensemble()
         nb = len(ens.lengths)
         U = torch.tensor(ens.U, device="cuda")
         s = pp.Solver(ndim=1, lengths=ens.lengths, dxs=ens.dx, bcs=[1] * (2 * nb), precision=prec)
+        plan, plan_ms = s.batch_tune(U, 1.0 / 12.0)       # launch plan (length classes)
         s.batch_run(U.clone(), ens.t_end, 2, 1.0 / 12.0)   # warm-up (graph, kernels)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
-            steps = s.batch_run(U, ens.t_end, args.steps, 1.0 / 12.0)
+            steps = s.batch_run(U, ens.t_end, 10 ** 8 if args.full else args.steps, 1.0 / 12.0)
             flags = 0
         except pp.PPError as e:
             steps, flags = s.last_batch_steps(), e.code
@@ -117,8 +155,11 @@ def other_workload(args):
         out.update(metric="cell-updates/s, 4096-problem 1D Riemann ensemble",
                    value=cu / wall, steps=int(max(steps)), ms_per_step=1e3 * wall / max(steps),
                    config={"workload": f"{nb} Riemann problems, N in [256,4096] (sum "
-                                       f"{int(ens.lengths.sum())} cells), {prec_name}, "
-                                       f"{args.steps} steps per problem (bounded; t_end 0.2 not reached)",
+                                       f"{int(ens.lengths.sum())} cells), {prec_name}, " +
+                                       (f"to t_end {ens.t_end}" if args.full else
+                                          f"{args.steps} steps per problem (bounded; t_end "
+                                          f"{ens.t_end} not reached)"),
+                           "launch_plan": plan, "plan_ms_per_step": plan_ms,
                            "problems_out_of_G": int(sum(1 for i in range(nb) if
                                                         p[ens.offsets[i]:ens.offsets[i + 1]].min() <= 0
                                                         or Uh[0, ens.offsets[i]:ens.offsets[i + 1]].min() <= 0)),
@@ -154,6 +195,16 @@ def other_workload(args):
                                status=flags, wall_s=wall, **extra))
         s.close()
     print(json.dumps(out), flush=True)
+
+
+def kernel_source_hash():
+    """sha256 of the HIP sources the traffic counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("ppcweno.hip", "ppc_device.h"):
+        with open(os.path.join(ROOT, "paper_1402_5618_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def cpu_baseline(n, steps):
@@ -225,15 +276,19 @@ def main():
     mass_drift = float(abs(rmx["U"][0].sum() - W.density_wave_2d(n, n)[0].sum())
                        / W.density_wave_2d(n, n)[0].sum())
 
-    # dominant kernel of the step and its roofline (algorithmic bytes / launch)
-    dom = max(timing, key=lambda k: timing[k][0])
+    # dominant kernel of the step (a line kernel) and its roofline: it is
+    # bound by FP64 VALU work, so the roofline is algorithmic FP64 operations
+    # per launch over the measured launch time; its HBM rate is given beside
+    dom = max(("x", "y"), key=lambda k: timing[k][0])
     ms_tot, launches = timing[dom]
     avg_ms = ms_tot / max(launches, 1)
-    if dom == "combine":
-        bytes_launch = cells * (160.0 + 192.0 + 192.0) / 3.0
-    else:
-        bytes_launch = cells * BYTES_PER_SWEEP_CELL
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    achieved_tflops = FLOPS_PER_SWEEP_CELL * cells / (avg_ms * 1e-3) / 1e12
+    achieved_gbs = BYTES_PER_SWEEP_CELL * cells / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    if TRAFFIC_RECORD is not None and TRAFFIC_RECORD["src_sha256"] == kernel_source_hash():
+        rec = TRAFFIC_RECORD[dom]
+        traffic = rec["fetch_kib"] * 1024 / TRAFFIC_RECORD["fetch_factor"] + \
+            rec["write_kib"] * 1024 / TRAFFIC_RECORD["write_factor"]
 
     line = {
         "metric": "cell-updates/s, 2D 2048^2 FP64 vs mixed-FP32 at fixed L1 error; % HBM BW",
@@ -270,14 +325,18 @@ def main():
             },
         },
         "roofline": {
-            "bound": "hbm",
-            "kernel": {"x": "line_kernel x-lines", "y": "line_kernel y-lines",
-                       "combine": "combine2d_kernel"}[dom],
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "bound": "alu",
+            "kernel": {"x": "line_kernel x-lines", "y": "line_kernel y-lines"}[dom],
+            "achieved": achieved_tflops,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / FP64_PEAK_TFLOPS,
+            "traffic": traffic,
+            "flops_per_cell": FLOPS_PER_SWEEP_CELL,
+            "cells_per_launch": cells,
+            "avg_launch_ms": avg_ms,
+            "hbm_algorithmic_GBs": achieved_gbs,
+            "hbm_frac": achieved_gbs / HBM_PEAK_GBS,
         },
         "cpu_baseline": None,
     }

@@ -127,6 +127,25 @@ int pp_cweno_batch_step(pp_cweno_ctx *ctx, double *Upacked, const double *dt_dev
 int pp_cweno_batch_run(pp_cweno_ctx *ctx, double *Upacked, double t_end, int64_t nsteps_max,
                        double cfl, int64_t *steps_out);
 
+/* Batched ensembles: choose the launch plan used by pp_cweno_batch_step and
+ * pp_cweno_batch_run.  The problems, sorted by length, are cut into length
+ * classes, each processed by one persistent launch per stage with the kernel
+ * shape of its longest problem (how many rows of the tridiagonal systems of
+ * eq. (CWENO-FV) one lane chases serially, and so how large the separator
+ * system solved by parallel cyclic reduction is):
+ *   plan 0: one class;  plan 1: > 2048 cells | the rest;
+ *   plan 2: > 2048 | 1025..2048 | <= 1024 cells.
+ * force_plan in [0, 2] sets that plan without timing.  force_plan < 0 times
+ * one step of every plan on a device copy of Upacked (per-problem dt from cfl
+ * and the initial averages; Upacked is left unchanged) and keeps the fastest.
+ * *plan_out (may be NULL) receives the plan; ms_out (host [3], may be NULL)
+ * the measured ms per step of each plan (force_plan < 0 only).  The plan does
+ * not change any result, since the problems are independent.  Synchronises;
+ * allocates a device copy of the state on first use.  Not to be called while
+ * a batched run is in flight on the same context. */
+int pp_cweno_batch_tune(pp_cweno_ctx *ctx, const double *Upacked, double cfl, int force_plan,
+                        int *plan_out, double *ms_out);
+
 /* out_dev[0] = max(|u|+a) (2D: also out_dev[1] = max(|v|+a)) over the cell
  * averages of U (device pointers). */
 int pp_cweno_max_speed(pp_cweno_ctx *ctx, const double *U, double *out_dev);

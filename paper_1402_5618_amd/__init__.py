@@ -21,7 +21,8 @@ PP_DT_CFL, PP_DT_H53 = 0, 1
 
 EXPORTED = [
     "pp_cweno_config_defaults", "pp_cweno_init", "pp_cweno_rhs", "pp_cweno_stage",
-    "pp_cweno_step", "pp_cweno_run", "pp_cweno_batch_step", "pp_cweno_batch_run",
+    "pp_cweno_step", "pp_cweno_run", "pp_cweno_batch_step", "pp_cweno_batch_tune",
+    "pp_cweno_batch_run",
     "pp_cweno_max_speed", "pp_cweno_status", "pp_cweno_debug_line", "pp_cweno_set_timing",
     "pp_cweno_get_timing", "pp_cweno_last_error", "pp_cweno_destroy",
 ]
@@ -67,6 +68,8 @@ def lib():
                                             ctypes.c_double, ctypes.c_int, P(ctypes.c_double),
                                             P(ctypes.c_int64)]),
             "pp_cweno_batch_step": (ctypes.c_int, [_VP, _VP, _VP]),
+            "pp_cweno_batch_tune": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int,
+                                                   P(ctypes.c_int), P(ctypes.c_double)]),
             "pp_cweno_batch_run": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int64,
                                                   ctypes.c_double, P(ctypes.c_int64)]),
             "pp_cweno_max_speed": (ctypes.c_int, [_VP, _VP, _VP]),
@@ -157,6 +160,15 @@ class Solver:
 
     def batch_step(self, U, dt_dev):
         return self._check(lib().pp_cweno_batch_step(self._ctx, _ptr(U), _ptr(dt_dev)))
+
+    def batch_tune(self, U=None, cfl=1.0 / 12.0, force_plan=-1):
+        """Pick the batched launch plan: timed over every plan on a copy of U
+        (force_plan < 0) or set directly.  Returns (plan, [ms per plan])."""
+        plan = ctypes.c_int()
+        ms = (ctypes.c_double * 3)(-1.0, -1.0, -1.0)
+        self._check(lib().pp_cweno_batch_tune(self._ctx, _ptr(U), float(cfl), int(force_plan),
+                                              ctypes.byref(plan), ms))
+        return plan.value, list(ms)
 
     def batch_run(self, U, t_end, nsteps_max=1 << 62, cfl=1.0 / 12.0):
         """Per-problem step counts; raises PPError(PP_ESTATE) after the run if

@@ -1294,7 +1294,18 @@ struct pp_cweno_ctx {
     int* d_order = nullptr;
     int* d_counter = nullptr;
     double* d_dtcopy = nullptr;
+    double* d_tune = nullptr;   // autotuner's scratch copy of the packed state
     int n_sm = 0;
+    // batched launch plan: the length-sorted problems are cut into classes
+    // (contiguous in d_order, longest first), one persistent launch per class
+    // and stage, each with the kernel shape and LDS of its longest problem
+    struct LenClass {
+        int begin = 0, count = 0, maxn = 0;
+    };
+    std::vector<int> order_host;
+    int plan = 0;
+    int nclass = 0;
+    LenClass cls[3];
     // measurement: event pairs around kernel launches, per class
     bool timing = false;
     std::vector<hipEvent_t> ev[3];
@@ -1558,7 +1569,30 @@ int step_single(pp_cweno_ctx* ctx, double* U, const double* dt_dev, double dt_va
     return PP_OK;
 }
 
-// One SSP-RK3 step of every active problem of a batch: 3 persistent launches.
+constexpr int kNumPlans = 3;
+
+// Launch plan p: 0 = one class, 1 = split at 2048 cells (the longer lines need
+// two waves per system), 2 = split at 2048 and 1024 cells.
+void set_plan(pp_cweno_ctx* ctx, int p) {
+    const int cuts[kNumPlans][2] = {{0, 0}, {2048, 0}, {2048, 1024}};
+    ctx->plan = p;
+    ctx->nclass = 0;
+    const int nb = (int)ctx->order_host.size();
+    int i = 0;
+    for (int c = 0; c < 3 && i < nb; ++c) {
+        const int cut = c < 2 ? cuts[p][c] : 0;   // class c takes lengths > cut
+        auto& k = ctx->cls[ctx->nclass];
+        k.begin = i;
+        k.maxn = (int)ctx->lengths[ctx->order_host[i]];
+        while (i < nb && ctx->lengths[ctx->order_host[i]] > cut) ++i;
+        k.count = i - k.begin;
+        if (k.count > 0) ++ctx->nclass;
+        if (cut == 0) break;
+    }
+}
+
+// One SSP-RK3 step of every active problem of a batch: 3 persistent launches
+// per length class of the current plan.
 // advance: the stage-3 epilogue advances t, step count and dt per problem.
 int batch_step_launch(pp_cweno_ctx* ctx, double* Upacked, double* dtl, bool advance, double cfl,
                       double t_end, long long steps_max) {
@@ -1572,27 +1606,31 @@ int batch_step_launch(pp_cweno_ctx* ctx, double* Upacked, double* dtl, bool adva
     A.tline = ctx->d_t;
     A.stepline = ctx->d_steps;
     A.steps_max = steps_max;
-    A.order = ctx->d_order;
-    A.nlines = (int)ctx->cfg.nbatch;
     A.mode = 1;
     A.t_end = t_end;
     A.cfl = cfl;
     const double* Uin[3] = {Upacked, ctx->U1, ctx->U2};
     double* Uout[3] = {ctx->U1, ctx->U2, Upacked};
-    const int grid = ctx->n_sm;
     for (int st = 1; st <= 3; ++st) {
-        hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, ctx->stream, ctx->d_counter + st);
-        HIPCHK(ctx, hipGetLastError());
-        A.counter = ctx->d_counter + st;
         A.U = Uin[st - 1];
         A.U0 = Upacked;
         A.out = Uout[st - 1];
         A.stage = (st == 3 && !advance) ? 0 : st;
         A.rk_a = kRK[st][0];
         A.rk_b = kRK[st][1];
-        int r = ctx->maxn <= 2048 ? launch_line<3, 1, 1, 6>(ctx, A, ctx->maxn, true, grid)
-                                  : launch_line<3, 1, 2, 3>(ctx, A, ctx->maxn, true, grid);
-        if (r) return r;
+        for (int c = 0; c < ctx->nclass; ++c) {
+            const auto& k = ctx->cls[c];
+            int* counter = ctx->d_counter + 4 * c + st;
+            hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, ctx->stream, counter);
+            HIPCHK(ctx, hipGetLastError());
+            A.counter = counter;
+            A.order = ctx->d_order + k.begin;
+            A.nlines = k.count;
+            const int grid = std::min(k.count, ctx->n_sm);
+            int r = k.maxn <= 2048 ? launch_line<3, 1, 1, 6>(ctx, A, k.maxn, true, grid)
+                                   : launch_line<3, 1, 2, 3>(ctx, A, k.maxn, true, grid);
+            if (r) return r;
+        }
     }
     return PP_OK;
 }
@@ -1719,7 +1757,7 @@ int pp_cweno_init(const pp_cweno_config* cfg, pp_cweno_ctx** out) {
             !dmalloc((void**)&ctx->d_t, sizeof(double) * nb) ||
             !dmalloc((void**)&ctx->d_steps, sizeof(long long) * nb) ||
             !dmalloc((void**)&ctx->d_order, sizeof(int) * nb) ||
-            !dmalloc((void**)&ctx->d_counter, sizeof(int) * 4) ||
+            !dmalloc((void**)&ctx->d_counter, sizeof(int) * 16) ||
             !dmalloc((void**)&ctx->U1, sizeof(double) * 3 * ctx->total) ||
             !dmalloc((void**)&ctx->U2, sizeof(double) * 3 * ctx->total))
             return bail(PP_ENOMEM);
@@ -1733,6 +1771,8 @@ int pp_cweno_init(const pp_cweno_config* cfg, pp_cweno_ctx** out) {
             hip_fail(ctx, e2, "hipMemcpy");
             return bail(PP_EDEVICE);
         }
+        ctx->order_host = order;
+        set_plan(ctx, 0);
     } else {
         ctx->ncell = c.nx * (c.ndim == 2 ? c.ny : 1);
         const size_t bytes = sizeof(double) * ctx->nc * ctx->ncell;
@@ -1876,6 +1916,75 @@ int pp_cweno_batch_step(pp_cweno_ctx* ctx, double* Upacked, const double* dt_dev
     return batch_step_launch(ctx, Upacked, ctx->d_dtcopy, false, 0.0, 0.0, 0);
 }
 
+int pp_cweno_batch_tune(pp_cweno_ctx* ctx, const double* Upacked, double cfl, int force_plan,
+                        int* plan_out, double* ms_out) {
+    if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
+    if (ctx->cfg.nbatch <= 0) return fail(ctx, PP_EINVAL, "context has no batch");
+    if (force_plan >= kNumPlans) return fail(ctx, PP_EINVAL, "unknown launch plan");
+    if (force_plan >= 0) {
+        set_plan(ctx, force_plan);
+        if (plan_out) *plan_out = force_plan;
+        return PP_OK;
+    }
+    if (!Upacked) return fail(ctx, PP_EINVAL, "Upacked is NULL");
+    if (!(cfl > 0.0)) return fail(ctx, PP_EINVAL, "cfl must be > 0");
+    const int nb = (int)ctx->cfg.nbatch;
+    const size_t bytes = sizeof(double) * 3 * ctx->total;
+    if (!ctx->d_tune && hipMalloc((void**)&ctx->d_tune, bytes) != hipSuccess) {
+        ctx->d_tune = nullptr;
+        return fail(ctx, PP_ENOMEM, "autotuner scratch");
+    }
+    // per-problem dt of the initial state (the run's first step)
+    hipLaunchKernelGGL(batch_init_kernel, dim3(nb), dim3(256), 0, ctx->stream, Upacked, ctx->total,
+                       ctx->d_off, ctx->d_n, ctx->d_h, ctx->d_dt, ctx->d_t, ctx->d_steps,
+                       ctx->cfg.gamma, cfl, 1e300);
+    HIPCHK(ctx, hipGetLastError());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ctx, PP_EDEVICE, "hipEventCreate");
+    }
+    const int reps = 3;
+    int best = -1;
+    float best_ms = 0.0f;
+    int r = PP_OK;
+    for (int p = 0; p < kNumPlans && r == PP_OK; ++p) {
+        set_plan(ctx, p);
+        float ms = -1.0f;
+        // one warm-up step, then reps timed steps of the same state and dt
+        for (int it = 0; it <= reps && r == PP_OK; ++it) {
+            if (hipMemcpyAsync(ctx->d_tune, Upacked, bytes, hipMemcpyDeviceToDevice, ctx->stream) !=
+                    hipSuccess ||
+                hipMemcpyAsync(ctx->d_dtcopy, ctx->d_dt, sizeof(double) * nb,
+                               hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess) {
+                r = fail(ctx, PP_EDEVICE, "autotuner copy");
+                break;
+            }
+            if (it == 1) (void)hipEventRecord(e0, ctx->stream);
+            r = batch_step_launch(ctx, ctx->d_tune, ctx->d_dtcopy, false, 0.0, 0.0, 0);
+        }
+        if (r) break;
+        (void)hipEventRecord(e1, ctx->stream);
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            r = fail(ctx, PP_EDEVICE, "autotuner timing");
+            break;
+        }
+        ms /= reps;   // includes the two state copies of each repetition
+        if (ms_out) ms_out[p] = ms;
+        if (best < 0 || ms < best_ms) {
+            best = p;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r) return r;
+    set_plan(ctx, best);
+    if (plan_out) *plan_out = best;
+    return PP_OK;
+}
+
 int pp_cweno_batch_run(pp_cweno_ctx* ctx, double* Upacked, double t_end, int64_t nsteps_max,
                        double cfl, int64_t* steps_out) {
     if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
@@ -2008,7 +2117,7 @@ void pp_cweno_destroy(pp_cweno_ctx* ctx) {
     void* bufs[] = {ctx->U1, ctx->U2, ctx->UA, ctx->UB, ctx->U1B, ctx->U2B, ctx->Lx, ctx->LyB,
                     ctx->scal, ctx->d_off, ctx->d_n, ctx->d_h, ctx->d_bc, ctx->d_dt, ctx->d_t,
                     ctx->d_steps,
-                    ctx->d_order, ctx->d_counter, ctx->d_dtcopy};
+                    ctx->d_order, ctx->d_counter, ctx->d_dtcopy, ctx->d_tune};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     for (int k = 0; k < 3; ++k)

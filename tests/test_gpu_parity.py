@@ -172,19 +172,22 @@ def ensemble(nprob, n_lo, n_hi, seed=1402):
     return W.riemann_ensemble(nprob=nprob, seed=seed, n_lo=n_lo, n_hi=n_hi)
 
 
-@pytest.mark.parametrize("n_lo,n_hi", [(8, 40), (256, 4096)])
-def test_batch_step_parity(n_lo, n_hi):
-    """One SSP-RK3 step of every problem (persistent launch per stage) against
-    the oracle's stages, each problem with its own dt; one problem inactive."""
+@pytest.mark.parametrize("n_lo,n_hi,plan", [(8, 40, 0), (256, 4096, 0), (256, 4096, 1),
+                                             (256, 4096, 2)])
+def test_batch_step_parity(n_lo, n_hi, plan):
+    """One SSP-RK3 step of every problem (persistent launches per stage and
+    length class of the launch plan) against the oracle's stages, each
+    problem with its own dt; one problem inactive."""
     pp = gpu()
     ens = ensemble(24, n_lo, n_hi)
-    print(f"case batch n in [{n_lo},{n_hi}] total={ens.U.shape[1]}", flush=True)
+    print(f"case batch n in [{n_lo},{n_hi}] total={ens.U.shape[1]} plan={plan}", flush=True)
     nb = len(ens.lengths)
     dts = np.array([(1.0 / 12.0) * ens.dx[i] /
                     oracle.max_speed_1d(ens.U[:, ens.offsets[i]:ens.offsets[i + 1]])
                     for i in range(nb)])
     dts[5] = 0.0
     s = pp.Solver(ndim=1, lengths=ens.lengths, dxs=ens.dx, bcs=[1] * (2 * nb))
+    assert s.batch_tune(force_plan=plan)[0] == plan
     Ud = dev(ens.U)
     s.batch_step(Ud, dev(dts))
     torch.cuda.synchronize()
@@ -200,6 +203,35 @@ def test_batch_step_parity(n_lo, n_hi):
         U2 = oracle.stage_1d(U, U1, 2, dts[i], (1, 1), h)
         U3 = oracle.stage_1d(U, U2, 3, dts[i], (1, 1), h)
         assert comp_rel(got[:, sl], U3) <= TOL_STAGE, i
+    s.close()
+
+
+def test_batch_tune_picks_a_plan_and_results_agree():
+    """The autotuner times every launch plan on a copy of the state (left
+    unchanged) and keeps the fastest; the plans agree to rounding."""
+    pp = gpu()
+    ens = ensemble(40, 256, 4096, seed=11)
+    nb = len(ens.lengths)
+    print(f"case tune total={ens.U.shape[1]}", flush=True)
+    s = pp.Solver(ndim=1, lengths=ens.lengths, dxs=ens.dx, bcs=[1] * (2 * nb))
+    U0 = dev(ens.U)
+    plan, ms = s.batch_tune(U0, 1.0 / 12.0)
+    print(f"plan {plan}, ms per step {ms}", flush=True)
+    assert 0 <= plan <= 2 and all(m > 0 for m in ms) and ms[plan] == min(ms)
+    assert np.array_equal(U0.cpu().numpy(), ens.U)
+    dts = dev(np.array([(1.0 / 12.0) * ens.dx[i] /
+                        oracle.max_speed_1d(ens.U[:, ens.offsets[i]:ens.offsets[i + 1]])
+                        for i in range(nb)]))
+    outs = []
+    for p in range(3):
+        s.batch_tune(force_plan=p)
+        Ud = dev(ens.U)
+        s.batch_step(Ud, dts)
+        outs.append(Ud.cpu().numpy())
+    for p in (1, 2):
+        for i in range(nb):
+            sl = slice(ens.offsets[i], ens.offsets[i + 1])
+            assert comp_rel(outs[p][:, sl], outs[0][:, sl]) <= TOL_STAGE, (p, i)
     s.close()
 
 
