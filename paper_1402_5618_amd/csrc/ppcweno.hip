@@ -458,7 +458,7 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     // exchange scratch, and the reduction scratch after the largest area
     const long long area0 = (long long)NC * LP;
     const long long area1 = (W > 1 || !MIXED) ? (long long)NS * 512 : 0;
-    const long long area2 = (long long)NS * (padn<PSH>(A.seg_max + 1) + 1) + (long long)NC * NT;
+    const long long area2 = (long long)NS * (padn<PSH>(A.seg_max + 1) + 1);
     long long area = area0 + area1;
     area = area > area2 ? area : area2;
     double* sx = smem + area0;
@@ -770,7 +770,6 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     const int SMAX = A.seg_max;
     const int SS = padn<PSH>(SMAX + 1) + 1;
     double* sRes = smem;                         // [NS][SS], slots padded
-    double* sX = smem + (long long)NS * SS;      // [NC][NT] face-flux exchange
     double smax_speed = 0.0;
     unsigned bad = 0u;
     // SEG1: the whole line is one segment (the loop disappears at compile time)
@@ -849,12 +848,9 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
             }
         }
         __syncthreads();
-        // fluxes: thread t owns cells [c0, c1) and their right faces
-        const int cpt = (S + NT - 1) / NT;
-        const int c0 = g0 + tid * cpt;
-        const int c1 = min(g1, c0 + cpt);
-        double Fr[CPT][NC];
-        double F0[NC];
+        // fluxes: face f = g0 + r (between cells f-1 and f), r = 0..S, strided
+        // over the threads; a single segment of a periodic line skips face 0,
+        // which is face n
         auto face = [&](int f, double (&F)[NC]) {
             double Ul[NC], Ur[NC];
             int ql = f - g0, qr = f - g0 + 1;   // slots of cells f-1 and f
@@ -887,65 +883,59 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
                 for (int c = 0; c < NC; ++c) A.dbg_flux[(long long)c * (n + 1) + f] = F[c];
             }
         };
-        // one segment of a periodic line: face 0 is face n (last thread)
         const bool wrap0 = SEG1 && cyclic;
-        const int tlast = (S - 1) / cpt;
-        if (c0 < c1) {
-            if (tid == 0 && !wrap0) face(g0, F0);
+        const int r_lo = wrap0 ? 1 : 0;
+        constexpr int KF = CPT + 1;   // faces per thread at most
+        double Fr[KF][NC];
 #pragma unroll
-            for (int j = 0; j < CPT; ++j)
-                if (c0 + j < c1) face(c0 + j + 1, Fr[j]);
-            const int jl = c1 - c0 - 1;
+        for (int kk = 0; kk < KF; ++kk) {
+            const int r = r_lo + tid + kk * NT;
+            if (r <= S) face(g0 + r, Fr[kk]);
+        }
+        __syncthreads();   // staging reads done: the flux table takes its place
+        double* sF = smem;   // [NC][S + 1]
+        const int FS = S + 1;
 #pragma unroll
-            for (int j = 0; j < CPT; ++j)
-                if (j == jl) {
+        for (int kk = 0; kk < KF; ++kk) {
+            const int r = r_lo + tid + kk * NT;
+            if (r <= S) {
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) sX[c * NT + tid] = Fr[j][c];
-                }
+                for (int c = 0; c < NC; ++c) sF[c * FS + r] = Fr[kk][c];
+            }
         }
         __syncthreads();
-        if (c0 < c1) {
-            double Fl[NC];
+        // flux difference and epilogue, cells strided over the threads so the
+        // global loads and stores are coalesced
+        const double ih = 1.0 / h;
+        for (int q = tid; q < S; q += NT) {
+            const int i = g0 + q;
+            double o[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c)
-                Fl[c] = (tid == 0) ? (wrap0 ? sX[c * NT + tlast] : F0[c]) : sX[c * NT + tid - 1];
-            if (wrap0 && tid == 0 && A.dbg_flux) {
-#pragma unroll
-                for (int c = 0; c < NC; ++c) A.dbg_flux[(long long)c * (n + 1)] = Fl[c];
-            }
-            const double ih = 1.0 / h;
-#pragma unroll
-            for (int j = 0; j < CPT; ++j) {
-                if (c0 + j < c1) {
-                    const int i = c0 + j;
-                    double o[NC];
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) {
-                        const double L = -(Fr[j][c] - Fl[c]) * ih;
-                        const long long at = base + (long long)c * A.cs + i;
-                        if (A.mode == 0) {
-                            o[c] = L;
-                        } else {
-                            const double us = A.U[at];
-                            const double u0 = (A.rk_a != 0.0) ? A.U0[at] : 0.0;
-                            o[c] = A.rk_a * u0 + A.rk_b * (us + dt * L);
-                        }
-                        A.out[at] = o[c];
-                        Fl[c] = Fr[j][c];
-                    }
-                    if (A.mode == 1) {
-                        double m2 = 0.0;
-#pragma unroll
-                        for (int c = 1; c < NC - 1; ++c) m2 += o[c] * o[c];
-                        const double p = (A.gamma - 1.0) * (o[NC - 1] - 0.5 * m2 / o[0]);
-                        bool fin = true;
-#pragma unroll
-                        for (int c = 0; c < NC; ++c) fin = fin && isfinite(o[c]);
-                        if (!fin) bad |= 1u;
-                        if (!(o[0] > 0.0) || !(p > 0.0)) bad |= 2u;
-                        if (A.stage == 3) smax_speed = fmax(smax_speed, wave_speed<NC, NRM>(A.gamma, o));
-                    }
+            for (int c = 0; c < NC; ++c) {
+                const double Fl = sF[c * FS + ((wrap0 && q == 0) ? S : q)];
+                const double L = -(sF[c * FS + q + 1] - Fl) * ih;
+                if (wrap0 && q == 0 && A.dbg_flux) A.dbg_flux[(long long)c * (n + 1)] = Fl;
+                const long long at = base + (long long)c * A.cs + i;
+                if (A.mode == 0) {
+                    o[c] = L;
+                } else {
+                    const double us = A.U[at];
+                    const double u0 = (A.rk_a != 0.0) ? A.U0[at] : 0.0;
+                    o[c] = A.rk_a * u0 + A.rk_b * (us + dt * L);
                 }
+                A.out[at] = o[c];
+            }
+            if (A.mode == 1) {
+                // state checks without divisions: rho > 0 and rho E - |m|^2/2 > 0
+                double m2 = 0.0;
+#pragma unroll
+                for (int c = 1; c < NC - 1; ++c) m2 += o[c] * o[c];
+                bool fin = true;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) fin = fin && isfinite(o[c]);
+                if (!fin) bad |= 1u;
+                if (!(o[0] > 0.0) || !(o[0] * o[NC - 1] - 0.5 * m2 > 0.0)) bad |= 2u;
+                if (A.stage == 3) smax_speed = fmax(smax_speed, wave_speed<NC, NRM>(A.gamma, o));
             }
         }
         __syncthreads();
@@ -1360,7 +1350,7 @@ size_t line_lds_bytes(int nmax, int seg_max) {
     const long long LP = padn<SH>(nmax + 2 * kNG - 1) + 1;
     const long long a0 = (long long)NC * LP;
     const long long a1 = (W > 1 || !MIXED) ? (long long)NS * 512 : 0;
-    const long long a2 = (long long)NS * (padn<SH>(seg_max + 1) + 1) + (long long)NC * NT;
+    const long long a2 = (long long)NS * (padn<SH>(seg_max + 1) + 1);
     long long m = std::max(a0 + a1, a2);
     return (size_t)(m + NT) * sizeof(double);
 }
