@@ -168,50 +168,80 @@ __device__ __forceinline__ T pcr_solve(T A, T B, T C, T D, int k, int P, bool cy
     return cyclic ? D / (A + B + C) : D / B;
 }
 
-// Both chunked systems of one component at once (FP64): the "-" system on
-// lane order k and the "+" system on mirrored order P-1-k, so its neighbours
-// k-1 / k+1 in elimination order are the physical lanes k+1 / k-1.  Row of
-// either: A R_prev + B R + C R_next = D.  sx: this component's [8][128] LDS
-// slots (value-major, so a wave's accesses are bank-conflict free); every
-// thread of the block must call (barriers inside).
-__device__ __forceinline__ void pcr_pair(double (&A)[2], double (&B)[2], double (&C)[2],
-                                         double (&D)[2], int k, int P, bool cyclic, double* sx) {
-    for (int s = 1; s < P; s <<= 1) {
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            sx[(4 * q) * 128 + k] = A[q];
-            sx[(4 * q + 1) * 128 + k] = B[q];
-            sx[(4 * q + 2) * 128 + k] = C[q];
-            sx[(4 * q + 3) * 128 + k] = D[q];
+// Parallel cyclic reduction of a tridiagonal system of M <= 64 unknowns held
+// one row per lane of a single wave (lane shuffles, no barriers).  Row l:
+// a y_{l-1} + b y_l + c y_{l+1} = d, indices mod M when cyclic.  Returns y_l.
+__device__ __forceinline__ double pcr_wave(double a, double b, double c, double d, int l, int M,
+                                           bool cyclic) {
+    for (int s = 1; s < M; s <<= 1) {
+        const int lm = (l - s) & (M - 1), lp = (l + s) & (M - 1);
+        double am = __shfl(a, lm), bm = __shfl(b, lm), cm = __shfl(c, lm), dm = __shfl(d, lm);
+        double ap = __shfl(a, lp), bp = __shfl(b, lp), cp = __shfl(c, lp), dp = __shfl(d, lp);
+        if (!cyclic) {
+            if (l - s < 0) { am = 0.0; bm = 1.0; cm = 0.0; dm = 0.0; }
+            if (l + s >= M) { ap = 0.0; bp = 1.0; cp = 0.0; dp = 0.0; }
         }
-        __syncthreads();
-        const int lo = (k - s) & (P - 1);   // physical lane k - s
-        const int hi = (k + s) & (P - 1);   // physical lane k + s
+        const double al = -a * rcp_pos(bm), bt = -c * rcp_pos(bp);
+        const double na = al * am, nc = bt * cp;
+        const double nb = b + al * cm + bt * ap, nd = d + al * dm + bt * dp;
+        a = na; b = nb; c = nc; d = nd;
+    }
+    return cyclic ? d / (a + b + c) : d / b;
+}
+
+// Separator systems of one component, P <= 128 unknowns each: the "-" system
+// in lane order and the "+" system in mirrored order (index P-1-k for lane k).
+// The rows go through LDS to one wave per system (wave 0 of the component:
+// "-", wave 1: "+").  With P = 128 each lane takes an even and an odd row,
+// eliminates the even unknowns (one cyclic-reduction step; the next lane's
+// even row by shuffle), the 64 odd unknowns are solved by pcr_wave and the
+// even ones recovered; with P <= 64 one row per lane.  Lane k receives its
+// separators R (own) and L (previous in elimination order) of both systems.
+// sxc: this component's [8][128] LDS slots.  All threads of the block call.
+__device__ __forceinline__ void sep_solve_pair(const double (&A)[2], const double (&B)[2],
+                                               const double (&C)[2], const double (&D)[2], int k,
+                                               int P, bool cyclic, double* sxc, double& Rm,
+                                               double& Lm, double& Rp, double& Lp) {
+    __syncthreads();
+    if (k < P) {
+        const int ii[2] = {k, P - 1 - k};
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const double* v = sx + (4 * q) * 128;
-            const int m = q == 0 ? lo : hi;   // previous in elimination order
-            const int p = q == 0 ? hi : lo;   // next in elimination order
-            double Am = v[m], Bm = v[128 + m], Cm = v[256 + m], Dm = v[384 + m];
-            double Ap = v[p], Bp = v[128 + p], Cp = v[256 + p], Dp = v[384 + p];
-            if (!cyclic) {
-                const bool mout = q == 0 ? (k - s < 0) : (k + s >= P);
-                const bool pout = q == 0 ? (k + s >= P) : (k - s < 0);
-                if (mout) { Am = 0.0; Bm = 1.0; Cm = 0.0; Dm = 0.0; }
-                if (pout) { Ap = 0.0; Bp = 1.0; Cp = 0.0; Dp = 0.0; }
-            }
-            const double al = -A[q] * rcp_t(Bm), bt = -C[q] * rcp_t(Bp);
-            const double nA = al * Am, nC = bt * Cp;
-            const double nB = B[q] + al * Cm + bt * Ap, nD = D[q] + al * Dm + bt * Dp;
-            A[q] = nA;
-            B[q] = nB;
-            C[q] = nC;
-            D[q] = nD;
+            sxc[q * 512 + ii[q]] = A[q];
+            sxc[q * 512 + 128 + ii[q]] = B[q];
+            sxc[q * 512 + 256 + ii[q]] = C[q];
+            sxc[q * 512 + 384 + ii[q]] = D[q];
         }
     }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) D[q] = cyclic ? D[q] / (A[q] + B[q] + C[q]) : D[q] / B[q];
+    __syncthreads();
+    const int q = k >> 6, l = k & 63;
+    double* row = sxc + q * 512;   // rows of system q; results go to its A slots
+    if (P == 128) {
+        const int e = 2 * l, o = 2 * l + 1;
+        const double Ae = row[e], Be = row[128 + e], Ce = row[256 + e], De = row[384 + e];
+        const double Ao = row[o], Bo = row[128 + o], Co = row[256 + o], Do = row[384 + o];
+        const int ln = (l + 1) & 63;
+        double An = __shfl(Ae, ln), Bn = __shfl(Be, ln), Cn = __shfl(Ce, ln), Dn = __shfl(De, ln);
+        if (!cyclic && l == 63) { An = 0.0; Bn = 1.0; Cn = 0.0; Dn = 0.0; }
+        const double al = -Ao * rcp_pos(Be), bt = -Co * rcp_pos(Bn);
+        const double y = pcr_wave(al * Ae, Bo + al * Ce + bt * An, bt * Cn, Do + al * De + bt * Dn,
+                                  l, 64, cyclic);
+        double ym = __shfl(y, (l - 1) & 63);
+        if (!cyclic && l == 0) ym = 0.0;
+        const double x = (De - Ae * ym - Ce * y) / Be;
+        row[e] = x;
+        row[o] = y;
+    } else {
+        const double a = l < P ? row[l] : 0.0, b = l < P ? row[128 + l] : 1.0;
+        const double c = l < P ? row[256 + l] : 0.0, d = l < P ? row[384 + l] : 0.0;
+        const double y = pcr_wave(a, b, c, d, l, P, cyclic);
+        if (l < P) row[l] = y;
+    }
+    __syncthreads();
+    Rm = sxc[k & (P - 1)];
+    Lm = (!cyclic && k == 0) ? 0.0 : sxc[(k - 1) & (P - 1)];
+    Rp = sxc[512 + ((P - 1 - k) & (P - 1))];
+    Lp = (!cyclic && k + 1 >= P) ? 0.0 : sxc[512 + ((P - 2 - k) & (P - 1))];
 }
 
 constexpr int kCHP = 16;   // paired FP64 path: rows per lane and side
@@ -390,14 +420,8 @@ __device__ __forceinline__ void paired_solve(const double* __restrict__ sUc, int
     double RB[2] = {be + ae * gS + ce * nf1, beP + aeP * gSp + ceP * np1};
     double RC[2] = {ce * nf2, ceP * np2};
     double RD[2] = {re - ae * gP - ce * nf0, reP - aeP * gPp - ceP * np0};
-    pcr_pair(RA, RB, RC, RD, k, P, cyclic, sxc);
-    __syncthreads();
-    sxc[k] = RD[0];
-    sxc[512 + k] = RD[1];
-    __syncthreads();
-    const double Rm = RD[0], Rp = RD[1];
-    const double Lm = (!cyclic && k == 0) ? 0.0 : sxc[kq];
-    const double Lp = (!cyclic && k + 1 >= P) ? 0.0 : sxc[512 + kn];
+    double Rm, Lm, Rp, Lp;
+    sep_solve_pair(RA, RB, RC, RD, k, P, cyclic, sxc, Rm, Lm, Rp, Lp);
     if (act) {
 #pragma unroll
         for (int j = 0; j < kCHP; ++j) {
