@@ -1075,80 +1075,72 @@ __global__ void __launch_bounds__(256) transpose_kernel(const double* __restrict
 
 // mode 0: Out = Lx + Ly (L only).  mode 1: Out = a Un + b (Us + dt (Lx + Ly)),
 // written in layout A (Out) and B (OutB); reduces min rho / min e of the
-// output into eps_out and (stage 3) max speeds into spd_out.
-__global__ void __launch_bounds__(256) combine2d_kernel(
+// output into eps_out and (stage 3) max speeds into spd_out.  64x64 tiles,
+// one component at a time, 1024 threads; every array is read and written in
+// 512-byte runs (a wave covers 64 consecutive doubles of one row).
+constexpr int TC = 64;
+__global__ void __launch_bounds__(1024) combine2d_kernel(
     const double* __restrict__ Lx, const double* __restrict__ LyB, const double* __restrict__ Us,
     const double* Un, double* Out, double* __restrict__ OutB, int nx,
     int ny, int mode, double ra, double rb, const double* dt_dev, double dt_val, double gamma,
     long long* eps_out, long long* spd_out, long long* eps_reset, Scal* scal, unsigned* status) {
-    __shared__ double tile[4][TT][TT + 1];
-    __shared__ double red[4][8];
+    __shared__ double tile[TC][TC + 1];
+    __shared__ double red[16][4];
     if (scal && !scal->active) return;
     if (eps_reset && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         eps_reset[0] = kEncPosInf;
         eps_reset[1] = kEncPosInf;
     }
     const long long cs = (long long)nx * ny;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    const int x0 = blockIdx.x * TT, y0 = blockIdx.y * TT;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int x0 = blockIdx.x * TC, y0 = blockIdx.y * TC;
     const double dt = dt_dev ? *dt_dev : dt_val;
     const bool rd0 = mode == 1 && ra != 0.0;
-    // every load of the tile is issued before the first barrier: Ly through
-    // LDS (transposed), Lx / Us / Un straight into registers
-    double lx[4][4], us[4][4], un[4][4];
+    double cell[4][4];   // [row][comp] of this thread's cells (x0 + tx, y0 + ty + 16 r)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
+        double lx[4], us[4], un[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int xx = ty + 8 * r;
+            const int xx = ty + 16 * r;
             const int y = y0 + tx, x = x0 + xx;
-            if (x < nx && y < ny) tile[c][xx][tx] = LyB[c * cs + (long long)x * ny + y];
+            if (x < nx && y < ny)
+                tile[xx][tx] = __builtin_nontemporal_load(&LyB[c * cs + (long long)x * ny + y]);
         }
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int x = x0 + tx, y = y0 + ty + 8 * r;
-            lx[r][c] = us[r][c] = un[r][c] = 0.0;
+            const int x = x0 + tx, y = y0 + ty + 16 * r;
+            lx[r] = us[r] = un[r] = 0.0;
             if (x < nx && y < ny) {
                 const long long at = c * cs + (long long)y * nx + x;
-                lx[r][c] = Lx[at];
-                if (mode == 1) us[r][c] = Us[at];
-                if (rd0) un[r][c] = Un[at];
+                lx[r] = __builtin_nontemporal_load(&Lx[at]);
+                if (mode == 1) us[r] = __builtin_nontemporal_load(&Us[at]);
+                if (rd0) un[r] = __builtin_nontemporal_load(&Un[at]);
             }
-        }
-    }
-    __syncthreads();
-    double cell[4][4];   // [row yy/8][comp]
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int yy = ty + 8 * r;
-            const int x = x0 + tx, y = y0 + yy;
-            const double L = lx[r][c] + tile[c][tx][yy];
-            const double v = (mode == 0) ? L : ra * un[r][c] + rb * (us[r][c] + dt * L);
-            if (x < nx && y < ny) Out[c * cs + (long long)y * nx + x] = v;
-            cell[r][c] = v;
-        }
-    }
-    if (mode == 1) {
-        __syncthreads();   // Ly reads done: the tiles take the transposed output
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) tile[c][ty + 8 * r][tx] = cell[r][c];
         }
         __syncthreads();
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int r = 0; r < 4; ++r) {
+            const int yy = ty + 16 * r;
+            const int x = x0 + tx, y = y0 + yy;
+            const double L = lx[r] + tile[tx][yy];
+            const double v = (mode == 0) ? L : ra * un[r] + rb * (us[r] + dt * L);
+            if (x < nx && y < ny) __builtin_nontemporal_store(v, &Out[c * cs + (long long)y * nx + x]);
+            cell[r][c] = v;
+        }
+        __syncthreads();   // tile reads done
+        if (mode == 1) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tile[ty + 16 * r][tx] = cell[r][c];
+            __syncthreads();
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int xx = ty + 8 * r;
+                const int xx = ty + 16 * r;
                 const int y = y0 + tx, x = x0 + xx;
-                if (x < nx && y < ny) OutB[c * cs + (long long)x * ny + y] = tile[c][tx][xx];
+                if (x < nx && y < ny)
+                    __builtin_nontemporal_store(tile[tx][xx], &OutB[c * cs + (long long)x * ny + y]);
             }
+            __syncthreads();   // before the next component's tile
         }
     }
     if (mode != 1) return;
@@ -1156,7 +1148,7 @@ __global__ void __launch_bounds__(256) combine2d_kernel(
     unsigned bad = 0u;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int x = x0 + tx, y = y0 + ty + 8 * r;
+        const int x = x0 + tx, y = y0 + ty + 16 * r;
         if (x >= nx || y >= ny) continue;
         const double q[4] = {cell[r][0], cell[r][1], cell[r][2], cell[r][3]};
         const double e = spec_e<4>(q);
@@ -1184,7 +1176,7 @@ __global__ void __launch_bounds__(256) combine2d_kernel(
     if (bad && status) atomicOr(status, bad);
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int i = 1; i < 4; ++i) {
+        for (int i = 1; i < 16; ++i) {
             mr = fmin(mr, red[i][0]); me = fmin(me, red[i][1]);
             sx = fmax(sx, red[i][2]); sy = fmax(sy, red[i][3]);
         }
@@ -1505,9 +1497,9 @@ int combine_2d(pp_cweno_ctx* ctx, const double* UsA, const double* Un, double* O
                int mode, double ra, double rb, const double* dt_dev, double dt_val,
                long long* eps_out, long long* spd_out, long long* eps_reset, bool run) {
     const auto& c = ctx->cfg;
-    dim3 grid((unsigned)((c.nx + TT - 1) / TT), (unsigned)((c.ny + TT - 1) / TT));
+    dim3 grid((unsigned)((c.nx + TC - 1) / TC), (unsigned)((c.ny + TC - 1) / TC));
     const int slot = timed_begin(ctx, 2);
-    hipLaunchKernelGGL(combine2d_kernel, grid, dim3(256), 0, ctx->stream, ctx->Lx, ctx->LyB, UsA,
+    hipLaunchKernelGGL(combine2d_kernel, grid, dim3(1024), 0, ctx->stream, ctx->Lx, ctx->LyB, UsA,
                        Un, Out, OutB, (int)c.nx, (int)c.ny, mode, ra, rb, dt_dev, dt_val, c.gamma,
                        eps_out, spd_out, eps_reset, run ? ctx->scal : nullptr,
                        ctx->scal ? &ctx->scal->status : nullptr);
