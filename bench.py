@@ -38,11 +38,18 @@ BYTES_PER_SWEEP_CELL = 64.0     # line kernel: read the stage input, write L
 # Thomas 4 x 2 x 8, limiter test (smooth data) 44, HLLC 108, flux difference 8.
 FLOPS_PER_SWEEP_CELL = 716.0
 
-# HBM traffic of the line kernels from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
-# (KiB per dispatch, 2048^2 density wave, FP64), scaled by the copy-kernel
-# calibration (FETCH reads 2.0x, WRITE 1.0x the bytes of a 1 GiB copy).  Valid
-# only for the kernel sources whose hash is recorded; otherwise reported null.
-TRAFFIC_RECORD = None
+# HBM traffic of the FP64 line kernels from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch, 2048^2 density wave), scaled by the copy
+# calibration: a 1 GiB device copy reads FETCH_SIZE 524300 KiB (x 2.0) and
+# WRITE_SIZE 1048576 KiB (x 1.0).  Valid only for the kernel sources whose
+# hash is recorded (profiles/line_kernel_2d_density_wave_2048_fp64.md);
+# otherwise traffic is reported null.
+TRAFFIC_RECORD = {
+    "src_sha256": "0a78c5867b68f0a8111c870f7afaf74a5682ae6299323c6f6e8edb83e726aeca",
+    "fetch_scale": 2.0, "write_scale": 1.0,
+    "x": {"fetch_kib": 66232.8, "write_kib": 147492.0},
+    "y": {"fetch_kib": 66166.6, "write_kib": 147479.0},
+}
 
 
 def parse():
@@ -287,8 +294,8 @@ def main():
     traffic = None
     if TRAFFIC_RECORD is not None and TRAFFIC_RECORD["src_sha256"] == kernel_source_hash():
         rec = TRAFFIC_RECORD[dom]
-        traffic = rec["fetch_kib"] * 1024 / TRAFFIC_RECORD["fetch_factor"] + \
-            rec["write_kib"] * 1024 / TRAFFIC_RECORD["write_factor"]
+        traffic = rec["fetch_kib"] * 1024 * TRAFFIC_RECORD["fetch_scale"] + \
+            rec["write_kib"] * 1024 * TRAFFIC_RECORD["write_scale"]
 
     line = {
         "metric": "cell-updates/s, 2D 2048^2 FP64 vs mixed-FP32 at fixed L1 error; % HBM BW",
