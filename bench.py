@@ -15,6 +15,7 @@ Other workloads (one JSON line each, bounded runs):
   --workload wave1d       Example 3.1 at N = 200, dt = w1 h^(5/3)/S, to t = 2
   --workload rarefaction1d / blast1d   the 1D positivity configurations, N = 4000
   --workload copy         plain device copy of a known size (counter calibration)
+  --workload accuracy     wall time against L1 error, FP64 and mixed, N = 128..2048
 
 Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--no-cpu] [--workload W]
 """
@@ -62,7 +63,7 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--workload", default="density2d",
                     choices=["density2d", "sedov2d", "ensemble", "wave1d", "rarefaction1d",
-                             "blast1d", "copy"])
+                             "blast1d", "copy", "accuracy"])
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     ap.add_argument("--full", action="store_true",
                     help="sedov2d / ensemble: run to the configuration's end time")
@@ -97,6 +98,50 @@ def other_workload(args):
         out.update(metric="device copy GB/s (read + write)", unit="GB/s",
                    value=2 * nbytes * args.steps / dt / 1e9, steps=args.steps,
                    config={"workload": f"copy of {nbytes} bytes x {args.steps}"})
+    elif args.workload == "accuracy":
+        # cost against L1 error (the paper's Table 2 / Fig. 1 methodology) for
+        # both forms: the 2D density wave to a fixed time on N^2 grids
+        T = 0.05
+        rows = []
+        for n in (128, 256, 512, 1024, 2048):
+            dx = 2.0 / n
+            U0 = W.density_wave_2d(n, n)
+            for name, pr in (("fp64", pp.PP_FP64), ("mixed", pp.PP_MIXED)):
+                U = torch.tensor(U0, device="cuda")
+                s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=(0, 0, 0, 0), precision=pr)
+                warm = U.clone()
+                s.run(warm, T, 3, 1.0 / 12.0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                t, k = s.run(U, T, 10 ** 7, 1.0 / 12.0)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                s.close()
+                Uh = U.cpu().numpy()
+                l1 = W.error_norms(Uh[0], W.density_wave_2d(n, n, t=t)[0], dx * dx)[0]
+                rows.append({"n": n, "form": name, "steps": k, "wall_s": wall, "l1_rho": l1,
+                             "cell_updates_per_s": n * n * k / wall})
+                print(f"accuracy: n={n} {name} steps={k} wall={wall:.3f}s L1={l1:.3e}",
+                      file=sys.stderr, flush=True)
+        # equal accuracy: for each FP64 point, the cheapest mixed run with an L1
+        # at least as small, if any
+        eq = []
+        for r in rows:
+            if r["form"] != "fp64":
+                continue
+            cands = [m for m in rows if m["form"] == "mixed" and m["l1_rho"] <= r["l1_rho"]]
+            if cands:
+                m = min(cands, key=lambda m: m["wall_s"])
+                eq.append({"l1_fp64": r["l1_rho"], "n_fp64": r["n"], "n_mixed": m["n"],
+                           "mixed_speedup": r["wall_s"] / m["wall_s"]})
+            else:
+                eq.append({"l1_fp64": r["l1_rho"], "n_fp64": r["n"], "n_mixed": None,
+                           "mixed_speedup": None})
+        out.update(metric="wall time against L1 error, 2D density wave to t=0.05",
+                   value=None, steps=None,
+                   config={"workload": "2D density wave, periodic [0,2]^2, CFL 1/12, t = 0.05, "
+                                       "N = 128..2048, FP64 and mixed", "table": rows,
+                           "equal_accuracy": eq})
     elif args.workload == "sedov2d":
         n = 1024
         dx = 1.1 / n
