@@ -256,7 +256,8 @@ constexpr int kCHP = 16;   // paired FP64 path: rows per lane and side
 // On return E0[j] = x_{r0+j}, F0[j] = y_{r0+j}.  All threads of the block
 // must call.
 __device__ __forceinline__ void paired_solve(const double* __restrict__ sUc, int n, int k, int P,
-                                             bool cyclic, double weps, double* sxc, int r0,
+                                             bool cyclic, double weps, double* sxc, double* cl,
+                                             int r0,
                                              int len, double (&E0)[kCHP], double (&E1)[kCHP],
                                              double (&E2)[kCHP], double (&F0)[kCHP],
                                              double (&F1)[kCHP], double (&F2)[kCHP]) {
@@ -266,16 +267,22 @@ __device__ __forceinline__ void paired_solve(const double* __restrict__ sUc, int
     // cell average of cell r0 + rel (rel >= -3)
     auto vrel = [&](int rel) -> double { return sUc[padn<4>(r0 + rel + kNG)]; };
     auto vabs = [&](int m) -> double { return sUc[padn<4>(m + kNG)]; };
-    // closure values: "-" side x_{-1}, x_n (nodes -1/2, n+1/2 seen from the
-    // ghost cells) and "+" side y_{-1}, y_n (mirror images)
-    double clo_m = 0.0, chi_m = 0.0, clo_p = 0.0, chi_p = 0.0;
+    // A non-periodic line is closed by the values just outside it ("-" side
+    // x_{-1}, x_n at nodes -1/2, n+1/2 seen from the ghost cells; "+" side
+    // y_{-1}, y_n, their mirror images).  They are formed first, parked in
+    // LDS (cl[0..3]) and applied after the chunk passes, which keeps them out
+    // of the unrolled loops: x_n and y_{-1} belong to the separator rows of
+    // the last / first chunk, x_{-1} and y_n are the L of the first "-" /
+    // last "+" chunk.
     if (act && !cyclic && k == 0) {
-        clo_m = weno5z_value(vabs(-3), vabs(-2), vabs(-1), vabs(0), vabs(1), weps);
-        chi_p = weno5z_value(vabs(1), vabs(0), vabs(-1), vabs(-2), vabs(-3), weps);
+        cl[0] = weno5z_value(vabs(-3), vabs(-2), vabs(-1), vabs(0), vabs(1), weps);   // x_{-1}
+        cl[1] = weno5z_value(vabs(1), vabs(0), vabs(-1), vabs(-2), vabs(-3), weps);   // y_{-1}
     }
     if (act && !cyclic && k == P - 1) {
-        chi_m = weno5z_value(vabs(n - 2), vabs(n - 1), vabs(n), vabs(n + 1), vabs(n + 2), weps);
-        clo_p = weno5z_value(vabs(n + 2), vabs(n + 1), vabs(n), vabs(n - 1), vabs(n - 2), weps);
+        cl[2] = weno5z_value(vabs(n - 2), vabs(n - 1), vabs(n), vabs(n + 1), vabs(n + 2),
+                             weps);                                                     // x_n
+        cl[3] = weno5z_value(vabs(n + 2), vabs(n + 1), vabs(n), vabs(n - 1), vabs(n - 2),
+                             weps);                                                     // y_n
     }
     // "-": x_j = P + Q L + S R, L = x_{r0-1}, R = x_{r1-1} (separator)
     // "+": y_j = P + Q L + S R, L = y_{r1},  R = y_{r0}   (separator)
@@ -318,10 +325,6 @@ __device__ __forceinline__ void paired_solve(const double* __restrict__ sUc, int
                 double a = (2.0 * w0 + w1) * third, bb = (w0 + 2.0 * (w1 + w2)) * third;
                 double c = w2 * third;
                 double r = (w0 * v1 + (5.0 * (w0 + w1) + w2) * v2 + (w1 + 5.0 * w2) * v3) * sixth;
-                if (!cyclic) {
-                    if (g == 0) { r -= a * clo_m; a = 0.0; }
-                    if (g == n - 1) { r -= c * chi_m; c = 0.0; }
-                }
                 if (j < L - 1) {
                     const double piv = (j == 0) ? bb : bb - a * cprev;
                     const double ip = rcp_pos(piv);
@@ -367,10 +370,6 @@ __device__ __forceinline__ void paired_solve(const double* __restrict__ sUc, int
                 double a = (2.0 * w0 + w1) * third, bb = (w0 + 2.0 * (w1 + w2)) * third;
                 double c = w2 * third;
                 double r = (w0 * vr + (5.0 * (w0 + w1) + w2) * vc + (w1 + 5.0 * w2) * vl) * sixth;
-                if (!cyclic) {
-                    if (g == n - 1) { r -= a * clo_p; a = 0.0; }
-                    if (g == 0) { r -= c * chi_p; c = 0.0; }
-                }
                 if (j > 0) {
                     const bool first = (j == L - 1);
                     const double piv = first ? bb : bb - a * cprev;
@@ -405,6 +404,17 @@ __device__ __forceinline__ void paired_solve(const double* __restrict__ sUc, int
             }
         }
     }
+    double xlo = 0.0, yhi = 0.0;   // x_{-1} (lane 0), y_n (lane P-1)
+    if (act && !cyclic && k == P - 1) {
+        re -= ce * cl[2];   // row n-1 of "-": the separator of the last chunk
+        ce = 0.0;
+        yhi = cl[3];
+    }
+    if (act && !cyclic && k == 0) {
+        reP -= ceP * cl[1];   // row 0 of "+": the separator of the first chunk
+        ceP = 0.0;
+        xlo = cl[0];
+    }
     // first-unknown relations of the neighbour chunks: "-" from lane k+1,
     // "+" from lane k-1
     const int kn = (k + 1) & (P - 1), kq = (k - 1) & (P - 1);
@@ -420,8 +430,18 @@ __device__ __forceinline__ void paired_solve(const double* __restrict__ sUc, int
     double RB[2] = {be + ae * gS + ce * nf1, beP + aeP * gSp + ceP * np1};
     double RC[2] = {ce * nf2, ceP * np2};
     double RD[2] = {re - ae * gP - ce * nf0, reP - aeP * gPp - ceP * np0};
+    if (!cyclic && k == 0) {   // the known x_{-1} moves to the right side
+        RD[0] -= RA[0] * xlo;
+        RA[0] = 0.0;
+    }
+    if (!cyclic && k == P - 1) {   // the known y_n likewise
+        RD[1] -= RA[1] * yhi;
+        RA[1] = 0.0;
+    }
     double Rm, Lm, Rp, Lp;
     sep_solve_pair(RA, RB, RC, RD, k, P, cyclic, sxc, Rm, Lm, Rp, Lp);
+    if (!cyclic && k == 0) Lm = xlo;
+    if (!cyclic && k == P - 1) Lp = yhi;
     if (act) {
 #pragma unroll
         for (int j = 0; j < kCHP; ++j) {
@@ -575,7 +595,8 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
 
     if constexpr (PAIRED) {
         double* sxc = sx + comp * 1024;   // [8][128] exchange slots of this component
-        paired_solve(sUc, n, k, P, cyclic, A.weno_eps, sxc, r0, len, E0, E1, E2, F0, F1, F2);
+        paired_solve(sUc, n, k, P, cyclic, A.weno_eps, sxc, red + 4 * comp, r0, len, E0, E1, E2,
+                     F0, F1, F2);
     } else if constexpr (!MIXED) {
         double ae = 0.0, be = 1.0, ce = 0.0, re = 0.0;
         double gP = 0.0, gQ = 1.0, gS = 0.0;   // x_{r1-2} = gP + gQ L + gS R
