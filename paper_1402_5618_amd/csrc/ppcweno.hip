@@ -26,6 +26,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "pp_cweno.h"
@@ -1333,6 +1334,9 @@ struct pp_cweno_ctx {
     int plan = 0;
     int nclass = 0;
     LenClass cls[3];
+    // largest dynamic LDS size already granted to each kernel (the attribute
+    // call is a driver round trip, not to be paid on every launch)
+    std::unordered_map<const void*, size_t> lds_granted;
     // measurement: event pairs around kernel launches, per class
     bool timing = false;
     std::vector<hipEvent_t> ev[3];
@@ -1421,7 +1425,11 @@ int launch_line_p(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int 
     else
         fn = seg >= nmax ? (const void*)line_kernel<NC, NRM, W, CPT, true, MIXED>
                          : (const void*)line_kernel<NC, NRM, W, CPT, false, MIXED>;
-    HIPCHK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    size_t& granted = ctx->lds_granted[fn];
+    if (lds > granted) {
+        HIPCHK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        granted = lds;
+    }
     void* args[] = {&A};
     HIPCHK(ctx, hipLaunchKernel(fn, dim3(persistent ? grid : A.nlines), dim3(NT), args, lds,
                                 ctx->stream));
