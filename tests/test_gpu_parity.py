@@ -41,8 +41,9 @@ def mixed_line(n, seed=0, a=0.0, b=1.0):
     return W.prim_to_cons_1d(rho, u, p, 1.4)
 
 
-CASES_1D = [(7, (0, 0)), (13, (1, 1)), (64, (0, 0)), (200, (1, 2)), (777, (2, 2)),
-            (2048, (0, 0)), (2049, (1, 1)), (4000, (1, 1))]
+CASES_1D = [(3, (1, 1)), (5, (0, 0)), (7, (0, 0)), (13, (1, 1)), (64, (0, 0)), (128, (2, 1)),
+            (200, (1, 2)), (777, (2, 2)), (2047, (0, 0)), (2048, (0, 0)), (2049, (1, 1)),
+            (4000, (1, 1)), (4096, (2, 2))]
 
 
 def stage_tolerance(U0, Us, st, dt, bc, h, ref, k=4):
@@ -58,6 +59,18 @@ def stage_tolerance(U0, Us, st, dt, bc, h, ref, k=4):
         fs = 1.0 + 1e-15 * rng.standard_normal(Us.shape)
         V = oracle.stage_1d(U0 * f0, Us * fs, st, dt, bc, h)
         sens = max(sens, comp_rel(V, ref))
+    return max(TOL_STAGE, 4.0 * sens)
+
+
+def step_tolerance(U0, dt, bc, h, ref, k=4):
+    """stage_tolerance for a whole SSP-RK3 step of the oracle."""
+    rng = np.random.default_rng(1402)
+    sens = 0.0
+    for _ in range(k):
+        V0 = U0 * (1.0 + 1e-15 * rng.standard_normal(U0.shape))
+        V1 = oracle.stage_1d(V0, V0, 1, dt, bc, h)
+        V2 = oracle.stage_1d(V0, V1, 2, dt, bc, h)
+        sens = max(sens, comp_rel(oracle.stage_1d(V0, V2, 3, dt, bc, h), ref))
     return max(TOL_STAGE, 4.0 * sens)
 
 
@@ -232,6 +245,80 @@ def test_batch_tune_picks_a_plan_and_results_agree():
         for i in range(nb):
             sl = slice(ens.offsets[i], ens.offsets[i + 1])
             assert comp_rel(outs[p][:, sl], outs[0][:, sl]) <= TOL_STAGE, (p, i)
+    s.close()
+
+
+def test_batch_step_extreme_lengths():
+    """Smallest and largest problems, both kernel shapes, in one batch."""
+    pp = gpu()
+    lengths = np.array([4096, 3, 2048, 2049, 17, 5], dtype=np.int64)
+    rng = np.random.default_rng(5)
+    Us, dxs = [], []
+    for n in lengths:
+        x = W.cell_centres(0.0, 1.0, int(n))
+        rho = 1.0 + 0.5 * (x > 0.5) + 0.05 * rng.standard_normal(int(n)) ** 2
+        p = 1.0 - 0.9 * (x > 0.5)
+        Us.append(W.prim_to_cons_1d(rho, 0.3 * np.sin(6 * x), p, 1.4))
+        dxs.append(1.0 / n)
+    U = np.concatenate(Us, axis=1)
+    nb = len(lengths)
+    dts = np.array([(1.0 / 12.0) * dxs[i] / oracle.max_speed_1d(Us[i]) for i in range(nb)])
+    print(f"case batch extreme lengths {list(lengths)}", flush=True)
+    s = pp.Solver(ndim=1, lengths=lengths, dxs=np.array(dxs), bcs=[1, 2] * nb)
+    for plan in (0, 1):
+        s.batch_tune(force_plan=plan)
+        Ud = dev(U)
+        s.batch_step(Ud, dev(dts))
+        got = Ud.cpu().numpy()
+        off = 0
+        for i in range(nb):
+            sl = slice(off, off + int(lengths[i]))
+            off += int(lengths[i])
+            h = dxs[i]
+            U1 = oracle.stage_1d(Us[i], Us[i], 1, dts[i], (1, 2), h)
+            U2 = oracle.stage_1d(Us[i], U1, 2, dts[i], (1, 2), h)
+            U3 = oracle.stage_1d(Us[i], U2, 3, dts[i], (1, 2), h)
+            err = comp_rel(got[:, sl], U3)
+            if err > TOL_STAGE:   # the 3-cell line has a limited state on e = eps
+                tol = step_tolerance(Us[i], dts[i], (1, 2), h, U3)
+                print(f"plan {plan} problem {i}: err {err:.2e}, conditioning bound {tol:.2e}",
+                      flush=True)
+                assert err <= tol, (plan, i)
+    s.close()
+
+
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (2, 2), (1, 2)])
+def test_1d_free_stream(bc):
+    """A uniform state is steady: |L| h stays at rounding of |F| (walls need
+    zero normal velocity)."""
+    pp = gpu()
+    n = 300
+    u = 0.0 if 2 in bc else 0.4
+    U = W.prim_to_cons_1d(np.full(n, 1.3), np.full(n, u), np.full(n, 2.0), 1.4)
+    s = pp.Solver(ndim=1, nx=n, dx=1.0 / n, bc=(*bc, 0, 0))
+    Ud = dev(U)
+    L = torch.empty_like(Ud)
+    s.rhs(Ud, L)
+    torch.cuda.synchronize()
+    F = max(abs(1.3 * u), 1.3 * u * u + 2.0, abs(u * (U[2, 0] + 2.0)))
+    assert np.abs(L.cpu().numpy()).max() / n <= 1e-13 * F
+    s.close()
+
+
+@pytest.mark.parametrize("nx,ny,bc", [(40, 24, (0, 0, 0, 0)), (33, 17, (1, 1, 2, 2))])
+def test_2d_free_stream(nx, ny, bc):
+    pp = gpu()
+    U = np.empty((4, ny, nx))
+    U[0] = 1.3
+    U[1] = 1.3 * 0.4 if bc[0] != 2 else 0.0
+    U[2] = 1.3 * -0.2 if bc[2] != 2 else 0.0
+    U[3] = 2.0 / 0.4 + 0.5 * (U[1] ** 2 + U[2] ** 2) / 1.3
+    s = pp.Solver(ndim=2, nx=nx, ny=ny, dx=1.0 / nx, dy=1.0 / ny, bc=bc)
+    Ud = dev(U)
+    L = torch.empty_like(Ud)
+    s.rhs(Ud, L)
+    torch.cuda.synchronize()
+    assert np.abs(L.cpu().numpy()).max() * min(1.0 / nx, 1.0 / ny) <= 1e-13 * 10.0
     s.close()
 
 
