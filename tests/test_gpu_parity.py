@@ -180,6 +180,49 @@ def test_2d_stage_parity(nx, ny, bc):
     s.close()
 
 
+@pytest.mark.parametrize("nsteps", [0, 5, 20])
+def test_2d_sedov_stage_parity(nsteps):
+    """Near-vacuum quarter-plane blast on 64^2 (reflective x = 0 and y = 0):
+    the three stages of one step from oracle snapshots, limiter active."""
+    pp = gpu()
+    n, ext = 64, 1.1
+    dx = ext / n
+    bc = (2, 1, 2, 1)
+    U = W.sedov_corner_2d(n, extent=ext)
+    dt = 0.0
+    for _ in range(nsteps + 1):
+        s_x, s_y = oracle.max_speed_2d(U)
+        dt = (1.0 / 12.0) / (s_x / dx + s_y / dx)
+        if _ == nsteps:
+            break
+        U1 = oracle.stage_2d(U, U, 1, dt, bc, dx, dx)
+        U2 = oracle.stage_2d(U, U1, 2, dt, bc, dx, dx)
+        U = oracle.stage_2d(U, U2, 3, dt, bc, dx, dx)
+    print(f"case sedov 64^2 after {nsteps} steps, dt {dt:.3e}", flush=True)
+    refs = [U]
+    for st in (1, 2, 3):
+        refs.append(oracle.stage_2d(U, refs[-1], st, dt, bc, dx, dx))
+    s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=bc)
+    Ud = dev(U)
+    for st in (1, 2, 3):
+        out = torch.empty_like(Ud)
+        s.stage(Ud, dev(refs[st - 1]), out, st, dt)
+        torch.cuda.synchronize()
+        err = comp_rel(out.cpu().numpy(), refs[st])
+        if err > TOL_STAGE:
+            # same conditioning bound as in 1D: the oracle against itself
+            rng = np.random.default_rng(st)
+            sens = 0.0
+            for _ in range(3):
+                V = oracle.stage_2d(U * (1 + 1e-15 * rng.standard_normal(U.shape)),
+                                    refs[st - 1] * (1 + 1e-15 * rng.standard_normal(U.shape)),
+                                    st, dt, bc, dx, dx)
+                sens = max(sens, comp_rel(V, refs[st]))
+            print(f"stage {st}: err {err:.2e}, conditioning bound {4 * sens:.2e}", flush=True)
+            assert err <= max(TOL_STAGE, 4.0 * sens)
+    s.close()
+
+
 # ------------------------------------------------------------ batched ensemble
 def ensemble(nprob, n_lo, n_hi, seed=1402):
     return W.riemann_ensemble(nprob=nprob, seed=seed, n_lo=n_lo, n_hi=n_hi)
