@@ -1268,9 +1268,9 @@ __global__ void init_scal_kernel(Scal* s) {
 // Start of a step: advance t by the previous dt, pick the new dt from the
 // wave speeds of the current state, clip to t_end / step budget, reset the
 // reductions this step will fill.
-__global__ void dt_kernel(Scal* s, int ndim, int rule, double cfl, double dx, double dy,
-                          double t_end, long long steps_max) {
-    if (!s->active) return;   // retired run: later launches change nothing
+__device__ __forceinline__ void dt_update(Scal* s, int ndim, int rule, double cfl, double dx,
+                                          double dy, double t_end, long long steps_max) {
+    if (!s->active) return;   // retired run: later calls change nothing
     if (s->dt > 0.0) {
         s->t += s->dt;
         s->steps += 1;
@@ -1290,6 +1290,43 @@ __global__ void dt_kernel(Scal* s, int ndim, int rule, double cfl, double dx, do
     s->spd[0] = s->spd[1] = kEncZero;
     s->eps[0][0] = s->eps[0][1] = kEncPosInf;
     s->eps[1][0] = s->eps[1][1] = kEncPosInf;
+}
+
+// Run step of a single grid: t and step count of the finished step, the next
+// dt (rule of the run) from the reduced wave speeds, or retire the run.
+__global__ void dt_kernel(Scal* s, int ndim, int rule, double cfl, double dx, double dy,
+                          double t_end, long long steps_max) {
+    dt_update(s, ndim, rule, cfl, dx, dy, t_end, steps_max);
+}
+
+// Whole 1D run of a single line in one workgroup: up to max_steps SSP-RK3
+// steps (3 stage passes each) with the dt update between steps on thread 0.
+// The line's state, stage buffers and scalars are written and read by this
+// workgroup only, so block barriers order them.  Ends when the run retires
+// (t_end, step budget, unusable dt) or after max_steps steps.
+struct RunArgs {
+    LineArgs st[3];   // the three stages of a step
+    int rule;
+    double cfl, t_end;
+    long long steps_total;
+    int max_steps;
+};
+
+template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED>
+__global__ void __launch_bounds__(2 * NC * 64 * W) run1d_kernel(RunArgs R) {
+    extern __shared__ double smem[];
+    Scal* s = R.st[0].scal;
+    for (int it = 0; it < R.max_steps; ++it) {
+        if (threadIdx.x == 0)
+            dt_update(s, 1, R.rule, R.cfl, R.st[0].h, 0.0, R.t_end, R.steps_total);
+        __syncthreads();
+        if (!s->active) break;
+#pragma unroll 1
+        for (int st = 0; st < 3; ++st) {   // one copy of the operator, stage args by index
+            line_op<NC, NRM, W, CPT, SEG1, MIXED>(R.st[st], 0, smem);
+            __syncthreads();
+        }
+    }
 }
 
 }  // namespace
@@ -1485,6 +1522,68 @@ int launch_1d(pp_cweno_ctx* ctx, const double* Us, const double* U0, double* out
     return launch_line<3, 1, 2, 3>(ctx, A, A.n, false, 1);
 }
 
+// eq. (RK3) stage coefficients (a, b): U_out = a U^n + b (U_s + dt L(U_s))
+const double kRK[4][2] = {{0, 0}, {0.0, 1.0}, {0.75, 0.25}, {1.0 / 3.0, 2.0 / 3.0}};
+
+// Device-resident 1D run: one workgroup, up to max_steps steps per launch.
+template <int NC, int NRM, int W, int CPT, bool MIXED>
+int launch_run1d_p(pp_cweno_ctx* ctx, RunArgs& R) {
+    constexpr int NT = 2 * NC * 64 * W;
+    const int nmax = R.st[0].n;
+    const int seg = pick_segment<NC, W, CPT, MIXED>(nmax);
+    for (auto& a : R.st) a.seg_max = seg;
+    const size_t lds = line_lds_bytes<NC, W, MIXED>(nmax, seg);
+    if (lds > kLdsBudget || (seg + NT - 1) / NT > CPT)
+        return fail(ctx, PP_EUNSUPPORTED, "line too long for the on-chip line kernel");
+    const void* fn = seg >= nmax ? (const void*)run1d_kernel<NC, NRM, W, CPT, true, MIXED>
+                                 : (const void*)run1d_kernel<NC, NRM, W, CPT, false, MIXED>;
+    size_t& granted = ctx->lds_granted[fn];
+    if (lds > granted) {
+        HIPCHK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        granted = lds;
+    }
+    void* args[] = {&R};
+    HIPCHK(ctx, hipLaunchKernel(fn, dim3(1), dim3(NT), args, lds, ctx->stream));
+    return PP_OK;
+}
+
+int launch_run1d(pp_cweno_ctx* ctx, double* U, int rule, double cfl, double t_end,
+                 long long steps_total, int max_steps) {
+    RunArgs R;
+    R.rule = rule;
+    R.cfl = cfl;
+    R.t_end = t_end;
+    R.steps_total = steps_total;
+    R.max_steps = max_steps;
+    const double* Uin[3] = {U, ctx->U1, ctx->U2};
+    double* Uout[3] = {ctx->U1, ctx->U2, U};
+    for (int st = 1; st <= 3; ++st) {
+        LineArgs& a = R.st[st - 1];
+        a = base_args(ctx);
+        a.U = Uin[st - 1];
+        a.U0 = U;
+        a.out = Uout[st - 1];
+        a.cs = ctx->cfg.nx;
+        a.ls = 0;
+        a.n = (int)ctx->cfg.nx;
+        a.nlines = 1;
+        a.bc_lo = ctx->cfg.bc[0];
+        a.bc_hi = ctx->cfg.bc[1];
+        a.h = ctx->cfg.dx;
+        a.mode = 1;
+        a.stage = st;
+        a.rk_a = kRK[st][0];
+        a.rk_b = kRK[st][1];
+        a.dt_dev = &ctx->scal->dt;
+        a.scal = ctx->scal;
+    }
+    const bool mixed = ctx->cfg.precision == PP_MIXED;
+    if (ctx->cfg.nx <= 2048)
+        return mixed ? launch_run1d_p<3, 1, 1, 6, true>(ctx, R)
+                     : launch_run1d_p<3, 1, 1, 6, false>(ctx, R);
+    return mixed ? launch_run1d_p<3, 1, 2, 3, true>(ctx, R) : launch_run1d_p<3, 1, 2, 3, false>(ctx, R);
+}
+
 // 2D sweeps of one stage input (Us in layout A and B) into Lx and LyB.
 int sweeps_2d(pp_cweno_ctx* ctx, const double* UsA, const double* UsB, const long long* eps_enc,
               bool run) {
@@ -1564,7 +1663,6 @@ int reset_scal(pp_cweno_ctx* ctx) {
     return PP_OK;
 }
 
-const double kRK[4][2] = {{0, 0}, {0.0, 1.0}, {0.75, 0.25}, {1.0 / 3.0, 2.0 / 3.0}};
 
 // One full SSP-RK3 step on a single grid (U in/out, layout A; for 2D the
 // B copy of U must be current in ctx->UB).  run = take dt and the epsilon
@@ -1895,11 +1993,26 @@ int pp_cweno_run(pp_cweno_ctx* ctx, double* U, double t_end, int64_t nsteps_max,
     if (!r) r = reduce_state(ctx, U, s->eps[2], s->spd);
     if (!r && c.ndim == 2) r = transpose_2d(ctx, U, ctx->UB);
     if (r) return r;
-    // (dt kernel, step) pairs are launched in batches; the dt kernel retires
-    // the run at t_end or after nsteps_max steps (later launches return at
-    // once), and each batch ends with a host check of the device scalars.
-    int64_t launched = 0;
     Scal host{};
+    if (c.ndim == 1) {
+        // one workgroup runs the line for up to 4096 steps per launch; the
+        // host checks the scalars between launches
+        for (;;) {
+            r = launch_run1d(ctx, U, rule, cfl, t_end, (long long)nsteps_max, 4096);
+            if (r) return r;
+            HIPCHK(ctx, hipMemcpyAsync(&host, s, sizeof(Scal), hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            if (!host.active) break;
+        }
+        if (t_out) *t_out = host.t;
+        if (steps_out) *steps_out = host.steps;
+        if (host.status) return fail(ctx, PP_ESTATE, "a stage left the admissible set or was not finite");
+        return PP_OK;
+    }
+    // 2D: (dt kernel, step) pairs are launched in batches; the dt kernel
+    // retires the run at t_end or after nsteps_max steps (later launches
+    // return at once), and each batch ends with a host check of the scalars.
+    int64_t launched = 0;
     for (;;) {
         const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(64, nsteps_max - launched + 1));
         for (int64_t i = 0; i < batch; ++i, ++launched) {
