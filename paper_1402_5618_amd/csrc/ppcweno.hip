@@ -255,16 +255,18 @@ constexpr int kCHP = 16;   // paired FP64 path: rows per lane and side
 //  separator system.  The smoothness indicators of cell j serve both rows of
 //  cell j; the "+" weights are the "-" weight products in mirrored order.
 // On return E0[j] = x_{r0+j}, F0[j] = y_{r0+j}.  All threads of the block
-// must call.
+// must call.  FULL: every lane holds exactly kCHP rows (n = kCHP P), so the
+// row guards of the unrolled loops vanish and each pass is one basic block.
+template <bool FULL>
 __device__ __forceinline__ void paired_solve(const double* __restrict__ sUc, int n, int k, int P,
                                              bool cyclic, double weps, double* sxc, double* cl,
                                              int r0,
                                              int len, double (&E0)[kCHP], double (&E1)[kCHP],
                                              double (&E2)[kCHP], double (&F0)[kCHP],
                                              double (&F1)[kCHP], double (&F2)[kCHP]) {
-    const double k13 = 13.0 / 12.0, third = 1.0 / 3.0, sixth = 1.0 / 6.0;
+    const double k13 = 13.0 / 12.0;
     const bool act = k < P;
-    const int L = len;
+    const int L = FULL ? kCHP : len;
     // cell average of cell r0 + rel (rel >= -3)
     auto vrel = [&](int rel) -> double { return sUc[padn<4>(r0 + rel + kNG)]; };
     auto vabs = [&](int m) -> double { return sUc[padn<4>(m + kNG)]; };
@@ -316,16 +318,20 @@ __device__ __forceinline__ void paired_solve(const double* __restrict__ sUc, int
                 const double G0 = (e0 + tt) * (e1 * e2);
                 const double G1 = (e1 + tt) * (e0 * e2);
                 const double G2 = (e2 + tt) * (e0 * e1);
-                // "-" weights (0.2, 0.5, 0.3) on (G0, G1, G2); "+" on (G2, G1, G0)
+                // "-" weights (0.2, 0.5, 0.3) on (G0, G1, G2); "+" on (G2, G1, G0).
+                // The "-" rows are built from the unnormalised weights, times
+                // 6: a row's scale cancels in its own pivot (chase, back
+                // substitution and separator reduction alike), so that weight
+                // sum is never divided out.  The "+" weights are normalised
+                // (two of them are kept for pass 2, w1 = 1 - w0 - w2).
                 const double am0 = 0.2 * G0, am1 = 0.5 * G1, am2 = 0.3 * G2;
                 const double ap0 = 0.2 * G2, ap2 = 0.3 * G0;
-                const double im = rcp_pos(am0 + am1 + am2), ipw = rcp_pos(ap0 + am1 + ap2);
-                const double w0 = am0 * im, w1 = am1 * im, w2 = am2 * im;
-                F0[j] = ap0 * ipw;   // "+" w0; its w1 is recovered as 1 - w0 - w2
+                const double ipw = rcp_pos(ap0 + am1 + ap2);
+                F0[j] = ap0 * ipw;
                 F2[j] = ap2 * ipw;
-                double a = (2.0 * w0 + w1) * third, bb = (w0 + 2.0 * (w1 + w2)) * third;
-                double c = w2 * third;
-                double r = (w0 * v1 + (5.0 * (w0 + w1) + w2) * v2 + (w1 + 5.0 * w2) * v3) * sixth;
+                double a = 4.0 * am0 + 2.0 * am1, bb = 2.0 * am0 + 4.0 * (am1 + am2);
+                double c = 2.0 * am2;
+                double r = am0 * v1 + (5.0 * (am0 + am1) + am2) * v2 + (am1 + 5.0 * am2) * v3;
                 if (j < L - 1) {
                     const double piv = (j == 0) ? bb : bb - a * cprev;
                     const double ip = rcp_pos(piv);
@@ -368,9 +374,10 @@ __device__ __forceinline__ void paired_solve(const double* __restrict__ sUc, int
                 const int g = r0 + j;
                 const double vl = vrel(j - 1);
                 const double w0 = F0[j], w2 = F2[j], w1 = 1.0 - w0 - w2;
-                double a = (2.0 * w0 + w1) * third, bb = (w0 + 2.0 * (w1 + w2)) * third;
-                double c = w2 * third;
-                double r = (w0 * vr + (5.0 * (w0 + w1) + w2) * vc + (w1 + 5.0 * w2) * vl) * sixth;
+                // (rows times 6, like the "-" rows)
+                double a = 4.0 * w0 + 2.0 * w1, bb = 2.0 * w0 + 4.0 * (w1 + w2);
+                double c = 2.0 * w2;
+                double r = w0 * vr + (5.0 * (w0 + w1) + w2) * vc + (w1 + 5.0 * w2) * vl;
                 if (j > 0) {
                     const bool first = (j == L - 1);
                     const double piv = first ? bb : bb - a * cprev;
@@ -511,35 +518,57 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
 
     // ---- phase 0: stage the line with ghosts; limiter epsilon
     double mr = INFINITY, me = INFINITY;
-    for (int q = tid; q < n + 2 * kNG; q += NT) {
+    // KL slots per thread and round: every load of a round is in flight
+    // before the first LDS store, so the line costs one memory latency
+    constexpr int KL = CPT + 1;
+    // source cell of slot q (cell q - 3); slots past the line read cell 0 and
+    // are not stored, which keeps the loads unconditional (one basic block)
+    auto src_of = [&](int q, bool& flip) -> int {
         const int i = q - kNG;   // cell index, -3..n+2
-        int src;
-        double sgn[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) sgn[c] = 1.0;
+        int src = 0;
+        flip = false;
         if (i >= 0 && i < n) {
             src = i;
-        } else if (cyclic) {
-            src = (i + n) % n;
-        } else {
-            const int bc = i < 0 ? bc_lo : bc_hi;
-            if (bc == PP_BC_TRANSMISSIVE) {
-                src = i < 0 ? 0 : n - 1;
-            } else {   // reflective: mirror image, normal momentum negated
-                src = i < 0 ? (-i - 1) : (2 * n - 1 - i);
-                src = src < 0 ? 0 : (src >= n ? n - 1 : src);
-                sgn[NRM] = -1.0;
+        } else if (q < n + 2 * kNG) {
+            if (cyclic) {
+                src = (i + n) % n;
+            } else {
+                const int bc = i < 0 ? bc_lo : bc_hi;
+                if (bc == PP_BC_TRANSMISSIVE) {
+                    src = i < 0 ? 0 : n - 1;
+                } else {   // reflective: mirror image, normal momentum negated
+                    src = i < 0 ? (-i - 1) : (2 * n - 1 - i);
+                    src = src < 0 ? 0 : (src >= n ? n - 1 : src);
+                    flip = true;
+                }
             }
         }
-        double cell[NC];
+        return src;
+    };
+    for (int q0 = tid; q0 < n + 2 * kNG; q0 += KL * NT) {
+        double cell[KL][NC];
+        bool flip[KL];
+        int srck[KL];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            cell[c] = U[(long long)c * A.cs + src];
-            sU[c * LP + padn<PSH>(q)] = sgn[c] * cell[c];
-        }
-        if (i >= 0 && i < n && A.eps_enc == nullptr) {
-            mr = fmin(mr, cell[0]);
-            me = fmin(me, spec_e<NC>(cell));
+        for (int kk = 0; kk < KL; ++kk) srck[kk] = src_of(q0 + kk * NT, flip[kk]);
+#pragma unroll
+        for (int kk = 0; kk < KL; ++kk)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) cell[kk][c] = U[(long long)c * A.cs + srck[kk]];
+#pragma unroll
+        for (int kk = 0; kk < KL; ++kk) {
+            const int q = q0 + kk * NT;
+            const int i = q - kNG;
+            if (q < n + 2 * kNG) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    sU[c * LP + padn<PSH>(q)] =
+                        (c == NRM && flip[kk]) ? -cell[kk][c] : cell[kk][c];
+                if (i >= 0 && i < n && A.eps_enc == nullptr) {
+                    mr = fmin(mr, cell[kk][0]);
+                    me = fmin(me, spec_e<NC>(cell[kk]));
+                }
+            }
         }
     }
     double eps_rho, eps_e;
@@ -566,11 +595,13 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     const int k = tid % PL;
     const int comp = sys >> 1;
     const bool rev = !PAIRED && (sys & 1) != 0;
-    int P = PL;
-    while (P > n) P >>= 1;                  // chunks: power of two, <= n
+    int P = PL, lgP = __builtin_ctz(PL);
+    while (P > n) { P >>= 1; --lgP; }       // chunks: power of two, <= n
     const bool act = k < P;
-    const int r0 = act ? (int)(((long long)k * n) / P) : 0;
-    const int r1 = act ? (int)(((long long)(k + 1) * n) / P) : 0;
+    // chunk bounds floor(k n / P): lines hold at most 4096 cells and k <= P <=
+    // 128, so the product fits 32 bits and the division is a shift
+    const int r0 = act ? (int)(((unsigned)k * (unsigned)n) >> lgP) : 0;
+    const int r1 = act ? (int)(((unsigned)(k + 1) * (unsigned)n) >> lgP) : 0;
     const int len = r1 - r0;
     const int knext = (k + 1) & (P - 1), kprev = (k - 1) & (P - 1);
     const double* sUc = sU + comp * LP;
@@ -596,8 +627,12 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
 
     if constexpr (PAIRED) {
         double* sxc = sx + comp * 1024;   // [8][128] exchange slots of this component
-        paired_solve(sUc, n, k, P, cyclic, A.weno_eps, sxc, red + 4 * comp, r0, len, E0, E1, E2,
-                     F0, F1, F2);
+        if (n == kCHP * P)
+            paired_solve<true>(sUc, n, k, P, cyclic, A.weno_eps, sxc, red + 4 * comp, r0, len, E0,
+                               E1, E2, F0, F1, F2);
+        else
+            paired_solve<false>(sUc, n, k, P, cyclic, A.weno_eps, sxc, red + 4 * comp, r0, len, E0,
+                                E1, E2, F0, F1, F2);
     } else if constexpr (!MIXED) {
         double ae = 0.0, be = 1.0, ce = 0.0, re = 0.0;
         double gP = 0.0, gQ = 1.0, gS = 0.0;   // x_{r1-2} = gP + gQ L + gS R
@@ -826,7 +861,55 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
         const int S = g1 - g0;
         const int left = cyclic ? (g0 - 1 + n) % n : g0 - 1;
         const int right = cyclic ? g1 % n : g1;
-        if (PAIRED && act) {
+        // cell averages for the limiter, slots q = qb + kk NT (cells g0-1 ..
+        // g1).  The host keeps S <= CPT NT, so KL = CPT + 1 slots per thread
+        // cover the segment; the loads are issued before the staging so their
+        // latency overlaps it, and they are unconditional (slots off the line
+        // read cell 0 and are skipped).
+        const int qend = S + (SEG1 ? 1 : 2);
+        const int qb = tid + (SEG1 ? 1 : 0);
+        double Ubk[KL][NC];
+        int cellk[KL];
+#pragma unroll
+        for (int kk = 0; kk < KL; ++kk) {
+            const int q = qb + kk * NT;
+            const int cell = (q == 0) ? left : (q == S + 1 ? right : g0 + q - 1);
+            cellk[kk] = (q < qend && cell >= 0 && cell < n) ? cell : -1;
+            const int src = cellk[kk] >= 0 ? cell : 0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) Ubk[kk][c] = U[(long long)c * A.cs + src];
+        }
+        static_assert(kCHP == 16, "the paired path pads one slot per 16 rows");
+        if (PAIRED && SEG1 && act && n == kCHP * P) {
+            // every lane holds 16 cells of the one segment: slot padn<4>(16 k
+            // + j + 1) = 17 k + padn<4>(j + 1); periodic ghost slots 0 and
+            // n + 1 take cells n - 1 (last lane) and 0 (lane 0)
+            double* rowm = sRes + (2 * comp) * SS;
+            double* rowp = rowm + SS;
+            double* bm = rowm + 17 * k;
+            double* bp = rowp + 17 * k;
+#pragma unroll
+            for (int j = 0; j < CHP; ++j) {
+                bm[padn<4>(j + 1)] = E0[j];
+                bp[padn<4>(j + 1)] = F0[j];
+            }
+            if (cyclic && k == 0) {
+                rowm[padn<4>(n + 1)] = E0[0];
+                rowp[padn<4>(n + 1)] = F0[0];
+            }
+            if (cyclic && k == P - 1) {
+                rowm[0] = E0[CHP - 1];
+                rowp[0] = F0[CHP - 1];
+            }
+            if (A.dbg_um) {
+#pragma unroll
+                for (int j = 0; j < CHP; ++j) A.dbg_um[(long long)comp * n + r0 + j] = E0[j];
+            }
+            if (A.dbg_up) {
+#pragma unroll
+                for (int j = 0; j < CHP; ++j) A.dbg_up[(long long)comp * n + r0 + j] = F0[j];
+            }
+        } else if (PAIRED && act) {
             double* rowm = sRes + (2 * comp) * SS;
             double* rowp = rowm + SS;
 #pragma unroll
@@ -875,18 +958,17 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
         __syncthreads();
         // limiter on slots 0..S+1 (cells g0-1 .. g1); a single segment reads its
         // edge neighbours from slots S and 1 instead (periodic) or not at all
-        for (int q = tid + (SEG1 ? 1 : 0); q < S + (SEG1 ? 1 : 2); q += NT) {
-            const int cell = (q == 0) ? left : (q == S + 1 ? right : g0 + q - 1);
-            if (cell < 0 || cell >= n) continue;
-            double Ub[NC], Um[NC], Up[NC];
-            const int pq = padn<PSH>(q);
+#pragma unroll
+        for (int kk = 0; kk < KL; ++kk) {
+            if (cellk[kk] < 0) continue;
+            const int pq = padn<PSH>(qb + kk * NT);
+            double Um[NC], Up[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                Ub[c] = U[(long long)c * A.cs + cell];
                 Um[c] = sRes[(2 * c) * SS + pq];
                 Up[c] = sRes[(2 * c + 1) * SS + pq];
             }
-            pp_limit<NC>(A.w1, A.i12, eps_rho, eps_e, Ub, Um, Up);
+            pp_limit<NC>(A.w1, A.i12, eps_rho, eps_e, Ubk[kk], Um, Up);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 sRes[(2 * c) * SS + pq] = Um[c];
@@ -924,10 +1006,6 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
             } else {
                 hllc_flux<NC, NRM>(A.gamma, Ul, Ur, F);
             }
-            if (A.dbg_flux) {
-#pragma unroll
-                for (int c = 0; c < NC; ++c) A.dbg_flux[(long long)c * (n + 1) + f] = F[c];
-            }
         };
         const bool wrap0 = SEG1 && cyclic;
         const int r_lo = wrap0 ? 1 : 0;
@@ -959,8 +1037,12 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const double Fl = sF[c * FS + ((wrap0 && q == 0) ? S : q)];
-                const double L = -(sF[c * FS + q + 1] - Fl) * ih;
-                if (wrap0 && q == 0 && A.dbg_flux) A.dbg_flux[(long long)c * (n + 1)] = Fl;
+                const double Fr = sF[c * FS + q + 1];
+                const double L = -(Fr - Fl) * ih;
+                if (A.dbg_flux) {   // (kept out of the flux phase: no stores there)
+                    if (q == 0) A.dbg_flux[(long long)c * (n + 1) + g0] = Fl;
+                    A.dbg_flux[(long long)c * (n + 1) + i + 1] = Fr;
+                }
                 const long long at = base + (long long)c * A.cs + i;
                 if (A.mode == 0) {
                     o[c] = L;

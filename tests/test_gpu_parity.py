@@ -42,7 +42,8 @@ def mixed_line(n, seed=0, a=0.0, b=1.0):
 
 
 CASES_1D = [(3, (1, 1)), (5, (0, 0)), (7, (0, 0)), (13, (1, 1)), (64, (0, 0)), (128, (2, 1)),
-            (200, (1, 2)), (777, (2, 2)), (2047, (0, 0)), (2048, (0, 0)), (2049, (1, 1)),
+            (200, (1, 2)), (777, (2, 2)), (2047, (0, 0)), (2048, (0, 0)), (2048, (1, 2)), (2048, (2, 2)),
+            (2049, (1, 1)),
             (4000, (1, 1)), (4096, (2, 2))]
 
 
