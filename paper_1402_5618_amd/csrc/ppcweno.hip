@@ -481,7 +481,10 @@ __device__ __forceinline__ void rows_from_w(float w0, float w2, float& a, float&
 // CPT cells per thread in phase 2, SEG1 = the line is one phase-2 segment,
 // MIXED = float reconstruction/solve with one FP64-residual refinement
 // sweep and a float HLLC (limiter and accumulation stay double).
-template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED>
+// LOOPED: the caller runs line_op in a loop; the thread index is then passed
+// through an empty asm so that values derived from it are recomputed per
+// line rather than hoisted out of the loop and kept (spilled) across the solve.
+template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED, bool LOOPED = false>
 __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) {
     constexpr int NS = 2 * NC;
     constexpr int LANES = 64 * W;
@@ -489,7 +492,8 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     // FP64 lines of up to 2048 cells: both sides of a component per lane
     constexpr bool PAIRED = !MIXED && W == 1;
     constexpr int PSH = PAIRED ? 4 : 5;   // chunk stride 16 (paired) or 32 rows
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
+    if constexpr (LOOPED) asm volatile("" : "+v"(tid));
 
     // ---- problem geometry
     const bool batched = A.off != nullptr;
@@ -1109,13 +1113,20 @@ template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED>
 __global__ void __launch_bounds__(2 * NC * 64 * W) line_kernel_persistent(LineArgs A) {
     extern __shared__ double smem[];
     __shared__ int next;
+    typedef __attribute__((address_space(4))) const LineArgs KArgs;
     for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(A.counter, 1);
+        // the arguments are re-read from the kernel-argument segment for every
+        // problem (the empty asm hides that they are loop invariant), so they
+        // are not hoisted into registers that would live across the solve
+        KArgs* ap = (KArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+        asm volatile("" : "+s"(ap));
+        const LineArgs& Ai = *(const LineArgs*)ap;
+        if (threadIdx.x == 0) next = atomicAdd(Ai.counter, 1);
         __syncthreads();
         const int q = next;
         __syncthreads();
-        if (q >= A.nlines) break;
-        line_op<NC, NRM, W, CPT, SEG1, MIXED>(A, A.order[q], smem);
+        if (q >= Ai.nlines) break;
+        line_op<NC, NRM, W, CPT, SEG1, MIXED, true>(Ai, Ai.order[q], smem);
         __syncthreads();
     }
 }
@@ -1405,7 +1416,12 @@ __global__ void __launch_bounds__(2 * NC * 64 * W) run1d_kernel(RunArgs R) {
         if (!s->active) break;
 #pragma unroll 1
         for (int st = 0; st < 3; ++st) {   // one copy of the operator, stage args by index
-            line_op<NC, NRM, W, CPT, SEG1, MIXED>(R.st[st], 0, smem);
+            // stage arguments re-read from the kernel-argument segment each
+            // time (see line_kernel_persistent)
+            typedef __attribute__((address_space(4))) const RunArgs KArgs;
+            KArgs* rp = (KArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+            asm volatile("" : "+s"(rp));
+            line_op<NC, NRM, W, CPT, SEG1, MIXED, true>(((const RunArgs*)rp)->st[st], 0, smem);
             __syncthreads();
         }
     }
@@ -1456,10 +1472,15 @@ struct pp_cweno_ctx {
     // largest dynamic LDS size already granted to each kernel (the attribute
     // call is a driver round trip, not to be paid on every launch)
     std::unordered_map<const void*, size_t> lds_granted;
-    // measurement: event pairs around kernel launches, per class
+    // measurement: event pairs around kernel launches, per class.  Within a
+    // run of back-to-back timed launches (chaining) a launch's begin event is
+    // the previous launch's end event, so each launch adds one record.
     bool timing = false;
-    std::vector<hipEvent_t> ev[3];
+    std::vector<hipEvent_t> ev[3];    // own events: 2 i (begin), 2 i + 1 (end)
+    std::vector<hipEvent_t> beg[3];   // begin event used by launch i
     int nev[3] = {0, 0, 0};
+    bool chaining = false;
+    hipEvent_t chain = nullptr;       // end event of the last launch, if chaining
 };
 
 namespace {
@@ -1487,20 +1508,51 @@ constexpr int kMaxTimed = 4096;
 // Record the start event of a timed launch of class k (0 x-lines, 1 y-lines,
 // 2 combine); returns the slot or -1.
 int timed_begin(pp_cweno_ctx* ctx, int k) {
-    if (!ctx->timing || ctx->nev[k] >= kMaxTimed) return -1;
-    const int i = ctx->nev[k]++;
+    if (!ctx->timing || ctx->nev[k] >= kMaxTimed) {
+        ctx->chain = nullptr;
+        return -1;
+    }
+    const int i = ctx->nev[k];
     while ((int)ctx->ev[k].size() < 2 * (i + 1)) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return -1;
+        if (hipEventCreate(&e) != hipSuccess) {
+            ctx->chain = nullptr;
+            return -1;
+        }
         ctx->ev[k].push_back(e);
     }
-    (void)hipEventRecord(ctx->ev[k][2 * i], ctx->stream);
+    if ((int)ctx->beg[k].size() < i + 1) ctx->beg[k].resize(i + 1);
+    ctx->nev[k] = i + 1;
+    if (ctx->chaining && ctx->chain) {
+        ctx->beg[k][i] = ctx->chain;   // nothing was enqueued since it was recorded
+    } else {
+        (void)hipEventRecord(ctx->ev[k][2 * i], ctx->stream);
+        ctx->beg[k][i] = ctx->ev[k][2 * i];
+    }
     return i;
 }
 
 void timed_end(pp_cweno_ctx* ctx, int k, int i) {
-    if (i >= 0) (void)hipEventRecord(ctx->ev[k][2 * i + 1], ctx->stream);
+    if (i < 0) {
+        ctx->chain = nullptr;
+        return;
+    }
+    (void)hipEventRecord(ctx->ev[k][2 * i + 1], ctx->stream);
+    ctx->chain = ctx->chaining ? ctx->ev[k][2 * i + 1] : nullptr;
 }
+
+// Scope of back-to-back timed launches (nothing else enqueued in between).
+struct TimedChain {
+    pp_cweno_ctx* ctx;
+    explicit TimedChain(pp_cweno_ctx* c) : ctx(c) {
+        ctx->chaining = true;
+        ctx->chain = nullptr;
+    }
+    ~TimedChain() {
+        ctx->chaining = false;
+        ctx->chain = nullptr;
+    }
+};
 
 // Dynamic LDS of the line kernel for lines of up to nmax cells.
 template <int NC, int W, bool MIXED>
@@ -1771,6 +1823,7 @@ int step_single(pp_cweno_ctx* ctx, double* U, const double* dt_dev, double dt_va
     const double* inB[3] = {ctx->UB, ctx->U1B, ctx->U2B};
     double* outA[3] = {ctx->U1, ctx->U2, U};
     double* outB[3] = {ctx->U1B, ctx->U2B, ctx->UB};
+    TimedChain chain(ctx);   // x, y, combine of each stage: nine launches in a row
     for (int st = 1; st <= 3; ++st) {
         const int in_slot = (st + 1) % 3;
         const int out_slot = st - 1;
@@ -2328,7 +2381,7 @@ int pp_cweno_get_timing(pp_cweno_ctx* ctx, double* out) {
         double tot = 0.0;
         for (int i = 0; i < ctx->nev[k]; ++i) {
             float ms = 0.0f;
-            HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[k][2 * i], ctx->ev[k][2 * i + 1]));
+            HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->beg[k][i], ctx->ev[k][2 * i + 1]));
             tot += ms;
         }
         out[2 * k] = tot;
