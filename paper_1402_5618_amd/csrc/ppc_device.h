@@ -44,6 +44,22 @@ __device__ __forceinline__ double rcp_pos(double x) {
     e = fma(-x, r, 1.0);
     return fma(r, e, r);
 }
+// Square root of a non-negative value (sound speeds, density ratios, the
+// limiter's discriminant): the hardware reciprocal-square-root estimate, one
+// Goldschmidt iteration for sqrt(x) and 1/(2 sqrt(x)) together, then one
+// residual correction g += (x - g^2) h (Markstein's formulation).  x = 0
+// returns 0.  Arguments below 2^-767 are outside its design range (the
+// products would lose precision); none arise from physical states here.
+__device__ __forceinline__ double sqrt_nn(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    return x > 0.0 ? g : x;
+}
 __device__ __forceinline__ float rcp_t(float x) {
     const float r0 = __builtin_amdgcn_rcpf(x);
     const float e = fmaf(-x, r0, 1.0f);
@@ -162,12 +178,12 @@ __device__ __forceinline__ void hllc_flux(double g, const double (&Ul)[NC], cons
     const double El = Ul[IE], Er = Ur[IE];
     const double pl = (g - 1.0) * (El - 0.5 * rl * (ul * ul + vl * vl));
     const double pr = (g - 1.0) * (Er - 0.5 * rr * (ur * ur + vr * vr));
-    const double al = sqrt(g * fmax(pl, 0.0) * irl), ar = sqrt(g * fmax(pr, 0.0) * irr);
+    const double al = sqrt_nn(g * fmax(pl, 0.0) * irl), ar = sqrt_nn(g * fmax(pr, 0.0) * irr);
     const double Hl = (El + pl) * irl, Hr = (Er + pr) * irr;
-    const double R = sqrt(rr * irl);
+    const double R = sqrt_nn(rr * irl);
     const double i1R = rcp_t(1.0 + R);
     const double ut = (ul + ur * R) * i1R, vt = (vl + vr * R) * i1R, Ht = (Hl + Hr * R) * i1R;
-    const double at = sqrt(fmax((g - 1.0) * (Ht - 0.5 * (ut * ut + vt * vt)), 0.0));
+    const double at = sqrt_nn(fmax((g - 1.0) * (Ht - 0.5 * (ut * ut + vt * vt)), 0.0));
     const double SL = fmin(ul - al, ut - at);
     const double SR = fmax(ur + ar, ut + at);
     const double den = rr * (SR - ur) - rl * (SL - ul);
@@ -318,7 +334,7 @@ __device__ __forceinline__ double pp_root(double eps, const double (&Ub)[NC],
     const double C = Ub[0] * Ub[IE] - 0.5 * m2 - eps * Ub[0] * Ub[0];
     if (C <= 0.0) return 0.0;
     const double disc = fmax(B * B - 4.0 * A * C, 0.0);
-    double t = 2.0 * C / (-B + sqrt(disc));
+    double t = 2.0 * C / (-B + sqrt_nn(disc));
     if (!(t >= 0.0)) t = 0.0;
     return fmin(t, 1.0);
 }
@@ -366,7 +382,7 @@ __device__ __forceinline__ double wave_speed(double g, const double (&U)[NC]) {
     for (int k = 1; k < NC - 1; ++k) m2 += U[k] * U[k];
     const double ir = rcp_t(U[0]);
     const double p = (g - 1.0) * (U[NC - 1] - 0.5 * m2 * ir);
-    return fabs(U[NRM] * ir) + sqrt(g * fmax(p, 0.0) * ir);
+    return fabs(U[NRM] * ir) + sqrt_nn(g * fmax(p, 0.0) * ir);
 }
 
 }  // namespace ppc
