@@ -522,57 +522,35 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
 
     // ---- phase 0: stage the line with ghosts; limiter epsilon
     double mr = INFINITY, me = INFINITY;
-    // KL slots per thread and round: every load of a round is in flight
-    // before the first LDS store, so the line costs one memory latency
-    constexpr int KL = CPT + 1;
-    // source cell of slot q (cell q - 3); slots past the line read cell 0 and
-    // are not stored, which keeps the loads unconditional (one basic block)
-    auto src_of = [&](int q, bool& flip) -> int {
+    for (int q = tid; q < n + 2 * kNG; q += NT) {
         const int i = q - kNG;   // cell index, -3..n+2
-        int src = 0;
-        flip = false;
+        int src;
+        double sgn[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sgn[c] = 1.0;
         if (i >= 0 && i < n) {
             src = i;
-        } else if (q < n + 2 * kNG) {
-            if (cyclic) {
-                src = (i + n) % n;
-            } else {
-                const int bc = i < 0 ? bc_lo : bc_hi;
-                if (bc == PP_BC_TRANSMISSIVE) {
-                    src = i < 0 ? 0 : n - 1;
-                } else {   // reflective: mirror image, normal momentum negated
-                    src = i < 0 ? (-i - 1) : (2 * n - 1 - i);
-                    src = src < 0 ? 0 : (src >= n ? n - 1 : src);
-                    flip = true;
-                }
+        } else if (cyclic) {
+            src = (i + n) % n;
+        } else {
+            const int bc = i < 0 ? bc_lo : bc_hi;
+            if (bc == PP_BC_TRANSMISSIVE) {
+                src = i < 0 ? 0 : n - 1;
+            } else {   // reflective: mirror image, normal momentum negated
+                src = i < 0 ? (-i - 1) : (2 * n - 1 - i);
+                src = src < 0 ? 0 : (src >= n ? n - 1 : src);
+                sgn[NRM] = -1.0;
             }
         }
-        return src;
-    };
-    for (int q0 = tid; q0 < n + 2 * kNG; q0 += KL * NT) {
-        double cell[KL][NC];
-        bool flip[KL];
-        int srck[KL];
+        double cell[NC];
 #pragma unroll
-        for (int kk = 0; kk < KL; ++kk) srck[kk] = src_of(q0 + kk * NT, flip[kk]);
-#pragma unroll
-        for (int kk = 0; kk < KL; ++kk)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) cell[kk][c] = U[(long long)c * A.cs + srck[kk]];
-#pragma unroll
-        for (int kk = 0; kk < KL; ++kk) {
-            const int q = q0 + kk * NT;
-            const int i = q - kNG;
-            if (q < n + 2 * kNG) {
-#pragma unroll
-                for (int c = 0; c < NC; ++c)
-                    sU[c * LP + padn<PSH>(q)] =
-                        (c == NRM && flip[kk]) ? -cell[kk][c] : cell[kk][c];
-                if (i >= 0 && i < n && A.eps_enc == nullptr) {
-                    mr = fmin(mr, cell[kk][0]);
-                    me = fmin(me, spec_e<NC>(cell[kk]));
-                }
-            }
+        for (int c = 0; c < NC; ++c) {
+            cell[c] = U[(long long)c * A.cs + src];
+            sU[c * LP + padn<PSH>(q)] = sgn[c] * cell[c];
+        }
+        if (i >= 0 && i < n && A.eps_enc == nullptr) {
+            mr = fmin(mr, cell[0]);
+            me = fmin(me, spec_e<NC>(cell));
         }
     }
     double eps_rho, eps_e;
@@ -865,24 +843,6 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
         const int S = g1 - g0;
         const int left = cyclic ? (g0 - 1 + n) % n : g0 - 1;
         const int right = cyclic ? g1 % n : g1;
-        // cell averages for the limiter, slots q = qb + kk NT (cells g0-1 ..
-        // g1).  The host keeps S <= CPT NT, so KL = CPT + 1 slots per thread
-        // cover the segment; the loads are issued before the staging so their
-        // latency overlaps it, and they are unconditional (slots off the line
-        // read cell 0 and are skipped).
-        const int qend = S + (SEG1 ? 1 : 2);
-        const int qb = tid + (SEG1 ? 1 : 0);
-        double Ubk[KL][NC];
-        int cellk[KL];
-#pragma unroll
-        for (int kk = 0; kk < KL; ++kk) {
-            const int q = qb + kk * NT;
-            const int cell = (q == 0) ? left : (q == S + 1 ? right : g0 + q - 1);
-            cellk[kk] = (q < qend && cell >= 0 && cell < n) ? cell : -1;
-            const int src = cellk[kk] >= 0 ? cell : 0;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) Ubk[kk][c] = U[(long long)c * A.cs + src];
-        }
         static_assert(kCHP == 16, "the paired path pads one slot per 16 rows");
         if (PAIRED && SEG1 && act && n == kCHP * P) {
             // every lane holds 16 cells of the one segment: slot padn<4>(16 k
@@ -962,17 +922,18 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
         __syncthreads();
         // limiter on slots 0..S+1 (cells g0-1 .. g1); a single segment reads its
         // edge neighbours from slots S and 1 instead (periodic) or not at all
-#pragma unroll
-        for (int kk = 0; kk < KL; ++kk) {
-            if (cellk[kk] < 0) continue;
-            const int pq = padn<PSH>(qb + kk * NT);
-            double Um[NC], Up[NC];
+        for (int q = tid + (SEG1 ? 1 : 0); q < S + (SEG1 ? 1 : 2); q += NT) {
+            const int cell = (q == 0) ? left : (q == S + 1 ? right : g0 + q - 1);
+            if (cell < 0 || cell >= n) continue;
+            double Ub[NC], Um[NC], Up[NC];
+            const int pq = padn<PSH>(q);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
+                Ub[c] = U[(long long)c * A.cs + cell];
                 Um[c] = sRes[(2 * c) * SS + pq];
                 Up[c] = sRes[(2 * c + 1) * SS + pq];
             }
-            pp_limit<NC>(A.w1, A.i12, eps_rho, eps_e, Ubk[kk], Um, Up);
+            pp_limit<NC>(A.w1, A.i12, eps_rho, eps_e, Ub, Um, Up);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 sRes[(2 * c) * SS + pq] = Um[c];
@@ -1010,6 +971,10 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
             } else {
                 hllc_flux<NC, NRM>(A.gamma, Ul, Ur, F);
             }
+            if (A.dbg_flux) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) A.dbg_flux[(long long)c * (n + 1) + f] = F[c];
+            }
         };
         const bool wrap0 = SEG1 && cyclic;
         const int r_lo = wrap0 ? 1 : 0;
@@ -1041,12 +1006,8 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const double Fl = sF[c * FS + ((wrap0 && q == 0) ? S : q)];
-                const double Fr = sF[c * FS + q + 1];
-                const double L = -(Fr - Fl) * ih;
-                if (A.dbg_flux) {   // (kept out of the flux phase: no stores there)
-                    if (q == 0) A.dbg_flux[(long long)c * (n + 1) + g0] = Fl;
-                    A.dbg_flux[(long long)c * (n + 1) + i + 1] = Fr;
-                }
+                const double L = -(sF[c * FS + q + 1] - Fl) * ih;
+                if (wrap0 && q == 0 && A.dbg_flux) A.dbg_flux[(long long)c * (n + 1)] = Fl;
                 const long long at = base + (long long)c * A.cs + i;
                 if (A.mode == 0) {
                     o[c] = L;
