@@ -46,10 +46,10 @@ FLOPS_PER_SWEEP_CELL = 716.0
 # hash is recorded (profiles/line_kernel_2d_density_wave_2048_fp64.md);
 # otherwise traffic is reported null.
 TRAFFIC_RECORD = {
-    "src_sha256": "0a78c5867b68f0a8111c870f7afaf74a5682ae6299323c6f6e8edb83e726aeca",
+    "src_sha256": "e170f96bdf24eb9a41e6bbe81123a00fffa66cfe34b982dfbe418775edb687cd",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "x": {"fetch_kib": 66232.8, "write_kib": 147492.0},
-    "y": {"fetch_kib": 66166.6, "write_kib": 147479.0},
+    "x": {"fetch_kib": 66992.5, "write_kib": 184320.0},
+    "y": {"fetch_kib": 66881.2, "write_kib": 184320.0},
 }
 
 
