@@ -358,3 +358,34 @@ def test_mirror_symmetry_of_a_reversed_line(bc):
     L = oracle.rhs_1d(U, bc, h=1.0 / n)
     Lr = oracle.rhs_1d(U[:, ::-1] * M, bc[::-1], h=1.0 / n)
     np.testing.assert_allclose(Lr[:, ::-1] * M, L, atol=1e-12 * np.abs(L).max())
+
+
+# ------------------------------------------------- suite input generators
+def test_suite_generators_integrate_the_printed_data():
+    """Exact cell averages: the totals equal the integrals of the paper's
+    piecewise data (Examples 3.2-3.10), so the inputs carry no quadrature
+    error into the GPU suite runs."""
+    import math
+    g = 1.4
+    # Lax on [-5, 5]
+    U = W.lax_1d(200)
+    h = 10.0 / 200
+    assert abs(U[0].sum() * h - (0.445 * 5 + 0.5 * 5)) < 1e-12
+    assert abs(U[1].sum() * h - 0.445 * 0.698 * 5) < 1e-12
+    # Sod (classical data, see the generator's note)
+    U = W.sod_1d(100)
+    assert abs(U[2].sum() * 0.1 - (1.0 / (g - 1) * 5 + 0.1 / (g - 1) * 5)) < 1e-12
+    # Shu-Osher: the sine integrates in closed form
+    U = W.shu_osher_1d(200)
+    h = 10.0 / 200
+    mass = 3.857143 * 1.0 + 9.0 + 0.2 * (math.cos(-20.0) - math.cos(25.0)) / 5.0
+    assert abs(U[0].sum() * h - mass) < 1e-12
+    # a cell that straddles x = -4 (n = 190: edges at -5 + k/19) mixes both pieces
+    U = W.shu_osher_1d(190)
+    assert np.all(np.isfinite(U)) and U[1].max() <= 3.857143 * 2.629369 + 1e-12
+    # LeBlanc: p = (gamma - 1) rho e with gamma = 5/3
+    U = W.leblanc_1d(400)
+    assert abs(U[2][0] - (1.0 * 0.1)) < 1e-15 and abs(U[2][-1] - 1e-3 * 1e-7) < 1e-22
+    # Woodward-Colella: total energy of the three pressure slabs
+    U = W.woodward_colella_1d(200)
+    assert abs(U[2].sum() / 200 - (1000 * 0.1 + 0.01 * 0.8 + 100 * 0.1) / (g - 1)) < 1e-9

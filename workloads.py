@@ -91,6 +91,66 @@ def riemann_1d(a, b, n, x0, left, right, gamma=1.4):
     return piecewise_1d(a, b, n, [(a, x0) + tuple(left), (x0, b) + tuple(right)], gamma)
 
 
+def lax_1d(n: int = 200, gamma: float = 1.4) -> np.ndarray:
+    """Example 3.2 (Lax shock tube) on [-5, 5]: (0.445, 0.698, 3.528) |
+    (0.5, 0, 0.571), interface at x = 0; run to t = 1.4, Neumann ends."""
+    return riemann_1d(-5.0, 5.0, n, 0.0, (0.445, 0.698, 3.528), (0.5, 0.0, 0.571), gamma)
+
+
+def sod_1d(n: int = 100, gamma: float = 1.4) -> np.ndarray:
+    """Example 3.3 (Sod shock tube) on [-5, 5], run to t = 2.  The printed
+    states, (0.125, 0, 1) | (1, 0, 1), have equal pressures and no velocity
+    (a stationary contact only), which contradicts the waves the example
+    describes (a left rarefaction, a right contact and shock); the classical
+    data of the cited survey, (1, 0, 1) | (0.125, 0, 0.1), produce them and
+    are used."""
+    return riemann_1d(-5.0, 5.0, n, 0.0, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), gamma)
+
+
+def shu_osher_1d(n: int = 200, gamma: float = 1.4) -> np.ndarray:
+    """Example 3.4 (Mach 3 shock / entropy wave) on [-5, 5], run to t = 1.8:
+    (3.857143, 2.629369, 10.33333) for x < -4, then rho = 1 + 0.2 sin(5x),
+    u = 0, p = 1.  Exact cell averages (the sine integrates in closed form)."""
+    h = 10.0 / n
+    edges = -5.0 + np.arange(n + 1) * h
+    lo, hi = edges[:-1], edges[1:]
+    wl = np.clip(np.minimum(hi, -4.0) - lo, 0.0, None)          # length left of -4
+    a = np.maximum(lo, -4.0)                                     # right piece [a, hi]
+    wr = np.clip(hi - a, 0.0, None)
+    sin_int = np.where(wr > 0, (np.cos(5.0 * a) - np.cos(5.0 * hi)) / 5.0, 0.0)
+    L = prim_to_cons_1d(3.857143, 2.629369, 10.33333, gamma)
+    rho = (wl * L[0] + wr + 0.2 * sin_int) / h
+    mom = wl * L[1] / h
+    E = (wl * L[2] + wr * (1.0 / (gamma - 1.0))) / h
+    return np.stack([rho, mom, E])
+
+
+def woodward_colella_1d(n: int = 200, gamma: float = 1.4) -> np.ndarray:
+    """Example 3.5 (interacting blast waves) on [0, 1], reflective walls, run
+    to t = 0.038: p = 1000 | 0.01 | 100 with rho = 1, u = 0."""
+    return piecewise_1d(0.0, 1.0, n, [(0.0, 0.1, 1.0, 0.0, 1000.0), (0.1, 0.9, 1.0, 0.0, 0.01),
+                                      (0.9, 1.0, 1.0, 0.0, 100.0)], gamma)
+
+
+def low_density_123_1d(n: int = 400, gamma: float = 1.4) -> np.ndarray:
+    """Example 3.6 on [0, 1] (h = 0.0025), run to t = 0.1:
+    (1, -2, 0.4) | (1, 2, 0.4)."""
+    return riemann_1d(0.0, 1.0, n, 0.5, (1.0, -2.0, 0.4), (1.0, 2.0, 0.4), gamma)
+
+
+def strong_shock_1d(n: int = 200, gamma: float = 1.4) -> np.ndarray:
+    """Example 3.7 on [0, 1], run to t = 2.5e-6: (1, 0, 1e10) | (0.125, 0, 0.1)."""
+    return riemann_1d(0.0, 1.0, n, 0.5, (1.0, 0.0, 1e10), (0.125, 0.0, 0.1), gamma)
+
+
+def leblanc_1d(n: int = 400, gamma: float = 5.0 / 3.0) -> np.ndarray:
+    """Example 3.10 on [0, 9] with gamma = 5/3, run to t = 6: (rho, u, e) =
+    (1, 0, 0.1) | (1e-3, 0, 1e-7) at x = 3, so p = (gamma - 1) rho e."""
+    g = gamma
+    return piecewise_1d(0.0, 9.0, n, [(0.0, 3.0, 1.0, 0.0, (g - 1.0) * 1.0 * 0.1),
+                                      (3.0, 9.0, 1e-3, 0.0, (g - 1.0) * 1e-3 * 1e-7)], g)
+
+
 def double_rarefaction_1d(n: int = 4000, gamma: float = 1.4) -> np.ndarray:
     """Example 3.8 on [-1, 1]: (7, -1, 0.2) | (7, +1, 0.2) (right-state sign as
     in the problem's name: two rarefactions moving apart)."""
