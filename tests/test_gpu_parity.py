@@ -403,10 +403,15 @@ def test_batch_run_matches_oracle_driver():
 
 
 # ------------------------------------------------- full sizes / whole runs
-def test_2d_2048_stage_sampled_parity():
-    """The benchmarked 2048^2 periodic grid, one stage, in the bench's launch
-    configuration; the oracle evaluates sampled cells one by one from the row
-    and column line operators (with the grid-wide limiter epsilon)."""
+@pytest.mark.parametrize("bc", [(0, 0, 0, 0), (1, 2, 2, 1), (2, 2, 1, 1)])
+def test_2d_2048_stage_sampled_parity(bc):
+    """The benchmarked 2048^2 grid, one stage, in the bench's launch
+    configuration (every lane of a line holds 16 rows); the oracle evaluates
+    sampled cells one by one from the row and column line operators (with
+    the grid-wide limiter epsilon).  Periodic as benchmarked, and closed
+    lines with transmissive and reflective ends (closure rows, image states
+    and the normal-momentum sign in both directions), sampled also at the
+    edges."""
     pp = gpu()
     n = 2048
     dx = 2.0 / n
@@ -416,7 +421,8 @@ def test_2d_2048_stage_sampled_parity():
     U[0] += 0.3 * (((xx - 700) ** 2 + (yy - 900) ** 2) < 200 ** 2)
     sx, sy = oracle.max_speed_2d(U)
     dt = (1.0 / 12.0) / (sx / dx + sy / dx)
-    s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=(0, 0, 0, 0))
+    print(f"2048^2 stage parity, bc {bc}", flush=True)
+    s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=bc)
     Ud = dev(U)
     out = torch.empty_like(Ud)
     s.stage(Ud, Ud, out, 1, dt)
@@ -425,9 +431,13 @@ def test_2d_2048_stage_sampled_parity():
     er, ee = oracle.eps(U)
     rng = np.random.default_rng(5)
     pts = [(int(y), int(x)) for y, x in rng.integers(0, n, size=(12, 2))] + [(900, 500), (700, 700)]
+    if bc[0] != 0:
+        pts += [(0, 0), (0, n - 1), (n - 1, 0), (n - 1, n - 1), (1, 2), (n - 2, n - 3), (1000, 1)]
     for (y, x) in pts:
-        Lx = oracle.line_op(np.ascontiguousarray(U[:, y, :]), 0, 0, dx, eps_rho=er, eps_e=ee, nrm=1)
-        Ly = oracle.line_op(np.ascontiguousarray(U[:, :, x]), 0, 0, dx, eps_rho=er, eps_e=ee, nrm=2)
+        Lx = oracle.line_op(np.ascontiguousarray(U[:, y, :]), bc[0], bc[1], dx, eps_rho=er,
+                            eps_e=ee, nrm=1)
+        Ly = oracle.line_op(np.ascontiguousarray(U[:, :, x]), bc[2], bc[3], dx, eps_rho=er,
+                            eps_e=ee, nrm=2)
         ref = U[:, y, x] + dt * (Lx[:, x] + Ly[:, y])
         scale = np.abs(U).reshape(4, -1).max(axis=1)
         assert np.all(np.abs(got[:, y, x] - ref) <= TOL_STAGE * scale), (y, x)
