@@ -589,3 +589,33 @@ def test_mixed_2d_step_bound_and_conservation():
     assert comp_rel(got, ref) <= TOL_MIXED_STAGE
     np.testing.assert_allclose(got.sum(axis=(1, 2)), U.sum(axis=(1, 2)), rtol=1e-13)
     s.close()
+
+
+def test_2d_timing_events_cover_every_launch():
+    """pp_cweno_set_timing / get_timing on a 2D run: each of the three
+    kernel classes is timed once per stage (three per step), the chained
+    events of a step give positive durations, and their sum fits inside the
+    wall time of the run."""
+    import time
+    pp = gpu()
+    n = 256
+    dx = 2.0 / n
+    U = dev(W.density_wave_2d(n, n))
+    s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=(0, 0, 0, 0))
+    s.run(U, 1e30, 2, 1.0 / 12.0)
+    torch.cuda.synchronize()
+    s.set_timing(True)
+    t0 = time.perf_counter()
+    t, steps = s.run(U, 1e30, 7, 1.0 / 12.0)
+    torch.cuda.synchronize()
+    wall_ms = 1e3 * (time.perf_counter() - t0)
+    tm = s.get_timing()
+    s.set_timing(False)
+    s.close()
+    assert steps == 7
+    # the run launches one retired step beyond the last (it returns at once)
+    for k in ("x", "y", "combine"):
+        ms, launches = tm[k]
+        assert launches in (21, 24), (k, launches)
+        assert ms > 0.0
+    assert sum(ms for ms, _ in tm.values()) < wall_ms
