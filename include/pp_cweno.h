@@ -66,6 +66,15 @@ enum { PP_FP64 = 0, PP_MIXED = 1 };
  * last step is shortened to land on t_end. */
 enum { PP_DT_CFL = 0, PP_DT_H53 = 1 };
 
+/* Numerical flux at the faces.  PP_FLUX_HLLC: eq. (HLLC) with the acoustic
+ * wave speeds (acoustic ws), the default and the paper's scheme.
+ * PP_FLUX_LF: the Lax-Friedrichs flux the paper names as a more dissipative
+ * alternative for the low-density example (Example 3.6; not defined there),
+ * taken in its local form F = (f(U-) + f(U+))/2 - alpha (U+ - U-)/2 with
+ * alpha = max(|u| + a) of the two interface states; evaluated in double in
+ * both precisions. */
+enum { PP_FLUX_HLLC = 0, PP_FLUX_LF = 1 };
+
 typedef struct {
     int ndim;            /* 1, or 2 (dimension-by-dimension sweeps)                    */
     int64_t nx, ny;      /* cells (ny = 1 in 1D); nx <= 4096 in 1D, nx, ny <= 2048 in 2D */
@@ -82,10 +91,11 @@ typedef struct {
     const double *dxs;      /* host [nbatch] spacing per problem (batched only)         */
     const int *bcs;         /* host [nbatch][2] boundary codes (batched; non-periodic)  */
     void *stream;        /* hipStream_t to enqueue on (NULL: the null stream)           */
+    int flux;            /* PP_FLUX_HLLC (default) or PP_FLUX_LF                        */
 } pp_cweno_config;
 
 /* Fill *cfg with defaults: ndim 1, gamma 1.4, epsilons 1e-13, gl_w1 1/12, FP64,
- * periodic, no batch, null stream.  Sizes and spacings are left zero. */
+ * HLLC, periodic, no batch, null stream.  Sizes and spacings are left zero. */
 void pp_cweno_config_defaults(pp_cweno_config *cfg);
 
 /* Validate cfg, allocate device scratch, and return a context in *out

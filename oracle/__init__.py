@@ -36,7 +36,7 @@ class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("eps_cap", ctypes.c_double), ("gl_w1", ctypes.c_double),
                 ("linear", ctypes.c_int), ("first_order", ctypes.c_int),
-                ("limiter", ctypes.c_int)]
+                ("limiter", ctypes.c_int), ("flux", ctypes.c_int)]
 
 
 class LineDbg(ctypes.Structure):
@@ -45,8 +45,11 @@ class LineDbg(ctypes.Structure):
 
 
 def params(gamma=1.4, weno_eps=1e-13, eps_cap=1e-13, gl_w1=1.0 / 12.0, linear=False,
-           first_order=False, limiter=True) -> Params:
-    return Params(gamma, weno_eps, eps_cap, gl_w1, int(linear), int(first_order), int(limiter))
+           first_order=False, limiter=True, flux=0) -> Params:
+    """flux: 0 HLLC (eq. (HLLC)), 1 local Lax-Friedrichs (the alternative the
+    paper names for Example 3.6)."""
+    return Params(gamma, weno_eps, eps_cap, gl_w1, int(linear), int(first_order), int(limiter),
+                  int(flux))
 
 
 _lib = None
@@ -68,6 +71,7 @@ def lib():
             "orc_cyclic": (_I, [_I, _D, _D, _D, _D, _D]),
             "orc_dense_solve": (_I, [_I, _D, _D, _D]),
             "orc_hllc": (None, [_DBL, _I, _I, _D, _D, _D]),
+            "orc_lf": (None, [_DBL, _I, _I, _D, _D, _D]),
             "orc_hllc_speeds": (None, [_DBL, _I, _I, _D, _D, _D]),
             "orc_limit_cell": (_I, [_I, _DBL, _DBL, _DBL, _D, _D, _D]),
             "orc_eps": (None, [_L, _I, _D, _DBL, _D, _D]),
@@ -141,6 +145,14 @@ def hllc(Ul, Ur, gamma=1.4, nrm=1):
     Ul, Ur = _f64(Ul), _f64(Ur)
     F = np.empty_like(Ul)
     lib().orc_hllc(gamma, len(Ul), nrm, _d(Ul), _d(Ur), _d(F))
+    return F
+
+
+def lf(Ul, Ur, gamma=1.4, nrm=1):
+    """Local Lax-Friedrichs flux (the reading of the paper's unnamed form)."""
+    Ul, Ur = _f64(Ul), _f64(Ur)
+    F = np.empty_like(Ul)
+    lib().orc_lf(gamma, len(Ul), nrm, _d(Ul), _d(Ur), _d(F))
     return F
 
 

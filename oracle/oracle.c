@@ -34,6 +34,7 @@ typedef struct {
     int linear;       /* 1: weights forced to (c0,c1,c2): linear scheme, eqs (5th-order1/2) */
     int first_order;  /* 1: no reconstruction, U+- = cell average: scheme (1DEulerFV-First) */
     int limiter;      /* 1: apply the positivity-preserving limiter */
+    int flux;         /* 0: HLLC, eq. (HLLC); 1: local Lax-Friedrichs (see lf below) */
 } orc_params;
 
 /* Optional per-line intermediate results for tests (any pointer may be NULL). */
@@ -376,6 +377,32 @@ static void hllc(double g, int ncomp, int nrm, const double *Ul, const double *U
     }
 }
 
+/* Lax-Friedrichs flux, which the paper names (Example 3.6) as a more
+ * dissipative alternative to HLLC without defining it.  Reading: the local
+ * form, F = (f(Ul) + f(Ur))/2 - alpha (Ur - Ul)/2 with alpha the larger of
+ * |u| + a over the two states; sound speeds from max(p, 0) as in HLLC. */
+static void lf(double g, int ncomp, int nrm, const double *Ul, const double *Ur, double *F)
+{
+    int ie = ncomp - 1, tg = (ncomp == 4) ? 3 - nrm : -1;
+    double rl = Ul[0], ul = Ul[nrm] / rl, vl = tg > 0 ? Ul[tg] / rl : 0.0, El = Ul[ie];
+    double rr = Ur[0], ur = Ur[nrm] / rr, vr = tg > 0 ? Ur[tg] / rr : 0.0, Er = Ur[ie];
+    double pl = (g - 1.0) * (El - 0.5 * rl * (ul * ul + vl * vl));
+    double pr = (g - 1.0) * (Er - 0.5 * rr * (ur * ur + vr * vr));
+    double al = sqrt(g * fmax(pl, 0.0) / rl), ar = sqrt(g * fmax(pr, 0.0) / rr);
+    double alpha = fmax(fabs(ul) + al, fabs(ur) + ar);
+    double Fl[4], Fr[4];
+    Fl[0] = rl * ul; Fl[nrm] = rl * ul * ul + pl; Fl[ie] = ul * (El + pl);
+    Fr[0] = rr * ur; Fr[nrm] = rr * ur * ur + pr; Fr[ie] = ur * (Er + pr);
+    if (tg > 0) { Fl[tg] = rl * ul * vl; Fr[tg] = rr * ur * vr; }
+    for (int k = 0; k < ncomp; ++k) F[k] = 0.5 * (Fl[k] + Fr[k]) - 0.5 * alpha * (Ur[k] - Ul[k]);
+}
+
+/* Exported for unit tests. */
+void orc_lf(double gamma, int ncomp, int nrm, const double *Ul, const double *Ur, double *F)
+{
+    lf(gamma, ncomp, nrm, Ul, Ur, F);
+}
+
 /* Exported for unit tests. */
 void orc_hllc(double gamma, int ncomp, int nrm, const double *Ul, const double *Ur, double *F)
 {
@@ -607,7 +634,10 @@ long orc_line_op(int n, int ncomp, int nrm, const double *u, int bc_lo, int bc_h
                 Ur[k] = (bc_hi == 2 && k == nrm) ? -Ul[k] : Ul[k];
             }
         }
-        hllc(P->gamma, ncomp, nrm, Ul, Ur, Ff);
+        if (P->flux == 1)
+            lf(P->gamma, ncomp, nrm, Ul, Ur, Ff);
+        else
+            hllc(P->gamma, ncomp, nrm, Ul, Ur, Ff);
         for (int k = 0; k < ncomp; ++k) F[(size_t)k * (n + 1) + f] = Ff[k];
     }
 

@@ -18,6 +18,7 @@ PP_OK, PP_EINVAL, PP_ENOMEM, PP_EDEVICE, PP_ESTATE, PP_EUNSUPPORTED = 0, -1, -2,
 PP_BC_PERIODIC, PP_BC_TRANSMISSIVE, PP_BC_REFLECTIVE = 0, 1, 2
 PP_FP64, PP_MIXED = 0, 1
 PP_DT_CFL, PP_DT_H53 = 0, 1
+PP_FLUX_HLLC, PP_FLUX_LF = 0, 1
 
 EXPORTED = [
     "pp_cweno_config_defaults", "pp_cweno_init", "pp_cweno_rhs", "pp_cweno_stage",
@@ -43,6 +44,7 @@ class Config(ctypes.Structure):
         ("gl_w1", ctypes.c_double), ("nbatch", ctypes.c_int64),
         ("lengths", ctypes.POINTER(ctypes.c_int64)), ("dxs", ctypes.POINTER(ctypes.c_double)),
         ("bcs", ctypes.POINTER(ctypes.c_int)), ("stream", ctypes.c_void_p),
+        ("flux", ctypes.c_int),
     ]
 
 
@@ -110,12 +112,14 @@ class Solver:
 
     def __init__(self, ndim=1, nx=0, ny=1, dx=0.0, dy=0.0, gamma=1.4, bc=(0, 0, 0, 0),
                  precision=PP_FP64, weno_eps=1e-13, pp_eps_cap=1e-13, gl_w1=1.0 / 12.0,
-                 lengths=None, dxs=None, bcs=None, stream=None):
+                 lengths=None, dxs=None, bcs=None, stream=None, flux=None):
         c = default_config()
         c.ndim, c.nx, c.ny, c.dx, c.dy, c.gamma = ndim, nx, ny, dx, dy, gamma
         for i in range(4):
             c.bc[i] = int(bc[i]) if i < len(bc) else 0
         c.precision, c.weno_eps, c.pp_eps_cap, c.gl_w1 = precision, weno_eps, pp_eps_cap, gl_w1
+        if flux is not None:
+            c.flux = int(flux)
         self._keep = []
         if lengths is not None:
             nb = len(lengths)

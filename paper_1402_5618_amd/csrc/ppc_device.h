@@ -223,6 +223,43 @@ __device__ __forceinline__ void hllc_flux(double g, const double (&Ul)[NC], cons
     }
 }
 
+// Local Lax-Friedrichs flux, the more dissipative alternative the paper
+// names for Example 3.6 (not defined there): F = (f(Ul) + f(Ur))/2 -
+// alpha (Ur - Ul)/2 with alpha = max(|u| + a) over the two states, sound
+// speeds from max(p, 0) as in HLLC.
+template <int NC, int NRM>
+__device__ __forceinline__ void lf_flux(double g, const double (&Ul)[NC], const double (&Ur)[NC],
+                                        double (&F)[NC]) {
+    constexpr int IE = NC - 1;
+    constexpr int TG = (NC == 4) ? 3 - NRM : -1;
+    const double rl = Ul[0], rr = Ur[0];
+    const double irl = rcp_t(rl), irr = rcp_t(rr);
+    const double ul = Ul[NRM] * irl, ur = Ur[NRM] * irr;
+    double vl = 0.0, vr = 0.0;
+    if constexpr (TG > 0) {
+        vl = Ul[TG] * irl;
+        vr = Ur[TG] * irr;
+    }
+    const double El = Ul[IE], Er = Ur[IE];
+    const double pl = (g - 1.0) * (El - 0.5 * rl * (ul * ul + vl * vl));
+    const double pr = (g - 1.0) * (Er - 0.5 * rr * (ur * ur + vr * vr));
+    const double al = sqrt_nn(g * fmax(pl, 0.0) * irl), ar = sqrt_nn(g * fmax(pr, 0.0) * irr);
+    const double alpha = fmax(fabs(ul) + al, fabs(ur) + ar);
+    double Fl[NC], Fr[NC];
+    Fl[0] = rl * ul;
+    Fl[NRM] = rl * ul * ul + pl;
+    Fl[IE] = ul * (El + pl);
+    Fr[0] = rr * ur;
+    Fr[NRM] = rr * ur * ur + pr;
+    Fr[IE] = ur * (Er + pr);
+    if constexpr (TG > 0) {
+        Fl[TG] = rl * ul * vl;
+        Fr[TG] = rr * ur * vr;
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) F[k] = 0.5 * (Fl[k] + Fr[k]) - 0.5 * alpha * (Ur[k] - Ul[k]);
+}
+
 // Mixed precision HLLC: primitives (rho, u_n, u_t, p) and E are formed in
 // double from the limited conserved states (so p never suffers float
 // cancellation near vacuum), then the wave speeds, contact, star states and

@@ -74,6 +74,7 @@ struct LineArgs {
     int n, nlines;
     int bc_lo, bc_hi;
     int seg_max;            // max cells per phase-2 segment
+    int flux;               // PP_FLUX_HLLC or PP_FLUX_LF
     double h, gamma, w1, i12, weno_eps, eps_cap, t_end, cfl;
     const long long* eps_enc;  // encoded (min rho, min e) of the whole grid, or nullptr
     const double* dt_dev;      // stage mode: dt on the device, or nullptr -> dt_val
@@ -966,7 +967,9 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
                 for (int c = 0; c < NC; ++c)
                     Ur[c] = (bc_hi == PP_BC_REFLECTIVE && c == NRM) ? -Ul[c] : Ul[c];
             }
-            if constexpr (MIXED) {
+            if (A.flux == PP_FLUX_LF) {
+                lf_flux<NC, NRM>(A.gamma, Ul, Ur, F);   // double in both precisions
+            } else if constexpr (MIXED) {
                 hllc_flux_f32<NC, NRM>(A.gamma, Ul, Ur, F);
             } else {
                 hllc_flux<NC, NRM>(A.gamma, Ul, Ur, F);
@@ -1581,6 +1584,7 @@ LineArgs base_args(const pp_cweno_ctx* ctx) {
     A.w1 = ctx->cfg.gl_w1;
     A.i12 = 1.0 / (1.0 - 2.0 * ctx->cfg.gl_w1);
     A.weno_eps = ctx->cfg.weno_eps;
+    A.flux = ctx->cfg.flux;
     A.eps_cap = ctx->cfg.pp_eps_cap;
     A.rk_a = 0.0;
     A.rk_b = 1.0;
@@ -1890,6 +1894,8 @@ int pp_cweno_init(const pp_cweno_config* cfg, pp_cweno_ctx** out) {
     if (c.ndim != 1 && c.ndim != 2) return fail(nullptr, PP_EINVAL, "ndim must be 1 or 2");
     if (!(c.gamma > 1.0)) return fail(nullptr, PP_EINVAL, "gamma must be > 1");
     if (!(c.gl_w1 > 0.0 && c.gl_w1 < 0.5)) return fail(nullptr, PP_EINVAL, "gl_w1 must be in (0, 1/2)");
+    if (c.flux != PP_FLUX_HLLC && c.flux != PP_FLUX_LF)
+        return fail(nullptr, PP_EINVAL, "flux must be PP_FLUX_HLLC or PP_FLUX_LF");
     if (!(c.weno_eps > 0.0) || !(c.pp_eps_cap > 0.0))
         return fail(nullptr, PP_EINVAL, "epsilons must be > 0");
     if (c.precision != PP_FP64 && c.precision != PP_MIXED)

@@ -619,3 +619,66 @@ def test_2d_timing_events_cover_every_launch():
         assert launches in (21, 24), (k, launches)
         assert ms > 0.0
     assert sum(ms for ms, _ in tm.values()) < wall_ms
+
+
+@pytest.mark.parametrize("n,bc", [(200, (1, 2)), (777, (2, 2)), (2048, (0, 0)), (2048, (1, 2)),
+                                  (4000, (1, 1))])
+def test_1d_stage_parity_lax_friedrichs(n, bc):
+    """The Lax-Friedrichs flux option (PP_FLUX_LF) through all three stages,
+    against the oracle with the same flux: the paired full-chunk path
+    (2048), the general paired path and the two-wave long-line path (4000)."""
+    pp = gpu()
+    print(f"case lf n={n} bc={bc}", flush=True)
+    h = 1.0 / n
+    U = mixed_line(n, seed=n + 7)
+    dt = (1.0 / 12.0) * h / oracle.max_speed_1d(U)
+    P = oracle.params(flux=1)
+    s = pp.Solver(ndim=1, nx=n, dx=h, bc=(*bc, 0, 0), flux=pp.PP_FLUX_LF)
+    Ud = dev(U)
+    U1 = oracle.stage_1d(U, U, 1, dt, bc, h, P)
+    U2 = oracle.stage_1d(U, U1, 2, dt, bc, h, P)
+    U3 = oracle.stage_1d(U, U2, 3, dt, bc, h, P)
+    o1, o2, o3 = (torch.empty_like(Ud) for _ in range(3))
+    s.stage(Ud, Ud, o1, 1, dt)
+    s.stage(Ud, dev(U1), o2, 2, dt)
+    s.stage(Ud, dev(U2), o3, 3, dt)
+    torch.cuda.synchronize()
+    for st, (got, ref) in enumerate(((o1, U1), (o2, U2), (o3, U3)), start=1):
+        err = comp_rel(got.cpu().numpy(), ref)
+        assert err <= TOL_STAGE, (st, err)
+    # the flux option changes the result (the two fluxes differ at the jumps)
+    Uh = oracle.stage_1d(U, U, 1, dt, bc, h)
+    assert comp_rel(Uh, U1) > 1e-8
+    s.close()
+
+
+def test_2d_stage_parity_lax_friedrichs():
+    """2D sweeps and combine with the Lax-Friedrichs flux (both normal
+    directions, reflective and transmissive ends)."""
+    pp = gpu()
+    nx, ny, bc = 48, 40, (1, 2, 2, 1)
+    x = W.cell_centres(0, 1, nx)[None, :]
+    y = W.cell_centres(0, 1, ny)[:, None]
+    rho = 1 + 0.3 * np.sin(2 * np.pi * (x + 2 * y)) + 0.5 * ((x - 0.5) ** 2 + (y - 0.4) ** 2 < 0.06)
+    u = 0.3 * np.cos(2 * np.pi * y) + 0 * x
+    v = -0.2 * np.sin(2 * np.pi * x) + 0 * y
+    p = 1 + 0.5 * (x > 0.6) + 0 * y
+    U = np.stack([rho, rho * u, rho * v, p / 0.4 + 0.5 * rho * (u * u + v * v)])
+    dx, dy = 1.0 / nx, 1.0 / ny
+    s_x, s_y = oracle.max_speed_2d(U)
+    dt = (1.0 / 12.0) / (s_x / dx + s_y / dy)
+    P = oracle.params(flux=1)
+    s = pp.Solver(ndim=2, nx=nx, ny=ny, dx=dx, dy=dy, bc=bc, flux=pp.PP_FLUX_LF)
+    Ud = dev(U)
+    ref1 = oracle.stage_2d(U, U, 1, dt, bc, dx, dy, P)
+    o1 = torch.empty_like(Ud)
+    s.stage(Ud, Ud, o1, 1, dt)
+    torch.cuda.synchronize()
+    assert comp_rel(o1.cpu().numpy(), ref1) <= TOL_STAGE
+    s.close()
+
+
+def test_flux_option_is_validated():
+    pp = gpu()
+    with pytest.raises(pp.PPError):
+        pp.Solver(ndim=1, nx=64, dx=1.0 / 64, bc=(0, 0, 0, 0), flux=2)

@@ -46,12 +46,12 @@ CASES = {
 }
 
 
-def gpu_run(U0, bc, h, T, gamma):
+def gpu_run(U0, bc, h, T, gamma, flux=0):
     import torch
     import paper_1402_5618_amd as pp
 
     n = U0.shape[1]
-    s = pp.Solver(ndim=1, nx=n, dx=h, gamma=gamma, bc=(bc[0], bc[1], 0, 0))
+    s = pp.Solver(ndim=1, nx=n, dx=h, gamma=gamma, bc=(bc[0], bc[1], 0, 0), flux=flux)
     U = torch.tensor(U0, device="cuda")
     code = pp.PP_OK
     try:
@@ -124,3 +124,22 @@ def test_planar_sedov_gpu_minima():
     g = printed("planar_sedov")
     assert 0.5 < Ug[0].min() / g["min_rho"] < 2.0
     assert abs(W.specific_internal_energy(Ug).min() / g["min_e"] - 1) < 0.01
+
+
+@pytest.mark.gpu
+def test_low_density_123_with_lax_friedrichs():
+    """Example 3.6 with the Lax-Friedrichs flux, the option the paper names
+    for damping oscillations of the HLLC run in the low-density centre: the
+    run matches the oracle's run with the same flux and stays positive.
+    (The paper omits those results; at N = 400 with component-wise
+    reconstruction the oracle shows no reduction of the centre velocity
+    variation, 0.543 with LF against 0.526 with HLLC, so none is asserted.)"""
+    make, bc, h, T, gamma, tol = CASES["low_density_123"]
+    U0 = make()
+    Ug, t, steps, code = gpu_run(U0, bc, h, T, gamma, flux=1)
+    Uo, info = oracle.run_1d(U0, bc, h, T, p=oracle.params(gamma=gamma, flux=1))
+    assert code == 0 and steps == info["steps"]
+    for c in range(3):
+        d = np.abs(Ug[c] - Uo[c]).sum() / np.abs(Uo[c]).sum()
+        assert d <= tol, (c, d)
+    assert Ug[0].min() > 0 and W.pressure(Ug, gamma).min() > 0

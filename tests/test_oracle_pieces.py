@@ -253,6 +253,72 @@ def test_hllc_wave_speeds_give_positive_star_states():
         assert SR >= ur + ar - 1e-13 * (abs(ur) + ar)
 
 
+# ------------------------------------------------ Lax-Friedrichs flux
+@pytest.mark.parametrize("ncomp,nrm", [(3, 1), (4, 1), (4, 2)])
+def test_lf_consistency(ncomp, nrm):
+    """F(U, U) = f(U): the dissipation term vanishes for equal states."""
+    for _ in range(50):
+        U = rand_state(ncomp)
+        np.testing.assert_allclose(oracle.lf(U, U, nrm=nrm), euler_flux(U, nrm),
+                                   rtol=1e-13, atol=1e-13 * np.abs(U).max())
+
+
+def test_lf_mirror_covariance_and_dissipation():
+    """Mirror covariance as for HLLC; and the flux is more dissipative than
+    HLLC: across an isolated stationary contact HLLC carries no mass, while
+    Lax-Friedrichs carries -alpha (rho_r - rho_l) / 2 with alpha the larger
+    sound speed of the two sides."""
+    M = np.array([1.0, -1.0, 1.0])
+    for _ in range(50):
+        Ul, Ur = rand_state(), rand_state()
+        F = oracle.lf(Ul, Ur)
+        Fm = oracle.lf(Ur * M, Ul * M)
+        np.testing.assert_allclose(Fm, F * np.array([-1.0, 1.0, -1.0]), rtol=1e-12,
+                                   atol=1e-12 * np.abs(F).max())
+    p = 1.3
+    for rl, rr in ((1.0, 0.125), (0.2, 3.0)):
+        Ul = np.array([rl, 0.0, p / (GAMMA - 1)])
+        Ur = np.array([rr, 0.0, p / (GAMMA - 1)])
+        alpha = max(math.sqrt(GAMMA * p / rl), math.sqrt(GAMMA * p / rr))
+        F = oracle.lf(Ul, Ur)
+        np.testing.assert_allclose(F, [-0.5 * alpha * (rr - rl), p, 0.0], rtol=1e-13, atol=1e-15)
+        assert abs(oracle.hllc(Ul, Ur)[0]) < 1e-14
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_first_order_lf_scheme_preserves_positivity(seed):
+    """The first-order scheme with the local Lax-Friedrichs flux keeps states
+    in G at CFL 1/2 on random near-vacuum data (the flux is positivity
+    preserving for lambda alpha <= 1)."""
+    rng = np.random.default_rng(100 + seed)
+    n = 200
+    rho = 10 ** rng.uniform(-6, 0, n)
+    u = rng.uniform(-5, 5, n)
+    p = 10 ** rng.uniform(-10, 0, n)
+    U = W.prim_to_cons_1d(rho, u, p, GAMMA)
+    h = 1.0 / n
+    dt = 0.5 * h / oracle.max_speed_1d(U)
+    P = oracle.params(first_order=True, limiter=False, flux=1)
+    for bc in ((0, 0), (1, 1), (2, 2)):
+        U1 = oracle.stage_1d(U, U, 1, dt, bc, h, P)
+        assert np.all(U1[0] > 0)
+        assert np.all(W.specific_internal_energy(U1) > 0)
+
+
+def test_lf_scheme_fifth_order_on_smooth_data():
+    """With either flux the scheme stays fifth order on the smooth wave
+    (Example 3.1, dt = w1 h^(5/3) / max(|u|+a)): the flux only sees the
+    O(h^5) jump of the reconstructed interface values."""
+    errs = []
+    for n in (20, 40):
+        U, info = oracle.run_1d(W.density_wave_1d(n), (0, 0), 2.0 / n, 2.0, rule=1,
+                                p=oracle.params(flux=1))
+        ex = W.density_wave_1d(n, t=info["t"])
+        errs.append(W.error_norms(U[0], ex[0], 2.0 / n)[0])
+    order = math.log2(errs[0] / errs[1])
+    assert 4.5 < order < 6.5, (errs, order)
+
+
 @pytest.mark.parametrize("seed", range(3))
 def test_first_order_scheme_preserves_positivity(seed):
     """Special case U+- = cell averages: scheme (1DEulerFV-First) with HLLC
