@@ -79,3 +79,14 @@ def test_null_arguments():
     assert L.pp_cweno_stage(None, None, None, None, 1, 0.1) == pp.PP_EINVAL
     assert L.pp_cweno_status(None, None) == pp.PP_EINVAL
     L.pp_cweno_destroy(None)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; --gpus N > 1 exits with a message and does
+    not touch a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
