@@ -682,3 +682,25 @@ def test_flux_option_is_validated():
     pp = gpu()
     with pytest.raises(pp.PPError):
         pp.Solver(ndim=1, nx=64, dx=1.0 / 64, bc=(0, 0, 0, 0), flux=2)
+
+
+@pytest.mark.parametrize("n,bc", [(200, (1, 2)), (2048, (0, 0)), (4000, (1, 1))])
+def test_mixed_stage_bound_lax_friedrichs(n, bc):
+    """Mixed precision with the Lax-Friedrichs flux (evaluated in double):
+    one stage within the mixed-precision bound of the FP64 oracle with the
+    same flux."""
+    pp = gpu()
+    h = 1.0 / n
+    U = mixed_line(n, seed=13 * n)
+    dt = (1.0 / 12.0) * h / oracle.max_speed_1d(U)
+    ref = oracle.stage_1d(U, U, 1, dt, bc, h, oracle.params(flux=1))
+    s = pp.Solver(ndim=1, nx=n, dx=h, bc=(*bc, 0, 0), precision=pp.PP_MIXED,
+                  flux=pp.PP_FLUX_LF)
+    Ud = dev(U)
+    out = torch.empty_like(Ud)
+    s.stage(Ud, Ud, out, 1, dt)
+    torch.cuda.synchronize()
+    e = comp_rel(out.cpu().numpy(), ref)
+    print(f"mixed lf stage n={n}: {e:.2e}", flush=True)
+    assert e <= TOL_MIXED_STAGE
+    s.close()
