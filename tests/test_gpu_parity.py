@@ -704,3 +704,27 @@ def test_mixed_stage_bound_lax_friedrichs(n, bc):
     print(f"mixed lf stage n={n}: {e:.2e}", flush=True)
     assert e <= TOL_MIXED_STAGE
     s.close()
+
+
+def test_max_speed_entry_point():
+    """pp_cweno_max_speed: max(|u|+a) over the cell averages (2D: and
+    max(|v|+a)) against the oracle's reductions, 1D and 2D."""
+    pp = gpu()
+    n = 777
+    U = mixed_line(n, seed=5)
+    s = pp.Solver(ndim=1, nx=n, dx=1.0 / n, bc=(1, 1, 0, 0))
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    s.max_speed(dev(U), out)
+    torch.cuda.synchronize()
+    ref = oracle.max_speed_1d(U)
+    assert abs(out[0].item() - ref) <= 1e-14 * ref
+    s.close()
+    nx, ny = 40, 24
+    U2 = W.density_wave_2d(nx, ny)
+    U2[1] *= 1.7   # make the two directions differ
+    s = pp.Solver(ndim=2, nx=nx, ny=ny, dx=2.0 / nx, dy=2.0 / ny, bc=(0, 0, 0, 0))
+    s.max_speed(dev(U2), out)
+    torch.cuda.synchronize()
+    rx, ry = oracle.max_speed_2d(U2)
+    assert abs(out[0].item() - rx) <= 1e-14 * rx and abs(out[1].item() - ry) <= 1e-14 * ry
+    s.close()
