@@ -194,11 +194,35 @@ def other_workload(args):
         s.batch_run(U.clone(), ens.t_end, 2, 1.0 / 12.0)   # warm-up (graph, kernels)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        try:
-            steps = s.batch_run(U, ens.t_end, 10 ** 8 if args.full else args.steps, 1.0 / 12.0)
-            flags = 0
-        except pp.PPError as e:
-            steps, flags = s.last_batch_steps(), e.code
+        flags = 0
+        t_min = None
+        if args.full:
+            # to t_end in pieces of `chunk` steps per problem (pp_cweno_batch_continue
+            # resumes exactly), one progress line per piece on stderr
+            chunk, cap = 2000, 2000
+            try:
+                s.batch_run(U, ens.t_end, cap, 1.0 / 12.0)
+            except pp.PPError as e:
+                flags = e.code
+            while True:
+                try:
+                    steps, ts = s.batch_continue(U, ens.t_end, cap, 1.0 / 12.0)
+                except pp.PPError as e:
+                    flags = e.code
+                    steps, ts = s.last_batch_steps(), s.last_batch_times()
+                t_min = min(ts)
+                running = sum(1 for t in ts if t < ens.t_end)
+                print(f"ensemble: {running} problems running, t_min {t_min:.4g} of {ens.t_end}, "
+                      f"max steps {max(steps)}, {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
+                if running == 0 or time.perf_counter() - t0 > args.max_wall:
+                    break
+                cap += chunk
+        else:
+            try:
+                steps = s.batch_run(U, ens.t_end, args.steps, 1.0 / 12.0)
+            except pp.PPError as e:
+                steps, flags = s.last_batch_steps(), e.code
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         cu = float(np.dot(np.asarray(steps, dtype=np.float64), ens.lengths))
@@ -208,7 +232,9 @@ def other_workload(args):
                    value=cu / wall, steps=int(max(steps)), ms_per_step=1e3 * wall / max(steps),
                    config={"workload": f"{nb} Riemann problems, N in [256,4096] (sum "
                                        f"{int(ens.lengths.sum())} cells), {prec_name}, " +
-                                       (f"to t_end {ens.t_end}" if args.full else
+                                       (f"to t_end {ens.t_end} (reached by every problem: "
+                                        f"{t_min is not None and t_min >= ens.t_end}; slowest at "
+                                        f"t = {t_min})" if args.full else
                                           f"{args.steps} steps per problem (bounded; t_end "
                                           f"{ens.t_end} not reached)"),
                            "launch_plan": plan, "plan_ms_per_step": plan_ms,

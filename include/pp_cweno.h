@@ -137,6 +137,19 @@ int pp_cweno_batch_step(pp_cweno_ctx *ctx, double *Upacked, const double *dt_dev
 int pp_cweno_batch_run(pp_cweno_ctx *ctx, double *Upacked, double t_end, int64_t nsteps_max,
                        double cfl, int64_t *steps_out);
 
+/* Continue the last pp_cweno_batch_run on the same context and state: every
+ * problem with t < t_end and fewer than nsteps_max steps (the total over the
+ * run and its continuations) resumes from its stored t and step count with
+ * the dt of its current averages, exactly as the uninterrupted run would.
+ * Lets a long run advance in bounded pieces.  steps_out and t_out (host
+ * [nbatch], may be NULL) receive each problem's step count and time.  The
+ * status of the run is kept across continuations (PP_ESTATE once any stage
+ * has left the admissible set).  PP_EINVAL if no run was started on the
+ * context, or after pp_cweno_batch_tune (which resets the per-problem times).
+ * Synchronises. */
+int pp_cweno_batch_continue(pp_cweno_ctx *ctx, double *Upacked, double t_end, int64_t nsteps_max,
+                            double cfl, int64_t *steps_out, double *t_out);
+
 /* Batched ensembles: choose the launch plan used by pp_cweno_batch_step and
  * pp_cweno_batch_run.  The problems, sorted by length, are cut into length
  * classes, each processed by one persistent launch per stage with the kernel

@@ -23,7 +23,7 @@ PP_FLUX_HLLC, PP_FLUX_LF = 0, 1
 EXPORTED = [
     "pp_cweno_config_defaults", "pp_cweno_init", "pp_cweno_rhs", "pp_cweno_stage",
     "pp_cweno_step", "pp_cweno_run", "pp_cweno_batch_step", "pp_cweno_batch_tune",
-    "pp_cweno_batch_run",
+    "pp_cweno_batch_run", "pp_cweno_batch_continue",
     "pp_cweno_max_speed", "pp_cweno_status", "pp_cweno_debug_line", "pp_cweno_set_timing",
     "pp_cweno_get_timing", "pp_cweno_last_error", "pp_cweno_destroy",
 ]
@@ -74,6 +74,9 @@ def lib():
                                                    P(ctypes.c_int), P(ctypes.c_double)]),
             "pp_cweno_batch_run": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int64,
                                                   ctypes.c_double, P(ctypes.c_int64)]),
+            "pp_cweno_batch_continue": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int64,
+                                                       ctypes.c_double, P(ctypes.c_int64),
+                                                       P(ctypes.c_double)]),
             "pp_cweno_max_speed": (ctypes.c_int, [_VP, _VP, _VP]),
             "pp_cweno_status": (ctypes.c_int, [_VP, P(ctypes.c_uint32)]),
             "pp_cweno_debug_line": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
@@ -183,6 +186,21 @@ class Solver:
         self._check(lib().pp_cweno_batch_run(self._ctx, _ptr(U), float(t_end), int(nsteps_max),
                                              float(cfl), steps))
         return list(steps)
+
+    def batch_continue(self, U, t_end, nsteps_max=1 << 62, cfl=1.0 / 12.0):
+        """Continue the last batch_run: returns (per-problem steps, per-problem
+        t); raises PPError(PP_ESTATE) like batch_run (counts then via
+        last_batch_steps)."""
+        nb = self.cfg.nbatch
+        steps = (ctypes.c_int64 * nb)()
+        ts = (ctypes.c_double * nb)()
+        self._last_steps, self._last_t = steps, ts
+        self._check(lib().pp_cweno_batch_continue(self._ctx, _ptr(U), float(t_end),
+                                                  int(nsteps_max), float(cfl), steps, ts))
+        return list(steps), list(ts)
+
+    def last_batch_times(self):
+        return list(self._last_t)
 
     def last_batch_steps(self):
         return list(self._last_steps)

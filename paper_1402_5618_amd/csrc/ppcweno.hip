@@ -1103,7 +1103,8 @@ __global__ void __launch_bounds__(256) batch_init_kernel(const double* __restric
                                                          long long total, const long long* off,
                                                          const int* nl, const double* hl,
                                                          double* dtl, double* tl, long long* sl,
-                                                         double gamma, double cfl, double t_end) {
+                                                         double gamma, double cfl, double t_end,
+                                                         int resume, long long steps_max) {
     __shared__ double red[4];
     const int b = blockIdx.x;
     const long long o = off[b];
@@ -1119,11 +1120,19 @@ __global__ void __launch_bounds__(256) batch_init_kernel(const double* __restric
     if (threadIdx.x == 0) {
         S = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
         double dt = cfl * hl[b] / S;
-        if (!(dt > 0.0) || !isfinite(dt)) dt = 0.0;
-        if (dt > t_end) dt = t_end;
+        if (!resume) {
+            if (!(dt > 0.0) || !isfinite(dt)) dt = 0.0;
+            if (dt > t_end) dt = t_end;
+            tl[b] = 0.0;
+            sl[b] = 0;
+        } else {
+            // continue from the stored t and step count with the dt the
+            // stage-3 epilogue would have set (same averages, same rule)
+            const double t = tl[b];
+            if (!(dt > 0.0) || !isfinite(dt) || t >= t_end || sl[b] >= steps_max) dt = 0.0;
+            else if (t + dt > t_end) dt = t_end - t;
+        }
         dtl[b] = dt;
-        tl[b] = 0.0;
-        sl[b] = 0;
     }
 }
 
@@ -1423,6 +1432,7 @@ struct pp_cweno_ctx {
     double* d_dtcopy = nullptr;
     double* d_tune = nullptr;   // autotuner's scratch copy of the packed state
     int n_sm = 0;
+    bool batch_started = false;   // a batched run has set the per-problem t and steps
     // batched launch plan: the length-sorted problems are cut into classes
     // (contiguous in d_order, longest first), one persistent launch per class
     // and stage, each with the kernel shape and LDS of its longest problem
@@ -2184,10 +2194,12 @@ int pp_cweno_batch_tune(pp_cweno_ctx* ctx, const double* Upacked, double cfl, in
         ctx->d_tune = nullptr;
         return fail(ctx, PP_ENOMEM, "autotuner scratch");
     }
-    // per-problem dt of the initial state (the run's first step)
+    // per-problem dt of the initial state (the run's first step); this
+    // overwrites the per-problem t and steps, so no run can be continued
     hipLaunchKernelGGL(batch_init_kernel, dim3(nb), dim3(256), 0, ctx->stream, Upacked, ctx->total,
                        ctx->d_off, ctx->d_n, ctx->d_h, ctx->d_dt, ctx->d_t, ctx->d_steps,
-                       ctx->cfg.gamma, cfl, 1e300);
+                       ctx->cfg.gamma, cfl, 1e300, 0, 0LL);
+    ctx->batch_started = false;
     HIPCHK(ctx, hipGetLastError());
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(ctx, hipEventCreate(&e0));
@@ -2235,20 +2247,24 @@ int pp_cweno_batch_tune(pp_cweno_ctx* ctx, const double* Upacked, double cfl, in
     return PP_OK;
 }
 
-int pp_cweno_batch_run(pp_cweno_ctx* ctx, double* Upacked, double t_end, int64_t nsteps_max,
-                       double cfl, int64_t* steps_out) {
+static int batch_run_impl(pp_cweno_ctx* ctx, double* Upacked, double t_end, int64_t nsteps_max,
+                          double cfl, int64_t* steps_out, double* t_out, bool resume) {
     if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
     if (!Upacked) return fail(ctx, PP_EINVAL, "Upacked is NULL");
     if (ctx->cfg.nbatch <= 0) return fail(ctx, PP_EINVAL, "context has no batch");
     if (!(t_end > 0.0) || !(cfl > 0.0) || nsteps_max < 1)
         return fail(ctx, PP_EINVAL, "t_end and cfl must be > 0, nsteps_max >= 1");
+    if (resume && !ctx->batch_started)
+        return fail(ctx, PP_EINVAL, "pp_cweno_batch_continue needs a pp_cweno_batch_run first");
     const int nb = (int)ctx->cfg.nbatch;
-    int r = reset_scal(ctx);
+    int r = 0;
+    if (!resume) r = reset_scal(ctx);   // a continued run keeps the sticky status
     if (r) return r;
     hipLaunchKernelGGL(batch_init_kernel, dim3(nb), dim3(256), 0, ctx->stream, Upacked, ctx->total,
                        ctx->d_off, ctx->d_n, ctx->d_h, ctx->d_dt, ctx->d_t, ctx->d_steps,
-                       ctx->cfg.gamma, cfl, t_end);
+                       ctx->cfg.gamma, cfl, t_end, resume ? 1 : 0, (long long)nsteps_max);
     HIPCHK(ctx, hipGetLastError());
+    ctx->batch_started = true;
     // K steps (3 persistent launches each) captured once in a graph on a
     // private stream, replayed until every problem has retired
     const int K = 8;
@@ -2305,10 +2321,21 @@ int pp_cweno_batch_run(pp_cweno_ctx* ctx, double* Upacked, double t_end, int64_t
         HIPCHK(ctx, hipMemcpy(st.data(), ctx->d_steps, sizeof(long long) * nb, hipMemcpyDeviceToHost));
         for (int i = 0; i < nb; ++i) steps_out[i] = st[i];
     }
+    if (t_out) HIPCHK(ctx, hipMemcpy(t_out, ctx->d_t, sizeof(double) * nb, hipMemcpyDeviceToHost));
     unsigned status = 0;
     HIPCHK(ctx, hipMemcpy(&status, &ctx->scal->status, sizeof(unsigned), hipMemcpyDeviceToHost));
     if (status) return fail(ctx, PP_ESTATE, "a stage left the admissible set or was not finite");
     return PP_OK;
+}
+
+int pp_cweno_batch_run(pp_cweno_ctx* ctx, double* Upacked, double t_end, int64_t nsteps_max,
+                       double cfl, int64_t* steps_out) {
+    return batch_run_impl(ctx, Upacked, t_end, nsteps_max, cfl, steps_out, nullptr, false);
+}
+
+int pp_cweno_batch_continue(pp_cweno_ctx* ctx, double* Upacked, double t_end, int64_t nsteps_max,
+                            double cfl, int64_t* steps_out, double* t_out) {
+    return batch_run_impl(ctx, Upacked, t_end, nsteps_max, cfl, steps_out, t_out, true);
 }
 
 int pp_cweno_status(pp_cweno_ctx* ctx, uint32_t* flags) {

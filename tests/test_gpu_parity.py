@@ -728,3 +728,43 @@ def test_max_speed_entry_point():
     rx, ry = oracle.max_speed_2d(U2)
     assert abs(out[0].item() - rx) <= 1e-14 * rx and abs(out[1].item() - ry) <= 1e-14 * ry
     s.close()
+
+
+def test_batch_continue_equals_one_run():
+    """pp_cweno_batch_continue: a run cut into pieces (5 steps, then to 12,
+    then to t_end) ends bitwise equal to the uninterrupted run, with the same
+    per-problem step counts and times; it refuses to start without a run and
+    after the tuner has reset the per-problem times."""
+    pp = gpu()
+    # 48 mild Riemann problems (they stay in G), lengths across both classes
+    rng = np.random.default_rng(7)
+    lengths = rng.integers(64, 2600, size=48).astype(np.int64)
+    parts = []
+    for n in lengths:
+        sl = (rng.uniform(0.5, 2.0), rng.uniform(-0.5, 0.5), rng.uniform(0.5, 2.0))
+        sr = (rng.uniform(0.5, 2.0), rng.uniform(-0.5, 0.5), rng.uniform(0.5, 2.0))
+        parts.append(W.riemann_1d(0.0, 1.0, int(n), 0.5, sl, sr))
+    U0 = np.concatenate(parts, axis=1)
+    nb, t_end = len(lengths), 0.01
+    s = pp.Solver(ndim=1, lengths=lengths, dxs=1.0 / lengths.astype(np.float64), bcs=[1] * (2 * nb))
+    with pytest.raises(pp.PPError):
+        s.batch_continue(dev(U0), t_end, 10)
+    U1 = dev(U0)
+    steps1 = s.batch_run(U1, t_end, 1 << 40, 1.0 / 12.0)
+    torch.cuda.synchronize()
+    U2 = dev(U0)
+    a = s.batch_run(U2, t_end, 5, 1.0 / 12.0)
+    assert max(a) == 5
+    b, tb = s.batch_continue(U2, t_end, 12, 1.0 / 12.0)
+    assert max(b) == 12 and max(tb) < t_end
+    c, tc = s.batch_continue(U2, t_end, 1 << 40, 1.0 / 12.0)
+    torch.cuda.synchronize()
+    assert c == steps1
+    assert all(abs(t - t_end) <= 1e-15 for t in tc)
+    assert torch.equal(U1, U2)
+    s.batch_tune(force_plan=0)   # direct plan choice leaves the times alone
+    s.batch_continue(U2, t_end, 1 << 40, 1.0 / 12.0)
+    s.batch_tune(dev(U0), 1.0 / 12.0)   # timed tuning resets them
+    with pytest.raises(pp.PPError):
+        s.batch_continue(U2, t_end, 1 << 40, 1.0 / 12.0)
+    s.close()
