@@ -2272,35 +2272,71 @@ static int batch_run_impl(pp_cweno_ctx* ctx, double* Upacked, double t_end, int6
     hipEvent_t ev = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    auto cleanup = [&]() {
-        ctx->stream = user;
+    // A retired problem (dt = 0) stays retired for the rest of the run.  Once
+    // the active set has halved, each class is cut down to its active
+    // problems (same kernel shape and LDS as the full class), so the tail of
+    // a run launches neither workgroups nor scans for finished lines; every
+    // line is still advanced by one workgroup, so the results do not change.
+    // The full order is put back before returning.
+    const std::vector<int> full_order = ctx->order_host;
+    const int full_nclass = ctx->nclass;
+    pp_cweno_ctx::LenClass full_cls[3];
+    for (int c = 0; c < 3; ++c) full_cls[c] = ctx->cls[c];
+    bool compacted = false;
+    auto destroy_graph = [&]() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    };
+    auto cleanup = [&]() -> hipError_t {
+        ctx->stream = user;
+        destroy_graph();
+        hipError_t er = hipSuccess;
+        if (compacted) {
+            if (gs) er = hipStreamSynchronize(gs);
+            ctx->order_host = full_order;
+            ctx->nclass = full_nclass;
+            for (int c = 0; c < 3; ++c) ctx->cls[c] = full_cls[c];
+            if (er == hipSuccess)
+                er = hipMemcpy(ctx->d_order, full_order.data(), sizeof(int) * nb, hipMemcpyHostToDevice);
+        }
         if (ev) (void)hipEventDestroy(ev);
         if (gs) (void)hipStreamDestroy(gs);
+        return er;
+    };
+    auto capture = [&]() -> int {
+        hipError_t ec = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal);
+        if (ec != hipSuccess) return hip_fail(ctx, ec, "hipStreamBeginCapture");
+        ctx->stream = gs;
+        int rc = 0;
+        for (int k = 0; k < K && rc == 0; ++k)
+            rc = batch_step_launch(ctx, Upacked, ctx->d_dt, true, cfl, t_end, nsteps_max);
+        ec = hipStreamEndCapture(gs, &graph);
+        ctx->stream = user;
+        if (rc) return rc;
+        if (ec != hipSuccess) return hip_fail(ctx, ec, "hipStreamEndCapture");
+        ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ec != hipSuccess) return hip_fail(ctx, ec, "hipGraphInstantiate");
+        return 0;
     };
     hipError_t e = hipStreamCreateWithFlags(&gs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(ev, user);
     if (e == hipSuccess) e = hipStreamWaitEvent(gs, ev, 0);
-    if (e == hipSuccess) e = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
         cleanup();
         return hip_fail(ctx, e, "graph capture setup");
     }
-    ctx->stream = gs;
-    for (int k = 0; k < K && r == 0; ++k) r = batch_step_launch(ctx, Upacked, ctx->d_dt, true, cfl, t_end, nsteps_max);
-    e = hipStreamEndCapture(gs, &graph);
-    if (r || e != hipSuccess) {
+    r = capture();
+    if (r) {
         cleanup();
-        return r ? r : hip_fail(ctx, e, "hipStreamEndCapture");
-    }
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        cleanup();
-        return hip_fail(ctx, e, "hipGraphInstantiate");
+        return r;
     }
     std::vector<double> dts(nb);
+    std::vector<int> act;
+    act.reserve(nb);
+    int compact_ref = nb;
     const int64_t max_replays = nsteps_max / K + 2;
     for (int64_t rep = 0; rep < max_replays; ++rep) {
         e = hipGraphLaunch(exec, gs);
@@ -2311,11 +2347,43 @@ static int batch_run_impl(pp_cweno_ctx* ctx, double* Upacked, double t_end, int6
             cleanup();
             return hip_fail(ctx, e, "graph replay");
         }
-        bool any = false;
-        for (double d : dts) any = any || d > 0.0;
-        if (!any) break;
+        int active = 0;
+        for (double d : dts) active += d > 0.0;
+        if (active == 0) break;
+        if (2 * active > compact_ref) continue;
+        // cut every class of the full plan down to its active problems
+        act.clear();
+        int nc = 0;
+        for (int c = 0; c < full_nclass; ++c) {
+            const int begin = (int)act.size();
+            for (int i = full_cls[c].begin; i < full_cls[c].begin + full_cls[c].count; ++i)
+                if (dts[full_order[i]] > 0.0) act.push_back(full_order[i]);
+            const int count = (int)act.size() - begin;
+            if (count == 0) continue;
+            ctx->cls[nc].begin = begin;
+            ctx->cls[nc].count = count;
+            ctx->cls[nc].maxn = full_cls[c].maxn;
+            ++nc;
+        }
+        compacted = true;
+        ctx->nclass = nc;
+        ctx->order_host = act;
+        destroy_graph();
+        e = hipMemcpyAsync(ctx->d_order, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, gs);
+        if (e == hipSuccess) e = hipStreamSynchronize(gs);
+        if (e != hipSuccess) {
+            cleanup();
+            return hip_fail(ctx, e, "active-set upload");
+        }
+        r = capture();
+        if (r) {
+            cleanup();
+            return r;
+        }
+        compact_ref = active;
     }
-    cleanup();
+    e = cleanup();
+    if (e != hipSuccess) return hip_fail(ctx, e, "restoring the batch order");
     if (steps_out) {
         std::vector<long long> st(nb);
         HIPCHK(ctx, hipMemcpy(st.data(), ctx->d_steps, sizeof(long long) * nb, hipMemcpyDeviceToHost));
