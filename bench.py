@@ -68,8 +68,8 @@ def parse():
     ap.add_argument("--full", action="store_true",
                     help="sedov2d / ensemble: run to the configuration's end time")
     ap.add_argument("--max-wall", type=float, default=240.0,
-                    help="sedov2d --full: stop after this many seconds (the near-vacuum "
-                         "centre makes t = 1 take ~1e7 steps)")
+                    help="--full runs stop after this many seconds (sedov2d: the near-vacuum "
+                         "centre makes t = 1 take ~1e7 steps; the full ensemble takes ~260 s)")
     return ap.parse_args()
 
 
