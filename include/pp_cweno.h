@@ -140,12 +140,15 @@ int pp_cweno_batch_run(pp_cweno_ctx *ctx, double *Upacked, double t_end, int64_t
 /* Continue the last pp_cweno_batch_run on the same context and state: every
  * problem with t < t_end and fewer than nsteps_max steps (the total over the
  * run and its continuations) resumes from its stored t and step count with
- * the dt of its current averages, exactly as the uninterrupted run would.
- * Lets a long run advance in bounded pieces.  steps_out and t_out (host
+ * the dt of its current averages; with the same t_end this is exactly what
+ * the uninterrupted run would do (a later t_end also works, but the steps
+ * already clipped to the earlier one stay clipped).  Lets a long run advance
+ * in bounded pieces.  steps_out and t_out (host
  * [nbatch], may be NULL) receive each problem's step count and time.  The
  * status of the run is kept across continuations (PP_ESTATE once any stage
  * has left the admissible set).  PP_EINVAL if no run was started on the
- * context, or after pp_cweno_batch_tune (which resets the per-problem times).
+ * context, or after a timed pp_cweno_batch_tune (force_plan < 0: it steps a
+ * copy of the state and resets the per-problem times; a forced plan does not).
  * Synchronises. */
 int pp_cweno_batch_continue(pp_cweno_ctx *ctx, double *Upacked, double t_end, int64_t nsteps_max,
                             double cfl, int64_t *steps_out, double *t_out);
