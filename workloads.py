@@ -102,8 +102,8 @@ def sod_1d(n: int = 100, gamma: float = 1.4) -> np.ndarray:
     states, (0.125, 0, 1) | (1, 0, 1), have equal pressures and no velocity
     (a stationary contact only), which contradicts the waves the example
     describes (a left rarefaction, a right contact and shock); the classical
-    data of the cited survey, (1, 0, 1) | (0.125, 0, 0.1), produce them and
-    are used."""
+    data of Sod's 1978 survey that the paper cites, (1, 0, 1) | (0.125, 0, 0.1),
+    produce them and are used."""
     return riemann_1d(-5.0, 5.0, n, 0.0, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), gamma)
 
 
