@@ -36,7 +36,7 @@ class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("eps_cap", ctypes.c_double), ("gl_w1", ctypes.c_double),
                 ("linear", ctypes.c_int), ("first_order", ctypes.c_int),
-                ("limiter", ctypes.c_int), ("flux", ctypes.c_int)]
+                ("limiter", ctypes.c_int), ("flux", ctypes.c_int), ("recon", ctypes.c_int)]
 
 
 class LineDbg(ctypes.Structure):
@@ -45,11 +45,13 @@ class LineDbg(ctypes.Structure):
 
 
 def params(gamma=1.4, weno_eps=1e-13, eps_cap=1e-13, gl_w1=1.0 / 12.0, linear=False,
-           first_order=False, limiter=True, flux=0) -> Params:
+           first_order=False, limiter=True, flux=0, recon=0) -> Params:
     """flux: 0 HLLC (eq. (HLLC)), 1 local Lax-Friedrichs (the alternative the
-    paper names for Example 3.6)."""
+    paper names for Example 3.6).  recon: 0 the compact reconstruction
+    (Sec. 2.2), 1 explicit WENO-JS, 2 explicit WENO-Z (the non-compact
+    schemes the paper compares against in Sec. 3)."""
     return Params(gamma, weno_eps, eps_cap, gl_w1, int(linear), int(first_order), int(limiter),
-                  int(flux))
+                  int(flux), int(recon))
 
 
 _lib = None

@@ -35,6 +35,8 @@ typedef struct {
     int first_order;  /* 1: no reconstruction, U+- = cell average: scheme (1DEulerFV-First) */
     int limiter;      /* 1: apply the positivity-preserving limiter */
     int flux;         /* 0: HLLC, eq. (HLLC); 1: local Lax-Friedrichs (see lf below) */
+    int recon;        /* 0: compact (FVCW, Sec 2.2); 1: explicit WENO-JS; 2: explicit
+                       * WENO-Z (the non-compact schemes of Sec 3, see weno5_explicit) */
 } orc_params;
 
 /* Optional per-line intermediate results for tests (any pointer may be NULL). */
@@ -157,6 +159,28 @@ static double weno5z_minus(const double v[5], const orc_params *P)
     return w[0] * q0 + w[1] * q1 + w[2] * q2;
 }
 
+/* Sec 3 comparison schemes: the classical explicit fifth-order finite-volume
+ * WENO value at node j+1/2 ("-" side) from v[0..4] = ubar_{j-2..j+2}, with
+ * the Jiang-Shu weights alpha_k = d_k / (beta_k + eps)^2 (kind 1, eps = 1e-6
+ * as in Jiang and Shu's paper: a reading, the paper states none) or the
+ * WENO-Z weights of eq. (weight) with d_k in place of c_k (kind 2). */
+#define WENO_JS_EPS 1e-6
+static double weno5_explicit(const double v[5], int kind, const orc_params *P)
+{
+    static const double D5[3] = {0.1, 0.6, 0.3};
+    if (kind == 2) return weno5z_minus(v, P);
+    double q0 = (2.0 * v[0] - 7.0 * v[1] + 11.0 * v[2]) / 6.0;
+    double q1 = (-v[1] + 5.0 * v[2] + 2.0 * v[3]) / 6.0;
+    double q2 = (2.0 * v[2] + 5.0 * v[3] - v[4]) / 6.0;
+    double b[3], al[3], s = 0.0;
+    beta_minus(v, b);
+    for (int k = 0; k < 3; ++k) {
+        al[k] = P->linear ? D5[k] : D5[k] / sq(b[k] + WENO_JS_EPS);
+        s += al[k];
+    }
+    return (al[0] * q0 + al[1] * q1 + al[2] * q2) / s;
+}
+
 /* ------------------------------------------------------- tridiagonal solves
  * Chasing (Thomas) elimination, no pivoting: a_i x_{i-1} + b_i x_i + c_i x_{i+1} = r_i,
  * i = 0..n-1, a_0 and c_{n-1} ignored.  Returns 0, or -1 on a zero pivot. */
@@ -276,6 +300,18 @@ static int recon_scalar(int n, int cyclic, const double *ue, const orc_params *P
     double *a = work, *b = work + n, *c = work + 2 * n, *r = work + 3 * n;
     double *w5 = work + 4 * n;
     double v[5], beta[3], w[3];
+    if (P->recon != 0) {
+        /* explicit schemes: each face value from its own five averages; the
+         * "+" value at node i-1/2 is the "-" formula on the stencil mirrored
+         * about that node (cells i+2 .. i-2) */
+        for (int i = 0; i < n; ++i) {
+            for (int k = 0; k < 5; ++k) v[k] = ue[i + 1 + k];
+            um[i] = weno5_explicit(v, P->recon, P);
+            for (int k = 0; k < 5; ++k) v[k] = ue[i + 5 - k];
+            up[i] = weno5_explicit(v, P->recon, P);
+        }
+        return 0;
+    }
     /* "-" system: row i sits at node i+1/2; stencil cells i-2..i+2. */
     for (int i = 0; i < n; ++i) {
         for (int k = 0; k < 5; ++k) v[k] = ue[i + 1 + k];

@@ -1,6 +1,8 @@
 """Pins of the CPU oracle's building blocks against what the paper and the
 mathematics fix (no GPU).  Each test names the passage it checks."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -455,3 +457,73 @@ def test_suite_generators_integrate_the_printed_data():
     # Woodward-Colella: total energy of the three pressure slabs
     U = W.woodward_colella_1d(200)
     assert abs(U[2].sum() / 200 - (1000 * 0.1 + 0.01 * 0.8 + 100 * 0.1) / (g - 1)) < 1e-9
+
+
+# --------------------------------------- explicit WENO-JS / WENO-Z (Sec. 3)
+def _explicit_avgs(n, antideriv, a=0.0, b=2.0):
+    """Exact averages of cells -3..n+2 from an antiderivative."""
+    h = (b - a) / n
+    e = a + np.arange(-3, n + 4) * h
+    F = antideriv(e)
+    return (F[1:] - F[:-1]) / h, h, e
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_explicit_weno_reproduces_quadratics(kind):
+    """Each candidate of the explicit reconstruction is exact for quadratics,
+    so any convex weighting is: face values of 1 + 2x - 3x^2 from its exact
+    averages, both sides, to rounding."""
+    n = 12
+    ue, h, e = _explicit_avgs(n, lambda x: x + x ** 2 - x ** 3)
+    um, up = oracle.recon_scalar(ue, False, oracle.params(recon=kind))
+    q = lambda x: 1 + 2 * x - 3 * x ** 2
+    np.testing.assert_allclose(um, q(e[4:4 + n]), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(up, q(e[3:3 + n]), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind,linear", [(1, True), (1, False), (2, False)])
+def test_explicit_weno_fifth_order(kind, linear):
+    """Face values of sin(pi x) from exact averages converge at fifth order
+    (measured orders 4.97-5.00 for N = 20..160), with the linear weights
+    (0.1, 0.6, 0.3) and with either nonlinear weight rule."""
+    errs = []
+    for n in (20, 40, 80):
+        ue, h, e = _explicit_avgs(n, lambda x: -np.cos(np.pi * x) / np.pi)
+        um, up = oracle.recon_scalar(ue, False, oracle.params(recon=kind, linear=linear))
+        errs.append(max(np.abs(um - np.sin(np.pi * e[4:4 + n])).max(),
+                        np.abs(up - np.sin(np.pi * e[3:3 + n])).max()))
+    for a, b in zip(errs[:-1], errs[1:]):
+        assert 4.8 < np.log2(a / b) < 5.2, errs
+
+
+@pytest.mark.parametrize("kind,tol", [(1, 1e-10), (2, 1e-20)])
+def test_explicit_weno_is_essentially_non_oscillatory(kind, tol):
+    """At a unit step the nonlinear weights pick the candidate that does not
+    cross it: the face of the jump sees 0 from the left and 1 from the right
+    (the linear weights give 0.4 there instead, a mistake in the weights
+    fails this)."""
+    n = 20
+    ue = np.zeros(n + 6)
+    ue[3 + 10:] = 1.0
+    um, up = oracle.recon_scalar(ue, False, oracle.params(recon=kind))
+    assert abs(um[9]) < tol and abs(up[10] - 1.0) < tol
+    lm, _ = oracle.recon_scalar(ue, False, oracle.params(recon=kind, linear=True))
+    assert abs(lm[9] - 0.4) < 1e-14
+
+
+def test_explicit_weno_js_matches_table2_column():
+    """Table 2's WENO-JS columns (Example 3.1, lambda max(|u|+a) = 0.16,
+    t = 2), run by the oracle's explicit WENO-JS scheme with the same HLLC
+    flux and SSP-RK3: L1 and Linf within 2 % of the printed values at
+    N = 15, 30, 60 (measured 1.000-1.010; at N = 120 the time error adds 4 %)."""
+    with open(os.path.join(os.path.dirname(__file__), "golden",
+                           "table2_wenojs_conservative.json")) as f:
+        rows = {r[0]: r for r in json.load(f)["rows"]}
+    for n in (15, 30, 60):
+        U0 = W.density_wave_1d(n)
+        U, info = oracle.run_1d(U0, (0, 0), 2.0 / n, 2.0, cfl=0.16, rule=0,
+                                p=oracle.params(recon=1))
+        assert abs(info["t"] - 2.0) < 1e-12
+        l1, l2, linf = W.error_norms(U[0], W.density_wave_1d(n, t=info["t"])[0], 2.0 / n)
+        assert abs(l1 / rows[n][1] - 1) < 0.02, (n, l1, rows[n][1])
+        assert abs(linf / rows[n][2] - 1) < 0.02, (n, linf, rows[n][2])
