@@ -75,6 +75,16 @@ enum { PP_DT_CFL = 0, PP_DT_H53 = 1 };
  * both precisions. */
 enum { PP_FLUX_HLLC = 0, PP_FLUX_LF = 1 };
 
+/* Interface reconstruction (Sec. 2.2 and the comparisons of Sec. 3).
+ * PP_RECON_CWENO: the compact scheme, solution-dependent tridiagonal systems
+ * (the default and the paper's method).  PP_RECON_WENOJS / PP_RECON_WENOZ:
+ * the classical explicit fifth-order finite-volume WENO the paper compares
+ * against, with Jiang-Shu weights (eps 1e-6, a reading; the paper gives
+ * none) or WENO-Z weights (weno_eps), each face value from its own five
+ * averages.  The limiter, flux and stage update are shared.  The explicit
+ * schemes run in FP64 without a batch (else PP_EUNSUPPORTED at init). */
+enum { PP_RECON_CWENO = 0, PP_RECON_WENOJS = 1, PP_RECON_WENOZ = 2 };
+
 typedef struct {
     int ndim;            /* 1, or 2 (dimension-by-dimension sweeps)                    */
     int64_t nx, ny;      /* cells (ny = 1 in 1D); nx <= 4096 in 1D, nx, ny <= 2048 in 2D */
@@ -92,10 +102,12 @@ typedef struct {
     const int *bcs;         /* host [nbatch][2] boundary codes (batched; non-periodic)  */
     void *stream;        /* hipStream_t to enqueue on (NULL: the null stream)           */
     int flux;            /* PP_FLUX_HLLC (default) or PP_FLUX_LF                        */
+    int recon;           /* PP_RECON_CWENO (default), PP_RECON_WENOJS or PP_RECON_WENOZ  */
 } pp_cweno_config;
 
 /* Fill *cfg with defaults: ndim 1, gamma 1.4, epsilons 1e-13, gl_w1 1/12, FP64,
- * HLLC, periodic, no batch, null stream.  Sizes and spacings are left zero. */
+ * HLLC, compact reconstruction, periodic, no batch, null stream.  Sizes and
+ * spacings are left zero. */
 void pp_cweno_config_defaults(pp_cweno_config *cfg);
 
 /* Validate cfg, allocate device scratch, and return a context in *out

@@ -19,6 +19,7 @@ PP_BC_PERIODIC, PP_BC_TRANSMISSIVE, PP_BC_REFLECTIVE = 0, 1, 2
 PP_FP64, PP_MIXED = 0, 1
 PP_DT_CFL, PP_DT_H53 = 0, 1
 PP_FLUX_HLLC, PP_FLUX_LF = 0, 1
+PP_RECON_CWENO, PP_RECON_WENOJS, PP_RECON_WENOZ = 0, 1, 2
 
 EXPORTED = [
     "pp_cweno_config_defaults", "pp_cweno_init", "pp_cweno_rhs", "pp_cweno_stage",
@@ -45,6 +46,7 @@ class Config(ctypes.Structure):
         ("lengths", ctypes.POINTER(ctypes.c_int64)), ("dxs", ctypes.POINTER(ctypes.c_double)),
         ("bcs", ctypes.POINTER(ctypes.c_int)), ("stream", ctypes.c_void_p),
         ("flux", ctypes.c_int),
+        ("recon", ctypes.c_int),
     ]
 
 
@@ -115,7 +117,7 @@ class Solver:
 
     def __init__(self, ndim=1, nx=0, ny=1, dx=0.0, dy=0.0, gamma=1.4, bc=(0, 0, 0, 0),
                  precision=PP_FP64, weno_eps=1e-13, pp_eps_cap=1e-13, gl_w1=1.0 / 12.0,
-                 lengths=None, dxs=None, bcs=None, stream=None, flux=None):
+                 lengths=None, dxs=None, bcs=None, stream=None, flux=None, recon=None):
         c = default_config()
         c.ndim, c.nx, c.ny, c.dx, c.dy, c.gamma = ndim, nx, ny, dx, dy, gamma
         for i in range(4):
@@ -123,6 +125,8 @@ class Solver:
         c.precision, c.weno_eps, c.pp_eps_cap, c.gl_w1 = precision, weno_eps, pp_eps_cap, gl_w1
         if flux is not None:
             c.flux = int(flux)
+        if recon is not None:
+            c.recon = int(recon)
         self._keep = []
         if lengths is not None:
             nb = len(lengths)

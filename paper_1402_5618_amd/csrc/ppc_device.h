@@ -157,6 +157,26 @@ __device__ __forceinline__ double weno5z_value(double v0, double v1, double v2, 
     return (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
 }
 
+// The comparison scheme of Sec 3 (Jiang-Shu WENO): the same candidates and
+// indicators as above with alpha_k = d_k / (beta_k + eps)^2, eps = 1e-6 (Jiang
+// and Shu's value; the paper states none).
+constexpr double kWenoJsEps = 1e-6;
+__device__ __forceinline__ double weno5js_value(double v0, double v1, double v2, double v3,
+                                                double v4) {
+    const double k13 = 13.0 / 12.0;
+    double s0 = v0 - 2.0 * v1 + v2, t0 = v0 - 4.0 * v1 + 3.0 * v2;
+    double s1 = v1 - 2.0 * v2 + v3, t1 = v1 - v3;
+    double s2 = v2 - 2.0 * v3 + v4, t2 = 3.0 * v2 - 4.0 * v3 + v4;
+    double d0 = k13 * s0 * s0 + 0.25 * t0 * t0 + kWenoJsEps;
+    double d1 = k13 * s1 * s1 + 0.25 * t1 * t1 + kWenoJsEps;
+    double d2 = k13 * s2 * s2 + 0.25 * t2 * t2 + kWenoJsEps;
+    double a0 = 0.1 / (d0 * d0), a1 = 0.6 / (d1 * d1), a2 = 0.3 / (d2 * d2);
+    double p0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) / 6.0;
+    double p1 = (-v1 + 5.0 * v2 + 2.0 * v3) / 6.0;
+    double p2 = (2.0 * v2 + 5.0 * v3 - v4) / 6.0;
+    return (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
+}
+
 // ------------------------------------------------------------- Sec 2.4
 // HLLC flux across a face with normal momentum component NRM (1: x, 2: y).
 // Contact speed with rho_r in its right term, S_R = max of its candidates,

@@ -485,13 +485,18 @@ __device__ __forceinline__ void rows_from_w(float w0, float w2, float& a, float&
 // LOOPED: the caller runs line_op in a loop; the thread index is then passed
 // through an empty asm so that values derived from it are recomputed per
 // line rather than hoisted out of the loop and kept (spilled) across the solve.
-template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED, bool LOOPED = false>
+// RECON: the reconstruction, PP_RECON_CWENO (the compact scheme) or one of the
+// explicit comparison schemes (FP64 only; phase 1 then evaluates every face
+// value from its own five averages and solves nothing).
+template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED, bool LOOPED = false,
+          int RECON = PP_RECON_CWENO>
 __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) {
+    static_assert(RECON == PP_RECON_CWENO || !MIXED, "explicit schemes run in FP64");
     constexpr int NS = 2 * NC;
     constexpr int LANES = 64 * W;
     constexpr int NT = NS * LANES;
     // FP64 lines of up to 2048 cells: both sides of a component per lane
-    constexpr bool PAIRED = !MIXED && W == 1;
+    constexpr bool PAIRED = !MIXED && W == 1 && RECON == PP_RECON_CWENO;
     constexpr int PSH = PAIRED ? 4 : 5;   // chunk stride 16 (paired) or 32 rows
     int tid = threadIdx.x;
     if constexpr (LOOPED) asm volatile("" : "+v"(tid));
@@ -616,6 +621,21 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
         else
             paired_solve<false>(sUc, n, k, P, cyclic, A.weno_eps, sxc, red + 4 * comp, r0, len, E0,
                                 E1, E2, F0, F1, F2);
+    } else if constexpr (RECON != PP_RECON_CWENO) {
+        // explicit scheme: x_g is the "-" value at node g+1/2 of this
+        // system's (possibly reversed) line, from cells g-2 .. g+2
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < kCH; ++j) {
+                if (j < len) {
+                    const int g = r0 + j;
+                    E0[j] = RECON == PP_RECON_WENOJS
+                                ? weno5js_value(ub(g - 2), ub(g - 1), ub(g), ub(g + 1), ub(g + 2))
+                                : weno5z_value(ub(g - 2), ub(g - 1), ub(g), ub(g + 1), ub(g + 2),
+                                               A.weno_eps);
+                }
+            }
+        }
     } else if constexpr (!MIXED) {
         double ae = 0.0, be = 1.0, ce = 0.0, re = 0.0;
         double gP = 0.0, gQ = 1.0, gS = 0.0;   // x_{r1-2} = gP + gQ L + gS R
@@ -1064,11 +1084,11 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     }
 }
 
-template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED>
+template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED, int RECON = PP_RECON_CWENO>
 __global__ void __launch_bounds__(2 * NC * 64 * W) line_kernel(LineArgs A) {
     extern __shared__ double smem[];
     if (A.scal && !A.scal->active) return;
-    line_op<NC, NRM, W, CPT, SEG1, MIXED>(A, blockIdx.x, smem);
+    line_op<NC, NRM, W, CPT, SEG1, MIXED, false, RECON>(A, blockIdx.x, smem);
 }
 
 // Batched ensemble: one persistent launch per stage; workgroups pop problem
@@ -1529,10 +1549,10 @@ struct TimedChain {
 };
 
 // Dynamic LDS of the line kernel for lines of up to nmax cells.
-template <int NC, int W, bool MIXED>
+template <int NC, int W, bool MIXED, int RECON = PP_RECON_CWENO>
 size_t line_lds_bytes(int nmax, int seg_max) {
     constexpr int NS = 2 * NC, LANES = 64 * W, NT = NS * LANES;
-    constexpr int SH = (!MIXED && W == 1) ? 4 : 5;   // as the kernel's padding
+    constexpr int SH = (!MIXED && W == 1 && RECON == PP_RECON_CWENO) ? 4 : 5;   // as the kernel's padding
     const long long LP = padn<SH>(nmax + 2 * kNG - 1) + 1;
     const long long a0 = (long long)NC * LP;
     const long long a1 = (W > 1 || !MIXED) ? (long long)NS * 512 : 0;
@@ -1543,12 +1563,12 @@ size_t line_lds_bytes(int nmax, int seg_max) {
 
 constexpr size_t kLdsBudget = 160 * 1024;
 
-template <int NC, int W, int CPT, bool MIXED>
+template <int NC, int W, int CPT, bool MIXED, int RECON = PP_RECON_CWENO>
 int pick_segment(int nmax) {
     constexpr int NT = 2 * NC * 64 * W;
     int seg = nmax;
     while (seg > 64 &&
-           (line_lds_bytes<NC, W, MIXED>(nmax, seg) > kLdsBudget || (seg + NT - 1) / NT > CPT))
+           (line_lds_bytes<NC, W, MIXED, RECON>(nmax, seg) > kLdsBudget || (seg + NT - 1) / NT > CPT))
         seg = (seg + 1) / 2;
     return seg;
 }
@@ -1581,8 +1601,36 @@ int launch_line_p(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int 
     return PP_OK;
 }
 
+// One line launch of an explicit comparison scheme (FP64, not persistent).
+template <int NC, int NRM, int W, int CPT, int RECON>
+int launch_line_explicit(pp_cweno_ctx* ctx, LineArgs A, int nmax) {
+    constexpr int NT = 2 * NC * 64 * W;
+    const int seg = pick_segment<NC, W, CPT, false, RECON>(nmax);
+    A.seg_max = seg;
+    const size_t lds = line_lds_bytes<NC, W, false, RECON>(nmax, seg);
+    if (lds > kLdsBudget || (seg + NT - 1) / NT > CPT)
+        return fail(ctx, PP_EUNSUPPORTED, "line too long for the on-chip line kernel");
+    const void* fn = seg >= nmax ? (const void*)line_kernel<NC, NRM, W, CPT, true, false, RECON>
+                                 : (const void*)line_kernel<NC, NRM, W, CPT, false, false, RECON>;
+    size_t& granted = ctx->lds_granted[fn];
+    if (lds > granted) {
+        HIPCHK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        granted = lds;
+    }
+    void* args[] = {&A};
+    HIPCHK(ctx, hipLaunchKernel(fn, dim3(A.nlines), dim3(NT), args, lds, ctx->stream));
+    return PP_OK;
+}
+
 template <int NC, int NRM, int W, int CPT>
 int launch_line(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int grid) {
+    if (ctx->cfg.recon != PP_RECON_CWENO) {
+        // init admits explicit schemes only in FP64 and without a batch
+        if (persistent) return fail(ctx, PP_EUNSUPPORTED, "explicit schemes are not batched");
+        return ctx->cfg.recon == PP_RECON_WENOJS
+                   ? launch_line_explicit<NC, NRM, W, CPT, PP_RECON_WENOJS>(ctx, A, nmax)
+                   : launch_line_explicit<NC, NRM, W, CPT, PP_RECON_WENOZ>(ctx, A, nmax);
+    }
     if (ctx->cfg.precision == PP_MIXED)
         return launch_line_p<NC, NRM, W, CPT, true>(ctx, A, nmax, persistent, grid);
     return launch_line_p<NC, NRM, W, CPT, false>(ctx, A, nmax, persistent, grid);
@@ -1906,6 +1954,10 @@ int pp_cweno_init(const pp_cweno_config* cfg, pp_cweno_ctx** out) {
     if (!(c.gl_w1 > 0.0 && c.gl_w1 < 0.5)) return fail(nullptr, PP_EINVAL, "gl_w1 must be in (0, 1/2)");
     if (c.flux != PP_FLUX_HLLC && c.flux != PP_FLUX_LF)
         return fail(nullptr, PP_EINVAL, "flux must be PP_FLUX_HLLC or PP_FLUX_LF");
+    if (c.recon != PP_RECON_CWENO && c.recon != PP_RECON_WENOJS && c.recon != PP_RECON_WENOZ)
+        return fail(nullptr, PP_EINVAL, "recon must be PP_RECON_CWENO, _WENOJS or _WENOZ");
+    if (c.recon != PP_RECON_CWENO && (c.precision != PP_FP64 || c.nbatch > 0))
+        return fail(nullptr, PP_EUNSUPPORTED, "explicit schemes run in FP64 and unbatched");
     if (!(c.weno_eps > 0.0) || !(c.pp_eps_cap > 0.0))
         return fail(nullptr, PP_EINVAL, "epsilons must be > 0");
     if (c.precision != PP_FP64 && c.precision != PP_MIXED)
@@ -2106,7 +2158,7 @@ int pp_cweno_run(pp_cweno_ctx* ctx, double* U, double t_end, int64_t nsteps_max,
     if (!r && c.ndim == 2) r = transpose_2d(ctx, U, ctx->UB);
     if (r) return r;
     Scal host{};
-    if (c.ndim == 1) {
+    if (c.ndim == 1 && c.recon == PP_RECON_CWENO) {
         // one workgroup runs the line for up to 4096 steps per launch; the
         // host checks the scalars between launches
         for (;;) {
@@ -2121,7 +2173,8 @@ int pp_cweno_run(pp_cweno_ctx* ctx, double* U, double t_end, int64_t nsteps_max,
         if (host.status) return fail(ctx, PP_ESTATE, "a stage left the admissible set or was not finite");
         return PP_OK;
     }
-    // 2D: (dt kernel, step) pairs are launched in batches; the dt kernel
+    // 2D, and the explicit comparison schemes in 1D: (dt kernel, step) pairs
+    // are launched in batches; the dt kernel
     // retires the run at t_end or after nsteps_max steps (later launches
     // return at once), and each batch ends with a host check of the scalars.
     int64_t launched = 0;

@@ -30,7 +30,7 @@ def test_config_defaults():
     c = pp.default_config()
     assert c.ndim == 1 and c.gamma == 1.4 and c.weno_eps == 1e-13 and c.pp_eps_cap == 1e-13
     assert abs(c.gl_w1 - 1.0 / 12.0) < 1e-16 and c.precision == pp.PP_FP64 and c.nbatch == 0
-    assert c.flux == pp.PP_FLUX_HLLC
+    assert c.flux == pp.PP_FLUX_HLLC and c.recon == pp.PP_RECON_CWENO
 
 
 def _init(**kw):
@@ -60,6 +60,10 @@ def _init(**kw):
     (dict(weno_eps=0.0), pp.PP_EINVAL),
     (dict(flux=2), pp.PP_EINVAL),
     (dict(flux=-1), pp.PP_EINVAL),
+    (dict(recon=3), pp.PP_EINVAL),
+    (dict(recon=-1), pp.PP_EINVAL),
+    (dict(recon=1, precision=1), pp.PP_EUNSUPPORTED),   # explicit schemes: FP64 only
+    (dict(recon=2, nbatch=2), pp.PP_EUNSUPPORTED),      # and not batched
     (dict(nx=5000), pp.PP_EUNSUPPORTED),
     (dict(ndim=2, ny=3000, dy=0.1, nx=64), pp.PP_EUNSUPPORTED),
     (dict(ndim=2, ny=64, dy=0.0), pp.PP_EINVAL),

@@ -706,6 +706,94 @@ def test_mixed_stage_bound_lax_friedrichs(n, bc):
     s.close()
 
 
+@pytest.mark.parametrize("recon", [1, 2])
+@pytest.mark.parametrize("n,bc", [(5, (0, 0)), (7, (1, 2)), (200, (2, 1)), (2048, (0, 0)),
+                                  (3000, (1, 1))])
+def test_1d_stage_parity_explicit(recon, n, bc):
+    """The explicit comparison schemes (PP_RECON_WENOJS / _WENOZ): all three
+    stages against the oracle with the same reconstruction, on short,
+    ragged, full single-wave and two-wave lines with every boundary kind."""
+    pp = gpu()
+    print(f"case explicit recon={recon} n={n} bc={bc}", flush=True)
+    h = 1.0 / n
+    U = mixed_line(n, seed=n + 31)
+    dt = (1.0 / 12.0) * h / oracle.max_speed_1d(U)
+    P = oracle.params(recon=recon)
+    s = pp.Solver(ndim=1, nx=n, dx=h, bc=(*bc, 0, 0), recon=recon)
+    Ud = dev(U)
+    U1 = oracle.stage_1d(U, U, 1, dt, bc, h, P)
+    U2 = oracle.stage_1d(U, U1, 2, dt, bc, h, P)
+    U3 = oracle.stage_1d(U, U2, 3, dt, bc, h, P)
+    o1, o2, o3 = (torch.empty_like(Ud) for _ in range(3))
+    s.stage(Ud, Ud, o1, 1, dt)
+    s.stage(Ud, dev(U1), o2, 2, dt)
+    s.stage(Ud, dev(U2), o3, 3, dt)
+    torch.cuda.synchronize()
+    for st, (got, ref) in enumerate(((o1, U1), (o2, U2), (o3, U3)), start=1):
+        err = comp_rel(got.cpu().numpy(), ref)
+        assert err <= TOL_STAGE, (st, err)
+    # a different scheme from the compact one
+    assert comp_rel(oracle.stage_1d(U, U, 1, dt, bc, h), U1) > 1e-8
+    s.close()
+
+
+@pytest.mark.parametrize("recon", [1, 2])
+@pytest.mark.parametrize("nx,ny,bc", [(48, 40, (1, 2, 2, 1)), (64, 64, (0, 0, 0, 0))])
+def test_2d_stage_parity_explicit(recon, nx, ny, bc):
+    """2D sweeps and combine with the explicit schemes."""
+    pp = gpu()
+    x = W.cell_centres(0, 1, nx)[None, :]
+    y = W.cell_centres(0, 1, ny)[:, None]
+    rho = 1 + 0.3 * np.sin(2 * np.pi * (x + 2 * y)) + 0.5 * ((x - 0.5) ** 2 + (y - 0.4) ** 2 < 0.06)
+    u = 0.3 * np.cos(2 * np.pi * y) + 0 * x
+    v = -0.2 * np.sin(2 * np.pi * x) + 0 * y
+    p = 1 + 0.5 * (x > 0.6) + 0 * y
+    U = np.stack([rho, rho * u, rho * v, p / 0.4 + 0.5 * rho * (u * u + v * v)])
+    dx, dy = 1.0 / nx, 1.0 / ny
+    s_x, s_y = oracle.max_speed_2d(U)
+    dt = (1.0 / 12.0) / (s_x / dx + s_y / dy)
+    P = oracle.params(recon=recon)
+    s = pp.Solver(ndim=2, nx=nx, ny=ny, dx=dx, dy=dy, bc=bc, recon=recon)
+    Ud = dev(U)
+    ref1 = oracle.stage_2d(U, U, 1, dt, bc, dx, dy, P)
+    ref2 = oracle.stage_2d(U, ref1, 2, dt, bc, dx, dy, P)
+    o1, o2 = torch.empty_like(Ud), torch.empty_like(Ud)
+    s.stage(Ud, Ud, o1, 1, dt)
+    s.stage(Ud, dev(ref1), o2, 2, dt)
+    torch.cuda.synchronize()
+    assert comp_rel(o1.cpu().numpy(), ref1) <= TOL_STAGE
+    assert comp_rel(o2.cpu().numpy(), ref2) <= TOL_STAGE
+    s.close()
+
+
+def test_explicit_wenojs_run_matches_oracle_and_table2():
+    """A whole 1D run with the explicit WENO-JS scheme (Example 3.1, N = 60,
+    lambda max(|u|+a) = 0.16, t = 2) through pp_cweno_run: the same step
+    count and final time as the oracle's run, the state within 1e-11, and
+    the L1 error within 2 % of Table 2's printed WENO-JS value."""
+    import json
+    import os
+    pp = gpu()
+    n = 60
+    h = 2.0 / n
+    U0 = W.density_wave_1d(n)
+    s = pp.Solver(ndim=1, nx=n, dx=h, bc=(0, 0, 0, 0), recon=pp.PP_RECON_WENOJS)
+    Ud = dev(U0)
+    t, steps = s.run(Ud, 2.0, 1 << 40, 0.16, pp.PP_DT_CFL)
+    torch.cuda.synchronize()
+    got = Ud.cpu().numpy()
+    ref, info = oracle.run_1d(U0, (0, 0), h, 2.0, cfl=0.16, rule=0,
+                              p=oracle.params(recon=1))
+    assert steps == info["steps"] and abs(t - info["t"]) <= 1e-13
+    assert comp_rel(got, ref) <= 1e-11
+    with open(os.path.join(os.path.dirname(__file__), "golden",
+                           "table2_wenojs_conservative.json")) as f:
+        printed = {r[0]: r for r in json.load(f)["rows"]}[n][1]
+    l1 = W.error_norms(got[0], W.density_wave_1d(n, t=t)[0], h)[0]
+    assert abs(l1 / printed - 1) < 0.02, (l1, printed)
+    s.close()
+
+
 def test_max_speed_entry_point():
     """pp_cweno_max_speed: max(|u|+a) over the cell averages (2D: and
     max(|v|+a)) against the oracle's reductions, 1D and 2D."""
