@@ -100,15 +100,20 @@ def other_workload(args):
                    config={"workload": f"copy of {nbytes} bytes x {args.steps}"})
     elif args.workload == "accuracy":
         # cost against L1 error (the paper's Table 2 / Fig. 1 methodology) for
-        # both forms: the 2D density wave to a fixed time on N^2 grids
+        # both forms of the compact scheme and the explicit WENO-JS / WENO-Z
+        # schemes it is compared with: the 2D density wave to a fixed time on
+        # N^2 grids
         T = 0.05
         rows = []
+        forms = (("fp64", pp.PP_FP64, pp.PP_RECON_CWENO), ("mixed", pp.PP_MIXED, pp.PP_RECON_CWENO),
+                 ("wenojs", pp.PP_FP64, pp.PP_RECON_WENOJS), ("wenoz", pp.PP_FP64, pp.PP_RECON_WENOZ))
         for n in (128, 256, 512, 1024, 2048):
             dx = 2.0 / n
             U0 = W.density_wave_2d(n, n)
-            for name, pr in (("fp64", pp.PP_FP64), ("mixed", pp.PP_MIXED)):
+            for name, pr, rc in forms:
                 U = torch.tensor(U0, device="cuda")
-                s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=(0, 0, 0, 0), precision=pr)
+                s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=(0, 0, 0, 0), precision=pr,
+                              recon=rc)
                 warm = U.clone()
                 s.run(warm, T, 3, 1.0 / 12.0)
                 torch.cuda.synchronize()
@@ -123,25 +128,31 @@ def other_workload(args):
                              "cell_updates_per_s": n * n * k / wall})
                 print(f"accuracy: n={n} {name} steps={k} wall={wall:.3f}s L1={l1:.3e}",
                       file=sys.stderr, flush=True)
-        # equal accuracy: for each FP64 point, the cheapest mixed run with an L1
-        # at least as small, if any
-        eq = []
-        for r in rows:
-            if r["form"] != "fp64":
-                continue
-            cands = [m for m in rows if m["form"] == "mixed" and m["l1_rho"] <= r["l1_rho"]]
-            if cands:
-                m = min(cands, key=lambda m: m["wall_s"])
-                eq.append({"l1_fp64": r["l1_rho"], "n_fp64": r["n"], "n_mixed": m["n"],
-                           "mixed_speedup": r["wall_s"] / m["wall_s"]})
-            else:
-                eq.append({"l1_fp64": r["l1_rho"], "n_fp64": r["n"], "n_mixed": None,
-                           "mixed_speedup": None})
+        def equal_accuracy(other):
+            # for each compact FP64 point, the cheapest `other` run with an L1
+            # at least as small, if any, and the compact run's speedup over it
+            eq = []
+            for r in rows:
+                if r["form"] != "fp64":
+                    continue
+                cands = [m for m in rows if m["form"] == other and m["l1_rho"] <= r["l1_rho"]]
+                m = min(cands, key=lambda m: m["wall_s"]) if cands else None
+                eq.append({"l1_fp64": r["l1_rho"], "n_fp64": r["n"],
+                           "n_" + other: m["n"] if m else None,
+                           "fp64_speedup": (m["wall_s"] / r["wall_s"]) if m else None})
+            return eq
+        eq = equal_accuracy("mixed")
+        for e in eq:   # the mixed form's speedup over FP64 at equal accuracy
+            sp = e.pop("fp64_speedup")
+            e["mixed_speedup"] = 1.0 / sp if sp else None
         out.update(metric="wall time against L1 error, 2D density wave to t=0.05",
                    value=None, steps=None,
                    config={"workload": "2D density wave, periodic [0,2]^2, CFL 1/12, t = 0.05, "
-                                       "N = 128..2048, FP64 and mixed", "table": rows,
-                           "equal_accuracy": eq})
+                                       "N = 128..2048; compact scheme in FP64 and mixed, "
+                                       "explicit WENO-JS and WENO-Z in FP64", "table": rows,
+                           "equal_accuracy": eq,
+                           "compact_vs_wenojs": equal_accuracy("wenojs"),
+                           "compact_vs_wenoz": equal_accuracy("wenoz")})
     elif args.workload == "sedov2d":
         n = 1024
         dx = 1.1 / n

@@ -157,24 +157,39 @@ __device__ __forceinline__ double weno5z_value(double v0, double v1, double v2, 
     return (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
 }
 
-// The comparison scheme of Sec 3 (Jiang-Shu WENO): the same candidates and
-// indicators as above with alpha_k = d_k / (beta_k + eps)^2, eps = 1e-6 (Jiang
-// and Shu's value; the paper states none).
+// The explicit comparison schemes of Sec 3: the classical fifth-order WENO
+// value at node j+1/2 ("-" side) from v0..v4 = ubar_{j-2..j+2}, with the
+// Jiang-Shu weights alpha_k = d_k / (beta_k + 1e-6)^2 (JS = true; Jiang and
+// Shu's epsilon, the paper states none) or the WENO-Z weights of eq. (weight)
+// with the linear weights d = (0.1, 0.6, 0.3) (JS = false, epsilon eps).
+// As in wenoz_weights, the three weight divisions share one denominator:
+//   JS: alpha_k ~ d_k prod_{l != k} e_l,   Z: alpha_k ~ d_k (e_k + tau^2) prod_{l != k} e_l,
+// e_k = (beta_k + eps)^2, so one reciprocal normalises them.
 constexpr double kWenoJsEps = 1e-6;
-__device__ __forceinline__ double weno5js_value(double v0, double v1, double v2, double v3,
-                                                double v4) {
-    const double k13 = 13.0 / 12.0;
-    double s0 = v0 - 2.0 * v1 + v2, t0 = v0 - 4.0 * v1 + 3.0 * v2;
-    double s1 = v1 - 2.0 * v2 + v3, t1 = v1 - v3;
-    double s2 = v2 - 2.0 * v3 + v4, t2 = 3.0 * v2 - 4.0 * v3 + v4;
-    double d0 = k13 * s0 * s0 + 0.25 * t0 * t0 + kWenoJsEps;
-    double d1 = k13 * s1 * s1 + 0.25 * t1 * t1 + kWenoJsEps;
-    double d2 = k13 * s2 * s2 + 0.25 * t2 * t2 + kWenoJsEps;
-    double a0 = 0.1 / (d0 * d0), a1 = 0.6 / (d1 * d1), a2 = 0.3 / (d2 * d2);
-    double p0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) / 6.0;
-    double p1 = (-v1 + 5.0 * v2 + 2.0 * v3) / 6.0;
-    double p2 = (2.0 * v2 + 5.0 * v3 - v4) / 6.0;
-    return (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
+template <bool JS>
+__device__ __forceinline__ double weno5_explicit(double v0, double v1, double v2, double v3,
+                                                 double v4, double eps) {
+    const double k13 = 13.0 / 12.0, sixth = 1.0 / 6.0;
+    const double s0 = v0 - 2.0 * v1 + v2, t0 = v0 - 4.0 * v1 + 3.0 * v2;
+    const double s1 = v1 - 2.0 * v2 + v3, t1 = v1 - v3;
+    const double s2 = v2 - 2.0 * v3 + v4, t2 = 3.0 * v2 - 4.0 * v3 + v4;
+    const double b0 = k13 * s0 * s0 + 0.25 * t0 * t0;
+    const double b1 = k13 * s1 * s1 + 0.25 * t1 * t1;
+    const double b2 = k13 * s2 * s2 + 0.25 * t2 * t2;
+    const double ep = JS ? kWenoJsEps : eps;
+    const double d0 = b0 + ep, d1 = b1 + ep, d2 = b2 + ep;
+    const double e0 = d0 * d0, e1 = d1 * d1, e2 = d2 * d2;
+    double a0 = 0.1 * (e1 * e2), a1 = 0.6 * (e0 * e2), a2 = 0.3 * (e0 * e1);
+    if constexpr (!JS) {
+        const double tau = b2 - b0, tt = tau * tau;
+        a0 *= e0 + tt;
+        a1 *= e1 + tt;
+        a2 *= e2 + tt;
+    }
+    const double p0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * sixth;
+    const double p1 = (-v1 + 5.0 * v2 + 2.0 * v3) * sixth;
+    const double p2 = (2.0 * v2 + 5.0 * v3 - v4) * sixth;
+    return (a0 * p0 + a1 * p1 + a2 * p2) * rcp_t(a0 + a1 + a2);
 }
 
 // ------------------------------------------------------------- Sec 2.4

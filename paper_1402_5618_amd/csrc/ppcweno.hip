@@ -629,10 +629,8 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
             for (int j = 0; j < kCH; ++j) {
                 if (j < len) {
                     const int g = r0 + j;
-                    E0[j] = RECON == PP_RECON_WENOJS
-                                ? weno5js_value(ub(g - 2), ub(g - 1), ub(g), ub(g + 1), ub(g + 2))
-                                : weno5z_value(ub(g - 2), ub(g - 1), ub(g), ub(g + 1), ub(g + 2),
-                                               A.weno_eps);
+                    E0[j] = weno5_explicit<RECON == PP_RECON_WENOJS>(
+                        ub(g - 2), ub(g - 1), ub(g), ub(g + 1), ub(g + 2), A.weno_eps);
                 }
             }
         }
