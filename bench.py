@@ -46,10 +46,10 @@ FLOPS_PER_SWEEP_CELL = 716.0
 # hash is recorded (profiles/line_kernel_2d_density_wave_2048_fp64.md);
 # otherwise traffic is reported null.
 TRAFFIC_RECORD = {
-    "src_sha256": "8f7f4daf370783b2c567e074b4aca450ccc7781f1a562d7627d5593593d2886c",
+    "src_sha256": "ade9d42fbbeb3fcc1b5651f60dad0a31ce3d9a737880a6896e00d03d1839124c",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "x": {"fetch_kib": 66902.4, "write_kib": 184320.0},
-    "y": {"fetch_kib": 67142.2, "write_kib": 184320.0},
+    "x": {"fetch_kib": 66724.2, "write_kib": 184320.0},
+    "y": {"fetch_kib": 67176.2, "write_kib": 184320.0},
 }
 
 
