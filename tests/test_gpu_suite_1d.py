@@ -46,12 +46,13 @@ CASES = {
 }
 
 
-def gpu_run(U0, bc, h, T, gamma, flux=0):
+def gpu_run(U0, bc, h, T, gamma, flux=0, recon=0):
     import torch
     import paper_1402_5618_amd as pp
 
     n = U0.shape[1]
-    s = pp.Solver(ndim=1, nx=n, dx=h, gamma=gamma, bc=(bc[0], bc[1], 0, 0), flux=flux)
+    s = pp.Solver(ndim=1, nx=n, dx=h, gamma=gamma, bc=(bc[0], bc[1], 0, 0), flux=flux,
+                  recon=recon)
     U = torch.tensor(U0, device="cuda")
     code = pp.PP_OK
     try:
@@ -142,4 +143,26 @@ def test_low_density_123_with_lax_friedrichs():
     for c in range(3):
         d = np.abs(Ug[c] - Uo[c]).sum() / np.abs(Uo[c]).sum()
         assert d <= tol, (c, d)
+    assert Ug[0].min() > 0 and W.pressure(Ug, gamma).min() > 0
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("recon", [1, 2])
+@pytest.mark.parametrize("name", ["sod", "shu_osher", "woodward_colella", "leblanc"])
+def test_suite_explicit_schemes_match_oracle(name, recon):
+    """The explicit WENO-JS (1) and WENO-Z (2) comparison schemes run to the
+    final times of four suite examples (transmissive and reflective ends,
+    gamma 1.4 and 5/3) through pp_cweno_run, against the oracle's runs with
+    the same reconstruction: equal steps and times, the states within the
+    suite's bound, positivity."""
+    make, bc, h, T, gamma, tol = CASES[name]
+    U0 = make()
+    print(f"case {name} recon={recon}", flush=True)
+    Ug, t, steps, code = gpu_run(U0, bc, h, T, gamma, recon=recon)
+    Uo, info = oracle.run_1d(U0, bc, h, T, p=oracle.params(gamma=gamma, recon=recon))
+    assert code == 0 and steps == info["steps"], (code, steps, info["steps"])
+    assert abs(t - info["t"]) <= 1e-12 * T
+    for c in range(3):
+        d = np.abs(Ug[c] - Uo[c]).sum() / np.abs(Uo[c]).sum()
+        assert d <= tol, (name, c, d)
     assert Ug[0].min() > 0 and W.pressure(Ug, gamma).min() > 0
