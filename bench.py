@@ -60,7 +60,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=12,
+                    help="oracle steps of the full grid for cpu_baseline (about 10 s on 16 threads)")
     ap.add_argument("--workload", default="density2d",
                     choices=["density2d", "sedov2d", "ensemble", "wave1d", "rarefaction1d",
                              "blast1d", "copy", "accuracy"])
