@@ -444,6 +444,43 @@ def test_2d_2048_stage_sampled_parity(bc):
     s.close()
 
 
+@pytest.mark.parametrize("recon,bc", [(1, (0, 0, 0, 0)), (2, (1, 2, 2, 1))])
+def test_2d_2048_stage_sampled_parity_explicit(recon, bc):
+    """The explicit schemes at the 2048^2 size the accuracy comparison runs
+    (single-segment staging, one workgroup per CU), one stage, sampled cells
+    against the oracle's row and column operators with the same
+    reconstruction."""
+    pp = gpu()
+    n = 2048
+    dx = 2.0 / n
+    U = W.density_wave_2d(n, n)
+    yy, xx = np.mgrid[0:n, 0:n]
+    U[0] += 0.3 * (((xx - 700) ** 2 + (yy - 900) ** 2) < 200 ** 2)
+    sx, sy = oracle.max_speed_2d(U)
+    dt = (1.0 / 12.0) / (sx / dx + sy / dx)
+    print(f"2048^2 explicit stage parity, recon {recon} bc {bc}", flush=True)
+    s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=bc, recon=recon)
+    Ud = dev(U)
+    out = torch.empty_like(Ud)
+    s.stage(Ud, Ud, out, 1, dt)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    er, ee = oracle.eps(U)
+    P = oracle.params(recon=recon)
+    rng = np.random.default_rng(9)
+    pts = [(int(y), int(x)) for y, x in rng.integers(0, n, size=(10, 2))] + [(900, 500)]
+    pts += [(0, 0), (n - 1, n - 1), (1, 2)]
+    scale = np.abs(U).reshape(4, -1).max(axis=1)
+    for (y, x) in pts:
+        Lx = oracle.line_op(np.ascontiguousarray(U[:, y, :]), bc[0], bc[1], dx, p=P, eps_rho=er,
+                            eps_e=ee, nrm=1)
+        Ly = oracle.line_op(np.ascontiguousarray(U[:, :, x]), bc[2], bc[3], dx, p=P, eps_rho=er,
+                            eps_e=ee, nrm=2)
+        ref = U[:, y, x] + dt * (Lx[:, x] + Ly[:, y])
+        assert np.all(np.abs(got[:, y, x] - ref) <= TOL_STAGE * scale), (y, x)
+    s.close()
+
+
 def test_1d_density_wave_full_run():
     """Example 3.1 at N = 200 to t = 2 with dt = w1 h^(5/3) / max(|u|+a):
     ~120k steps through pp_cweno_run against the oracle's run."""
