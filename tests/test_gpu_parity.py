@@ -263,6 +263,42 @@ def test_batch_step_parity(n_lo, n_hi, plan):
     s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_ensemble_step_sampled_parity(precision):
+    """The benchmarked ensemble at full size (4096 seeded Riemann problems,
+    N in [256, 4096], 8.8 M cells) in the bench's launch configuration (the
+    autotuner's plan): one step of every problem with its own dt, sampled
+    problems (the longest, the shortest and random ones) against the
+    oracle's stages; FP64 to the stage tolerance, mixed to its bound."""
+    pp = gpu()
+    ens = W.riemann_ensemble()
+    nb = len(ens.lengths)
+    print(f"case full ensemble {precision}: {nb} problems, {ens.U.shape[1]} cells", flush=True)
+    s = pp.Solver(ndim=1, lengths=ens.lengths, dxs=ens.dx, bcs=[1] * (2 * nb),
+                  precision=pp.PP_FP64 if precision == "fp64" else pp.PP_MIXED)
+    plan, _ = s.batch_tune(dev(ens.U), 1.0 / 12.0)
+    rng = np.random.default_rng(21)
+    sample = sorted(set([int(np.argmax(ens.lengths)), int(np.argmin(ens.lengths))] +
+                        [int(i) for i in rng.integers(0, nb, size=10)]))
+    dts = np.array([(1.0 / 12.0) * ens.dx[i] /
+                    oracle.max_speed_1d(ens.U[:, ens.offsets[i]:ens.offsets[i + 1]])
+                    for i in range(nb)])
+    Ud = dev(ens.U)
+    s.batch_step(Ud, dev(dts))
+    torch.cuda.synchronize()
+    got = Ud.cpu().numpy()
+    tol = TOL_STAGE if precision == "fp64" else TOL_MIXED_STAGE
+    for i in sample:
+        sl = slice(ens.offsets[i], ens.offsets[i + 1])
+        U = ens.U[:, sl]
+        h = ens.dx[i]
+        U1 = oracle.stage_1d(U, U, 1, dts[i], (1, 1), h)
+        U2 = oracle.stage_1d(U, U1, 2, dts[i], (1, 1), h)
+        U3 = oracle.stage_1d(U, U2, 3, dts[i], (1, 1), h)
+        assert comp_rel(got[:, sl], U3) <= tol, (plan, i, int(ens.lengths[i]))
+    s.close()
+
+
 def test_batch_tune_picks_a_plan_and_results_agree():
     """The autotuner times every launch plan on a copy of the state (left
     unchanged) and keeps the fastest; the plans agree to rounding."""
