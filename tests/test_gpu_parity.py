@@ -224,6 +224,55 @@ def test_2d_sedov_stage_parity(nsteps):
     s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_2d_sedov_1024_stage_sampled_parity(precision):
+    """The near-vacuum blast at its benchmarked size (1024^2, reflective
+    x = 0 and y = 0, transmissive far ends), first stage from the initial
+    state in the bench's launch configuration: sampled cells around the
+    energy-carrying corner cell, on the reflective walls and far away,
+    against the oracle's row and column operators (FP64 to the stage
+    tolerance, mixed to its bound)."""
+    pp = gpu()
+    n, ext = 1024, 1.1
+    dx = ext / n
+    bc = (2, 1, 2, 1)
+    U = W.sedov_corner_2d(n, extent=ext)
+    sx, sy = oracle.max_speed_2d(U)
+    dt = (1.0 / 12.0) / (sx / dx + sy / dx)
+    print(f"case sedov 1024^2 {precision}, dt {dt:.3e}", flush=True)
+    s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=bc,
+                  precision=pp.PP_FP64 if precision == "fp64" else pp.PP_MIXED)
+    Ud = dev(U)
+    out = torch.empty_like(Ud)
+    s.stage(Ud, Ud, out, 1, dt)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    er, ee = oracle.eps(U)
+    rng = np.random.default_rng(3)
+    pts = [(0, 0), (0, 1), (1, 0), (1, 1), (2, 2), (0, 3), (3, 0), (n - 1, n - 1), (0, n - 1)]
+    pts += [(int(y), int(x)) for y, x in rng.integers(0, n, size=(6, 2))]
+    tol = TOL_STAGE if precision == "fp64" else TOL_MIXED_STAGE
+
+    def ref_at(V, y, x):
+        Lx = oracle.line_op(np.ascontiguousarray(V[:, y, :]), bc[0], bc[1], dx, eps_rho=er,
+                            eps_e=ee, nrm=1)
+        Ly = oracle.line_op(np.ascontiguousarray(V[:, :, x]), bc[2], bc[3], dx, eps_rho=er,
+                            eps_e=ee, nrm=2)
+        return V[:, y, x] + dt * (Lx[:, x] + Ly[:, y])
+
+    refs = {pt: ref_at(U, *pt) for pt in pts}
+    # per-component scale: the input's largest magnitude, or the sampled
+    # outputs' (the momenta start at zero; the corner samples carry the blast)
+    scale = np.maximum(np.abs(U).reshape(4, -1).max(axis=1),
+                       np.abs(np.array(list(refs.values()))).max(axis=0))
+    assert np.all(scale > 0)
+    for (y, x) in pts:
+        ref = refs[(y, x)]
+        err = np.max(np.abs(got[:, y, x] - ref) / scale)
+        assert err <= tol, (y, x, err)
+    s.close()
+
+
 # ------------------------------------------------------------ batched ensemble
 def ensemble(nprob, n_lo, n_hi, seed=1402):
     return W.riemann_ensemble(nprob=nprob, seed=seed, n_lo=n_lo, n_hi=n_hi)
