@@ -669,6 +669,31 @@ def test_1d_vacuum_blast_run():
     s.close()
 
 
+def test_1d_double_rarefaction_4000_run():
+    """The N = 4000 double rarefaction of the positivity stress case, through
+    pp_cweno_run (the whole-run kernel with device dt) to t = 0.05 (1441
+    steps, the limiter acting on ~7700 cell-stages near the evacuated
+    centre), against the oracle's run: equal step counts and times, relative
+    L1 differences per component within 1e-9, positivity."""
+    pp = gpu()
+    n = 4000
+    h = 2.0 / n
+    U0 = W.double_rarefaction_1d(n)
+    ref, info = oracle.run_1d(U0, (1, 1), h, 0.05)
+    assert info["limited"] > 0
+    s = pp.Solver(ndim=1, nx=n, dx=h, bc=(1, 1, 0, 0))
+    Ud = dev(U0)
+    t, steps = s.run(Ud, 0.05, 1 << 40)
+    torch.cuda.synchronize()
+    got = Ud.cpu().numpy()
+    assert steps == info["steps"] and abs(t - info["t"]) <= 1e-14
+    d = [float(np.abs(got[k] - ref[k]).sum() / np.abs(ref[k]).sum()) for k in range(3)]
+    print(f"double rarefaction relative L1 differences {d}", flush=True)
+    assert max(d) <= 1e-9
+    assert got[0].min() > 0 and W.pressure(got).min() > 0
+    s.close()
+
+
 # --------------------------------------------------------- mixed precision
 TOL_MIXED_STAGE = 1e-6   # per stage output, relative: float weights/rows/HLLC
 
