@@ -1033,3 +1033,34 @@ def test_batch_continue_equals_one_run():
     with pytest.raises(pp.PPError):
         s.batch_continue(U2, t_end, 1 << 40, 1.0 / 12.0)
     s.close()
+
+
+@pytest.mark.parametrize("ndim", [1, 2])
+def test_runs_are_bitwise_reproducible(ndim):
+    """Deterministic replay: every reduction on the path is a min or a max
+    (order-independent), so two runs of the same problem end bitwise equal,
+    and so do their step counts and times (1D: the whole-run kernel on the
+    N = 4000 double rarefaction with the limiter active; 2D: 40 steps of the
+    512^2 density wave with a blob)."""
+    pp = gpu()
+    if ndim == 1:
+        n = 4000
+        U0 = W.double_rarefaction_1d(n)
+        s = pp.Solver(ndim=1, nx=n, dx=2.0 / n, bc=(1, 1, 0, 0))
+        t_end, cap = 0.02, 1 << 40
+    else:
+        n = 512
+        U0 = W.density_wave_2d(n, n)
+        yy, xx = np.mgrid[0:n, 0:n]
+        U0[0] += 0.3 * (((xx - 200) ** 2 + (yy - 300) ** 2) < 60 ** 2)
+        s = pp.Solver(ndim=2, nx=n, ny=n, dx=2.0 / n, dy=2.0 / n, bc=(0, 0, 0, 0))
+        t_end, cap = 1.0, 40
+    outs = []
+    for _ in range(2):
+        Ud = dev(U0)
+        t, steps = s.run(Ud, t_end, cap, 1.0 / 12.0)
+        torch.cuda.synchronize()
+        outs.append((Ud, t, steps))
+    assert outs[0][1] == outs[1][1] and outs[0][2] == outs[1][2]
+    assert torch.equal(outs[0][0], outs[1][0])
+    s.close()
