@@ -1064,3 +1064,38 @@ def test_runs_are_bitwise_reproducible(ndim):
     assert outs[0][1] == outs[1][1] and outs[0][2] == outs[1][2]
     assert torch.equal(outs[0][0], outs[1][0])
     s.close()
+
+
+def test_status_reports_nonfinite_and_inadmissible_states():
+    """Failure detection forced from the host: the sticky status word after
+    a stage is clear on admissible data, has bit 0 after a non-finite input
+    cell and bit 1 after a CFL violation that drives the output out of G
+    (the oracle's stage with the same dt leaves G too), and is cleared by
+    reading it; a run from a non-finite state stops with PP_ESTATE."""
+    pp = gpu()
+    n = 256
+    h = 1.0 / n
+    U = mixed_line(n, seed=3)
+    dt = (1.0 / 12.0) * h / oracle.max_speed_1d(U)
+    s = pp.Solver(ndim=1, nx=n, dx=h, bc=(1, 1, 0, 0))
+    out = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    Ud = dev(U)
+    s.stage(Ud, Ud, out, 1, dt)
+    assert s.status() == (pp.PP_OK, 0)
+    V = U.copy()
+    V[0, 100] = np.nan
+    Vd = dev(V)
+    s.stage(Vd, Vd, out, 1, dt)
+    code, flags = s.status()
+    assert code == pp.PP_ESTATE and flags & 1
+    assert s.status() == (pp.PP_OK, 0)          # reading clears it
+    big = 100.0 * dt
+    ref = oracle.stage_1d(U, U, 1, big, (1, 1), h)
+    assert ref[0].min() < 0 or W.pressure(ref).min() < 0
+    s.stage(Ud, Ud, out, 1, big)
+    code, flags = s.status()
+    assert code == pp.PP_ESTATE and flags & 2
+    with pytest.raises(pp.PPError) as e:
+        s.run(dev(V), 0.1, 100)
+    assert e.value.code == pp.PP_ESTATE
+    s.close()
