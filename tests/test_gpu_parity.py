@@ -1099,3 +1099,34 @@ def test_status_reports_nonfinite_and_inadmissible_states():
         s.run(dev(V), 0.1, 100)
     assert e.value.code == pp.PP_ESTATE
     s.close()
+
+
+def test_user_stream_and_caller_ownership():
+    """Stream semantics and ownership at the boundary: a context made on a
+    side stream (default priority) enqueues its stage there, and after that
+    stream is synchronised the result equals the same stage on the default
+    stream bitwise; closing the contexts leaves the caller's arrays intact."""
+    pp = gpu()
+    n = 512
+    h = 1.0 / n
+    U = mixed_line(n, seed=9)
+    dt = (1.0 / 12.0) * h / oracle.max_speed_1d(U)
+    Ud = dev(U)
+    out_a = torch.empty_like(Ud)
+    s0 = pp.Solver(ndim=1, nx=n, dx=h, bc=(1, 2, 0, 0))
+    s0.stage(Ud, Ud, out_a, 1, dt)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        Us = Ud.clone()
+        out_b = torch.empty_like(Us)
+    s1 = pp.Solver(ndim=1, nx=n, dx=h, bc=(1, 2, 0, 0), stream=side.cuda_stream)
+    s1.stage(Us, Us, out_b, 1, dt)
+    side.synchronize()
+    assert torch.equal(out_a, out_b)
+    s1.close()
+    s0.close()
+    torch.cuda.synchronize()
+    assert torch.equal(Us, Ud) and torch.equal(out_a, out_b)
+    assert comp_rel(out_b.cpu().numpy(), oracle.stage_1d(U, U, 1, dt, (1, 2), h)) <= TOL_STAGE
