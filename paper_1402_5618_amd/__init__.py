@@ -95,7 +95,11 @@ def lib():
     return _lib
 
 
-def _ptr(t):
+def _ptr(t, numel=None, at_least=False):
+    """Device address of a contiguous float64 GPU tensor, after checking that
+    it holds the `numel` elements the kernels will touch (exactly, or at
+    least that many for small result buffers): the C ABI takes bare
+    pointers and cannot check sizes itself."""
     if t is None:
         return None
     if not (t.is_cuda and t.is_contiguous()):
@@ -103,6 +107,9 @@ def _ptr(t):
     import torch
     if t.dtype != torch.float64:
         raise ValueError("expected float64")
+    if numel is not None and (t.numel() < numel if at_least else t.numel() != numel):
+        raise ValueError(f"expected {'at least ' if at_least else ''}{numel} elements, "
+                         f"got {t.numel()}")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -143,6 +150,14 @@ class Solver:
             stream = torch.cuda.current_stream().cuda_stream
         c.stream = ctypes.c_void_p(stream)
         self.cfg = c
+        # elements of a state array in this context's layout
+        if lengths is not None:
+            self._nstate = 3 * int(sum(int(v) for v in lengths))
+        elif ndim == 2:
+            self._nstate = 4 * int(nx) * int(ny)
+        else:
+            self._nstate = 3 * int(nx)
+        self._nb = len(lengths) if lengths is not None else 0
         self._ctx = ctypes.c_void_p()
         self._check(lib().pp_cweno_init(ctypes.byref(c), ctypes.byref(self._ctx)), init=True)
 
@@ -153,32 +168,36 @@ class Solver:
         return code
 
     def rhs(self, U, L):
-        return self._check(lib().pp_cweno_rhs(self._ctx, _ptr(U), _ptr(L)))
+        n = self._nstate
+        return self._check(lib().pp_cweno_rhs(self._ctx, _ptr(U, n), _ptr(L, n)))
 
     def stage(self, U0, Us, Uout, stage, dt):
-        return self._check(lib().pp_cweno_stage(self._ctx, _ptr(U0), _ptr(Us), _ptr(Uout),
-                                                int(stage), float(dt)))
+        n = self._nstate
+        return self._check(lib().pp_cweno_stage(self._ctx, _ptr(U0, n), _ptr(Us, n),
+                                                _ptr(Uout, n), int(stage), float(dt)))
 
     def step(self, U, dt):
-        return self._check(lib().pp_cweno_step(self._ctx, _ptr(U), float(dt)))
+        return self._check(lib().pp_cweno_step(self._ctx, _ptr(U, self._nstate), float(dt)))
 
     def run(self, U, t_end, nsteps_max=1 << 62, cfl=1.0 / 12.0, rule=PP_DT_CFL):
         t = ctypes.c_double()
         n = ctypes.c_int64()
-        self._check(lib().pp_cweno_run(self._ctx, _ptr(U), float(t_end), int(nsteps_max),
-                                       float(cfl), int(rule), ctypes.byref(t), ctypes.byref(n)))
+        self._check(lib().pp_cweno_run(self._ctx, _ptr(U, self._nstate), float(t_end),
+                                       int(nsteps_max), float(cfl), int(rule), ctypes.byref(t),
+                                       ctypes.byref(n)))
         return t.value, n.value
 
     def batch_step(self, U, dt_dev):
-        return self._check(lib().pp_cweno_batch_step(self._ctx, _ptr(U), _ptr(dt_dev)))
+        return self._check(lib().pp_cweno_batch_step(self._ctx, _ptr(U, self._nstate),
+                                                     _ptr(dt_dev, self._nb)))
 
     def batch_tune(self, U=None, cfl=1.0 / 12.0, force_plan=-1):
         """Pick the batched launch plan: timed over every plan on a copy of U
         (force_plan < 0) or set directly.  Returns (plan, [ms per plan])."""
         plan = ctypes.c_int()
         ms = (ctypes.c_double * 3)(-1.0, -1.0, -1.0)
-        self._check(lib().pp_cweno_batch_tune(self._ctx, _ptr(U), float(cfl), int(force_plan),
-                                              ctypes.byref(plan), ms))
+        self._check(lib().pp_cweno_batch_tune(self._ctx, _ptr(U, self._nstate), float(cfl),
+                                              int(force_plan), ctypes.byref(plan), ms))
         return plan.value, list(ms)
 
     def batch_run(self, U, t_end, nsteps_max=1 << 62, cfl=1.0 / 12.0):
@@ -187,8 +206,8 @@ class Solver:
         nb = self.cfg.nbatch
         steps = (ctypes.c_int64 * nb)()
         self._last_steps = steps
-        self._check(lib().pp_cweno_batch_run(self._ctx, _ptr(U), float(t_end), int(nsteps_max),
-                                             float(cfl), steps))
+        self._check(lib().pp_cweno_batch_run(self._ctx, _ptr(U, self._nstate), float(t_end),
+                                             int(nsteps_max), float(cfl), steps))
         return list(steps)
 
     def batch_continue(self, U, t_end, nsteps_max=1 << 62, cfl=1.0 / 12.0):
@@ -199,8 +218,9 @@ class Solver:
         steps = (ctypes.c_int64 * nb)()
         ts = (ctypes.c_double * nb)()
         self._last_steps, self._last_t = steps, ts
-        self._check(lib().pp_cweno_batch_continue(self._ctx, _ptr(U), float(t_end),
-                                                  int(nsteps_max), float(cfl), steps, ts))
+        self._check(lib().pp_cweno_batch_continue(self._ctx, _ptr(U, self._nstate),
+                                                  float(t_end), int(nsteps_max), float(cfl),
+                                                  steps, ts))
         return list(steps), list(ts)
 
     def last_batch_times(self):
@@ -210,7 +230,8 @@ class Solver:
         return list(self._last_steps)
 
     def max_speed(self, U, out):
-        return self._check(lib().pp_cweno_max_speed(self._ctx, _ptr(U), _ptr(out)))
+        return self._check(lib().pp_cweno_max_speed(self._ctx, _ptr(U, self._nstate),
+                                                    _ptr(out, self.cfg.ndim, at_least=True)))
 
     def status(self):
         f = ctypes.c_uint32()
@@ -218,8 +239,9 @@ class Solver:
         return code, f.value
 
     def debug_line(self, U, um=None, up=None, flux=None):
-        return self._check(lib().pp_cweno_debug_line(self._ctx, _ptr(U), _ptr(um), _ptr(up),
-                                                     _ptr(flux)))
+        n = self._nstate
+        return self._check(lib().pp_cweno_debug_line(self._ctx, _ptr(U, n), _ptr(um, n),
+                                                     _ptr(up, n), _ptr(flux, n + 3)))
 
     def set_timing(self, on=True):
         return self._check(lib().pp_cweno_set_timing(self._ctx, int(bool(on))))

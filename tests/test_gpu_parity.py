@@ -1130,3 +1130,34 @@ def test_user_stream_and_caller_ownership():
     torch.cuda.synchronize()
     assert torch.equal(Us, Ud) and torch.equal(out_a, out_b)
     assert comp_rel(out_b.cpu().numpy(), oracle.stage_1d(U, U, 1, dt, (1, 2), h)) <= TOL_STAGE
+
+
+def test_binding_rejects_wrong_sizes_before_any_launch():
+    """The C ABI takes bare device pointers; the binding checks every array
+    against the context's layout (and dtype, device, contiguity) and raises
+    before anything is enqueued, leaving the context usable."""
+    pp = gpu()
+    n = 64
+    s = pp.Solver(ndim=1, nx=n, dx=1.0 / n, bc=(1, 1, 0, 0))
+    good = dev(mixed_line(n, seed=1))
+    short = torch.zeros(3 * n - 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        s.rhs(good, short)
+    with pytest.raises(ValueError):
+        s.step(torch.zeros(3 * n + 3, dtype=torch.float64, device="cuda"), 1e-4)
+    with pytest.raises(ValueError):
+        s.rhs(good.float(), torch.empty_like(good))
+    with pytest.raises(ValueError):
+        s.rhs(good.cpu(), torch.empty_like(good))
+    with pytest.raises(ValueError):
+        s.max_speed(good, torch.zeros(0, dtype=torch.float64, device="cuda"))
+    L = torch.empty_like(good)
+    s.rhs(good, L)            # still usable
+    torch.cuda.synchronize()
+    assert torch.isfinite(L).all()
+    s.close()
+    ens = W.riemann_ensemble(nprob=4, seed=3, n_lo=8, n_hi=20)
+    sb = pp.Solver(ndim=1, lengths=ens.lengths, dxs=ens.dx, bcs=[1] * 8)
+    with pytest.raises(ValueError):
+        sb.batch_step(dev(ens.U), torch.zeros(3, dtype=torch.float64, device="cuda"))
+    sb.close()
