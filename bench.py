@@ -33,6 +33,9 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6         # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 BYTES_PER_CELL_UPDATE = 544.0   # algorithmic bytes of one 2D SSP-RK3 cell-update
 BYTES_PER_SWEEP_CELL = 64.0     # line kernel: read the stage input, write L
+# combine, averaged over the three stages: reads U0 (not in stage 1), Us, Lx,
+# Ly and writes both layouts, 32 B per cell each: (160 + 192 + 192) / 3
+BYTES_PER_COMBINE_CELL = 544.0 / 3.0
 # Algorithmic FP64 operations of one line sweep per 2D cell (4 components),
 # counted from the scheme's formulas (+ - * / sqrt = 1 each): indicators shared
 # by the two sides 4 x 33, WENO-Z weights 4 x 2 x 23, rows 4 x 2 x 22,
@@ -417,6 +420,13 @@ def main():
             "t_reached": r64["t"],
             "status_flags": r64["flags"],
             "kernel_ms_per_launch": {k: (v[0] / max(v[1], 1)) for k, v in timing.items()},
+            # the HBM-bound kernel of the step: algorithmic bytes per launch
+            # (the stage average) over its HIP-event launch time
+            "combine_hbm": {
+                "achieved_GBs": BYTES_PER_COMBINE_CELL * n * n /
+                (timing["combine"][0] / max(timing["combine"][1], 1) * 1e-3) / 1e9,
+                "peak_GBs": HBM_PEAK_GBS,
+            },
             "mixed": {
                 "value": value_mx,
                 "ms_per_step": 1e3 * rmx["wall"] / steps,
