@@ -368,6 +368,80 @@ def test_limiter_bounds_and_structure():
     assert n_active > 50
 
 
+def _bisect_largest(ok, iters=200):
+    """Largest t in [0, 1] with ok(t), for a predicate true at 0 that stays
+    false once it turns false (bisection; no formula of the limiter used)."""
+    if ok(1.0):
+        return 1.0
+    lo, hi = 0.0, 1.0
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        if mid <= lo or mid >= hi:
+            break
+        if ok(mid):
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_limiter_thetas_are_the_binding_scalings(seed):
+    """Sec 2.4, steps 2 and 4, pinned by what theta1 and theta2 ARE rather
+    than by their formulas: theta1 is the largest scaling toward the cell
+    average that keeps the three Gauss-Lobatto densities (the two interface
+    values and the interior value fixed by the quadrature mean) at or above
+    eps; theta2 is the smallest over the three points of the largest t with
+    e((1-t) Ubar + t W) >= eps_e, found here by bisection on e itself.  Also
+    checks that when a theta is below 1 its constraint binds: the limited
+    minimum density equals eps, the limited minimum e equals eps_e."""
+    rng = np.random.default_rng(100 + seed)
+    w1 = 1.0 / 12.0
+    n_th1 = n_th2 = 0
+    for _ in range(300):
+        ncomp = 3 if rng.uniform() < 0.5 else 4
+        r = 10 ** rng.uniform(-1, 1)
+        vel = rng.uniform(-2, 2, size=ncomp - 2)
+        pr = 10 ** rng.uniform(-1, 1)
+        Ub = np.array([r, *(r * vel), pr / (GAMMA - 1) + 0.5 * r * (vel ** 2).sum()])
+        # thresholds far above roundoff so "equals eps" is checkable
+        er = Ub[0] * rng.uniform(0.05, 0.6)
+        ee = spec_e(Ub) * rng.uniform(0.05, 0.6)
+        scale = np.abs(Ub) + 0.3 * Ub[-1]
+        Um = Ub + rng.normal(size=ncomp) * scale * rng.uniform(0.2, 1.5)
+        Up = Ub + rng.normal(size=ncomp) * scale * rng.uniform(0.2, 1.5)
+        Lm, Lp, _ = oracle.limit_cell(Ub, Um, Up, er, ee, w1)
+
+        # --- independent reference
+        def gl_mid(a, b):   # interior value fixed by the Gauss-Lobatto mean
+            return (Ub - w1 * b - w1 * a) / (1 - 2 * w1)
+
+        rho3 = np.array([Um[0], Up[0], gl_mid(Um, Up)[0]])
+        th1 = _bisect_largest(lambda t: np.all(Ub[0] + t * (rho3 - Ub[0]) >= er))
+        Hm, Hp = Um.copy(), Up.copy()
+        Hm[0] = Ub[0] + th1 * (Um[0] - Ub[0])
+        Hp[0] = Ub[0] + th1 * (Up[0] - Ub[0])
+        ts = []
+        for Wa in (Hm, Hp, gl_mid(Hm, Hp)):
+            ts.append(_bisect_largest(lambda t: spec_e(Ub + t * (Wa - Ub)) >= ee))
+        th2 = min(ts)
+        Rm = Ub + th2 * (Hm - Ub)
+        Rp = Ub + th2 * (Hp - Ub)
+        tol = 1e-9 * (np.abs(Ub) + np.abs(Um) + np.abs(Up))
+        assert np.all(np.abs(Lm - Rm) <= tol), (Lm, Rm, th1, th2)
+        assert np.all(np.abs(Lp - Rp) <= tol), (Lp, Rp, th1, th2)
+        # --- the constraint binds where a theta is below 1
+        if th1 < 1.0 and th2 == 1.0:
+            n_th1 += 1
+            rmin = min(Lm[0], Lp[0], gl_mid(Lm, Lp)[0])
+            assert abs(rmin - er) <= 1e-10 * Ub[0], (rmin, er)
+        if th2 < 1.0:
+            n_th2 += 1
+            emin = min(spec_e(Lm), spec_e(Lp), spec_e(gl_mid(Lm, Lp)))
+            assert abs(emin - ee) <= 1e-8 * spec_e(Ub), (emin, ee)
+    assert n_th1 > 10 and n_th2 > 30, (n_th1, n_th2)
+
+
 def test_limiter_is_exact_noop_on_positive_states():
     w1 = 1.0 / 12.0
     for _ in range(100):
