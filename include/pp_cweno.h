@@ -59,12 +59,26 @@ enum { PP_BC_PERIODIC = 0, PP_BC_TRANSMISSIVE = 1, PP_BC_REFLECTIVE = 2 };
  * accumulation in double.  Inputs and outputs are float64 in both cases. */
 enum { PP_FP64 = 0, PP_MIXED = 1 };
 
-/* Time-step rules for pp_cweno_run (reading of condition (CFL-CD)):
- *  PP_DT_CFL : dt = cfl * h / S            (1D),  cfl / (Sx/dx + Sy/dy) (2D)
- *  PP_DT_H53 : dt = cfl * h^(5/3) / S      (Example 3.1, Table 1; 1D only)
- * with S = max(|u|+a) over the cell averages at the start of each step; the
- * last step is shortened to land on t_end. */
-enum { PP_DT_CFL = 0, PP_DT_H53 = 1 };
+/* Time-step rules (readings of condition (CFL-CD) of the theorem in Sec. 2.4);
+ * in every rule the last step is shortened to land on t_end:
+ *  PP_DT_CFL     : dt = cfl * h / S (1D), cfl / (Sx/dx + Sy/dy) (2D), with
+ *                  S = max(|u|+a) over the cell averages at the start of
+ *                  each step.
+ *  PP_DT_H53     : dt = cfl * h^(5/3) / S  (Example 3.1, Table 1; 1D only).
+ *  PP_DT_PP      : dt = cfl * h / S with S over the cell averages AND the
+ *                  limited interface states of the step's input, the states
+ *                  the theorem's proof advances by first-order HLLC steps.
+ *                  The inputs of stages 2 and 3 are checked against
+ *                  dt * S_s / h <= gl_w1 with the same dt; a stage that breaks
+ *                  it sets status bit 2 (informative: not PP_ESTATE).  Near
+ *                  vacuum the density-limited interface states keep their
+ *                  pressure, so S can become huge and dt tiny.  1D only.
+ *  PP_DT_RESTART : PP_DT_CFL's dt; a step in which any stage output leaves
+ *                  the admissible set (rho <= 0, p <= 0 or not finite) is
+ *                  discarded and redone from U^n with half the dt, up to 60
+ *                  times (then the run stops with PP_ESTATE).  The next step
+ *                  starts again from the averages' dt.  1D only. */
+enum { PP_DT_CFL = 0, PP_DT_H53 = 1, PP_DT_PP = 2, PP_DT_RESTART = 3 };
 
 /* Numerical flux at the faces.  PP_FLUX_HLLC: eq. (HLLC) with the acoustic
  * wave speeds (acoustic ws), the default and the paper's scheme.
@@ -103,6 +117,8 @@ typedef struct {
     void *stream;        /* hipStream_t to enqueue on (NULL: the null stream)           */
     int flux;            /* PP_FLUX_HLLC (default) or PP_FLUX_LF                        */
     int recon;           /* PP_RECON_CWENO (default), PP_RECON_WENOJS or PP_RECON_WENOZ  */
+    int batch_rule;      /* time-step rule of the batched driver, per problem:
+                            PP_DT_CFL (default), PP_DT_PP or PP_DT_RESTART              */
 } pp_cweno_config;
 
 /* Fill *cfg with defaults: ndim 1, gamma 1.4, epsilons 1e-13, gl_w1 1/12, FP64,
@@ -143,9 +159,12 @@ int pp_cweno_run(pp_cweno_ctx *ctx, double *U, double t_end, int64_t nsteps_max,
 int pp_cweno_batch_step(pp_cweno_ctx *ctx, double *Upacked, const double *dt_dev);
 
 /* Batched ensemble driver: advance every problem to t_end with per-problem
- * dt = cfl * dx_i / S_i (S_i from problem i's averages), nsteps_max steps at
- * most; steps_out (host [nbatch], may be NULL) receives each problem's step
- * count.  Synchronises. */
+ * dt = cfl * dx_i / S_i under the config's batch_rule (PP_DT_CFL: S_i from
+ * problem i's averages; PP_DT_PP: from its averages and limited interface
+ * states; PP_DT_RESTART: PP_DT_CFL with the step redone at half dt when a
+ * stage output of that problem leaves G), nsteps_max steps at most (redone
+ * steps not counted); steps_out (host [nbatch], may be NULL) receives each
+ * problem's step count.  Synchronises. */
 int pp_cweno_batch_run(pp_cweno_ctx *ctx, double *Upacked, double t_end, int64_t nsteps_max,
                        double cfl, int64_t *steps_out);
 
@@ -184,13 +203,20 @@ int pp_cweno_batch_continue(pp_cweno_ctx *ctx, double *Upacked, double t_end, in
 int pp_cweno_batch_tune(pp_cweno_ctx *ctx, const double *Upacked, double cfl, int force_plan,
                         int *plan_out, double *ms_out);
 
+/* Steps redone with half the dt under PP_DT_RESTART since the last
+ * pp_cweno_run or pp_cweno_batch_run on ctx (batched: summed over the
+ * problems; a continuation adds to it) into *out (host).  Synchronises. */
+int pp_cweno_restarts(pp_cweno_ctx *ctx, int64_t *out);
+
 /* out_dev[0] = max(|u|+a) (2D: also out_dev[1] = max(|v|+a)) over the cell
  * averages of U (device pointers). */
 int pp_cweno_max_speed(pp_cweno_ctx *ctx, const double *U, double *out_dev);
 
 /* Synchronise the stream and return the sticky status: *flags (may be NULL)
  * receives bit 0 = non-finite value seen, bit 1 = rho <= 0 or p <= 0 seen in a
- * stage output.  Returns PP_ESTATE if any bit is set (and clears them). */
+ * stage output, bit 2 = (PP_DT_PP only) a stage-2 or stage-3 input broke
+ * condition (CFL-CD) under its step's dt.  Returns PP_ESTATE if bit 0 or 1 is
+ * set; clears all bits. */
 int pp_cweno_status(pp_cweno_ctx *ctx, uint32_t *flags);
 
 /* Test hook: reconstructed interface states and face fluxes of the operator

@@ -93,8 +93,12 @@ def lib():
             "orc_max_speed_2d": (None, [_I, _I, _D, _DBL, _D]),
             "orc_run_2d": (_I, [_I, _I, _D, ctypes.POINTER(_I), _DBL, _DBL, _P, _DBL, _DBL,
                                 _L, _D]),
+            "orc_run_2d_rule": (_I, [_I, _I, _D, ctypes.POINTER(_I), _DBL, _DBL, _P, _DBL, _DBL,
+                                     _I, _L, _D]),
             "orc_run_batch": (_I, [_I, ctypes.POINTER(_L), _D, ctypes.POINTER(_I), _D, _P,
                                    _DBL, _DBL, _L, _D]),
+            "orc_run_batch_rule": (_I, [_I, ctypes.POINTER(_L), _D, ctypes.POINTER(_I), _D, _P,
+                                        _DBL, _DBL, _I, _L, _D, _D]),
             "orc_num_threads": (_I, []),
             "orc_weights": (None, [_D, _DBL, _D]),
         }
@@ -277,15 +281,22 @@ def max_speed_1d(U, gamma=1.4):
     return lib().orc_max_speed_1d(U.shape[1], _d(U), gamma)
 
 
+DT_CFL, DT_H53, DT_PP, DT_RESTART = 0, 1, 2, 3   # time-step rules (see orc_run_1d)
+
+
 def run_1d(U, bc, h, t_end, cfl=1.0 / 12.0, rule=0, p=None, max_steps=1 << 40):
-    """Advance to ``t_end``; returns (U, info dict)."""
+    """Advance to ``t_end``; returns (U, info dict).  ``viol``: stages whose
+    input broke condition (CFL-CD) under the step's dt (rule DT_PP only);
+    ``restarts``: steps redone at half dt (DT_RESTART); ``out_of_G``: stage
+    outputs with a cell outside G (of the attempts kept)."""
     p = p or params()
     U = _f64(U).copy()
-    out = np.zeros(5)
+    out = np.zeros(8)
     _check(lib().orc_run_1d(U.shape[1], _d(U), bc[0], bc[1], h, ctypes.byref(p), t_end, cfl, rule,
                             max_steps, _d(out)), "run_1d")
     return U, dict(t=out[0], steps=int(out[1]), limited=int(out[2]), min_rho=out[3],
-                   min_p=out[4])
+                   min_p=out[4], viol=int(out[5]), restarts=int(out[6]),
+                   out_of_G=int(out[7]))
 
 
 # ---------------------------------------------------------------------- 2D
@@ -322,19 +333,21 @@ def max_speed_2d(U, gamma=1.4):
     return out
 
 
-def run_2d(U, bc, dx, dy, t_end, cfl=1.0 / 12.0, p=None, max_steps=1 << 40):
+def run_2d(U, bc, dx, dy, t_end, cfl=1.0 / 12.0, p=None, max_steps=1 << 40, rule=0):
     p = p or params()
     U = _f64(U).copy()
-    out = np.zeros(5)
-    _check(lib().orc_run_2d(U.shape[2], U.shape[1], _d(U), _bc4(bc), dx, dy, ctypes.byref(p),
-                            t_end, cfl, max_steps, _d(out)), "run_2d")
+    out = np.zeros(6)
+    _check(lib().orc_run_2d_rule(U.shape[2], U.shape[1], _d(U), _bc4(bc), dx, dy, ctypes.byref(p),
+                                 t_end, cfl, rule, max_steps, _d(out)), "run_2d")
     return U, dict(t=out[0], steps=int(out[1]), limited=int(out[2]), min_rho=out[3],
-                   min_p=out[4])
+                   min_p=out[4], viol=int(out[5]))
 
 
 # ----------------------------------------------------------------- batched
-def run_batch(ens, t_end=None, cfl=1.0 / 12.0, p=None):
-    """Advance every problem of a ``workloads.Ensemble`` (transmissive BCs)."""
+def run_batch(ens, t_end=None, cfl=1.0 / 12.0, p=None, rule=0, viol_out=None):
+    """Advance every problem of a ``workloads.Ensemble`` (transmissive BCs).
+    ``viol_out`` (float64 [nprob], optional) receives each problem's count of
+    stages that broke (CFL-CD) (rule DT_PP)."""
     p = p or params()
     U = _f64(ens.U).copy()
     nprob = len(ens.lengths)
@@ -342,9 +355,10 @@ def run_batch(ens, t_end=None, cfl=1.0 / 12.0, p=None):
     bcs = (ctypes.c_int * (2 * nprob))(*([1] * (2 * nprob)))
     dxs = _f64(ens.dx)
     steps = np.zeros(nprob)
-    _check(lib().orc_run_batch(nprob, offs, _d(U), bcs, _d(dxs), ctypes.byref(p),
-                               ens.t_end if t_end is None else t_end, cfl, U.shape[1],
-                               _d(steps)), "run_batch")
+    viol = np.zeros(nprob) if viol_out is None else viol_out
+    _check(lib().orc_run_batch_rule(nprob, offs, _d(U), bcs, _d(dxs), ctypes.byref(p),
+                                    ens.t_end if t_end is None else t_end, cfl, rule, U.shape[1],
+                                    _d(steps), _d(viol)), "run_batch")
     return U, steps
 
 

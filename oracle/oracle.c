@@ -753,8 +753,9 @@ double orc_max_speed_1d(int n, const double *U, double gamma)
     return s;
 }
 
-/* Spatial operator of the first stage together with the wave-speed bound
- * of the step: max |u|+a over the averages and the limited interface states. */
+/* Spatial operator of a stage input together with the sup-norm of |u|+a
+ * over the cell averages and the limited interface states (the norm of
+ * condition (CFL-CD) under the time-step rule ORC_DT_PP below). */
 long orc_rhs_speed_1d(int n, const double *U, int bc_lo, int bc_hi, double h, const orc_params *P,
                       double *L, double *smax)
 {
@@ -766,32 +767,97 @@ long orc_rhs_speed_1d(int n, const double *U, int bc_lo, int bc_hi, double h, co
 
 /* Time-step rules: 0 -> dt = cfl h / S        (condition (CFL-CD));
  *                  1 -> dt = cfl h^(5/3) / S  (Example 3.1, Table 1),
- * reading: S = max(|u|+a) over the cell averages at the start of the step;
- * the last step is shortened to land on t_end. */
+ * with S = max(|u|+a) over the cell averages at the start of the step;
+ *                  2 -> dt = cfl h / S with S over the cell averages AND the
+ * limited interface states of the step's input (ORC_DT_PP).  The theorem of
+ * Sec. 2.4 writes the scheme as first-order HLLC steps of the interface
+ * states (the H_1, H_M of its proof), so its condition (CFL-CD) bounds
+ * |u|+a of those states, not only of the averages.  Under rule 2 the inputs
+ * of stages 2 and 3 are checked against the same bound with the step's dt:
+ * a stage whose input has dt S_s / h > w^_1 is counted (out[5]).
+ * In all rules the last step is shortened to land on t_end. */
+#define ORC_DT_PP 2
+#define ORC_DT_RESTART 3
+#define ORC_MAX_HALVINGS 60
 static double dt_rule_1d(int rule, double cfl, double h, double smax)
 {
     return rule == 1 ? cfl * pow(h, 5.0 / 3.0) / smax : cfl * h / smax;
 }
 
+/* 1 if every cell of [3][n] is finite with rho > 0 and p > 0 (the set G). */
+static int in_G_1d(int n, const double *U, double g)
+{
+    for (int i = 0; i < n; ++i) {
+        double r = U[i], m = U[n + i], E = U[2 * n + i];
+        if (!(r > 0.0) || !((g - 1.0) * (E - 0.5 * m * m / r) > 0.0)) return 0;
+    }
+    return 1;
+}
+
 /* Advance U ([3][n], in place) to t_end (or max_steps).  out[0] = t reached,
  * out[1] = steps, out[2] = total limited cells, out[3] = min rho, out[4] = min p
- * over all step outputs.  Returns 0 or a negative code (-4: no valid dt). */
+ * over all step outputs, out[5] = stages whose input broke (CFL-CD) under the
+ * step's dt (rule 2 only), out[6] = steps redone with half the dt (rule 3),
+ * out[7] = stage outputs with a cell outside G (rho <= 0, p <= 0 or not
+ * finite; under rule 3 only those of the attempts kept).
+ * Returns 0 or a negative code (-4: no valid dt). */
 int orc_run_1d(int n, double *U, int bc_lo, int bc_hi, double h, const orc_params *P,
                double t_end, double cfl, int rule, long max_steps, double *out)
 {
     size_t m = 3u * (size_t)n;
     double *U1 = (double *)malloc(sizeof(double) * m), *U2 = (double *)malloc(sizeof(double) * m);
-    if (!U1 || !U2) { free(U1); free(U2); return -2; }
+    double *L = (double *)malloc(sizeof(double) * m);
+    if (!U1 || !U2 || !L) { free(U1); free(U2); free(L); return -2; }
     double t = 0.0, minr = INFINITY, minp = INFINITY;
-    long steps = 0, lim = 0;
+    long steps = 0, lim = 0, viol = 0, restarts = 0, outG = 0;
     int rc = 0;
     while (t < t_end && steps < max_steps) {
-        double dt = dt_rule_1d(rule, cfl, h, orc_max_speed_1d(n, U, P->gamma));
-        if (!(dt > 0.0) || dt == INFINITY) { rc = -4; break; }
-        if (t + dt > t_end) dt = t_end - t;
-        long r1 = orc_stage_1d(n, U, U, U1, 1, dt, bc_lo, bc_hi, h, P);
-        long r2 = r1 >= 0 ? orc_stage_1d(n, U, U1, U2, 2, dt, bc_lo, bc_hi, h, P) : r1;
-        long r3 = r2 >= 0 ? orc_stage_1d(n, U, U2, U1, 3, dt, bc_lo, bc_hi, h, P) : r2;
+        long r1, r2, r3;
+        double dt;
+        if (rule == ORC_DT_PP) {
+            double S;
+            r1 = orc_rhs_speed_1d(n, U, bc_lo, bc_hi, h, P, L, &S);
+            if (r1 < 0) { rc = (int)r1; break; }
+            dt = cfl * h / S;
+            if (!(dt > 0.0) || dt == INFINITY) { rc = -4; break; }
+            if (t + dt > t_end) dt = t_end - t;
+            rk3_combine((long)m, 1, dt, U, U, L, U1);
+            outG += !in_G_1d(n, U1, P->gamma);
+            r2 = orc_rhs_speed_1d(n, U1, bc_lo, bc_hi, h, P, L, &S);
+            if (r2 >= 0) {
+                if (dt * S > P->gl_w1 * h) ++viol;
+                rk3_combine((long)m, 2, dt, U, U1, L, U2);
+                outG += !in_G_1d(n, U2, P->gamma);
+                r3 = orc_rhs_speed_1d(n, U2, bc_lo, bc_hi, h, P, L, &S);
+                if (r3 >= 0) {
+                    if (dt * S > P->gl_w1 * h) ++viol;
+                    rk3_combine((long)m, 3, dt, U, U2, L, U1);
+                    outG += !in_G_1d(n, U1, P->gamma);
+                }
+            } else {
+                r3 = r2;
+            }
+        } else {
+            dt = dt_rule_1d(rule, cfl, h, orc_max_speed_1d(n, U, P->gamma));
+            if (!(dt > 0.0) || dt == INFINITY) { rc = -4; break; }
+            if (t + dt > t_end) dt = t_end - t;
+            for (int halvings = 0;; ++halvings) {
+                long bad = 0;   /* stage outputs of this attempt outside G */
+                r1 = orc_stage_1d(n, U, U, U1, 1, dt, bc_lo, bc_hi, h, P);
+                bad += r1 >= 0 && !in_G_1d(n, U1, P->gamma);
+                r2 = r1 >= 0 ? orc_stage_1d(n, U, U1, U2, 2, dt, bc_lo, bc_hi, h, P) : r1;
+                bad += r2 >= 0 && !in_G_1d(n, U2, P->gamma);
+                r3 = r2 >= 0 ? orc_stage_1d(n, U, U2, U1, 3, dt, bc_lo, bc_hi, h, P) : r2;
+                bad += r3 >= 0 && !in_G_1d(n, U1, P->gamma);
+                if (rule != ORC_DT_RESTART || bad == 0 || r3 < 0) {
+                    outG += bad;
+                    break;
+                }
+                if (halvings == ORC_MAX_HALVINGS) { r3 = -4; break; }
+                dt *= 0.5;   /* redo the step from U^n with half the step */
+                ++restarts;
+            }
+        }
         if (r3 < 0) { rc = (int)r3; break; }
         lim += r1 + r2 + r3;
         memcpy(U, U1, sizeof(double) * m);
@@ -805,7 +871,10 @@ int orc_run_1d(int n, double *U, int bc_lo, int bc_hi, double h, const orc_param
         ++steps;
     }
     out[0] = t; out[1] = (double)steps; out[2] = (double)lim; out[3] = minr; out[4] = minp;
-    free(U1); free(U2);
+    out[5] = (double)viol;
+    out[6] = (double)restarts;
+    out[7] = (double)outG;
+    free(U1); free(U2); free(L);
     return rc;
 }
 
@@ -895,25 +964,52 @@ void orc_max_speed_2d(int nx, int ny, const double *U, double gamma, double *out
     out[1] = sy;
 }
 
-/* Reading: dt = cfl / (Sx/dx + Sy/dy) with Sx = max(|u|+a), Sy = max(|v|+a)
- * over the cell averages at the start of the step; last step clipped. */
-int orc_run_2d(int nx, int ny, double *U, const int *bc, double dx, double dy,
-               const orc_params *P, double t_end, double cfl, long max_steps, double *out)
+/* Reading: dt = cfl / (Sx/dx + Sy/dy) with Sx, Sy the sup-norms of |u|+a
+ * and |v|+a: over the cell averages at the start of the step (rule 0), or
+ * over the averages and the limited interface states of the x- and y-lines
+ * of the step's input (rule 2, ORC_DT_PP, with the stage-2 and stage-3 inputs
+ * checked against dt (Sx_s/dx + Sy_s/dy) <= w^_1, out[5]); last step clipped. */
+int orc_run_2d_rule(int nx, int ny, double *U, const int *bc, double dx, double dy,
+                    const orc_params *P, double t_end, double cfl, int rule, long max_steps,
+                    double *out)
 {
     size_t m = 4u * (size_t)nx * (size_t)ny;
     double *U1 = (double *)malloc(sizeof(double) * m), *U2 = (double *)malloc(sizeof(double) * m);
-    if (!U1 || !U2) { free(U1); free(U2); return -2; }
+    double *L = (double *)malloc(sizeof(double) * m);
+    if (!U1 || !U2 || !L) { free(U1); free(U2); free(L); return -2; }
     double t = 0.0, minr = INFINITY, minp = INFINITY, s[2];
-    long steps = 0, lim = 0;
+    long steps = 0, lim = 0, viol = 0;
     int rc = 0;
     while (t < t_end && steps < max_steps) {
-        orc_max_speed_2d(nx, ny, U, P->gamma, s);
-        double dt = cfl / (s[0] / dx + s[1] / dy);
-        if (!(dt > 0.0) || dt == INFINITY) { rc = -4; break; }
-        if (t + dt > t_end) dt = t_end - t;
-        long r1 = orc_stage_2d(nx, ny, U, U, U1, 1, dt, bc, dx, dy, P);
-        long r2 = r1 >= 0 ? orc_stage_2d(nx, ny, U, U1, U2, 2, dt, bc, dx, dy, P) : r1;
-        long r3 = r2 >= 0 ? orc_stage_2d(nx, ny, U, U2, U1, 3, dt, bc, dx, dy, P) : r2;
+        long r1, r2, r3;
+        double dt;
+        if (rule == ORC_DT_PP) {
+            r1 = orc_rhs_2d_speed(nx, ny, U, bc, dx, dy, P, L, s);
+            if (r1 < 0) { rc = (int)r1; break; }
+            dt = cfl / (s[0] / dx + s[1] / dy);
+            if (!(dt > 0.0) || dt == INFINITY) { rc = -4; break; }
+            if (t + dt > t_end) dt = t_end - t;
+            rk3_combine((long)m, 1, dt, U, U, L, U1);
+            r2 = orc_rhs_2d_speed(nx, ny, U1, bc, dx, dy, P, L, s);
+            r3 = r2;
+            if (r2 >= 0) {
+                if (dt * (s[0] / dx + s[1] / dy) > P->gl_w1) ++viol;
+                rk3_combine((long)m, 2, dt, U, U1, L, U2);
+                r3 = orc_rhs_2d_speed(nx, ny, U2, bc, dx, dy, P, L, s);
+                if (r3 >= 0) {
+                    if (dt * (s[0] / dx + s[1] / dy) > P->gl_w1) ++viol;
+                    rk3_combine((long)m, 3, dt, U, U2, L, U1);
+                }
+            }
+        } else {
+            orc_max_speed_2d(nx, ny, U, P->gamma, s);
+            dt = cfl / (s[0] / dx + s[1] / dy);
+            if (!(dt > 0.0) || dt == INFINITY) { rc = -4; break; }
+            if (t + dt > t_end) dt = t_end - t;
+            r1 = orc_stage_2d(nx, ny, U, U, U1, 1, dt, bc, dx, dy, P);
+            r2 = r1 >= 0 ? orc_stage_2d(nx, ny, U, U1, U2, 2, dt, bc, dx, dy, P) : r1;
+            r3 = r2 >= 0 ? orc_stage_2d(nx, ny, U, U2, U1, 3, dt, bc, dx, dy, P) : r2;
+        }
         if (r3 < 0) { rc = (int)r3; break; }
         lim += r1 + r2 + r3;
         memcpy(U, U1, sizeof(double) * m);
@@ -928,31 +1024,49 @@ int orc_run_2d(int nx, int ny, double *U, const int *bc, double dx, double dy,
         ++steps;
     }
     out[0] = t; out[1] = (double)steps; out[2] = (double)lim; out[3] = minr; out[4] = minp;
-    free(U1); free(U2);
+    out[5] = (double)viol;
+    free(U1); free(U2); free(L);
     return rc;
+}
+
+int orc_run_2d(int nx, int ny, double *U, const int *bc, double dx, double dy,
+               const orc_params *P, double t_end, double cfl, long max_steps, double *out)
+{
+    return orc_run_2d_rule(nx, ny, U, bc, dx, dy, P, t_end, cfl, 0, max_steps, out);
 }
 
 /* ------------------------------------------------------- batched 1D ensemble
  * Independent problems packed [3][sum n_i]; each advances with its own dt
- * (rule 0) to t_end.  OpenMP over problems. Returns 0 or the first error. */
-int orc_run_batch(int nprob, const long *offsets, double *U, const int *bc, const double *dxs,
-                  const orc_params *P, double t_end, double cfl, long total, double *steps_out)
+ * (rule 0 or 2 of orc_run_1d) to t_end.  OpenMP over problems.  steps_out and
+ * viol_out (either may be NULL) receive each problem's step count and its
+ * count of stages that broke (CFL-CD) (rule 2).  Returns 0 or the first error. */
+int orc_run_batch_rule(int nprob, const long *offsets, double *U, const int *bc, const double *dxs,
+                       const orc_params *P, double t_end, double cfl, int rule, long total,
+                       double *steps_out, double *viol_out)
 {
     int err = 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < nprob; ++i) {
         int n = (int)(offsets[i + 1] - offsets[i]);
-        double *line = (double *)malloc(sizeof(double) * 3u * (size_t)n), out[5];
+        double *line = (double *)malloc(sizeof(double) * 3u * (size_t)n), out[8];
         for (int k = 0; k < 3; ++k)
             memcpy(line + (size_t)k * n, U + (size_t)k * total + offsets[i], sizeof(double) * n);
-        int r = orc_run_1d(n, line, bc[2 * i], bc[2 * i + 1], dxs[i], P, t_end, cfl, 0, 1L << 40, out);
+        int r = orc_run_1d(n, line, bc[2 * i], bc[2 * i + 1], dxs[i], P, t_end, cfl, rule, 1L << 40,
+                           out);
         if (r) err = r;
         for (int k = 0; k < 3; ++k)
             memcpy(U + (size_t)k * total + offsets[i], line + (size_t)k * n, sizeof(double) * n);
         if (steps_out) steps_out[i] = out[1];
+        if (viol_out) viol_out[i] = out[5];
         free(line);
     }
     return err;
+}
+
+int orc_run_batch(int nprob, const long *offsets, double *U, const int *bc, const double *dxs,
+                  const orc_params *P, double t_end, double cfl, long total, double *steps_out)
+{
+    return orc_run_batch_rule(nprob, offsets, U, bc, dxs, P, t_end, cfl, 0, total, steps_out, NULL);
 }
 
 int orc_num_threads(void)

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(PKG, "libppcweno.so")
 PP_OK, PP_EINVAL, PP_ENOMEM, PP_EDEVICE, PP_ESTATE, PP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PP_BC_PERIODIC, PP_BC_TRANSMISSIVE, PP_BC_REFLECTIVE = 0, 1, 2
 PP_FP64, PP_MIXED = 0, 1
-PP_DT_CFL, PP_DT_H53 = 0, 1
+PP_DT_CFL, PP_DT_H53, PP_DT_PP, PP_DT_RESTART = 0, 1, 2, 3
 PP_FLUX_HLLC, PP_FLUX_LF = 0, 1
 PP_RECON_CWENO, PP_RECON_WENOJS, PP_RECON_WENOZ = 0, 1, 2
 
@@ -25,7 +25,7 @@ EXPORTED = [
     "pp_cweno_config_defaults", "pp_cweno_init", "pp_cweno_rhs", "pp_cweno_stage",
     "pp_cweno_step", "pp_cweno_run", "pp_cweno_batch_step", "pp_cweno_batch_tune",
     "pp_cweno_batch_run", "pp_cweno_batch_continue",
-    "pp_cweno_max_speed", "pp_cweno_status", "pp_cweno_debug_line", "pp_cweno_set_timing",
+    "pp_cweno_restarts", "pp_cweno_max_speed", "pp_cweno_status", "pp_cweno_debug_line", "pp_cweno_set_timing",
     "pp_cweno_get_timing", "pp_cweno_last_error", "pp_cweno_destroy",
 ]
 
@@ -47,6 +47,7 @@ class Config(ctypes.Structure):
         ("bcs", ctypes.POINTER(ctypes.c_int)), ("stream", ctypes.c_void_p),
         ("flux", ctypes.c_int),
         ("recon", ctypes.c_int),
+        ("batch_rule", ctypes.c_int),
     ]
 
 
@@ -79,6 +80,7 @@ def lib():
             "pp_cweno_batch_continue": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int64,
                                                        ctypes.c_double, P(ctypes.c_int64),
                                                        P(ctypes.c_double)]),
+            "pp_cweno_restarts": (ctypes.c_int, [_VP, P(ctypes.c_int64)]),
             "pp_cweno_max_speed": (ctypes.c_int, [_VP, _VP, _VP]),
             "pp_cweno_status": (ctypes.c_int, [_VP, P(ctypes.c_uint32)]),
             "pp_cweno_debug_line": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
@@ -124,7 +126,8 @@ class Solver:
 
     def __init__(self, ndim=1, nx=0, ny=1, dx=0.0, dy=0.0, gamma=1.4, bc=(0, 0, 0, 0),
                  precision=PP_FP64, weno_eps=1e-13, pp_eps_cap=1e-13, gl_w1=1.0 / 12.0,
-                 lengths=None, dxs=None, bcs=None, stream=None, flux=None, recon=None):
+                 lengths=None, dxs=None, bcs=None, stream=None, flux=None, recon=None,
+                 batch_rule=None):
         c = default_config()
         c.ndim, c.nx, c.ny, c.dx, c.dy, c.gamma = ndim, nx, ny, dx, dy, gamma
         for i in range(4):
@@ -134,6 +137,8 @@ class Solver:
             c.flux = int(flux)
         if recon is not None:
             c.recon = int(recon)
+        if batch_rule is not None:
+            c.batch_rule = int(batch_rule)
         self._keep = []
         if lengths is not None:
             nb = len(lengths)
@@ -228,6 +233,12 @@ class Solver:
 
     def last_batch_steps(self):
         return list(self._last_steps)
+
+    def restarts(self):
+        """Steps redone with half the dt (PP_DT_RESTART) in the last run."""
+        v = ctypes.c_int64()
+        self._check(lib().pp_cweno_restarts(self._ctx, ctypes.byref(v)))
+        return v.value
 
     def max_speed(self, U, out):
         return self._check(lib().pp_cweno_max_speed(self._ctx, _ptr(U, self._nstate),

@@ -53,7 +53,12 @@ struct Scal {
     long long steps;
     int active;
     unsigned status;
+    unsigned stepbad;      // restart rule: status bits of the step being tried
+    long long restarts;    // restart rule: steps redone with half the dt
 };
+
+// Steps redone with half the dt before a run gives up (restart rule).
+constexpr int kMaxHalvings = 60;
 
 struct LineArgs {
     const double* U;        // stage input
@@ -87,6 +92,12 @@ struct LineArgs {
     double* dbg_um;
     double* dbg_up;
     double* dbg_flux;
+    int dtrule;             // PP_DT_*: PP_DT_PP reduces |u|+a over the limited interface
+                            // states; PP_DT_RESTART commits stage 3 only if the step stayed in G
+    unsigned* badline;      // batched, restart rule: status bits of each problem's step
+    int* halfline;          // batched, restart rule: halvings of each problem's current step
+    double* commit;         // batched, restart rule: state the stage-3 output is copied into
+    unsigned long long* restart_count;   // batched, restart rule: redone steps (all problems)
 };
 
 template <int NT>
@@ -511,7 +522,13 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     const bool cyclic = (bc_lo == PP_BC_PERIODIC);
     double dt = 0.0;
     if (A.mode == 1) dt = batched ? A.dtline[b] : (A.dt_dev ? *A.dt_dev : A.dt_val);
+    // mode 2 (stage 1 under the interface-state rule): dtline holds the time
+    // left to t_end until this stage has chosen the step
+    if (A.mode == 2 && batched) dt = A.dtline[b];
     if (batched && !(dt > 0.0)) return;  // finished problem: leave it untouched
+    // status bits of a stage output go to the problem's word under the
+    // restart rule (batched), else to the run's word
+    unsigned* const stat = (batched && A.badline) ? &A.badline[b] : A.status;
 
     const double* __restrict__ U = A.U + base;
     const int LP = padn<PSH>(n + 2 * kNG - 1) + 1;   // padded LDS length of one component
@@ -853,6 +870,7 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     const int SS = padn<PSH>(SMAX + 1) + 1;
     double* sRes = smem;                         // [NS][SS], slots padded
     double smax_speed = 0.0;
+    double smax_if = 0.0;   // interface-state rule: |u|+a over averages and limited states
     unsigned bad = 0u;
     // SEG1: the whole line is one segment (the loop disappears at compile time)
     const int nseg = SEG1 ? 1 : (n + SMAX - 1) / SMAX;
@@ -958,6 +976,15 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
                 sRes[(2 * c) * SS + pq] = Um[c];
                 sRes[(2 * c + 1) * SS + pq] = Up[c];
             }
+            if (A.dtrule == PP_DT_PP) {
+                // sup-norm of |u|+a over the averages and the limited
+                // interface states (condition (CFL-CD)); a non-finite speed
+                // makes the bound infinite, so no step is taken
+                const double sp = fmax(wave_speed<NC, NRM>(A.gamma, Ub),
+                                       fmax(wave_speed<NC, NRM>(A.gamma, Um),
+                                            wave_speed<NC, NRM>(A.gamma, Up)));
+                smax_if = isfinite(sp) ? fmax(smax_if, sp) : INFINITY;
+            }
         }
         __syncthreads();
         // fluxes: face f = g0 + r (between cells f-1 and f), r = 0..S, strided
@@ -1030,7 +1057,7 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
                 const double L = -(sF[c * FS + q + 1] - Fl) * ih;
                 if (wrap0 && q == 0 && A.dbg_flux) A.dbg_flux[(long long)c * (n + 1)] = Fl;
                 const long long at = base + (long long)c * A.cs + i;
-                if (A.mode == 0) {
+                if (A.mode != 1) {
                     o[c] = L;
                 } else {
                     const double us = A.U[at];
@@ -1054,25 +1081,123 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
         }
         __syncthreads();
     }
+    if (A.mode == 2) {
+        // stage 1 under the interface-state rule: the step's dt from the
+        // sup-norm over this stage input, then U1 = U + dt L over the L just
+        // written (same rounding as the one-pass stage 1)
+        const double S = block_max<NT>(smax_if, red);
+        if (tid == 0) {
+            double d = A.cfl * h / S;
+            const double rem = batched ? dt : (A.scal ? A.t_end - A.scal->t : 0.0);
+            if (!(d > 0.0) || !isfinite(d)) {
+                d = 0.0;
+                if (A.status) atomicOr(A.status, 1u);
+            } else if (d > rem) {
+                d = rem;
+            }
+            if (batched) {
+                A.dtline[b] = d;
+            } else if (A.scal) {
+                A.scal->dt = d;
+                if (!(d > 0.0)) A.scal->active = 0;
+            }
+            red[0] = d;
+        }
+        __syncthreads();
+        const double d = red[0];
+        __syncthreads();
+        if (d > 0.0) {
+            for (int q = tid; q < n; q += NT) {
+                double o[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const long long at = base + (long long)c * A.cs + q;
+                    o[c] = A.U[at] + d * A.out[at];
+                    A.out[at] = o[c];
+                }
+                double m2 = 0.0;
+#pragma unroll
+                for (int c = 1; c < NC - 1; ++c) m2 += o[c] * o[c];
+                bool fin = true;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) fin = fin && isfinite(o[c]);
+                if (!fin) bad |= 1u;
+                if (!(o[0] > 0.0) || !(o[0] * o[NC - 1] - 0.5 * m2 > 0.0)) bad |= 2u;
+            }
+            if (bad && stat) atomicOr(stat, bad);
+        }
+    }
     if (A.mode == 1) {
-        if (bad && A.status) atomicOr(A.status, bad);
+        if (A.dtrule == PP_DT_PP && A.stage >= 2) {
+            // the stage input against condition (CFL-CD) with the step's dt
+            const double S = block_max<NT>(smax_if, red);
+            if (dt * S > A.w1 * h) bad |= 4u;
+        }
+        if (bad && stat) atomicOr(stat, bad);
         if (A.stage == 3) {
             const double S = block_max<NT>(smax_speed, red);
             if (batched) {
-                if (tid == 0) {
-                    // next step of this problem: dt = cfl h / max(|u|+a) of the
-                    // new averages, clipped to t_end; 0 retires the problem
-                    const double t = A.tline[b] + dt;
-                    const long long st = A.stepline[b] + 1;
-                    A.tline[b] = t;
-                    A.stepline[b] = st;
-                    double dn = A.cfl * h / S;
-                    if (!(dn > 0.0) || !isfinite(dn)) {
-                        dn = 0.0;
-                        if (A.status) atomicOr(A.status, 1u);
+                unsigned sbad = 0u;
+                if (A.badline) {
+                    // restart rule: the step of this problem stands only if no
+                    // stage output left G; then the stage-3 output (in out) is
+                    // copied into the state, else the step is redone with half
+                    // the dt.  The word collects the bits of all three stages.
+                    if (tid == 0)
+                        red[0] = (double)__hip_atomic_load(&A.badline[b], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                    __syncthreads();
+                    sbad = (unsigned)red[0];
+                    __syncthreads();
+                    if (sbad == 0u) {
+                        for (int q = tid; q < n; q += NT) {
+#pragma unroll
+                            for (int c = 0; c < NC; ++c) {
+                                const long long at = base + (long long)c * A.cs + q;
+                                A.commit[at] = A.out[at];
+                            }
+                        }
                     }
-                    if (t >= A.t_end || st >= A.steps_max) dn = 0.0;
-                    else if (t + dn > A.t_end) dn = A.t_end - t;
+                }
+                if (tid == 0) {
+                    double dn;
+                    if (sbad != 0u) {
+                        // redo this step from U^n with half the dt
+                        const int hv = A.halfline[b] + 1;
+                        A.halfline[b] = hv;
+                        if (hv > kMaxHalvings) {
+                            dn = 0.0;
+                            if (A.status) atomicOr(A.status, sbad);
+                        } else {
+                            dn = 0.5 * dt;
+                            atomicAdd(A.restart_count, 1ull);
+                        }
+                        A.badline[b] = 0u;
+                    } else {
+                        // next step of this problem: dt = cfl h / max(|u|+a) of
+                        // the new averages (interface-state rule: the time left,
+                        // the next stage 1 picks dt), clipped to t_end; 0
+                        // retires the problem
+                        const double t = A.tline[b] + dt;
+                        const long long st = A.stepline[b] + 1;
+                        A.tline[b] = t;
+                        A.stepline[b] = st;
+                        if (A.badline) {
+                            A.halfline[b] = 0;
+                            A.badline[b] = 0u;
+                        }
+                        if (A.dtrule == PP_DT_PP) {
+                            dn = A.t_end - t;
+                        } else {
+                            dn = A.cfl * h / S;
+                            if (!(dn > 0.0) || !isfinite(dn)) {
+                                dn = 0.0;
+                                if (A.status) atomicOr(A.status, 1u);
+                            }
+                        }
+                        if (t >= A.t_end || st >= A.steps_max) dn = 0.0;
+                        else if (t + dn > A.t_end) dn = A.t_end - t;
+                    }
                     A.dtline[b] = dn;
                 }
             } else if (A.scal && tid == 0) {
@@ -1122,7 +1247,8 @@ __global__ void __launch_bounds__(256) batch_init_kernel(const double* __restric
                                                          const int* nl, const double* hl,
                                                          double* dtl, double* tl, long long* sl,
                                                          double gamma, double cfl, double t_end,
-                                                         int resume, long long steps_max) {
+                                                         int resume, long long steps_max,
+                                                         int rule, unsigned* badl, int* halfl) {
     __shared__ double red[4];
     const int b = blockIdx.x;
     const long long o = off[b];
@@ -1137,7 +1263,13 @@ __global__ void __launch_bounds__(256) batch_init_kernel(const double* __restric
     __syncthreads();
     if (threadIdx.x == 0) {
         S = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-        double dt = cfl * hl[b] / S;
+        // the interface-state rule keeps the time left to t_end here; its
+        // stage 1 picks the step
+        double dt = rule == PP_DT_PP ? t_end - (resume ? tl[b] : 0.0) : cfl * hl[b] / S;
+        if (badl) {
+            badl[b] = 0u;
+            halfl[b] = 0;
+        }
         if (!resume) {
             if (!(dt > 0.0) || !isfinite(dt)) dt = 0.0;
             if (dt > t_end) dt = t_end;
@@ -1347,6 +1479,8 @@ __global__ void init_scal_kernel(Scal* s) {
     s->steps = 0;
     s->active = 1;
     s->status = 0u;
+    s->stepbad = 0u;
+    s->restarts = 0;
 }
 
 // Start of a step: advance t by the previous dt, pick the new dt from the
@@ -1360,15 +1494,17 @@ __device__ __forceinline__ void dt_update(Scal* s, int ndim, int rule, double cf
         s->steps += 1;
     }
     const double sx = ord_dec(s->spd[0]), sy = ord_dec(s->spd[1]);
-    double dt;
-    if (ndim == 1) dt = (rule == PP_DT_H53 ? cfl * pow(dx, 5.0 / 3.0) : cfl * dx) / sx;
-    else dt = cfl / (sx / dx + sy / dy);
+    double dt = 0.0;
     bool go = s->t < t_end && s->steps < steps_max;
-    if (go && !(dt > 0.0 && isfinite(dt))) {
-        s->status |= 1u;   // no usable wave speed: stop the run
-        go = false;
+    if (rule != PP_DT_PP) {   // (the interface-state rule picks dt in stage 1)
+        if (ndim == 1) dt = (rule == PP_DT_H53 ? cfl * pow(dx, 5.0 / 3.0) : cfl * dx) / sx;
+        else dt = cfl / (sx / dx + sy / dy);
+        if (go && !(dt > 0.0 && isfinite(dt))) {
+            s->status |= 1u;   // no usable wave speed: stop the run
+            go = false;
+        }
+        if (go && s->t + dt > t_end) dt = t_end - s->t;
     }
-    if (go && s->t + dt > t_end) dt = t_end - s->t;
     s->active = go ? 1 : 0;
     s->dt = go ? dt : 0.0;
     s->spd[0] = s->spd[1] = kEncZero;
@@ -1399,22 +1535,69 @@ struct RunArgs {
 template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED>
 __global__ void __launch_bounds__(2 * NC * 64 * W) run1d_kernel(RunArgs R) {
     extern __shared__ double smem[];
+    __shared__ unsigned sbad;
     Scal* s = R.st[0].scal;
     for (int it = 0; it < R.max_steps; ++it) {
         if (threadIdx.x == 0)
             dt_update(s, 1, R.rule, R.cfl, R.st[0].h, 0.0, R.t_end, R.steps_total);
         __syncthreads();
         if (!s->active) break;
+        // restart rule: the step is tried, and redone from U^n with half the
+        // dt while a stage output leaves G; other rules take one attempt
 #pragma unroll 1
-        for (int st = 0; st < 3; ++st) {   // one copy of the operator, stage args by index
-            // stage arguments re-read from the kernel-argument segment each
-            // time (see line_kernel_persistent)
-            typedef __attribute__((address_space(4))) const RunArgs KArgs;
-            KArgs* rp = (KArgs*)__builtin_amdgcn_kernarg_segment_ptr();
-            asm volatile("" : "+s"(rp));
-            line_op<NC, NRM, W, CPT, SEG1, MIXED, true>(((const RunArgs*)rp)->st[st], 0, smem);
+        for (int attempt = 0;; ++attempt) {
+            if (R.rule == PP_DT_RESTART) {
+                if (threadIdx.x == 0) {
+                    s->stepbad = 0u;
+                    s->spd[0] = kEncZero;   // speeds of this attempt's stage-3 output only
+                }
+                __syncthreads();
+            }
+            bool live = true;
+#pragma unroll 1
+            for (int st = 0; st < 3; ++st) {   // one copy of the operator, stage args by index
+                // stage arguments re-read from the kernel-argument segment each
+                // time (see line_kernel_persistent)
+                typedef __attribute__((address_space(4))) const RunArgs KArgs;
+                KArgs* rp = (KArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+                asm volatile("" : "+s"(rp));
+                line_op<NC, NRM, W, CPT, SEG1, MIXED, true>(((const RunArgs*)rp)->st[st], 0, smem);
+                __syncthreads();
+                if (!s->active) {   // the interface-state rule found no usable dt
+                    live = false;
+                    break;
+                }
+            }
+            if (!live || R.rule != PP_DT_RESTART) break;
+            if (threadIdx.x == 0)
+                sbad = __hip_atomic_load(&s->stepbad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __syncthreads();
+            const unsigned bad = sbad;
+            if (bad == 0u) {
+                // the step stands: the stage-3 output becomes the state
+                const LineArgs& a3 = R.st[2];
+                const int n = a3.n;
+                for (int q = threadIdx.x; q < NC * n; q += blockDim.x) {
+                    const int c = q / n, i = q - c * n;
+                    a3.commit[(long long)c * a3.cs + i] = a3.out[(long long)c * a3.cs + i];
+                }
+                __syncthreads();
+                break;
+            }
+            if (threadIdx.x == 0) {
+                if (attempt >= kMaxHalvings) {
+                    s->status |= bad;
+                    s->active = 0;
+                    s->dt = 0.0;
+                } else {
+                    s->dt *= 0.5;
+                    s->restarts += 1;
+                }
+            }
+            __syncthreads();
+            if (!s->active) break;
         }
+        if (!s->active) break;
     }
 }
 
@@ -1449,6 +1632,8 @@ struct pp_cweno_ctx {
     int* d_counter = nullptr;
     double* d_dtcopy = nullptr;
     double* d_tune = nullptr;   // autotuner's scratch copy of the packed state
+    unsigned* d_bad = nullptr;  // restart rule: status bits of each problem's step
+    int* d_half = nullptr;      // restart rule: halvings of each problem's step
     int n_sm = 0;
     bool batch_started = false;   // a batched run has set the per-problem t and steps
     // batched launch plan: the length-sorted problems are cut into classes
@@ -1582,10 +1767,14 @@ int launch_line_p(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int 
     if (lds > kLdsBudget || (seg + NT - 1) / NT > CPT)
         return fail(ctx, PP_EUNSUPPORTED, "line too long for the on-chip line kernel");
     const void* fn;
-    if (persistent)
-        fn = seg >= nmax ? (const void*)line_kernel_persistent<NC, NRM, W, CPT, true, MIXED>
-                         : (const void*)line_kernel_persistent<NC, NRM, W, CPT, false, MIXED>;
-    else
+    if (persistent) {
+        // batched ensembles are 1D: no persistent 2D kernels are built
+        if constexpr (NC == 3)
+            fn = seg >= nmax ? (const void*)line_kernel_persistent<NC, NRM, W, CPT, true, MIXED>
+                             : (const void*)line_kernel_persistent<NC, NRM, W, CPT, false, MIXED>;
+        else
+            return fail(ctx, PP_EUNSUPPORTED, "persistent launches serve 1D ensembles only");
+    } else
         fn = seg >= nmax ? (const void*)line_kernel<NC, NRM, W, CPT, true, MIXED>
                          : (const void*)line_kernel<NC, NRM, W, CPT, false, MIXED>;
     size_t& granted = ctx->lds_granted[fn];
@@ -1710,8 +1899,11 @@ int launch_run1d(pp_cweno_ctx* ctx, double* U, int rule, double cfl, double t_en
     R.t_end = t_end;
     R.steps_total = steps_total;
     R.max_steps = max_steps;
+    const bool restart = rule == PP_DT_RESTART;
     const double* Uin[3] = {U, ctx->U1, ctx->U2};
-    double* Uout[3] = {ctx->U1, ctx->U2, U};
+    // restart rule: stage 3 writes U1 (free after stage 2), committed into U
+    // only if the step stays in G
+    double* Uout[3] = {ctx->U1, ctx->U2, restart ? ctx->U1 : U};
     for (int st = 1; st <= 3; ++st) {
         LineArgs& a = R.st[st - 1];
         a = base_args(ctx);
@@ -1725,12 +1917,19 @@ int launch_run1d(pp_cweno_ctx* ctx, double* U, int rule, double cfl, double t_en
         a.bc_lo = ctx->cfg.bc[0];
         a.bc_hi = ctx->cfg.bc[1];
         a.h = ctx->cfg.dx;
-        a.mode = 1;
+        a.mode = (rule == PP_DT_PP && st == 1) ? 2 : 1;
         a.stage = st;
         a.rk_a = kRK[st][0];
         a.rk_b = kRK[st][1];
         a.dt_dev = &ctx->scal->dt;
         a.scal = ctx->scal;
+        a.dtrule = rule;
+        a.cfl = cfl;
+        a.t_end = t_end;
+        if (restart) {
+            a.status = &ctx->scal->stepbad;
+            a.commit = U;
+        }
     }
     const bool mixed = ctx->cfg.precision == PP_MIXED;
     if (ctx->cfg.nx <= 2048)
@@ -1886,6 +2085,17 @@ void set_plan(pp_cweno_ctx* ctx, int p) {
 int batch_step_launch(pp_cweno_ctx* ctx, double* Upacked, double* dtl, bool advance, double cfl,
                       double t_end, long long steps_max) {
     LineArgs A = base_args(ctx);
+    // the driver's time-step rule; a step of given dt (advance = false)
+    // takes the plain stages
+    const int rule = advance ? ctx->cfg.batch_rule : PP_DT_CFL;
+    const bool restart = rule == PP_DT_RESTART;
+    A.dtrule = rule;
+    if (restart) {
+        A.badline = ctx->d_bad;
+        A.halfline = ctx->d_half;
+        A.commit = Upacked;
+        A.restart_count = (unsigned long long*)&ctx->scal->restarts;
+    }
     A.cs = ctx->total;
     A.off = ctx->d_off;
     A.nline = ctx->d_n;
@@ -1899,11 +2109,14 @@ int batch_step_launch(pp_cweno_ctx* ctx, double* Upacked, double* dtl, bool adva
     A.t_end = t_end;
     A.cfl = cfl;
     const double* Uin[3] = {Upacked, ctx->U1, ctx->U2};
-    double* Uout[3] = {ctx->U1, ctx->U2, Upacked};
+    // restart rule: stage 3 writes U1, copied into the state per problem only
+    // if that problem's step stayed in G
+    double* Uout[3] = {ctx->U1, ctx->U2, restart ? ctx->U1 : Upacked};
     for (int st = 1; st <= 3; ++st) {
         A.U = Uin[st - 1];
         A.U0 = Upacked;
         A.out = Uout[st - 1];
+        A.mode = (rule == PP_DT_PP && st == 1) ? 2 : 1;
         A.stage = (st == 3 && !advance) ? 0 : st;
         A.rk_a = kRK[st][0];
         A.rk_b = kRK[st][1];
@@ -1960,6 +2173,8 @@ int pp_cweno_init(const pp_cweno_config* cfg, pp_cweno_ctx** out) {
         return fail(nullptr, PP_EINVAL, "epsilons must be > 0");
     if (c.precision != PP_FP64 && c.precision != PP_MIXED)
         return fail(nullptr, PP_EINVAL, "precision must be PP_FP64 or PP_MIXED");
+    if (c.batch_rule != PP_DT_CFL && c.batch_rule != PP_DT_PP && c.batch_rule != PP_DT_RESTART)
+        return fail(nullptr, PP_EINVAL, "batch_rule must be PP_DT_CFL, PP_DT_PP or PP_DT_RESTART");
     const int naxes = c.ndim == 2 ? 2 : 1;
     for (int a = 0; a < naxes; ++a) {
         if (!bc_ok(c.bc[2 * a]) || !bc_ok(c.bc[2 * a + 1]))
@@ -2053,6 +2268,8 @@ int pp_cweno_init(const pp_cweno_config* cfg, pp_cweno_ctx** out) {
             !dmalloc((void**)&ctx->d_steps, sizeof(long long) * nb) ||
             !dmalloc((void**)&ctx->d_order, sizeof(int) * nb) ||
             !dmalloc((void**)&ctx->d_counter, sizeof(int) * 16) ||
+            !dmalloc((void**)&ctx->d_bad, sizeof(unsigned) * nb) ||
+            !dmalloc((void**)&ctx->d_half, sizeof(int) * nb) ||
             !dmalloc((void**)&ctx->U1, sizeof(double) * 3 * ctx->total) ||
             !dmalloc((void**)&ctx->U2, sizeof(double) * 3 * ctx->total))
             return bail(PP_ENOMEM);
@@ -2146,9 +2363,14 @@ int pp_cweno_run(pp_cweno_ctx* ctx, double* U, double t_end, int64_t nsteps_max,
     if (!U) return fail(ctx, PP_EINVAL, "U is NULL");
     if (!(t_end > 0.0) || !(cfl > 0.0) || nsteps_max < 0)
         return fail(ctx, PP_EINVAL, "t_end and cfl must be > 0, nsteps_max >= 0");
-    if (rule != PP_DT_CFL && rule != PP_DT_H53) return fail(ctx, PP_EINVAL, "unknown dt rule");
+    if (rule != PP_DT_CFL && rule != PP_DT_H53 && rule != PP_DT_PP && rule != PP_DT_RESTART)
+        return fail(ctx, PP_EINVAL, "unknown dt rule");
     if (rule == PP_DT_H53 && ctx->cfg.ndim != 1) return fail(ctx, PP_EINVAL, "h^(5/3) rule is 1D");
     if (ctx->cfg.nbatch > 0) return fail(ctx, PP_EINVAL, "use pp_cweno_batch_run for ensembles");
+    if ((rule == PP_DT_PP || rule == PP_DT_RESTART) &&
+        (ctx->cfg.ndim != 1 || ctx->cfg.recon != PP_RECON_CWENO))
+        return fail(ctx, PP_EUNSUPPORTED,
+                    "the interface-state and restart rules run the 1D compact scheme only");
     const auto& c = ctx->cfg;
     Scal* s = ctx->scal;
     int r = reset_scal(ctx);
@@ -2168,7 +2390,8 @@ int pp_cweno_run(pp_cweno_ctx* ctx, double* U, double t_end, int64_t nsteps_max,
         }
         if (t_out) *t_out = host.t;
         if (steps_out) *steps_out = host.steps;
-        if (host.status) return fail(ctx, PP_ESTATE, "a stage left the admissible set or was not finite");
+        if (host.status & 3u)
+            return fail(ctx, PP_ESTATE, "a stage left the admissible set or was not finite");
         return PP_OK;
     }
     // 2D, and the explicit comparison schemes in 1D: (dt kernel, step) pairs
@@ -2191,7 +2414,18 @@ int pp_cweno_run(pp_cweno_ctx* ctx, double* U, double t_end, int64_t nsteps_max,
     }
     if (t_out) *t_out = host.t;
     if (steps_out) *steps_out = host.steps;
-    if (host.status) return fail(ctx, PP_ESTATE, "a stage left the admissible set or was not finite");
+    if (host.status & 3u)
+        return fail(ctx, PP_ESTATE, "a stage left the admissible set or was not finite");
+    return PP_OK;
+}
+
+int pp_cweno_restarts(pp_cweno_ctx* ctx, int64_t* out) {
+    if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
+    if (!out) return fail(ctx, PP_EINVAL, "out is NULL");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    long long v = 0;
+    HIPCHK(ctx, hipMemcpy(&v, &ctx->scal->restarts, sizeof(v), hipMemcpyDeviceToHost));
+    *out = v;
     return PP_OK;
 }
 
@@ -2249,7 +2483,7 @@ int pp_cweno_batch_tune(pp_cweno_ctx* ctx, const double* Upacked, double cfl, in
     // overwrites the per-problem t and steps, so no run can be continued
     hipLaunchKernelGGL(batch_init_kernel, dim3(nb), dim3(256), 0, ctx->stream, Upacked, ctx->total,
                        ctx->d_off, ctx->d_n, ctx->d_h, ctx->d_dt, ctx->d_t, ctx->d_steps,
-                       ctx->cfg.gamma, cfl, 1e300, 0, 0LL);
+                       ctx->cfg.gamma, cfl, 1e300, 0, 0LL, PP_DT_CFL, nullptr, nullptr);
     ctx->batch_started = false;
     HIPCHK(ctx, hipGetLastError());
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -2311,9 +2545,11 @@ static int batch_run_impl(pp_cweno_ctx* ctx, double* Upacked, double t_end, int6
     int r = 0;
     if (!resume) r = reset_scal(ctx);   // a continued run keeps the sticky status
     if (r) return r;
+    const int rule = ctx->cfg.batch_rule;
     hipLaunchKernelGGL(batch_init_kernel, dim3(nb), dim3(256), 0, ctx->stream, Upacked, ctx->total,
                        ctx->d_off, ctx->d_n, ctx->d_h, ctx->d_dt, ctx->d_t, ctx->d_steps,
-                       ctx->cfg.gamma, cfl, t_end, resume ? 1 : 0, (long long)nsteps_max);
+                       ctx->cfg.gamma, cfl, t_end, resume ? 1 : 0, (long long)nsteps_max, rule,
+                       rule == PP_DT_RESTART ? ctx->d_bad : nullptr, ctx->d_half);
     HIPCHK(ctx, hipGetLastError());
     ctx->batch_started = true;
     // K steps (3 persistent launches each) captured once in a graph on a
@@ -2371,33 +2607,33 @@ static int batch_run_impl(pp_cweno_ctx* ctx, double* Upacked, double t_end, int6
         if (ec != hipSuccess) return hip_fail(ctx, ec, "hipGraphInstantiate");
         return 0;
     };
+    // error paths: report the first failure, and a failure of the cleanup
+    // after it in the same message
+    auto fail_after = [&](int code) -> int {
+        const hipError_t ce = cleanup();
+        if (ce != hipSuccess) ctx->err += std::string("; cleanup: ") + hipGetErrorString(ce);
+        return code;
+    };
     hipError_t e = hipStreamCreateWithFlags(&gs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(ev, user);
     if (e == hipSuccess) e = hipStreamWaitEvent(gs, ev, 0);
-    if (e != hipSuccess) {
-        cleanup();
-        return hip_fail(ctx, e, "graph capture setup");
-    }
+    if (e != hipSuccess) return fail_after(hip_fail(ctx, e, "graph capture setup"));
     r = capture();
-    if (r) {
-        cleanup();
-        return r;
-    }
+    if (r) return fail_after(r);
     std::vector<double> dts(nb);
     std::vector<int> act;
     act.reserve(nb);
     int compact_ref = nb;
-    const int64_t max_replays = nsteps_max / K + 2;
+    // a redone step (restart rule) takes a replay slot without advancing, so
+    // that rule replays until every problem has retired
+    const int64_t max_replays = rule == PP_DT_RESTART ? INT64_MAX : nsteps_max / K + 2;
     for (int64_t rep = 0; rep < max_replays; ++rep) {
         e = hipGraphLaunch(exec, gs);
         if (e == hipSuccess)
             e = hipMemcpyAsync(dts.data(), ctx->d_dt, sizeof(double) * nb, hipMemcpyDeviceToHost, gs);
         if (e == hipSuccess) e = hipStreamSynchronize(gs);
-        if (e != hipSuccess) {
-            cleanup();
-            return hip_fail(ctx, e, "graph replay");
-        }
+        if (e != hipSuccess) return fail_after(hip_fail(ctx, e, "graph replay"));
         int active = 0;
         for (double d : dts) active += d > 0.0;
         if (active == 0) break;
@@ -2422,15 +2658,9 @@ static int batch_run_impl(pp_cweno_ctx* ctx, double* Upacked, double t_end, int6
         destroy_graph();
         e = hipMemcpyAsync(ctx->d_order, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, gs);
         if (e == hipSuccess) e = hipStreamSynchronize(gs);
-        if (e != hipSuccess) {
-            cleanup();
-            return hip_fail(ctx, e, "active-set upload");
-        }
+        if (e != hipSuccess) return fail_after(hip_fail(ctx, e, "active-set upload"));
         r = capture();
-        if (r) {
-            cleanup();
-            return r;
-        }
+        if (r) return fail_after(r);
         compact_ref = active;
     }
     e = cleanup();
@@ -2443,7 +2673,7 @@ static int batch_run_impl(pp_cweno_ctx* ctx, double* Upacked, double t_end, int6
     if (t_out) HIPCHK(ctx, hipMemcpy(t_out, ctx->d_t, sizeof(double) * nb, hipMemcpyDeviceToHost));
     unsigned status = 0;
     HIPCHK(ctx, hipMemcpy(&status, &ctx->scal->status, sizeof(unsigned), hipMemcpyDeviceToHost));
-    if (status) return fail(ctx, PP_ESTATE, "a stage left the admissible set or was not finite");
+    if (status & 3u) return fail(ctx, PP_ESTATE, "a stage left the admissible set or was not finite");
     return PP_OK;
 }
 
@@ -2466,7 +2696,7 @@ int pp_cweno_status(pp_cweno_ctx* ctx, uint32_t* flags) {
     if (st) {
         unsigned zero = 0;
         HIPCHK(ctx, hipMemcpy(&ctx->scal->status, &zero, sizeof(unsigned), hipMemcpyHostToDevice));
-        return fail(ctx, PP_ESTATE, "a stage left the admissible set or was not finite");
+        if (st & 3u) return fail(ctx, PP_ESTATE, "a stage left the admissible set or was not finite");
     }
     return PP_OK;
 }
@@ -2513,7 +2743,8 @@ void pp_cweno_destroy(pp_cweno_ctx* ctx) {
     void* bufs[] = {ctx->U1, ctx->U2, ctx->UA, ctx->UB, ctx->U1B, ctx->U2B, ctx->Lx, ctx->LyB,
                     ctx->scal, ctx->d_off, ctx->d_n, ctx->d_h, ctx->d_bc, ctx->d_dt, ctx->d_t,
                     ctx->d_steps,
-                    ctx->d_order, ctx->d_counter, ctx->d_dtcopy, ctx->d_tune};
+                    ctx->d_order, ctx->d_counter, ctx->d_dtcopy, ctx->d_tune, ctx->d_bad,
+                    ctx->d_half};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     for (int k = 0; k < 3; ++k)

@@ -39,7 +39,7 @@ static orc_params params(int recon, int flux)
 
 int main(void)
 {
-    static double U[3 * 4096], out[5];
+    static double U[3 * 4096], out[8];
     int failures = 0;
     const int sizes[] = {3, 4, 5, 7, 33, 130};
     const int bcs[][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}};
@@ -51,8 +51,10 @@ int main(void)
                     if (bcs[b][0] == 0 && n < 5) continue; /* periodic needs 5 cells */
                     orc_params P = params(recon, flux);
                     riemann(n, U, 1.0, 0.3, 1.0, 0.125, -0.2, 0.1);
+                    /* rule 0 (averages) and rule 2 (interface states) by turns */
+                    int rule = ((si + b) & 1) ? 2 : 0;
                     int rc = orc_run_1d(n, U, bcs[b][0], bcs[b][1], 1.0 / n, &P, 0.05,
-                                        1.0 / 12.0, 0, 20, out);
+                                        1.0 / 12.0, rule, 20, out);
                     if (rc != 0) {
                         printf("1D run n=%d bc=%d,%d recon=%d flux=%d: rc %d\n", n, bcs[b][0],
                                bcs[b][1], recon, flux, rc);
@@ -65,6 +67,9 @@ int main(void)
         riemann(200, U, 7.0, -1.0, 0.2, 7.0, 1.0, 0.2);
         int rc = orc_run_1d(200, U, 1, 1, 0.01, &P, 0.2, 1.0 / 12.0, 0, 200, out);
         if (rc != 0 && rc != -4) { printf("double rarefaction: rc %d\n", rc); ++failures; }
+        riemann(200, U, 7.0, -1.0, 0.2, 7.0, 1.0, 0.2);
+        rc = orc_run_1d(200, U, 1, 1, 0.01, &P, 0.2, 1.0 / 12.0, 2, 200, out);
+        if (rc != 0) { printf("double rarefaction, rule 2: rc %d\n", rc); ++failures; }
     }
     /* 2D, every boundary kind on each side */
     {
@@ -81,7 +86,8 @@ int main(void)
                     V[360 + c] = p / 0.4 + 0.5 * r * (u * u + v * v);
                 }
             orc_params P = params(recon, 0);
-            int rc = orc_run_2d(12, 10, V, bc2, 1.0 / 12, 1.0 / 10, &P, 0.02, 1.0 / 12.0, 10, out);
+            int rc = orc_run_2d_rule(12, 10, V, bc2, 1.0 / 12, 1.0 / 10, &P, 0.02, 1.0 / 12.0,
+                                     recon == 1 ? 2 : 0, 10, out);
             if (rc != 0) { printf("2D run recon=%d: rc %d\n", recon, rc); ++failures; }
         }
     }

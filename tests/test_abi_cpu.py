@@ -69,6 +69,8 @@ def _init(**kw):
     (dict(ndim=2, ny=64, dy=0.0), pp.PP_EINVAL),
     (dict(nbatch=-1), pp.PP_EINVAL),
     (dict(nbatch=2), pp.PP_EINVAL),              # batch arrays missing
+    (dict(batch_rule=1), pp.PP_EINVAL),          # the h^(5/3) rule is not a batch rule
+    (dict(batch_rule=4), pp.PP_EINVAL),
 ])
 def test_invalid_configs_rejected_before_device(kw, code):
     got, msg = _init(**kw)
@@ -82,6 +84,7 @@ def test_null_arguments():
     assert L.pp_cweno_step(None, None, 0.1) == pp.PP_EINVAL
     assert L.pp_cweno_stage(None, None, None, None, 1, 0.1) == pp.PP_EINVAL
     assert L.pp_cweno_status(None, None) == pp.PP_EINVAL
+    assert L.pp_cweno_restarts(None, None) == pp.PP_EINVAL
     L.pp_cweno_destroy(None)
 
 

@@ -176,6 +176,78 @@ def test_vacuum_blast_full_run():
     assert W.specific_internal_energy(Uf).min() > 0.99 * 2.5e-10
 
 
+def _speed(U, gamma=1.4):
+    """|u| + a of each column of a [3][n] array (pressure floored at 0)."""
+    r, u = U[0], U[1] / U[0]
+    p = (gamma - 1) * (U[2] - 0.5 * r * u * u)
+    return np.abs(u) + np.sqrt(gamma * np.maximum(p, 0.0) / r)
+
+
+def test_interface_state_speed_bound():
+    """The norm of condition (CFL-CD) under the interface-state rule is the
+    largest |u|+a over the cell averages and the limited interface states
+    the operator passes to the flux, recomputed here from the line's
+    intermediate arrays."""
+    U, _ = oracle.run_1d(W.vacuum_blast_1d(400), (1, 1), 2.0 / 400, 1.0, max_steps=8)
+    L, dbg = oracle.line_op(U, 1, 1, 2.0 / 400, debug=True)
+    ref = max(_speed(U).max(), _speed(dbg["um_l"]).max(), _speed(dbg["up_l"]).max())
+    _, s = oracle.rhs_speed_1d(U, (1, 1), 2.0 / 400)
+    assert s == pytest.approx(ref, rel=1e-15) and s == dbg["smax"]
+    assert s > _speed(U).max()   # the limited states are faster than the averages here
+
+
+def test_interface_state_rule_first_step_and_positivity():
+    """Rule DT_PP: the first step is cfl h / S with S the bound above; the
+    blast keeps every step in G for 200 steps, and later stages whose input
+    breaks the bound are counted."""
+    n, h = 4000, 2.0 / 4000
+    U0 = W.vacuum_blast_1d(n)
+    _, s = oracle.rhs_speed_1d(U0, (1, 1), h)
+    _, one = oracle.run_1d(U0, (1, 1), h, 1.0, rule=oracle.DT_PP, max_steps=1)
+    assert one["t"] == (1.0 / 12.0) * h / s
+    _, info = oracle.run_1d(U0, (1, 1), h, 1.0, rule=oracle.DT_PP, max_steps=200)
+    assert info["min_rho"] > 0 and info["min_p"] > 0 and info["viol"] > 0
+    assert info["out_of_G"] == 0
+
+
+def test_restart_rule_redoes_a_step_at_half_dt():
+    """Rule DT_RESTART: a step that was redone k times equals one step of
+    the averages' rule at cfl / 2^k (halving is exact), whose stage outputs
+    all lie in G, while the step at cfl / 2^(k-1) has a stage output outside
+    G.  On the blast the rule keeps every step in G where the averages' rule
+    leaves it."""
+    n, h = 4000, 2.0 / 4000
+    U, t = W.vacuum_blast_1d(n), 0.0
+    found = False
+    for _ in range(200):
+        Un, info = oracle.run_1d(U, (1, 1), h, 1.0, rule=oracle.DT_RESTART, max_steps=1)
+        k = info["restarts"]
+        if k > 0:
+            cfl = (1.0 / 12.0) / 2 ** k
+            ref, i0 = oracle.run_1d(U, (1, 1), h, 1.0, cfl=cfl, rule=oracle.DT_CFL, max_steps=1)
+            assert np.array_equal(ref, Un) and i0["t"] == info["t"] and i0["out_of_G"] == 0
+            _, i1 = oracle.run_1d(U, (1, 1), h, 1.0, cfl=2 * cfl, rule=oracle.DT_CFL, max_steps=1)
+            assert i1["out_of_G"] > 0
+            found = True
+            break
+        U = Un
+    assert found
+    _, r0 = oracle.run_1d(W.vacuum_blast_1d(n), (1, 1), h, 1.0, max_steps=60)
+    _, r3 = oracle.run_1d(W.vacuum_blast_1d(n), (1, 1), h, 1.0, rule=oracle.DT_RESTART,
+                          max_steps=60)
+    assert r0["out_of_G"] > 0 and r0["min_p"] < 0
+    assert r3["out_of_G"] == 0 and r3["min_p"] > 0 and r3["restarts"] > 0
+
+
+@pytest.mark.slow
+def test_restart_rule_blast_full_run():
+    """The blast to t = 1e-3 under DT_RESTART: t_end reached, every stage
+    output kept in G (2208 steps, 1018 redone)."""
+    Uf, info = oracle.run_1d(W.vacuum_blast_1d(4000), (1, 1), 2.0 / 4000, 1e-3,
+                             rule=oracle.DT_RESTART)
+    assert info["t"] == 1e-3 and info["out_of_G"] == 0 and info["min_p"] > 0
+
+
 @pytest.mark.slow
 def test_planar_sedov_final_minima():
     """Example 3.9 (h = 0.005, t = 0.001): printed minima 4.731E-03 (rho) and
@@ -209,6 +281,25 @@ def test_2d_x_only_data_reduces_to_1d():
             np.testing.assert_allclose(L2[k2], np.broadcast_to(L1[k1], (ny, nx)),
                                        atol=1e-11 * np.abs(L1[k1]).max())
         assert np.abs(L2[2]).max() <= 1e-11 * np.abs(L1).max()
+
+
+def test_2d_interface_state_rule_reduces_to_1d():
+    """The 2D interface-state rule on data varying only in x takes the 1D
+    rule's steps (the y-lines are uniform, so S_y is the averages' sound
+    speed and the x-term is the 1D bound)."""
+    nx, ny = 64, 4
+    x = W.cell_centres(0, 1, nx)
+    U1 = W.prim_to_cons_1d(1 + 0.5 * (x > 0.5), 0.2 * np.ones(nx), 1 + 0.5 * (x < 0.3), 1.4)
+    U2 = np.zeros((4, ny, nx))
+    U2[0], U2[1], U2[3] = U1[0], U1[1], U1[2]
+    dx, dy = 1.0 / nx, 1e14   # dy large: the y-term of the step bound is negligible
+    _, s2 = oracle.rhs_speed_2d(U2, (1, 1, 0, 0), dx, dy)
+    _, s1 = oracle.rhs_speed_1d(U1, (1, 1), dx)
+    assert s2[0] == pytest.approx(s1, rel=1e-14)
+    R2, i2 = oracle.run_2d(U2, (1, 1, 0, 0), dx, dy, 1.0, max_steps=5, rule=oracle.DT_PP)
+    R1, i1 = oracle.run_1d(U1, (1, 1), dx, 1.0, rule=oracle.DT_PP, max_steps=5)
+    assert i2["t"] == pytest.approx(i1["t"], rel=1e-12)
+    np.testing.assert_allclose(R2[0], np.broadcast_to(R1[0], (ny, nx)), rtol=1e-11)
 
 
 def test_2d_sedov_is_symmetric_and_positive():
