@@ -1649,6 +1649,9 @@ struct pp_cweno_ctx {
     // largest dynamic LDS size already granted to each kernel (the attribute
     // call is a driver round trip, not to be paid on every launch)
     std::unordered_map<const void*, size_t> lds_granted;
+    // the allocation-free entry point: every 1D line kernel was granted its
+    // largest dynamic LDS at set-up, so launches skip the table above
+    bool lds_pregranted = false;
     // measurement: event pairs around kernel launches, per class.  Within a
     // run of back-to-back timed launches (chaining) a launch's begin event is
     // the previous launch's end event, so each launch adds one record.
@@ -1746,6 +1749,18 @@ size_t line_lds_bytes(int nmax, int seg_max) {
 
 constexpr size_t kLdsBudget = 160 * 1024;
 
+// Let kernel fn use lds bytes of dynamic LDS (once per size increase; the
+// attribute call is a driver round trip, not to be paid on every launch).
+int grant_lds(pp_cweno_ctx* ctx, const void* fn, size_t lds) {
+    if (ctx->lds_pregranted) return PP_OK;
+    size_t& granted = ctx->lds_granted[fn];
+    if (lds > granted) {
+        HIPCHK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        granted = lds;
+    }
+    return PP_OK;
+}
+
 template <int NC, int W, int CPT, bool MIXED, int RECON = PP_RECON_CWENO>
 int pick_segment(int nmax) {
     constexpr int NT = 2 * NC * 64 * W;
@@ -1777,10 +1792,9 @@ int launch_line_p(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int 
     } else
         fn = seg >= nmax ? (const void*)line_kernel<NC, NRM, W, CPT, true, MIXED>
                          : (const void*)line_kernel<NC, NRM, W, CPT, false, MIXED>;
-    size_t& granted = ctx->lds_granted[fn];
-    if (lds > granted) {
-        HIPCHK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        granted = lds;
+    {
+        const int rg = grant_lds(ctx, fn, lds);
+        if (rg) return rg;
     }
     void* args[] = {&A};
     HIPCHK(ctx, hipLaunchKernel(fn, dim3(persistent ? grid : A.nlines), dim3(NT), args, lds,
@@ -1799,10 +1813,9 @@ int launch_line_explicit(pp_cweno_ctx* ctx, LineArgs A, int nmax) {
         return fail(ctx, PP_EUNSUPPORTED, "line too long for the on-chip line kernel");
     const void* fn = seg >= nmax ? (const void*)line_kernel<NC, NRM, W, CPT, true, false, RECON>
                                  : (const void*)line_kernel<NC, NRM, W, CPT, false, false, RECON>;
-    size_t& granted = ctx->lds_granted[fn];
-    if (lds > granted) {
-        HIPCHK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        granted = lds;
+    {
+        const int rg = grant_lds(ctx, fn, lds);
+        if (rg) return rg;
     }
     void* args[] = {&A};
     HIPCHK(ctx, hipLaunchKernel(fn, dim3(A.nlines), dim3(NT), args, lds, ctx->stream));
@@ -1881,10 +1894,9 @@ int launch_run1d_p(pp_cweno_ctx* ctx, RunArgs& R) {
         return fail(ctx, PP_EUNSUPPORTED, "line too long for the on-chip line kernel");
     const void* fn = seg >= nmax ? (const void*)run1d_kernel<NC, NRM, W, CPT, true, MIXED>
                                  : (const void*)run1d_kernel<NC, NRM, W, CPT, false, MIXED>;
-    size_t& granted = ctx->lds_granted[fn];
-    if (lds > granted) {
-        HIPCHK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        granted = lds;
+    {
+        const int rg = grant_lds(ctx, fn, lds);
+        if (rg) return rg;
     }
     void* args[] = {&R};
     HIPCHK(ctx, hipLaunchKernel(fn, dim3(1), dim3(NT), args, lds, ctx->stream));
@@ -2139,27 +2151,9 @@ int batch_step_launch(pp_cweno_ctx* ctx, double* Upacked, double* dtl, bool adva
 
 bool bc_ok(int b) { return b == PP_BC_PERIODIC || b == PP_BC_TRANSMISSIVE || b == PP_BC_REFLECTIVE; }
 
-}  // namespace
-
-extern "C" {
-
-void pp_cweno_config_defaults(pp_cweno_config* cfg) {
-    if (!cfg) return;
-    std::memset(cfg, 0, sizeof(*cfg));
-    cfg->ndim = 1;
-    cfg->ny = 1;
-    cfg->gamma = 1.4;
-    cfg->weno_eps = 1e-13;
-    cfg->pp_eps_cap = 1e-13;
-    cfg->gl_w1 = 1.0 / 12.0;
-    cfg->precision = PP_FP64;
-}
-
-int pp_cweno_init(const pp_cweno_config* cfg, pp_cweno_ctx** out) {
-    if (!out) return fail(nullptr, PP_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (!cfg) return fail(nullptr, PP_EINVAL, "cfg is NULL");
-    const pp_cweno_config& c = *cfg;
+// Host-side validation of a configuration (PP_OK or the failing code, with
+// the message in the init error slot); no device call.
+int check_config(const pp_cweno_config& c) {
     if (c.ndim != 1 && c.ndim != 2) return fail(nullptr, PP_EINVAL, "ndim must be 1 or 2");
     if (!(c.gamma > 1.0)) return fail(nullptr, PP_EINVAL, "gamma must be > 1");
     if (!(c.gl_w1 > 0.0 && c.gl_w1 < 0.5)) return fail(nullptr, PP_EINVAL, "gl_w1 must be in (0, 1/2)");
@@ -2208,6 +2202,32 @@ int pp_cweno_init(const pp_cweno_config* cfg, pp_cweno_ctx** out) {
                 return fail(nullptr, PP_EUNSUPPORTED, "2D lines are limited to 2048 cells");
         }
     }
+    return PP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pp_cweno_config_defaults(pp_cweno_config* cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->ndim = 1;
+    cfg->ny = 1;
+    cfg->gamma = 1.4;
+    cfg->weno_eps = 1e-13;
+    cfg->pp_eps_cap = 1e-13;
+    cfg->gl_w1 = 1.0 / 12.0;
+    cfg->precision = PP_FP64;
+}
+
+int pp_cweno_init(const pp_cweno_config* cfg, pp_cweno_ctx** out) {
+    if (!out) return fail(nullptr, PP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cfg) return fail(nullptr, PP_EINVAL, "cfg is NULL");
+    const pp_cweno_config& c = *cfg;
+    const int v = check_config(c);
+    if (v) return v;
     auto* ctx = new (std::nothrow) pp_cweno_ctx();
     if (!ctx) return fail(nullptr, PP_ENOMEM, "host allocation failed");
     ctx->cfg = c;
