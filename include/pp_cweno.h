@@ -145,6 +145,23 @@ int pp_cweno_stage(pp_cweno_ctx *ctx, const double *U0, const double *Us, double
 /* One SSP-RK3 step of size dt, in place on U (device). */
 int pp_cweno_step(pp_cweno_ctx *ctx, double *U, double dt);
 
+/* pp_cweno_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * one SSP-RK3 step of size dt, in place on the 1D line U ([3][nx], device),
+ * for the configuration *cfg (ndim 1, no batch, compact reconstruction, FP64
+ * or mixed, nx <= 4096; validated on the host as pp_cweno_init does), with
+ * no context.  Results equal pp_cweno_step's for the same configuration.
+ * Its stage buffers and scalars live in a fixed device array of the library
+ * (192 KiB + 256 bytes per GPU, held until the process ends); the first call
+ * on a device looks up that device's copy and sets the kernels' LDS limits.
+ * It calls no hipMalloc / hipFree and allocates nothing.  Enqueued on
+ * cfg->stream; not synchronised.  Every call on a GPU shares that GPU's
+ * array, so calls that overlap on one GPU (two streams, two threads) race;
+ * serialise them.  The stage checks of the status word are not reported.
+ * Errors as pp_cweno_init (message via pp_cweno_last_error(NULL)); larger
+ * lines give PP_EUNSUPPORTED. */
+int pp_cweno_step_static(const pp_cweno_config *cfg, double *U, double dt);
+
 /* Advance U (in place) from t = 0 until t_end or nsteps_max steps, whichever
  * comes first, with the time-step rule `rule` (PP_DT_*) and factor cfl; dt is
  * computed on the device every step.  Writes the time reached and the number

@@ -23,7 +23,7 @@ PP_RECON_CWENO, PP_RECON_WENOJS, PP_RECON_WENOZ = 0, 1, 2
 
 EXPORTED = [
     "pp_cweno_config_defaults", "pp_cweno_init", "pp_cweno_rhs", "pp_cweno_stage",
-    "pp_cweno_step", "pp_cweno_run", "pp_cweno_batch_step", "pp_cweno_batch_tune",
+    "pp_cweno_step", "pp_cweno_step_static", "pp_cweno_run", "pp_cweno_batch_step", "pp_cweno_batch_tune",
     "pp_cweno_batch_run", "pp_cweno_batch_continue",
     "pp_cweno_restarts", "pp_cweno_max_speed", "pp_cweno_status", "pp_cweno_debug_line", "pp_cweno_set_timing",
     "pp_cweno_get_timing", "pp_cweno_last_error", "pp_cweno_destroy",
@@ -69,6 +69,7 @@ def lib():
             "pp_cweno_rhs": (ctypes.c_int, [_VP, _VP, _VP]),
             "pp_cweno_stage": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_double]),
             "pp_cweno_step": (ctypes.c_int, [_VP, _VP, ctypes.c_double]),
+            "pp_cweno_step_static": (ctypes.c_int, [P(Config), _VP, ctypes.c_double]),
             "pp_cweno_run": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int64,
                                             ctypes.c_double, ctypes.c_int, P(ctypes.c_double),
                                             P(ctypes.c_int64)]),
@@ -119,6 +120,28 @@ def default_config() -> Config:
     c = Config()
     lib().pp_cweno_config_defaults(ctypes.byref(c))
     return c
+
+
+def step_static(U, dt, nx, dx, bc=(1, 1), gamma=1.4, precision=PP_FP64, weno_eps=1e-13,
+                pp_eps_cap=1e-13, gl_w1=1.0 / 12.0, flux=None, stream=None):
+    """pp_cweno_step_static: one SSP-RK3 step of a 1D line U ([3][nx]) in
+    place, without a context and without device allocation (the library's
+    fixed scratch array).  Raises PPError on failure."""
+    c = default_config()
+    c.ndim, c.nx, c.ny, c.dx, c.gamma = 1, nx, 1, dx, gamma
+    c.bc[0], c.bc[1] = int(bc[0]), int(bc[1])
+    c.precision, c.weno_eps, c.pp_eps_cap, c.gl_w1 = precision, weno_eps, pp_eps_cap, gl_w1
+    if flux is not None:
+        c.flux = int(flux)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    c.stream = ctypes.c_void_p(stream)
+    code = lib().pp_cweno_step_static(ctypes.byref(c), _ptr(U, 3 * int(nx)), float(dt))
+    if code != PP_OK:
+        msg = lib().pp_cweno_last_error(None)
+        raise PPError(code, msg.decode() if msg else "")
+    return code
 
 
 class Solver:

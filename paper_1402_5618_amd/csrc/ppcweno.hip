@@ -25,6 +25,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -33,6 +34,14 @@
 #include "ppc_device.h"
 
 using namespace ppc;
+
+// Device scratch of the allocation-free entry point pp_cweno_step_static: the
+// run scalars (first 256 bytes) and the two stage buffers of a 1D line of up
+// to 4096 cells.  Every GPU holds its own copy; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device.
+constexpr int kStaticMaxN = 4096;
+constexpr int kStaticScalSlots = 32;   // doubles reserved for the scalars
+static __device__ __align__(256) double scratch[kStaticScalSlots + 2 * 3 * kStaticMaxN];
 
 namespace {
 
@@ -2151,6 +2160,61 @@ int batch_step_launch(pp_cweno_ctx* ctx, double* Upacked, double* dtl, bool adva
 
 bool bc_ok(int b) { return b == PP_BC_PERIODIC || b == PP_BC_TRANSMISSIVE || b == PP_BC_REFLECTIVE; }
 
+// Allocation-free entry point: per device, the address of that device's
+// copy of `scratch` and the dynamic-LDS grants of the 1D line kernels, set
+// up once (the first call with that device current).
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+double* g_static_base[kMaxDevices] = {};
+
+template <int W, bool MIXED>
+size_t lds_1d_max(int n_lo, int n_hi) {
+    size_t m = 0;
+    for (int n = n_lo; n <= n_hi; ++n) {
+        const int seg = pick_segment<3, W, (W == 1 ? 6 : 3), MIXED>(n);
+        m = std::max(m, line_lds_bytes<3, W, MIXED>(n, seg));
+    }
+    return m;
+}
+
+int static_scratch(int dev, double** out) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_base[dev]) {
+        static_assert(sizeof(Scal) <= kStaticScalSlots * sizeof(double), "scalars overflow");
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, PP_EDEVICE,
+                        std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        // the kernels a 1D step can launch (lines of up to 2048 cells: one
+        // wave per system; longer: two), each with its largest LDS
+        struct K { const void* fn; size_t lds; };
+        const size_t l1 = lds_1d_max<1, false>(3, 2048), l1m = lds_1d_max<1, true>(3, 2048);
+        const size_t l2 = lds_1d_max<2, false>(2049, kStaticMaxN);
+        const size_t l2m = lds_1d_max<2, true>(2049, kStaticMaxN);
+        const K ks[] = {
+            {(const void*)line_kernel<3, 1, 1, 6, true, false>, l1},
+            {(const void*)line_kernel<3, 1, 1, 6, false, false>, l1},
+            {(const void*)line_kernel<3, 1, 1, 6, true, true>, l1m},
+            {(const void*)line_kernel<3, 1, 1, 6, false, true>, l1m},
+            {(const void*)line_kernel<3, 1, 2, 3, true, false>, l2},
+            {(const void*)line_kernel<3, 1, 2, 3, false, false>, l2},
+            {(const void*)line_kernel<3, 1, 2, 3, true, true>, l2m},
+            {(const void*)line_kernel<3, 1, 2, 3, false, true>, l2m},
+        };
+        for (const K& k : ks) {
+            if (k.lds > kLdsBudget) return fail(nullptr, PP_EUNSUPPORTED, "line kernel LDS budget");
+            e = hipFuncSetAttribute(k.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)k.lds);
+            if (e != hipSuccess)
+                return fail(nullptr, PP_EDEVICE,
+                            std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+        }
+        g_static_base[dev] = (double*)p;
+    }
+    *out = g_static_base[dev];
+    return PP_OK;
+}
+
 // Host-side validation of a configuration (PP_OK or the failing code, with
 // the message in the init error slot); no device call.
 int check_config(const pp_cweno_config& c) {
@@ -2375,6 +2439,45 @@ int pp_cweno_step(pp_cweno_ctx* ctx, double* U, double dt) {
         if (r) return r;
     }
     return step_single(ctx, U, nullptr, dt, false);
+}
+
+int pp_cweno_step_static(const pp_cweno_config* cfg, double* U, double dt) {
+    if (!cfg || !U) return fail(nullptr, PP_EINVAL, "cfg or U is NULL");
+    const pp_cweno_config& c = *cfg;
+    const int v = check_config(c);
+    if (v) return v;
+    if (c.ndim != 1 || c.nbatch != 0)
+        return fail(nullptr, PP_EINVAL, "pp_cweno_step_static advances one 1D line");
+    if (c.recon != PP_RECON_CWENO)
+        return fail(nullptr, PP_EUNSUPPORTED, "pp_cweno_step_static runs the compact scheme");
+    if (c.nx > kStaticMaxN)
+        return fail(nullptr, PP_EUNSUPPORTED, "pp_cweno_step_static: at most 4096 cells");
+    if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(nullptr, PP_EINVAL, "dt must be finite and >= 0");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, PP_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(nullptr, PP_EUNSUPPORTED, "device index beyond the static scratch table");
+    double* base = nullptr;
+    int r = static_scratch(dev, &base);
+    if (r) return r;
+    // launch state on the stack; device memory is the scratch array only
+    pp_cweno_ctx ctx;
+    ctx.cfg = c;
+    ctx.cfg.lengths = nullptr;
+    ctx.cfg.dxs = nullptr;
+    ctx.cfg.bcs = nullptr;
+    ctx.stream = (hipStream_t)c.stream;
+    ctx.nc = 3;
+    ctx.ncell = c.nx;
+    ctx.scal = reinterpret_cast<Scal*>(base);
+    ctx.U1 = base + kStaticScalSlots;
+    ctx.U2 = ctx.U1 + 3 * kStaticMaxN;
+    ctx.lds_pregranted = true;
+    r = reset_scal(&ctx);   // clears the scalars the last call left
+    if (!r) r = step_single(&ctx, U, nullptr, dt, false);
+    if (r) g_init_err = ctx.err;
+    return r;
 }
 
 int pp_cweno_run(pp_cweno_ctx* ctx, double* U, double t_end, int64_t nsteps_max, double cfl,
