@@ -49,7 +49,8 @@ def params(gamma=1.4, weno_eps=1e-13, eps_cap=1e-13, gl_w1=1.0 / 12.0, linear=Fa
     """flux: 0 HLLC (eq. (HLLC)), 1 local Lax-Friedrichs (the alternative the
     paper names for Example 3.6).  recon: 0 the compact reconstruction
     (Sec. 2.2), 1 explicit WENO-JS, 2 explicit WENO-Z (the non-compact
-    schemes the paper compares against in Sec. 3)."""
+    schemes the paper compares against in Sec. 3), 3 the compact
+    reconstruction along characteristic fields (Sec. 2.3; 1D)."""
     return Params(gamma, weno_eps, eps_cap, gl_w1, int(linear), int(first_order), int(limiter),
                   int(flux), int(recon))
 
@@ -101,6 +102,9 @@ def lib():
                                         _DBL, _DBL, _I, _L, _D, _D]),
             "orc_num_threads": (_I, []),
             "orc_weights": (None, [_D, _DBL, _D]),
+            "orc_char_eigen": (None, [_DBL, _D, _D, _D, _D, _D]),
+            "orc_block_solve": (_I, [_I, _I, _D, _D, _D, _D, _D]),
+            "orc_recon_char": (_I, [_I, _I, _D, _P, _D, _D]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -368,6 +372,37 @@ def weights(v6, eps=1e-13):
     w = np.empty(6)
     lib().orc_weights(_d(v6), eps, _d(w))
     return w[:3], w[3:]
+
+
+def char_eigen(Ua, Ub, gamma=1.4):
+    """Left eigenvectors L (rows), right eigenvectors R (columns) and
+    eigenvalues at the Roe average of Ua and Ub (Sec. 2.3)."""
+    Ua, Ub = _f64(Ua), _f64(Ub)
+    L, R, lam = np.empty(9), np.empty(9), np.empty(3)
+    lib().orc_char_eigen(gamma, _d(Ua), _d(Ub), _d(L), _d(R), _d(lam))
+    return L.reshape(3, 3), R.reshape(3, 3), lam
+
+
+def block_solve(A, B, C, Y, cyclic=False):
+    """Block chasing solve of A_i X_{i-1} + B_i X_i + C_i X_{i+1} = Y_i
+    (3x3 blocks; cyclic: indices mod n)."""
+    A, B, C, Y = (_f64(v) for v in (A, B, C, Y))
+    n = Y.shape[0]
+    X = np.empty_like(Y)
+    _check(lib().orc_block_solve(n, int(cyclic), _d(A), _d(B), _d(C), _d(Y), _d(X)), "block")
+    return X
+
+
+def recon_char(ue, cyclic_line, p=None):
+    """Characteristic-wise reconstruction of a 1D line from ghost-extended
+    averages ``ue`` ([3][n+6], cells -3..n+2): (U-_{i+1/2}, U+_{i-1/2})."""
+    p = p or params()
+    ue = _f64(ue)
+    n = ue.shape[1] - 6
+    um, up = np.empty((3, n)), np.empty((3, n))
+    _check(lib().orc_recon_char(n, int(cyclic_line), _d(ue), ctypes.byref(p), _d(um), _d(up)),
+           "recon_char")
+    return um, up
 
 
 def num_threads() -> int:

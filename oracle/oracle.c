@@ -36,7 +36,8 @@ typedef struct {
     int limiter;      /* 1: apply the positivity-preserving limiter */
     int flux;         /* 0: HLLC, eq. (HLLC); 1: local Lax-Friedrichs (see lf below) */
     int recon;        /* 0: compact (FVCW, Sec 2.2); 1: explicit WENO-JS; 2: explicit
-                       * WENO-Z (the non-compact schemes of Sec 3, see weno5_explicit) */
+                       * WENO-Z (the non-compact schemes of Sec 3, see weno5_explicit);
+                       * 3: compact, characteristic-wise (Sec 2.3; 1D only) */
 } orc_params;
 
 /* Optional per-line intermediate results for tests (any pointer may be NULL). */
@@ -356,6 +357,332 @@ static int recon_scalar(int n, int cyclic, const double *ue, const orc_params *P
     return s;
 }
 
+/* ----------------------------------------------------------------- Sec 2.3
+ * Characteristic-wise compact reconstruction of the 1D Euler system
+ * (recon = 3): at each node the scalar rows of eq. (CWENO-FV) are formed per
+ * characteristic field from the characteristic variables l^(k) . Ubar of the
+ * Roe average at that node, and stacked into the 3x3 block tridiagonal
+ * system (1DEuler-FVC) in the conserved nodal values, solved by block
+ * chasing. */
+
+/* Roe average of the states Ua, Ub (rho, rho u, E) and, there, the left
+ * eigenvectors l^(k) (rows of L, eq. (leigenv)), the right eigenvectors
+ * r^(k) (columns of R, eq. (reigenv)) and the eigenvalues (eq. (eigen)).
+ * Reading: a Roe sound speed that is not positive (two states without
+ * pressure moving together) makes the node component-wise (L = R = I). */
+static void roe_eigen(double g, const double *Ua, const double *Ub, double L[3][3],
+                      double R[3][3], double lam[3])
+{
+    double ra = Ua[0], rb = Ub[0];
+    double ua = Ua[1] / ra, ub = Ub[1] / rb;
+    double pa = (g - 1.0) * (Ua[2] - 0.5 * ra * ua * ua);
+    double pb = (g - 1.0) * (Ub[2] - 0.5 * rb * ub * ub);
+    double Ha = (Ua[2] + pa) / ra, Hb = (Ub[2] + pb) / rb;
+    double sa = sqrt(ra), sb = sqrt(rb);
+    double u = (sa * ua + sb * ub) / (sa + sb);
+    double H = (sa * Ha + sb * Hb) / (sa + sb);
+    double a2 = (g - 1.0) * (H - 0.5 * u * u);
+    if (!(a2 > 0.0)) {
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) L[i][j] = R[i][j] = (i == j) ? 1.0 : 0.0;
+        lam[0] = lam[1] = lam[2] = u;
+        return;
+    }
+    double a = sqrt(a2);
+    double c1 = (g - 1.0) / a2, c2 = 0.5 * u * u * c1;
+    L[0][0] = 0.5 * (c2 + u / a); L[0][1] = 0.5 * (-c1 * u - 1.0 / a); L[0][2] = 0.5 * c1;
+    L[1][0] = 1.0 - c2;           L[1][1] = c1 * u;                    L[1][2] = -c1;
+    L[2][0] = 0.5 * (c2 - u / a); L[2][1] = 0.5 * (-c1 * u + 1.0 / a); L[2][2] = 0.5 * c1;
+    R[0][0] = 1.0;         R[0][1] = 1.0;           R[0][2] = 1.0;
+    R[1][0] = u - a;       R[1][1] = u;             R[1][2] = u + a;
+    R[2][0] = H - u * a;   R[2][1] = 0.5 * u * u;   R[2][2] = H + u * a;
+    lam[0] = u - a; lam[1] = u; lam[2] = u + a;
+}
+
+/* Exported for unit tests: L and R row-major [3][3]. */
+void orc_char_eigen(double gamma, const double *Ua, const double *Ub, double *Lo, double *Ro,
+                    double *lam)
+{
+    double L[3][3], R[3][3];
+    roe_eigen(gamma, Ua, Ub, L, R, lam);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) { Lo[3 * i + j] = L[i][j]; Ro[3 * i + j] = R[i][j]; }
+}
+
+/* Solve M X = Y for a 3x3 M and k right-hand columns (Y, X row-major 3 x k),
+ * Gaussian elimination with partial pivoting.  Returns 0 or -1 if singular. */
+static int solve3(const double M[3][3], int k, const double *Y, double *X)
+{
+    double T[3][3 + 8];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) T[i][j] = M[i][j];
+        for (int j = 0; j < k; ++j) T[i][3 + j] = Y[i * k + j];
+    }
+    for (int c = 0; c < 3; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < 3; ++i)
+            if (fabs(T[i][c]) > fabs(T[piv][c])) piv = i;
+        if (T[piv][c] == 0.0) return -1;
+        if (piv != c)
+            for (int j = 0; j < 3 + k; ++j) { double t = T[c][j]; T[c][j] = T[piv][j]; T[piv][j] = t; }
+        for (int i = c + 1; i < 3; ++i) {
+            double f = T[i][c] / T[c][c];
+            for (int j = c; j < 3 + k; ++j) T[i][j] -= f * T[c][j];
+        }
+    }
+    for (int j = 0; j < k; ++j)
+        for (int i = 2; i >= 0; --i) {
+            double v = T[i][3 + j];
+            for (int l = i + 1; l < 3; ++l) v -= T[i][l] * X[l * k + j];
+            X[i * k + j] = v / T[i][i];
+        }
+    return 0;
+}
+
+/* Y -= M X for 3x3 M and X, Y of k columns (row-major 3 x k). */
+static void sub_mul3(const double M[3][3], int k, const double *X, double *Y)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < k; ++j)
+            for (int l = 0; l < 3; ++l) Y[i * k + j] -= M[i][l] * X[l * k + j];
+}
+
+/* Block chasing (the paper's method for (1DEuler-FVC)):
+ * A_i X_{i-1} + B_i X_i + C_i X_{i+1} = Y_i, i = 0..n-1, 3x3 blocks (A_0 and
+ * C_{n-1} ignored), Y_i and X_i of k <= 4 columns ([n][3][k]).  Block LU
+ * without pivoting between blocks; each pivot block solved with partial
+ * pivoting.  Returns 0, -1 on a singular pivot block, -2 on no memory. */
+static int blk_thomas(int n, int k, const double (*A)[3][3], const double (*B)[3][3],
+                      const double (*C)[3][3], const double *Y, double *X)
+{
+    double (*Cp)[3][3] = (double (*)[3][3])malloc(sizeof(double) * 9u * (size_t)n);
+    double *Dp = (double *)malloc(sizeof(double) * 3u * (size_t)k * (size_t)n);
+    if (!Cp || !Dp) { free(Cp); free(Dp); return -2; }
+    int rc = 0;
+    for (int i = 0; i < n && rc == 0; ++i) {
+        double M[3][3], rhs[3 * 7], sol[3 * 7];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) M[r][c] = B[i][r][c];
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) rhs[r * (3 + k) + c] = (i < n - 1) ? C[i][r][c] : 0.0;
+            for (int c = 0; c < k; ++c) rhs[r * (3 + k) + 3 + c] = Y[(size_t)i * 3 * k + r * k + c];
+        }
+        if (i > 0) {
+            /* M = B_i - A_i Cp_{i-1};  rhs(Y part) -= A_i Dp_{i-1} */
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c)
+                    for (int l = 0; l < 3; ++l) M[r][c] -= A[i][r][l] * Cp[i - 1][l][c];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < k; ++c)
+                    for (int l = 0; l < 3; ++l)
+                        rhs[r * (3 + k) + 3 + c] -= A[i][r][l] * Dp[(size_t)(i - 1) * 3 * k + l * k + c];
+        }
+        rc = solve3(M, 3 + k, rhs, sol);
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) Cp[i][r][c] = sol[r * (3 + k) + c];
+            for (int c = 0; c < k; ++c) Dp[(size_t)i * 3 * k + r * k + c] = sol[r * (3 + k) + 3 + c];
+        }
+    }
+    if (rc == 0) {
+        for (int j = 0; j < 3 * k; ++j) X[(size_t)(n - 1) * 3 * k + j] = Dp[(size_t)(n - 1) * 3 * k + j];
+        for (int i = n - 2; i >= 0; --i) {
+            for (int j = 0; j < 3 * k; ++j) X[(size_t)i * 3 * k + j] = Dp[(size_t)i * 3 * k + j];
+            sub_mul3(Cp[i], k, &X[(size_t)(i + 1) * 3 * k], &X[(size_t)i * 3 * k]);
+        }
+    }
+    free(Cp);
+    free(Dp);
+    return rc;
+}
+
+/* Block cyclic system (indices mod n, n >= 3), one right-hand column: the
+ * last unknown is kept as a parameter, X_i = P_i + Q_i X_{n-1} from the
+ * leading (n-1) block rows (right-hand columns Y and the two coupling
+ * blocks), then the last block row gives X_{n-1}. */
+static int blk_cyclic(int n, const double (*A)[3][3], const double (*B)[3][3],
+                      const double (*C)[3][3], const double *Y, double *X)
+{
+    int m = n - 1;
+    double *Y4 = (double *)calloc((size_t)m * 12u, sizeof(double));
+    double *S4 = (double *)malloc(sizeof(double) * (size_t)m * 12u);
+    if (!Y4 || !S4) { free(Y4); free(S4); return -2; }
+    for (int i = 0; i < m; ++i)
+        for (int r = 0; r < 3; ++r) Y4[(size_t)i * 12 + r * 4] = Y[3 * i + r];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            Y4[r * 4 + 1 + c] -= A[0][r][c];                       /* row 0 couples X_{n-1} */
+            Y4[(size_t)(m - 1) * 12 + r * 4 + 1 + c] -= C[m - 1][r][c];  /* row n-2 too */
+        }
+    int rc = blk_thomas(m, 4, A, B, C, Y4, S4);
+    if (rc == 0) {
+        /* (B_{n-1} + A_{n-1} Q_{n-2} + C_{n-1} Q_0) X_{n-1} = Y_{n-1} - A_{n-1} P_{n-2} - C_{n-1} P_0 */
+        double M[3][3], rhs[3], xl[3];
+        const double *Sl = &S4[(size_t)(m - 1) * 12], *S0 = &S4[0];
+        for (int r = 0; r < 3; ++r) {
+            rhs[r] = Y[3 * (n - 1) + r];
+            for (int c = 0; c < 3; ++c) {
+                M[r][c] = B[n - 1][r][c];
+                for (int l = 0; l < 3; ++l)
+                    M[r][c] += A[n - 1][r][l] * Sl[l * 4 + 1 + c] + C[n - 1][r][l] * S0[l * 4 + 1 + c];
+            }
+            for (int l = 0; l < 3; ++l)
+                rhs[r] -= A[n - 1][r][l] * Sl[l * 4] + C[n - 1][r][l] * S0[l * 4];
+        }
+        rc = solve3(M, 1, rhs, xl);
+        if (rc == 0) {
+            for (int i = 0; i < m; ++i)
+                for (int r = 0; r < 3; ++r) {
+                    double v = S4[(size_t)i * 12 + r * 4];
+                    for (int c = 0; c < 3; ++c) v += S4[(size_t)i * 12 + r * 4 + 1 + c] * xl[c];
+                    X[3 * i + r] = v;
+                }
+            for (int r = 0; r < 3; ++r) X[3 * (n - 1) + r] = xl[r];
+        }
+    }
+    free(Y4);
+    free(S4);
+    return rc;
+}
+
+/* Exported for unit tests: A, B, C [n][3][3], Y, X [n][3]. */
+int orc_block_solve(int n, int cyclic, const double *A, const double *B, const double *C,
+                    const double *Y, double *X)
+{
+    if (cyclic) {
+        if (n < 3) return -3;
+        return blk_cyclic(n, (const double (*)[3][3])A, (const double (*)[3][3])B,
+                          (const double (*)[3][3])C, Y, X);
+    }
+    return blk_thomas(n, 1, (const double (*)[3][3])A, (const double (*)[3][3])B,
+                      (const double (*)[3][3])C, Y, X);
+}
+
+/* The characteristic-wise reconstruction of one 1D line: ue [3][n+6] holds
+ * the ghost-extended averages (cell i at ue[c][i+3]).  um[c][i] = U-_{i+1/2},
+ * up[c][i] = U+_{i-1/2}.  Rows of the "-" system sit at node i+1/2 with the
+ * eigenvectors of Roe(Ubar_i, Ubar_{i+1}); rows of the "+" system at node
+ * i-1/2 with those of Roe(Ubar_{i-1}, Ubar_i), the mirrored rows of Sec. 2.2,
+ * chased from the right end.  Non-periodic lines are closed as the
+ * component-wise ones (reading R10). */
+static int recon_char(int n, int cyclic, const double *ue, const orc_params *P, double *um,
+                      double *up)
+{
+    int ne = n + 2 * NG;
+    double (*A)[3][3] = (double (*)[3][3])malloc(sizeof(double) * 27u * (size_t)n);
+    double (*Bm)[3][3] = A ? A + n : NULL, (*Cm)[3][3] = A ? A + 2 * n : NULL;
+    double *Y = (double *)malloc(sizeof(double) * 6u * (size_t)n);
+    double *X = Y ? Y + 3 * n : NULL;
+    if (!A || !Y) { free(A); free(Y); return -2; }
+#define UE(c, m) ue[(size_t)(c) * ne + (m) + NG]
+    for (int side = 0; side < 2; ++side) {
+        for (int i = 0; i < n; ++i) {
+            double Ua[3], Ub[3], L[3][3], R[3][3], lam[3];
+            int ca = side == 0 ? i : i - 1;   /* Roe pair of the row's node */
+            for (int c = 0; c < 3; ++c) { Ua[c] = UE(c, ca); Ub[c] = UE(c, ca + 1); }
+            roe_eigen(P->gamma, Ua, Ub, L, R, lam);
+            for (int k = 0; k < 3; ++k) {
+                double v[5], beta[3], w[3], a, b, c, r;
+                for (int m = 0; m < 5; ++m) {
+                    v[m] = 0.0;
+                    for (int q = 0; q < 3; ++q) v[m] += L[k][q] * UE(q, i - 2 + m);
+                }
+                if (side == 0) {
+                    beta_minus(v, beta);
+                    side_weights(beta, P, w);
+                    row_minus(w, v[1], v[2], v[3], &a, &b, &c, &r);
+                } else {
+                    beta_plus(v, beta);
+                    side_weights(beta, P, w);
+                    row_plus(w, v[1], v[2], v[3], &a, &b, &c, &r);
+                }
+                for (int q = 0; q < 3; ++q) {
+                    A[i][k][q] = a * L[k][q];
+                    Bm[i][k][q] = b * L[k][q];
+                    Cm[i][k][q] = c * L[k][q];
+                }
+                Y[3 * i + k] = r;
+            }
+        }
+        int s;
+        if (side == 0) {
+            if (cyclic) {
+                s = blk_cyclic(n, (const double (*)[3][3])A, (const double (*)[3][3])Bm,
+                               (const double (*)[3][3])Cm, Y, X);
+            } else {
+                /* closure values U-_{-1/2} (cell -1) and U-_{n+1/2} (cell n) */
+                double xl[3], xr[3];
+                for (int c = 0; c < 3; ++c) {
+                    xl[c] = weno5z_minus(&ue[(size_t)c * ne + 0], P);
+                    xr[c] = weno5z_minus(&ue[(size_t)c * ne + n + 1], P);
+                }
+                for (int k = 0; k < 3; ++k)
+                    for (int q = 0; q < 3; ++q) {
+                        Y[k] -= A[0][k][q] * xl[q];
+                        Y[3 * (n - 1) + k] -= Cm[n - 1][k][q] * xr[q];
+                    }
+                s = blk_thomas(n, 1, (const double (*)[3][3])A, (const double (*)[3][3])Bm,
+                               (const double (*)[3][3])Cm, Y, X);
+            }
+            for (int i = 0; i < n && s == 0; ++i)
+                for (int c = 0; c < 3; ++c) um[(size_t)c * n + i] = X[3 * i + c];
+        } else {
+            if (!cyclic) {
+                /* closure values U+ at the left faces of cells -1 and n */
+                double xl[3], xr[3], mv[5];
+                for (int c = 0; c < 3; ++c) {
+                    for (int k = 0; k < 5; ++k) mv[k] = ue[(size_t)c * ne + 4 - k];
+                    xl[c] = weno5z_minus(mv, P);
+                    for (int k = 0; k < 5; ++k) mv[k] = ue[(size_t)c * ne + n + 5 - k];
+                    xr[c] = weno5z_minus(mv, P);
+                }
+                for (int k = 0; k < 3; ++k)
+                    for (int q = 0; q < 3; ++q) {
+                        Y[k] -= A[0][k][q] * xl[q];
+                        Y[3 * (n - 1) + k] -= Cm[n - 1][k][q] * xr[q];
+                    }
+            }
+            /* chased from the right end: the reversed system, A and C exchanged */
+            double (*rA)[3][3] = (double (*)[3][3])malloc(sizeof(double) * 27u * (size_t)n);
+            double *rY = (double *)malloc(sizeof(double) * 6u * (size_t)n);
+            if (!rA || !rY) { free(rA); free(rY); s = -2; }
+            else {
+                double (*rB)[3][3] = rA + n, (*rC)[3][3] = rA + 2 * n;
+                double *rX = rY + 3 * n;
+                for (int i = 0; i < n; ++i) {
+                    int j = n - 1 - i;
+                    for (int k = 0; k < 3; ++k) {
+                        for (int q = 0; q < 3; ++q) {
+                            rA[i][k][q] = Cm[j][k][q];
+                            rB[i][k][q] = Bm[j][k][q];
+                            rC[i][k][q] = A[j][k][q];
+                        }
+                        rY[3 * i + k] = Y[3 * j + k];
+                    }
+                }
+                s = cyclic ? blk_cyclic(n, (const double (*)[3][3])rA, (const double (*)[3][3])rB,
+                                        (const double (*)[3][3])rC, rY, rX)
+                           : blk_thomas(n, 1, (const double (*)[3][3])rA, (const double (*)[3][3])rB,
+                                        (const double (*)[3][3])rC, rY, rX);
+                for (int i = 0; i < n && s == 0; ++i)
+                    for (int c = 0; c < 3; ++c) up[(size_t)c * n + (n - 1 - i)] = rX[3 * i + c];
+                free(rA);
+                free(rY);
+            }
+        }
+        if (s) { free(A); free(Y); return s; }
+    }
+#undef UE
+    free(A);
+    free(Y);
+    return 0;
+}
+
+/* Exported for unit tests: ue [3][n+6] ghost-extended averages. */
+int orc_recon_char(int n, int cyclic, const double *ue, const orc_params *P, double *um, double *up)
+{
+    return recon_char(n, cyclic, ue, P, um, up);
+}
+
 /* ----------------------------------------------------------------- Sec 2.4
  * HLLC flux (eqs. (HLLC), (contact-v), (star-l), (acoustic ws)) across a
  * face whose normal momentum is component `nrm` (1: x, 2: y).
@@ -609,6 +936,11 @@ long orc_line_op(int n, int ncomp, int nrm, const double *u, int bc_lo, int bc_h
         }
     }
 
+    if (P->recon == 3 && !P->first_order) {
+        /* characteristic-wise (Sec. 2.3): all components at once; 1D only */
+        int s = ncomp == 3 ? recon_char(n, cyclic, ue, P, um, up) : -3;
+        if (s) { free(mem); return -10 + s; }
+    } else
     /* reconstruction, component by component (conservative variables) */
     for (int k = 0; k < ncomp; ++k) {
         double *mk = um + (size_t)k * n, *pk = up + (size_t)k * n;

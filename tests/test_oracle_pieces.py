@@ -601,3 +601,123 @@ def test_explicit_weno_js_matches_table2_column():
         l1, l2, linf = W.error_norms(U[0], W.density_wave_1d(n, t=info["t"])[0], 2.0 / n)
         assert abs(l1 / rows[n][1] - 1) < 0.02, (n, l1, rows[n][1])
         assert abs(linf / rows[n][2] - 1) < 0.02, (n, linf, rows[n][2])
+
+
+# ------------------------------------------- Sec 2.3: characteristic fields
+def _jacobian_printed(u, e_rho, g=GAMMA):
+    """The Jacobian A(U) of Sec. 2.3, in terms of u2/u1 = u and u3/u1 = E/rho.
+    The printed (2,1) entry reads -(gamma-3)/2 u^2; the derivative of
+    rho u^2 + p with respect to rho is +(gamma-3)/2 u^2, and only that sign
+    gives the eigenvalues u - a, u, u + a the text states (reading R28)."""
+    return np.array([
+        [0.0, 1.0, 0.0],
+        [0.5 * (g - 3) * u * u, (3 - g) * u, g - 1],
+        [-g * u * e_rho + (g - 1) * u ** 3, g * e_rho - 1.5 * (g - 1) * u * u, g * u],
+    ])
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_char_eigenvectors_diagonalise_the_jacobian(seed):
+    """L R = I; L A R = diag(u - a, u, u + a) with A the Jacobian of Sec. 2.3
+    at the Roe state (its printed (2,1) sign corrected); and Roe's defining
+    property R Lambda L (Ub - Ua) = F(Ub) - F(Ua), which fixes the averaged
+    state itself."""
+    for _ in range(50 + seed):
+        Ua = rand_state()
+        Ub = rand_state()
+        L, R, lam = oracle.char_eigen(Ua, Ub)
+        np.testing.assert_allclose(L @ R, np.eye(3), atol=1e-12)
+        u = lam[1]
+        a = 0.5 * (lam[2] - lam[0])
+        H = R[2, 2] - u * a          # r^(3) = (1, u + a, H + u a)
+        e_rho = (H + 0.5 * (GAMMA - 1) * u * u) / GAMMA   # E/rho of the state with (u, H)
+        A = _jacobian_printed(u, e_rho)
+        D = L @ A @ R
+        scale = np.abs(lam).max()
+        np.testing.assert_allclose(D, np.diag([u - a, u, u + a]), atol=1e-12 * scale)
+        dF = euler_flux(Ub) - euler_flux(Ua)
+        np.testing.assert_allclose(R @ np.diag(lam) @ L @ (Ub - Ua), dF,
+                                   atol=1e-11 * np.abs(dF).max() + 1e-14)
+
+
+@pytest.mark.parametrize("n,cyclic", [(1, False), (2, False), (3, False), (7, False), (12, False),
+                                      (3, True), (4, True), (9, True)])
+def test_block_chasing_matches_dense_solve(n, cyclic):
+    """The block chasing of (1DEuler-FVC) (and its cyclic form) against a
+    dense solve of the assembled 3n x 3n system."""
+    rng = np.random.default_rng(n + 10 * cyclic)
+    A = rng.normal(size=(n, 3, 3))
+    C = rng.normal(size=(n, 3, 3))
+    B = rng.normal(size=(n, 3, 3)) + 8 * np.eye(3)
+    Y = rng.normal(size=(n, 3))
+    X = oracle.block_solve(A, B, C, Y, cyclic)
+    M = np.zeros((3 * n, 3 * n))
+    for i in range(n):
+        M[3 * i:3 * i + 3, 3 * i:3 * i + 3] += B[i]
+        for blk, j in ((A[i], i - 1), (C[i], i + 1)):
+            if cyclic:
+                j %= n
+            elif not 0 <= j < n:
+                continue
+            M[3 * i:3 * i + 3, 3 * j:3 * j + 3] += blk
+    ref = oracle.dense_solve(M, Y.reshape(-1)).reshape(n, 3)
+    np.testing.assert_allclose(X, ref, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_char_reconstruction_exact_for_quadratics(seed):
+    """Every row of (1DEuler-FVC) is a characteristic combination of the
+    scalar rows of eq. (CWENO-FV), each exact for quadratics with any
+    weights, so the exact nodal values of quadratic conserved variables
+    solve the block system: the characteristic reconstruction (nonlinear
+    weights, node-dependent eigenvectors) reproduces them."""
+    rng = np.random.default_rng(400 + seed)
+    n, h = 23, 0.05
+    edges = (np.arange(-3, n + 4)) * h
+    coef = [np.array([1.0, 0.3, 0.5]) * rng.uniform(0.5, 1.5, 3),      # rho > 0
+            rng.normal(size=3) * 0.3,                                  # rho u
+            np.array([4.0, 0.5, 1.0]) * rng.uniform(0.5, 1.5, 3)]      # E: p > 0
+    ue = np.array([poly_avgs(c, edges) for c in coef])
+    um, up = oracle.recon_char(ue, False)
+    xr, xl = edges[4:n + 4], edges[3:n + 3]
+    for c in range(3):
+        scale = np.abs(ue[c]).max()
+        np.testing.assert_allclose(um[c], np.polynomial.polynomial.polyval(xr, coef[c]),
+                                   atol=1e-11 * scale)
+        np.testing.assert_allclose(up[c], np.polynomial.polynomial.polyval(xl, coef[c]),
+                                   atol=1e-11 * scale)
+
+
+def test_char_reconstruction_of_the_density_wave_equals_componentwise():
+    """Table 3 prints the same FVCW errors as Table 2: for the density wave
+    (u, p constant) the conserved variables are affine in rho, two
+    characteristic fields are constant and the component-wise nodal values
+    solve the block system, so the two reconstructions agree to roundoff."""
+    n = 40
+    U = W.density_wave_1d(n)
+    ue = np.concatenate([U[:, -3:], U, U[:, :3]], axis=1)
+    um_c, up_c = oracle.recon_char(ue, True)
+    for c in range(3):
+        um, up = oracle.recon_scalar(ue[c], True)
+        np.testing.assert_allclose(um_c[c], um, rtol=1e-13, atol=1e-13)
+        np.testing.assert_allclose(up_c[c], up, rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("cyclic", [True, False])
+def test_char_reconstruction_mirror_symmetry(cyclic):
+    """Reversing a line and negating its momentum mirrors it: the "-" values
+    of the mirrored line are the mirrored "+" values of the line.  Ties the
+    "-" rows (node i+1/2, Roe average of cells i, i+1) to the "+" rows (node
+    i-1/2, Roe average of cells i-1, i)."""
+    n = 30
+    x = W.cell_centres(0.0, 1.0, n)
+    U = W.prim_to_cons_1d(1 + 0.4 * (x > 0.4) + 0.1 * np.sin(5 * x), 0.3 * np.cos(3 * x),
+                          1 + 0.6 * (x < 0.7), GAMMA)
+    ue = np.concatenate([U[:, -3:], U, U[:, :3]], axis=1) if cyclic else \
+        np.concatenate([np.repeat(U[:, :1], 3, 1), U, np.repeat(U[:, -1:], 3, 1)], axis=1)
+    um, up = oracle.recon_char(ue, cyclic)
+    flip = np.array([1.0, -1.0, 1.0])[:, None]
+    um_r, up_r = oracle.recon_char(flip * ue[:, ::-1], cyclic)
+    scale = np.abs(U).max()
+    np.testing.assert_allclose(flip * um_r[:, ::-1], up, atol=1e-12 * scale)
+    np.testing.assert_allclose(flip * up_r[:, ::-1], um, atol=1e-12 * scale)
