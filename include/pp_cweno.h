@@ -89,15 +89,20 @@ enum { PP_DT_CFL = 0, PP_DT_H53 = 1, PP_DT_PP = 2, PP_DT_RESTART = 3 };
  * both precisions. */
 enum { PP_FLUX_HLLC = 0, PP_FLUX_LF = 1 };
 
-/* Interface reconstruction (Sec. 2.2 and the comparisons of Sec. 3).
- * PP_RECON_CWENO: the compact scheme, solution-dependent tridiagonal systems
- * (the default and the paper's method).  PP_RECON_WENOJS / PP_RECON_WENOZ:
+/* Interface reconstruction (Secs. 2.2, 2.3 and the comparisons of Sec. 3).
+ * PP_RECON_CWENO: the compact scheme on the conserved variables,
+ * solution-dependent tridiagonal systems per component (the default).
+ * PP_RECON_CHAR: the compact scheme along characteristic fields (Sec. 2.3,
+ * eqs. (cha-1), (1DEuler-FVC)): per node the rows of each field from the
+ * characteristic variables of the Roe average's left eigenvectors, a 3x3
+ * block tridiagonal system in the conserved nodal values per side; 1D,
+ * FP64, unbatched (the paper's choice for discontinuous problems).  PP_RECON_WENOJS / PP_RECON_WENOZ:
  * the classical explicit fifth-order finite-volume WENO the paper compares
  * against, with Jiang-Shu weights (eps 1e-6, a reading; the paper gives
  * none) or WENO-Z weights (weno_eps), each face value from its own five
  * averages.  The limiter, flux and stage update are shared.  The explicit
  * schemes run in FP64 without a batch (else PP_EUNSUPPORTED at init). */
-enum { PP_RECON_CWENO = 0, PP_RECON_WENOJS = 1, PP_RECON_WENOZ = 2 };
+enum { PP_RECON_CWENO = 0, PP_RECON_WENOJS = 1, PP_RECON_WENOZ = 2, PP_RECON_CHAR = 3 };
 
 typedef struct {
     int ndim;            /* 1, or 2 (dimension-by-dimension sweeps)                    */

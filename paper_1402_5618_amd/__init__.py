@@ -19,7 +19,7 @@ PP_BC_PERIODIC, PP_BC_TRANSMISSIVE, PP_BC_REFLECTIVE = 0, 1, 2
 PP_FP64, PP_MIXED = 0, 1
 PP_DT_CFL, PP_DT_H53, PP_DT_PP, PP_DT_RESTART = 0, 1, 2, 3
 PP_FLUX_HLLC, PP_FLUX_LF = 0, 1
-PP_RECON_CWENO, PP_RECON_WENOJS, PP_RECON_WENOZ = 0, 1, 2
+PP_RECON_CWENO, PP_RECON_WENOJS, PP_RECON_WENOZ, PP_RECON_CHAR = 0, 1, 2, 3
 
 EXPORTED = [
     "pp_cweno_config_defaults", "pp_cweno_init", "pp_cweno_rhs", "pp_cweno_stage",

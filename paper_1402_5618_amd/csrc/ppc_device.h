@@ -72,8 +72,9 @@ __device__ __forceinline__ float rcp_t(float x) {
 // j+1/2 from v0..v4 = ubar_{j-2..j+2}, then WENO-Z weights (power 2) with the
 // three divisions of eq. (weight) folded into one reciprocal:
 //   alpha_k ~ c_k (d_k^2 + tau^2) * prod_{l != k} d_l^2,  d_k = beta_k + eps.
-// Exact in real arithmetic; in FP64 no product leaves the normal range for
-// |ubar| < 1e50.
+// Exact in real arithmetic.  In FP64 the products grow like beta^6, so they
+// stay finite while differences of neighbouring averages stay below about
+// 1e25 (beta below ~1e51); eps keeps them far from underflow.
 template <typename T>
 __device__ __forceinline__ void wenoz_weights(T v0, T v1, T v2, T v3, T v4, T eps, T& w0, T& w1,
                                               T& w2) {
@@ -190,6 +191,71 @@ __device__ __forceinline__ double weno5_explicit(double v0, double v1, double v2
     const double p1 = (-v1 + 5.0 * v2 + 2.0 * v3) * sixth;
     const double p2 = (2.0 * v2 + 5.0 * v3 - v4) * sixth;
     return (a0 * p0 + a1 * p1 + a2 * p2) * rcp_t(a0 + a1 + a2);
+}
+
+// ------------------------------------------------------------- Sec 2.3
+// 3x3 blocks of the characteristic system, row-major in registers.
+__device__ __forceinline__ void mm3(const double (&A)[9], const double (&B)[9], double (&C)[9]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            C[3 * i + j] = fma(A[3 * i], B[j], fma(A[3 * i + 1], B[3 + j], A[3 * i + 2] * B[6 + j]));
+}
+__device__ __forceinline__ void mv3(const double (&A)[9], const double (&x)[3], double (&y)[3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) y[i] = fma(A[3 * i], x[0], fma(A[3 * i + 1], x[1], A[3 * i + 2] * x[2]));
+}
+// Inverse by the adjugate; the pivot blocks of the chase are nonsingular
+// for the scheme's rows (diagonal blocks b_k l^(k) dominate).
+__device__ __forceinline__ void inv3(const double (&M)[9], double (&I)[9]) {
+    const double c0 = M[4] * M[8] - M[5] * M[7];
+    const double c1 = M[5] * M[6] - M[3] * M[8];
+    const double c2 = M[3] * M[7] - M[4] * M[6];
+    const double id = rcp_t(M[0] * c0 + M[1] * c1 + M[2] * c2);
+    I[0] = c0 * id;
+    I[1] = (M[2] * M[7] - M[1] * M[8]) * id;
+    I[2] = (M[1] * M[5] - M[2] * M[4]) * id;
+    I[3] = c1 * id;
+    I[4] = (M[0] * M[8] - M[2] * M[6]) * id;
+    I[5] = (M[2] * M[3] - M[0] * M[5]) * id;
+    I[6] = c2 * id;
+    I[7] = (M[1] * M[6] - M[0] * M[7]) * id;
+    I[8] = (M[0] * M[4] - M[1] * M[3]) * id;
+}
+
+// Left eigenvectors of the Euler Jacobian at the Roe average of Ua and Ub
+// (rho, rho u, E): rows l^(1), l^(2), l^(3) of L for the fields u - a, u,
+// u + a.  A Roe sound speed that is not positive leaves the node
+// component-wise (L = I).
+__device__ __forceinline__ void roe_left(double g, const double (&Ua)[3], const double (&Ub)[3],
+                                         double (&L)[9]) {
+    const double ira = rcp_t(Ua[0]), irb = rcp_t(Ub[0]);
+    const double ua = Ua[1] * ira, ub = Ub[1] * irb;
+    const double pa = (g - 1.0) * (Ua[2] - 0.5 * Ua[1] * ua);
+    const double pb = (g - 1.0) * (Ub[2] - 0.5 * Ub[1] * ub);
+    const double Ha = (Ua[2] + pa) * ira, Hb = (Ub[2] + pb) * irb;
+    const double sa = sqrt_nn(Ua[0]), sb = sqrt_nn(Ub[0]);
+    const double iw = rcp_t(sa + sb);
+    const double u = (sa * ua + sb * ub) * iw, H = (sa * Ha + sb * Hb) * iw;
+    const double a2 = (g - 1.0) * (H - 0.5 * u * u);
+    if (!(a2 > 0.0)) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) L[i] = (i % 4 == 0) ? 1.0 : 0.0;
+        return;
+    }
+    const double ia2 = rcp_t(a2);
+    const double ia = sqrt_nn(a2) * ia2;   // 1/a
+    const double c1 = (g - 1.0) * ia2, c2 = 0.5 * u * u * c1;
+    L[0] = 0.5 * (c2 + u * ia);
+    L[1] = 0.5 * (-c1 * u - ia);
+    L[2] = 0.5 * c1;
+    L[3] = 1.0 - c2;
+    L[4] = c1 * u;
+    L[5] = -c1;
+    L[6] = 0.5 * (c2 - u * ia);
+    L[7] = 0.5 * (-c1 * u + ia);
+    L[8] = 0.5 * c1;
 }
 
 // ------------------------------------------------------------- Sec 2.4

@@ -43,7 +43,7 @@ int main(void)
     int failures = 0;
     const int sizes[] = {3, 4, 5, 7, 33, 130};
     const int bcs[][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}};
-    for (int recon = 0; recon < 3; ++recon)
+    for (int recon = 0; recon < 4; ++recon)   /* 3: characteristic-wise */
         for (int flux = 0; flux < 2; ++flux)
             for (unsigned si = 0; si < sizeof(sizes) / sizeof(sizes[0]); ++si)
                 for (int b = 0; b < 4; ++b) {

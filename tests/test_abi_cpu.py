@@ -60,7 +60,9 @@ def _init(**kw):
     (dict(weno_eps=0.0), pp.PP_EINVAL),
     (dict(flux=2), pp.PP_EINVAL),
     (dict(flux=-1), pp.PP_EINVAL),
-    (dict(recon=3), pp.PP_EINVAL),
+    (dict(recon=4), pp.PP_EINVAL),
+    (dict(recon=3, ndim=2, ny=64, dy=0.01), pp.PP_EUNSUPPORTED),   # characteristic: 1D
+    (dict(recon=3, precision=1), pp.PP_EUNSUPPORTED),             # and FP64
     (dict(recon=-1), pp.PP_EINVAL),
     (dict(recon=1, precision=1), pp.PP_EUNSUPPORTED),   # explicit schemes: FP64 only
     (dict(recon=2, nbatch=2), pp.PP_EUNSUPPORTED),      # and not batched
