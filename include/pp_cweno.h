@@ -177,7 +177,8 @@ int pp_cweno_run(pp_cweno_ctx *ctx, double *U, double t_end, int64_t nsteps_max,
 
 /* Batched ensemble: one SSP-RK3 step of every problem of the packed state
  * Upacked, problem i with its own dt_dev[i] (device array); problems with
- * dt_dev[i] <= 0 are left unchanged.  One persistent launch per stage. */
+ * dt_dev[i] <= 0 are left unchanged.  Per stage, one persistent launch per
+ * length class of the launch plan (a single launch under plans 0 and 3). */
 int pp_cweno_batch_step(pp_cweno_ctx *ctx, double *Upacked, const double *dt_dev);
 
 /* Batched ensemble driver: advance every problem to t_end with per-problem
@@ -208,20 +209,24 @@ int pp_cweno_batch_continue(pp_cweno_ctx *ctx, double *Upacked, double t_end, in
 
 /* Batched ensembles: choose the launch plan used by pp_cweno_batch_step and
  * pp_cweno_batch_run.  The problems, sorted by length, are cut into length
- * classes, each processed by one persistent launch per stage with the kernel
- * shape of its longest problem (how many rows of the tridiagonal systems of
- * eq. (CWENO-FV) one lane chases serially, and so how large the separator
- * system solved by parallel cyclic reduction is):
- *   plan 0: one class;  plan 1: > 2048 cells | the rest;
- *   plan 2: > 2048 | 1025..2048 | <= 1024 cells.
- * force_plan in [0, 2] sets that plan without timing.  force_plan < 0 times
+ * classes, each processed by one persistent launch per stage with the LDS of
+ * its longest problem and a kernel shape: how many lanes share one
+ * tridiagonal system of eq. (CWENO-FV) (64 w for w waves per system), and so
+ * how many rows each lane chases serially (n / (64 w)) and how large the
+ * separator system solved by parallel cyclic reduction is.
+ *   plan p % 3 = 0: one class;  1: > 2048 cells | the rest;
+ *                2: > 2048 | 1025..2048 | <= 1024 cells;
+ *   plan p / 3 = 0: classes of lines <= 2048 cells take one wave per system;
+ *                1: two waves per system (lines > 2048 always take two).
+ * force_plan in [0, 5] sets that plan without timing.  force_plan < 0 times
  * one step of every plan on a device copy of Upacked (per-problem dt from cfl
  * and the initial averages; Upacked is left unchanged) and keeps the fastest.
- * *plan_out (may be NULL) receives the plan; ms_out (host [3], may be NULL)
- * the measured ms per step of each plan (force_plan < 0 only).  The plan does
- * not change any result, since the problems are independent.  Synchronises;
- * allocates a device copy of the state on first use.  Not to be called while
- * a batched run is in flight on the same context. */
+ * *plan_out (may be NULL) receives the plan; ms_out (host [6], may be NULL)
+ * the measured ms per step of each plan (force_plan < 0 only).  The plan
+ * changes results only by the rounding of the chunk partition, since the
+ * problems are independent.  Synchronises; allocates a device copy of the
+ * state on first use.  Not to be called while a batched run is in flight on
+ * the same context. */
 int pp_cweno_batch_tune(pp_cweno_ctx *ctx, const double *Upacked, double cfl, int force_plan,
                         int *plan_out, double *ms_out);
 

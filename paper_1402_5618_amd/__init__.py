@@ -223,7 +223,7 @@ class Solver:
         """Pick the batched launch plan: timed over every plan on a copy of U
         (force_plan < 0) or set directly.  Returns (plan, [ms per plan])."""
         plan = ctypes.c_int()
-        ms = (ctypes.c_double * 3)(-1.0, -1.0, -1.0)
+        ms = (ctypes.c_double * 6)(*([-1.0] * 6))
         self._check(lib().pp_cweno_batch_tune(self._ctx, _ptr(U, self._nstate), float(cfl),
                                               int(force_plan), ctypes.byref(plan), ms))
         return plan.value, list(ms)

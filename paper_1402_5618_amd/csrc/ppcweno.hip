@@ -1989,6 +1989,7 @@ struct pp_cweno_ctx {
     // and stage, each with the kernel shape and LDS of its longest problem
     struct LenClass {
         int begin = 0, count = 0, maxn = 0;
+        int w = 1;   // waves per tridiagonal system (64 w lanes; rows per lane n / (64 w))
     };
     std::vector<int> order_host;
     int plan = 0;
@@ -2425,21 +2426,28 @@ int step_single(pp_cweno_ctx* ctx, double* U, const double* dt_dev, double dt_va
     return PP_OK;
 }
 
-constexpr int kNumPlans = 3;
+constexpr int kNumPlans = 6;
 
-// Launch plan p: 0 = one class, 1 = split at 2048 cells (the longer lines need
-// two waves per system), 2 = split at 2048 and 1024 cells.
+// Launch plan p: the length cut (p % 3: 0 = one class, 1 = split at 2048
+// cells, 2 = split at 2048 and 1024 cells) and the kernel shape of the
+// classes of lines up to 2048 cells (p / 3: one wave per system, i.e. chunks
+// of up to 32 rows, or 16 in the paired FP64 form, with a 64/128-unknown
+// separator system; or two waves per system, chunks of up to 16 rows and a
+// 128-unknown separator system, half as many resident lines per CU).  Lines
+// longer than 2048 cells always take two waves per system.
 void set_plan(pp_cweno_ctx* ctx, int p) {
-    const int cuts[kNumPlans][2] = {{0, 0}, {2048, 0}, {2048, 1024}};
+    const int cuts[3][2] = {{0, 0}, {2048, 0}, {2048, 1024}};
+    const int cp = p % 3, short_w = 1 + p / 3;
     ctx->plan = p;
     ctx->nclass = 0;
     const int nb = (int)ctx->order_host.size();
     int i = 0;
     for (int c = 0; c < 3 && i < nb; ++c) {
-        const int cut = c < 2 ? cuts[p][c] : 0;   // class c takes lengths > cut
+        const int cut = c < 2 ? cuts[cp][c] : 0;   // class c takes lengths > cut
         auto& k = ctx->cls[ctx->nclass];
         k.begin = i;
         k.maxn = (int)ctx->lengths[ctx->order_host[i]];
+        k.w = k.maxn > 2048 ? 2 : short_w;
         while (i < nb && ctx->lengths[ctx->order_host[i]] > cut) ++i;
         k.count = i - k.begin;
         if (k.count > 0) ++ctx->nclass;
@@ -2497,8 +2505,8 @@ int batch_step_launch(pp_cweno_ctx* ctx, double* Upacked, double* dtl, bool adva
             A.order = ctx->d_order + k.begin;
             A.nlines = k.count;
             const int grid = std::min(k.count, ctx->n_sm);
-            int r = k.maxn <= 2048 ? launch_line<3, 1, 1, 6>(ctx, A, k.maxn, true, grid)
-                                   : launch_line<3, 1, 2, 3>(ctx, A, k.maxn, true, grid);
+            int r = k.w == 1 ? launch_line<3, 1, 1, 6>(ctx, A, k.maxn, true, grid)
+                             : launch_line<3, 1, 2, 3>(ctx, A, k.maxn, true, grid);
             if (r) return r;
         }
     }
@@ -3125,6 +3133,7 @@ static int batch_run_impl(pp_cweno_ctx* ctx, double* Upacked, double t_end, int6
             ctx->cls[nc].begin = begin;
             ctx->cls[nc].count = count;
             ctx->cls[nc].maxn = full_cls[c].maxn;
+            ctx->cls[nc].w = full_cls[c].w;
             ++nc;
         }
         compacted = true;

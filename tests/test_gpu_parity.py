@@ -279,7 +279,8 @@ def ensemble(nprob, n_lo, n_hi, seed=1402):
 
 
 @pytest.mark.parametrize("n_lo,n_hi,plan", [(8, 40, 0), (256, 4096, 0), (256, 4096, 1),
-                                             (256, 4096, 2)])
+                                             (256, 4096, 2), (8, 40, 3), (256, 4096, 4),
+                                             (256, 4096, 5)])
 def test_batch_step_parity(n_lo, n_hi, plan):
     """One SSP-RK3 step of every problem (persistent launches per stage and
     length class of the launch plan) against the oracle's stages, each
@@ -359,18 +360,18 @@ def test_batch_tune_picks_a_plan_and_results_agree():
     U0 = dev(ens.U)
     plan, ms = s.batch_tune(U0, 1.0 / 12.0)
     print(f"plan {plan}, ms per step {ms}", flush=True)
-    assert 0 <= plan <= 2 and all(m > 0 for m in ms) and ms[plan] == min(ms)
+    assert 0 <= plan <= 5 and all(m > 0 for m in ms) and ms[plan] == min(ms)
     assert np.array_equal(U0.cpu().numpy(), ens.U)
     dts = dev(np.array([(1.0 / 12.0) * ens.dx[i] /
                         oracle.max_speed_1d(ens.U[:, ens.offsets[i]:ens.offsets[i + 1]])
                         for i in range(nb)]))
     outs = []
-    for p in range(3):
+    for p in range(6):
         s.batch_tune(force_plan=p)
         Ud = dev(ens.U)
         s.batch_step(Ud, dts)
         outs.append(Ud.cpu().numpy())
-    for p in (1, 2):
+    for p in range(1, 6):
         for i in range(nb):
             sl = slice(ens.offsets[i], ens.offsets[i + 1])
             assert comp_rel(outs[p][:, sl], outs[0][:, sl]) <= TOL_STAGE, (p, i)
