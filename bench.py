@@ -14,6 +14,11 @@ Other workloads (one JSON line each, bounded runs):
                           hipGraph replay, per-problem dt
   --workload wave1d       Example 3.1 at N = 200, dt = w1 h^(5/3)/S, to t = 2
   --workload rarefaction1d / blast1d   the 1D positivity configurations, N = 4000
+  --workload char1d       cost of the characteristic-wise against the component-wise
+                          reconstruction (Tables 2-3: density wave, CFL 0.16, t = 2,
+                          N = 28..224; and the N = 4000 double rarefaction per step)
+  --dt-rule cfl|pp|restart   time-step rule of ensemble / rarefaction1d / blast1d
+  --recon cweno|char      reconstruction of wave1d / rarefaction1d / blast1d
   --workload copy         plain device copy of a known size (counter calibration)
   --workload accuracy     wall time against L1 error, FP64 and mixed, N = 128..2048
 
@@ -67,7 +72,12 @@ def parse():
                     help="oracle steps of the full grid for cpu_baseline (about 10 s on 16 threads)")
     ap.add_argument("--workload", default="density2d",
                     choices=["density2d", "sedov2d", "ensemble", "wave1d", "rarefaction1d",
-                             "blast1d", "copy", "accuracy"])
+                             "blast1d", "copy", "accuracy", "char1d"])
+    ap.add_argument("--dt-rule", default="cfl", choices=["cfl", "pp", "restart"],
+                    help="ensemble / rarefaction1d / blast1d: averages' CFL, interface-state "
+                         "bound, or the averages' CFL with a step redone at half dt")
+    ap.add_argument("--recon", default="cweno", choices=["cweno", "char"],
+                    help="wave1d / rarefaction1d / blast1d: component-wise or characteristic-wise")
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     ap.add_argument("--full", action="store_true",
                     help="sedov2d / ensemble: run to the configuration's end time")
@@ -86,6 +96,8 @@ def other_workload(args):
     import workloads as W
     prec_name = args.precision or ("mixed" if args.workload in ("sedov2d", "ensemble") else "fp64")
     prec = pp.PP_MIXED if prec_name == "mixed" else pp.PP_FP64
+    rule_id = {"cfl": pp.PP_DT_CFL, "pp": pp.PP_DT_PP, "restart": pp.PP_DT_RESTART}[args.dt_rule]
+    recon_id = {"cweno": pp.PP_RECON_CWENO, "char": pp.PP_RECON_CHAR}[args.recon]
     out = {"unit": "cell-updates/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64" if prec_name == "fp64" else "f32+f64",
            "data": "synthetic", "warmup": 0}
@@ -204,7 +216,8 @@ def other_workload(args):
         ens = W.riemann_ensemble()
         nb = len(ens.lengths)
         U = torch.tensor(ens.U, device="cuda")
-        s = pp.Solver(ndim=1, lengths=ens.lengths, dxs=ens.dx, bcs=[1] * (2 * nb), precision=prec)
+        s = pp.Solver(ndim=1, lengths=ens.lengths, dxs=ens.dx, bcs=[1] * (2 * nb), precision=prec,
+                      batch_rule=rule_id)
         plan, plan_ms = s.batch_tune(U, 1.0 / 12.0)       # launch plan (length classes)
         s.batch_run(U.clone(), ens.t_end, 2, 1.0 / 12.0)   # warm-up (graph, kernels)
         torch.cuda.synchronize()
@@ -256,20 +269,68 @@ def other_workload(args):
                                           f"{args.steps} steps per problem (bounded; t_end "
                                           f"{ens.t_end} not reached)"),
                            "launch_plan": plan, "plan_ms_per_step": plan_ms,
+                           "dt_rule": args.dt_rule, "restarts": s.restarts(),
+                           "short_of_t_end": ([(i, float(ts[i]), int(steps[i])) for i in range(nb)
+                                               if ts[i] < ens.t_end][:16] if args.full else None),
                            "problems_out_of_G": int(sum(1 for i in range(nb) if
                                                         p[ens.offsets[i]:ens.offsets[i + 1]].min() <= 0
                                                         or Uh[0, ens.offsets[i]:ens.offsets[i + 1]].min() <= 0)),
                            "status": flags})
         s.close()
+    elif args.workload == "char1d":
+        # the paper's Tables 2-3 on the GPU: wall time and L1 of the density
+        # wave for the component-wise and the characteristic-wise
+        # reconstruction at lambda max(|u|+a) = 0.16 to t = 2, and the cost
+        # per step of both on a 4000-cell line
+        rows = []
+        for n in (28, 56, 112, 224):
+            h = 2.0 / n
+            for name, rc in (("component-wise", pp.PP_RECON_CWENO), ("characteristic", pp.PP_RECON_CHAR)):
+                s = pp.Solver(ndim=1, nx=n, dx=h, bc=(0, 0, 0, 0), recon=rc)
+                U = torch.tensor(W.density_wave_1d(n), device="cuda")
+                s.run(U.clone(), 2.0, 3, 0.16)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                t, k = s.run(U, 2.0, 10 ** 8, 0.16)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                s.close()
+                Uh = U.cpu().numpy()
+                l1 = W.error_norms(Uh[0], W.density_wave_1d(n, t=t)[0], h)[0]
+                rows.append({"n": n, "recon": name, "steps": k, "wall_s": wall, "l1_rho": l1,
+                             "us_per_step": 1e6 * wall / k})
+                print(f"char1d: n={n} {name} steps={k} wall={wall:.3f}s L1={l1:.3e}",
+                      file=sys.stderr, flush=True)
+        per_step = {}
+        for name, rc in (("component-wise", pp.PP_RECON_CWENO), ("characteristic", pp.PP_RECON_CHAR)):
+            s = pp.Solver(ndim=1, nx=4000, dx=2.0 / 4000, bc=(1, 1, 0, 0), recon=rc)
+            U = torch.tensor(W.double_rarefaction_1d(4000), device="cuda")
+            s.run(U.clone(), 0.6, 5, 1.0 / 12.0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t, k = s.run(U, 0.6, 200, 1.0 / 12.0)
+            torch.cuda.synchronize()
+            per_step[name] = 1e6 * (time.perf_counter() - t0) / k
+            s.close()
+        ratio = [r2["wall_s"] / r1["wall_s"] for r1, r2 in zip(rows[0::2], rows[1::2])]
+        out.update(metric="wall time of the characteristic against the component-wise "
+                          "reconstruction, 1D density wave to t=2",
+                   value=None, steps=None,
+                   config={"workload": "1D density wave (Example 3.1), periodic [0,2], "
+                                       "lambda max(|u|+a) = 0.16, t = 2, N = 28..224, FP64; "
+                                       "double rarefaction N = 4000, 200 steps",
+                           "table": rows, "char_over_component_wall": ratio,
+                           "us_per_step_n4000": per_step,
+                           "paper_char_over_component_cpu_n224": 29.22 / 8.86})
     else:
         if args.workload == "wave1d":
             n, h, U0, bc, T, rule = 200, 0.01, W.density_wave_1d(200), (0, 0), 2.0, pp.PP_DT_H53
         elif args.workload == "rarefaction1d":
-            n, h, U0, bc, T, rule = 4000, 2.0 / 4000, W.double_rarefaction_1d(4000), (1, 1), 0.6, pp.PP_DT_CFL
+            n, h, U0, bc, T, rule = 4000, 2.0 / 4000, W.double_rarefaction_1d(4000), (1, 1), 0.6, rule_id
         else:
-            n, h, U0, bc, T, rule = 4000, 2.0 / 4000, W.vacuum_blast_1d(4000), (1, 1), 1e-3, pp.PP_DT_CFL
+            n, h, U0, bc, T, rule = 4000, 2.0 / 4000, W.vacuum_blast_1d(4000), (1, 1), 1e-3, rule_id
         U = torch.tensor(U0, device="cuda")
-        s = pp.Solver(ndim=1, nx=n, dx=h, bc=(*bc, 0, 0), precision=prec)
+        s = pp.Solver(ndim=1, nx=n, dx=h, bc=(*bc, 0, 0), precision=prec, recon=recon_id)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
@@ -286,9 +347,10 @@ def other_workload(args):
         out.update(metric=f"cell-updates/s, 1D {args.workload} N={n}",
                    value=(n * steps / wall) if steps > 0 else None, steps=steps,
                    ms_per_step=(1e3 * wall / steps) if steps > 0 else None,
-                   config=dict(workload=f"1D {args.workload}, N={n}, to t={T}, {prec_name}",
+                   config=dict(workload=f"1D {args.workload}, N={n}, to t={T}, {prec_name}, "
+                                        f"{args.recon}, dt rule {args.dt_rule}",
                                min_rho=float(Uh[0].min()), min_p=float(W.pressure(Uh).min()),
-                               status=flags, wall_s=wall, **extra))
+                               status=flags, wall_s=wall, restarts=s.restarts(), **extra))
         s.close()
     print(json.dumps(out), flush=True)
 
@@ -315,19 +377,44 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def host_cpu():
+    """Model name and clock of the host CPU (from /proc/cpuinfo)."""
+    model, mhz = None, None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if model is None and line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                if mhz is None and line.startswith("cpu MHz"):
+                    mhz = float(line.split(":", 1)[1])
+    except OSError:
+        pass
+    return model, mhz
+
+
 def cpu_baseline(n, steps):
     """The CPU oracle (unchanged, OpenMP over lines) on a bounded sample of the
-    same workload: `steps` SSP-RK3 steps of the full grid."""
+    same workload: `steps` SSP-RK3 steps of the full grid on every host
+    thread, and one step on a single thread."""
     import oracle
     import workloads as W
     U = W.density_wave_2d(n, n)
     dx = 2.0 / n
+    threads = oracle.num_threads()
     t0 = time.perf_counter()
     oracle.run_2d(U, (0, 0, 0, 0), dx, dx, 1e30, cfl=1.0 / 12.0, max_steps=steps)
     dt = time.perf_counter() - t0
-    return {"value": n * n * steps / dt, "unit": "cell-updates/s", "cores": oracle.num_threads(),
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.run_2d(U, (0, 0, 0, 0), dx, dx, 1e30, cfl=1.0 / 12.0, max_steps=1)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(threads)
+    model, mhz = host_cpu()
+    return {"value": n * n * steps / dt, "unit": "cell-updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{steps} SSP-RK3 steps of the full {n}x{n} grid ({dt:.1f} s, FP64)"}
+            "sample": f"{steps} SSP-RK3 steps of the full {n}x{n} grid ({dt:.1f} s, FP64)",
+            "cpu_model": model, "cpu_mhz": mhz,
+            "one_thread": {"value": n * n / dt1, "sample": f"1 step of the full grid ({dt1:.1f} s)"}}
 
 
 def main():
@@ -442,6 +529,10 @@ def main():
         },
         "roofline": {
             "bound": "alu",
+            # what the counters show for this kernel: VALUBusy ~46 %, one
+            # workgroup (2 waves per SIMD) per CU, so issue latency rather
+            # than VALU throughput limits it
+            "counters": "VALU issue latency: VALUBusy ~46 %, one workgroup per CU",
             "kernel": {"x": "line_kernel x-lines", "y": "line_kernel y-lines"}[dom],
             "achieved": achieved_tflops,
             "peak": FP64_PEAK_TFLOPS,

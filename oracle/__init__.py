@@ -101,6 +101,7 @@ def lib():
             "orc_run_batch_rule": (_I, [_I, ctypes.POINTER(_L), _D, ctypes.POINTER(_I), _D, _P,
                                         _DBL, _DBL, _I, _L, _D, _D]),
             "orc_num_threads": (_I, []),
+            "orc_set_threads": (None, [_I]),
             "orc_weights": (None, [_D, _DBL, _D]),
             "orc_char_eigen": (None, [_DBL, _D, _D, _D, _D, _D]),
             "orc_block_solve": (_I, [_I, _I, _D, _D, _D, _D, _D]),
@@ -403,6 +404,11 @@ def recon_char(ue, cyclic_line, p=None):
     _check(lib().orc_recon_char(n, int(cyclic_line), _d(ue), ctypes.byref(p), _d(um), _d(up)),
            "recon_char")
     return um, up
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's later calls (bench.py's one-thread figure)."""
+    lib().orc_set_threads(int(n))
 
 
 def num_threads() -> int:

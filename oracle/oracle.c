@@ -1401,6 +1401,15 @@ int orc_run_batch(int nprob, const long *offsets, double *U, const int *bc, cons
     return orc_run_batch_rule(nprob, offsets, U, bc, dxs, P, t_end, cfl, 0, total, steps_out, NULL);
 }
 
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
