@@ -253,6 +253,17 @@ int pp_cweno_status(pp_cweno_ctx *ctx, uint32_t *flags);
 int pp_cweno_debug_line(pp_cweno_ctx *ctx, const double *U, double *um, double *up,
                         double *flux);
 
+/* Test hook: solve one tridiagonal system a_i x_{i-1} + b_i x_i + c_i x_{i+1}
+ * = r_i, i = 0..n-1 (cyclic != 0: indices mod n; otherwise a_0 and c_{n-1}
+ * are ignored), 3 <= n <= 4096, with the device's chunked chasing and
+ * parallel cyclic reduction of the separators (the solver of eq. (CWENO-FV)
+ * in the mixed form and on FP64 lines of more than 2048 cells; here in
+ * FP64, 64 lanes for n <= 2048, 128 above).  a, b, c, r, x: device arrays
+ * [n] owned by the caller (x may not alias the others).  Pivot-free, as the
+ * paper's chasing method.  Enqueued on the context's stream. */
+int pp_cweno_tridiag_solve_debug(pp_cweno_ctx *ctx, int64_t n, int cyclic, const double *a,
+                                 const double *b, const double *c, const double *r, double *x);
+
 /* Kernel timing for measurement: with on != 0, every later launch of the
  * line kernel (x and y lines) and of the 2D combine kernel is bracketed by
  * HIP events on the context's stream.  pp_cweno_get_timing synchronises and

@@ -25,7 +25,7 @@ EXPORTED = [
     "pp_cweno_config_defaults", "pp_cweno_init", "pp_cweno_rhs", "pp_cweno_stage",
     "pp_cweno_step", "pp_cweno_step_static", "pp_cweno_run", "pp_cweno_batch_step", "pp_cweno_batch_tune",
     "pp_cweno_batch_run", "pp_cweno_batch_continue",
-    "pp_cweno_restarts", "pp_cweno_max_speed", "pp_cweno_status", "pp_cweno_debug_line", "pp_cweno_set_timing",
+    "pp_cweno_restarts", "pp_cweno_max_speed", "pp_cweno_status", "pp_cweno_tridiag_solve_debug", "pp_cweno_debug_line", "pp_cweno_set_timing",
     "pp_cweno_get_timing", "pp_cweno_last_error", "pp_cweno_destroy",
 ]
 
@@ -85,6 +85,8 @@ def lib():
             "pp_cweno_max_speed": (ctypes.c_int, [_VP, _VP, _VP]),
             "pp_cweno_status": (ctypes.c_int, [_VP, P(ctypes.c_uint32)]),
             "pp_cweno_debug_line": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+            "pp_cweno_tridiag_solve_debug": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int,
+                                                            _VP, _VP, _VP, _VP, _VP]),
             "pp_cweno_set_timing": (ctypes.c_int, [_VP, ctypes.c_int]),
             "pp_cweno_get_timing": (ctypes.c_int, [_VP, P(ctypes.c_double)]),
             "pp_cweno_last_error": (ctypes.c_char_p, [_VP]),
@@ -276,6 +278,13 @@ class Solver:
         n = self._nstate
         return self._check(lib().pp_cweno_debug_line(self._ctx, _ptr(U, n), _ptr(um, n),
                                                      _ptr(up, n), _ptr(flux, n + 3)))
+
+    def tridiag_solve_debug(self, a, b, c, r, x, cyclic=False):
+        """Device chunked chase + PCR of one tridiagonal system (test hook)."""
+        n = r.numel()
+        return self._check(lib().pp_cweno_tridiag_solve_debug(
+            self._ctx, n, int(bool(cyclic)), _ptr(a, n), _ptr(b, n), _ptr(c, n), _ptr(r, n),
+            _ptr(x, n)))
 
     def set_timing(self, on=True):
         return self._check(lib().pp_cweno_set_timing(self._ctx, int(bool(on))))

@@ -483,6 +483,118 @@ __device__ __forceinline__ void paired_solve(const double* __restrict__ sUc, int
     }
 }
 
+// Chunked chasing of one tridiagonal system of eq. (CWENO-FV) (row g:
+// a x_{g-1} + b x_g + c x_{g+1} = r, indices mod n when cyclic) over the
+// P <= 64 W lanes of the system: lane k chases its rows [r0, r0 + len) with
+// the chunk's separators kept symbolic (x_j = P_j + Q_j L + S_j R), the
+// separator system goes through parallel cyclic reduction (pcr_solve), and
+// each lane recovers its rows into E0.  row(j, a, b, c, r) returns row r0 + j
+// and is called for j = 0, 1, ... in order (it may slide a window).  Every
+// thread of the system calls this (W > 1 exchanges through block barriers).
+template <int W, typename RowFn>
+__device__ __forceinline__ void chunk_chase_solve(RowFn&& row, bool act, int k, int P, int len,
+                                                  bool cyclic, double* sx, int sys,
+                                                  double (&E0)[kCH], double (&E1)[kCH],
+                                                  double (&E2)[kCH]) {
+    const int knext = (k + 1) & (P - 1), kprev = (k - 1) & (P - 1);
+    double ae = 0.0, be = 1.0, ce = 0.0, re = 0.0;
+    double gP = 0.0, gQ = 1.0, gS = 0.0;   // x_{r1-2} = gP + gQ L + gS R
+    double fP = 0.0, fQ = 0.0, fS = 1.0;   // x_{r0}   = fP + fQ L + fS R
+    if (act) {
+        double cprev = 0.0, pprev = 0.0, qprev = 0.0;
+#pragma unroll
+        for (int j = 0; j < kCH; ++j) {
+            if (j < len) {
+                double a, bb, c, r;
+                row(j, a, bb, c, r);
+                if (j < len - 1) {
+                    const double piv = (j == 0) ? bb : bb - a * cprev;
+                    const double ip = rcp_t(piv);
+                    const double cj = c * ip;
+                    const double pj = ((j == 0) ? r : r - a * pprev) * ip;
+                    const double qj = ((j == 0) ? -a : -a * qprev) * ip;
+                    E0[j] = cj; E1[j] = pj; E2[j] = qj;
+                    cprev = cj; pprev = pj; qprev = qj;
+                } else {
+                    ae = a; be = bb; ce = c; re = r;
+                }
+            }
+        }
+        // symbolic back substitution: x_j = P_j + Q_j L + S_j R
+        double Pn = 0.0, Qn = 0.0, Sn = 0.0;
+#pragma unroll
+        for (int j = kCH - 1; j >= 0; --j) {
+            if (j < len - 1) {
+                const double cj = E0[j];
+                double Pj, Qj, Sj;
+                if (j == len - 2) {
+                    Pj = E1[j]; Qj = E2[j]; Sj = -cj;
+                    gP = Pj; gQ = Qj; gS = Sj;
+                } else {
+                    Pj = E1[j] - cj * Pn; Qj = E2[j] - cj * Qn; Sj = -cj * Sn;
+                }
+                E0[j] = Pj; E1[j] = Qj; E2[j] = Sj;
+                Pn = Pj; Qn = Qj; Sn = Sj;
+            }
+        }
+        if (len >= 2) { fP = E0[0]; fQ = E1[0]; fS = E2[0]; }
+    }
+    double nf[3] = {fP, fQ, fS};
+    xch<W, 3>(nf, knext, sx, sys, k);
+    if (!cyclic && k + 1 >= P) nf[0] = nf[1] = nf[2] = 0.0;
+    const double Rk = pcr_solve<W, double>(ae * gQ, be + ae * gS + ce * nf[1], ce * nf[2],
+                                           re - ae * gP - ce * nf[0], k, P, cyclic, sx, sys);
+    double lv[1] = {Rk};
+    xch<W, 1>(lv, kprev, sx, sys, k);
+    const double Lk = (!cyclic && k == 0) ? 0.0 : lv[0];
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < kCH; ++j) {
+            if (j < len - 1) E0[j] = E0[j] + E1[j] * Lk + E2[j] * Rk;
+            else if (j == len - 1) E0[j] = Rk;
+        }
+    }
+}
+
+// Test hook kernel: the chunked chase of one caller-given tridiagonal
+// system (one workgroup of 64 W lanes).
+template <int W>
+__global__ void __launch_bounds__(64 * W) tridiag_debug_kernel(const double* __restrict__ a,
+                                                               const double* __restrict__ b,
+                                                               const double* __restrict__ c,
+                                                               const double* __restrict__ r,
+                                                               double* __restrict__ x, int n,
+                                                               int cyclic) {
+    __shared__ double sx[64 * W * 4];
+    const int k = threadIdx.x;
+    int P = 64 * W, lgP = W == 1 ? 6 : 7;
+    while (P > n) {
+        P >>= 1;
+        --lgP;
+    }
+    const bool act = k < P;
+    const int r0 = act ? (int)(((unsigned)k * (unsigned)n) >> lgP) : 0;
+    const int r1 = act ? (int)(((unsigned)(k + 1) * (unsigned)n) >> lgP) : 0;
+    double E0[kCH], E1[kCH], E2[kCH];
+    auto row = [&](int j, double& aa, double& bb, double& cc, double& rr) {
+        const int g = r0 + j;
+        aa = a[g];
+        bb = b[g];
+        cc = c[g];
+        rr = r[g];
+        if (!cyclic) {
+            if (g == 0) aa = 0.0;
+            if (g == n - 1) cc = 0.0;
+        }
+    };
+    chunk_chase_solve<W>(row, act, k, P, r1 - r0, cyclic != 0, sx, 0, E0, E1, E2);
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < kCH; ++j)
+            if (j < r1 - r0) x[r0 + j] = E0[j];
+    }
+}
+
 // ------------------------------------------------ Sec 2.3, characteristic
 // Scratch of the characteristic block solve of one line: per side, per row j
 // of a lane's chunk (at most kCharCH rows), kCharRec doubles per lane,
@@ -956,7 +1068,6 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     double F0[PAIRED ? CHP : 1], F1[PAIRED ? CHP : 1], F2[PAIRED ? CHP : 1];
     float X0[MIXED ? kCH : 1], Qf[MIXED ? kCH : 1], Sf[MIXED ? kCH : 1];
     float W0[MIXED ? kCH : 1], W2[MIXED ? kCH : 1];
-    double Lk = 0.0, Rk = 0.0;
     float Ld = 0.0f, Rd = 0.0f;   // mixed: separators of the correction solve
 
     if constexpr (PAIRED) {
@@ -999,73 +1110,27 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
             }
         }
     } else if constexpr (!MIXED) {
-        double ae = 0.0, be = 1.0, ce = 0.0, re = 0.0;
-        double gP = 0.0, gQ = 1.0, gS = 0.0;   // x_{r1-2} = gP + gQ L + gS R
-        double fP = 0.0, fQ = 0.0, fS = 1.0;   // x_{r0}   = fP + fQ L + fS R
+        const double weps = A.weno_eps;
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;   // sliding window ubar_{g-2..g+1}
         if (act) {
-            const double weps = A.weno_eps;
-            double v0 = ub(r0 - 2), v1 = ub(r0 - 1), v2 = ub(r0), v3 = ub(r0 + 1);
-            double cprev = 0.0, pprev = 0.0, qprev = 0.0;
-#pragma unroll
-            for (int j = 0; j < kCH; ++j) {
-                if (j < len) {
-                    const int g = r0 + j;
-                    const double v4 = ub(g + 2);
-                    double w0, w1, w2, a, bb, c, r;
-                    wenoz_weights<double>(v0, v1, v2, v3, v4, weps, w0, w1, w2);
-                    cweno_row<double>(w0, w1, w2, v1, v2, v3, a, bb, c, r);
-                    if (!cyclic) {
-                        if (g == 0) { r -= a * clo; a = 0.0; }
-                        if (g == n - 1) { r -= c * chi; c = 0.0; }
-                    }
-                    if (j < len - 1) {
-                        const double piv = (j == 0) ? bb : bb - a * cprev;
-                        const double ip = rcp_t(piv);
-                        const double cj = c * ip;
-                        const double pj = ((j == 0) ? r : r - a * pprev) * ip;
-                        const double qj = ((j == 0) ? -a : -a * qprev) * ip;
-                        E0[j] = cj; E1[j] = pj; E2[j] = qj;
-                        cprev = cj; pprev = pj; qprev = qj;
-                    } else {
-                        ae = a; be = bb; ce = c; re = r;
-                    }
-                    v0 = v1; v1 = v2; v2 = v3; v3 = v4;
-                }
-            }
-            // symbolic back substitution: x_j = P_j + Q_j L + S_j R
-            double Pn = 0.0, Qn = 0.0, Sn = 0.0;
-#pragma unroll
-            for (int j = kCH - 1; j >= 0; --j) {
-                if (j < len - 1) {
-                    const double cj = E0[j];
-                    double Pj, Qj, Sj;
-                    if (j == len - 2) {
-                        Pj = E1[j]; Qj = E2[j]; Sj = -cj;
-                        gP = Pj; gQ = Qj; gS = Sj;
-                    } else {
-                        Pj = E1[j] - cj * Pn; Qj = E2[j] - cj * Qn; Sj = -cj * Sn;
-                    }
-                    E0[j] = Pj; E1[j] = Qj; E2[j] = Sj;
-                    Pn = Pj; Qn = Qj; Sn = Sj;
-                }
-            }
-            if (len >= 2) { fP = E0[0]; fQ = E1[0]; fS = E2[0]; }
+            v0 = ub(r0 - 2);
+            v1 = ub(r0 - 1);
+            v2 = ub(r0);
+            v3 = ub(r0 + 1);
         }
-        double nf[3] = {fP, fQ, fS};
-        xch<W, 3>(nf, knext, sx, sys, k);
-        if (!cyclic && k + 1 >= P) nf[0] = nf[1] = nf[2] = 0.0;
-        Rk = pcr_solve<W, double>(ae * gQ, be + ae * gS + ce * nf[1], ce * nf[2],
-                                  re - ae * gP - ce * nf[0], k, P, cyclic, sx, sys);
-        double lv[1] = {Rk};
-        xch<W, 1>(lv, kprev, sx, sys, k);
-        Lk = (!cyclic && k == 0) ? 0.0 : lv[0];
-        if (act) {
-#pragma unroll
-            for (int j = 0; j < kCH; ++j) {
-                if (j < len - 1) E0[j] = E0[j] + E1[j] * Lk + E2[j] * Rk;
-                else if (j == len - 1) E0[j] = Rk;
+        auto row = [&](int j, double& a, double& bb, double& c, double& r) {
+            const int g = r0 + j;
+            const double v4 = ub(g + 2);
+            double w0, w1, w2;
+            wenoz_weights<double>(v0, v1, v2, v3, v4, weps, w0, w1, w2);
+            cweno_row<double>(w0, w1, w2, v1, v2, v3, a, bb, c, r);
+            if (!cyclic) {
+                if (g == 0) { r -= a * clo; a = 0.0; }
+                if (g == n - 1) { r -= c * chi; c = 0.0; }
             }
-        }
+            v0 = v1; v1 = v2; v2 = v3; v3 = v4;
+        };
+        chunk_chase_solve<W>(row, act, k, P, len, cyclic, sx, sys, E0, E1, E2);
     } else {
         // ---------------- pass A: float weights, rows and chasing
         float ae = 0.0f, be = 1.0f, ce = 0.0f, re = 0.0f;
@@ -3190,6 +3255,21 @@ int pp_cweno_debug_line(pp_cweno_ctx* ctx, const double* U, double* um, double* 
     if (!U) return fail(ctx, PP_EINVAL, "U is NULL");
     if (ctx->cfg.ndim != 1 || ctx->cfg.nbatch > 0) return fail(ctx, PP_EINVAL, "debug_line is 1D only");
     return launch_1d(ctx, U, nullptr, ctx->U2, 0, 0, 0.0, 1.0, nullptr, 0.0, false, um, up, flux);
+}
+
+int pp_cweno_tridiag_solve_debug(pp_cweno_ctx* ctx, int64_t n, int cyclic, const double* a,
+                                 const double* b, const double* c, const double* r, double* x) {
+    if (!ctx) return fail(nullptr, PP_EINVAL, "ctx is NULL");
+    if (!a || !b || !c || !r || !x) return fail(ctx, PP_EINVAL, "NULL row or solution pointer");
+    if (n < 3 || n > 4096) return fail(ctx, PP_EINVAL, "tridiagonal debug solve: 3 <= n <= 4096");
+    if (n <= 2048)
+        hipLaunchKernelGGL(tridiag_debug_kernel<1>, dim3(1), dim3(64), 0, ctx->stream, a, b, c, r,
+                           x, (int)n, cyclic ? 1 : 0);
+    else
+        hipLaunchKernelGGL(tridiag_debug_kernel<2>, dim3(1), dim3(128), 0, ctx->stream, a, b, c,
+                           r, x, (int)n, cyclic ? 1 : 0);
+    HIPCHK(ctx, hipGetLastError());
+    return PP_OK;
 }
 
 int pp_cweno_set_timing(pp_cweno_ctx* ctx, int on) {

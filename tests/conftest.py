@@ -20,3 +20,14 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "slow" in it.keywords:
             it.add_marker(skip)
+
+
+def pytest_terminal_summary(terminalreporter):
+    """List every GPU parity case that used the widened stage bar (the
+    oracle's own sensitivity where the limiter holds states on e = eps)."""
+    mod = sys.modules.get("test_gpu_parity") or sys.modules.get("tests.test_gpu_parity")
+    cases = getattr(mod, "WIDENED", None) if mod else None
+    if cases:
+        terminalreporter.write_line("widened stage bars (case, bar, limited cells):")
+        for c in cases:
+            terminalreporter.write_line(f"  {c[0]}: {c[1]:.2e}, {c[2]}")

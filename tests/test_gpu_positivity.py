@@ -48,18 +48,23 @@ def in_G(U):
 def test_blast_restart_rule_reaches_t_end_in_G():
     """The near-vacuum blast (N = 4000, transmissive) to t = 1e-3 under
     PP_DT_RESTART: the run ends at t_end with no stage output left outside G
-    (status clean), and agrees with the oracle's run of the same rule as two
-    runs through discrete decisions can: whether a step is redone depends on
-    the sign of a near-vacuum pressure, a roundoff-sized quantity at the
-    evacuated centre, so after the first differing decision the two
-    trajectories are different valid runs.  Checked: step counts within 2 %,
-    redone steps within 25 %, final states within 5 % (relative L1); the
-    step-level parity is the next test."""
+    (status clean).  Whether a step is redone depends on the sign of a
+    near-vacuum pressure, a roundoff-sized quantity at the evacuated centre,
+    so after the first differing decision two runs are different valid runs
+    of the rule: the oracle's own run, restarted from initial data perturbed
+    by 1e-15, is the yardstick.  Step counts, redone steps and the final
+    state (relative L1) must agree with the oracle's within 4x (and at least
+    2 %) of that run's own differences; the step-level parity is the next
+    test."""
     pp = gpu()
     n, h, T = 4000, 2.0 / 4000, 1e-3
     U0 = W.vacuum_blast_1d(n)
     ref, info = oracle.run_1d(U0, (1, 1), h, T, rule=oracle.DT_RESTART)
     assert info["t"] == T and info["restarts"] > 0 and in_G(ref)
+    rng = np.random.default_rng(1402)
+    alt, ialt = oracle.run_1d(U0 * (1.0 + 1e-15 * rng.standard_normal(U0.shape)), (1, 1), h, T,
+                              rule=oracle.DT_RESTART)
+    assert ialt["t"] == T and in_G(alt)
     s = pp.Solver(ndim=1, nx=n, dx=h, bc=(1, 1, 0, 0))
     Ud = dev(U0)
     t, steps = s.run(Ud, T, 1 << 40, 1.0 / 12.0, pp.PP_DT_RESTART)
@@ -67,14 +72,18 @@ def test_blast_restart_rule_reaches_t_end_in_G():
     code, flags = s.status()
     got = Ud.cpu().numpy()
     d = rel_l1(got, ref)
-    print(f"blast, restart rule: steps {steps} / {info['steps']}, restarts {restarts} / "
-          f"{info['restarts']}, relative L1 difference {d:.3e}", flush=True)
+    d_alt = rel_l1(alt, ref)
+    s_alt = abs(ialt["steps"] / info["steps"] - 1)
+    r_alt = abs(ialt["restarts"] / info["restarts"] - 1)
+    print(f"blast, restart rule: steps {steps} / {info['steps']} (perturbed oracle "
+          f"{ialt['steps']}), restarts {restarts} / {info['restarts']} ({ialt['restarts']}), "
+          f"relative L1 difference {d:.3e} (perturbed oracle {d_alt:.3e})", flush=True)
     assert code == pp.PP_OK and flags == 0
     assert t == pytest.approx(T, rel=1e-14)
-    assert abs(steps / info["steps"] - 1) <= 0.02
-    assert abs(restarts / info["restarts"] - 1) <= 0.25
     assert in_G(got)
-    assert d <= 0.05
+    assert abs(steps / info["steps"] - 1) <= max(0.02, 4 * s_alt)
+    assert abs(restarts / info["restarts"] - 1) <= max(0.02, 4 * r_alt)
+    assert d <= max(1e-9, 4 * d_alt)
     s.close()
 
 
