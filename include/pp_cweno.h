@@ -76,8 +76,9 @@ enum { PP_FP64 = 0, PP_MIXED = 1 };
  *  PP_DT_RESTART : PP_DT_CFL's dt; a step in which any stage output leaves
  *                  the admissible set (rho <= 0, p <= 0 or not finite) is
  *                  discarded and redone from U^n with half the dt, up to 60
- *                  times (then the run stops with PP_ESTATE).  The next step
- *                  starts again from the averages' dt.  1D only. */
+ *                  times; the run stops with PP_ESTATE after that, or as soon
+ *                  as half the dt no longer changes t in FP64 (a stall).  The
+ *                  next step starts again from the averages' dt.  1D only. */
 enum { PP_DT_CFL = 0, PP_DT_H53 = 1, PP_DT_PP = 2, PP_DT_RESTART = 3 };
 
 /* Numerical flux at the faces.  PP_FLUX_HLLC: eq. (HLLC) with the acoustic

@@ -1185,7 +1185,9 @@ int orc_run_1d(int n, double *U, int bc_lo, int bc_hi, double h, const orc_param
                     outG += bad;
                     break;
                 }
-                if (halvings == ORC_MAX_HALVINGS) { r3 = -4; break; }
+                /* no further attempt after ORC_MAX_HALVINGS halvings, nor once
+                 * half the step no longer moves t in FP64 (a stall) */
+                if (halvings == ORC_MAX_HALVINGS || t + 0.5 * dt == t) { r3 = -4; break; }
                 dt *= 0.5;   /* redo the step from U^n with half the step */
                 ++restarts;
             }

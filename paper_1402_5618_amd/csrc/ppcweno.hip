@@ -961,11 +961,17 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     const int bc_hi = batched ? A.bcline[2 * b + 1] : A.bc_hi;
     const long long base = batched ? A.off[b] : (long long)b * A.ls;
     const bool cyclic = (bc_lo == PP_BC_PERIODIC);
+    // stage epilogues (modes 1 and 2) and the time-step rules serve 1D lines
+    // only: the 2D sweeps (NC = 4) write L (mode 0), and their kernels carry
+    // none of that code
+    constexpr bool kEpi = (NC == 3);
+    const int mode = kEpi ? A.mode : 0;
+    const bool pprule = kEpi && A.dtrule == PP_DT_PP;
     double dt = 0.0;
-    if (A.mode == 1) dt = batched ? A.dtline[b] : (A.dt_dev ? *A.dt_dev : A.dt_val);
+    if (mode == 1) dt = batched ? A.dtline[b] : (A.dt_dev ? *A.dt_dev : A.dt_val);
     // mode 2 (stage 1 under the interface-state rule): dtline holds the time
     // left to t_end until this stage has chosen the step
-    if (A.mode == 2 && batched) dt = A.dtline[b];
+    if (mode == 2 && batched) dt = A.dtline[b];
     if (batched && !(dt > 0.0)) return;  // finished problem: leave it untouched
     // status bits of a stage output go to the problem's word under the
     // restart rule (batched), else to the run's word
@@ -1388,7 +1394,7 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
                 sRes[(2 * c) * SS + pq] = Um[c];
                 sRes[(2 * c + 1) * SS + pq] = Up[c];
             }
-            if (A.dtrule == PP_DT_PP) {
+            if (pprule) {
                 // sup-norm of |u|+a over the averages and the limited
                 // interface states (condition (CFL-CD)); a non-finite speed
                 // makes the bound infinite, so no step is taken
@@ -1469,7 +1475,7 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
                 const double L = -(sF[c * FS + q + 1] - Fl) * ih;
                 if (wrap0 && q == 0 && A.dbg_flux) A.dbg_flux[(long long)c * (n + 1)] = Fl;
                 const long long at = base + (long long)c * A.cs + i;
-                if (A.mode != 1) {
+                if (mode != 1) {
                     o[c] = L;
                 } else {
                     const double us = A.U[at];
@@ -1478,7 +1484,7 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
                 }
                 A.out[at] = o[c];
             }
-            if (A.mode == 1) {
+            if (mode == 1) {
                 // state checks without divisions: rho > 0 and rho E - |m|^2/2 > 0
                 double m2 = 0.0;
 #pragma unroll
@@ -1493,7 +1499,7 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
         }
         __syncthreads();
     }
-    if (A.mode == 2) {
+    if (mode == 2) {
         // stage 1 under the interface-state rule: the step's dt from the
         // sup-norm over this stage input, then U1 = U + dt L over the L just
         // written (same rounding as the one-pass stage 1)
@@ -1539,8 +1545,8 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
             if (bad && stat) atomicOr(stat, bad);
         }
     }
-    if (A.mode == 1) {
-        if (A.dtrule == PP_DT_PP && A.stage >= 2) {
+    if (mode == 1) {
+        if (pprule && A.stage >= 2) {
             // the stage input against condition (CFL-CD) with the step's dt
             const double S = block_max<NT>(smax_if, red);
             if (dt * S > A.w1 * h) bad |= 4u;
@@ -1577,7 +1583,8 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
                         // redo this step from U^n with half the dt
                         const int hv = A.halfline[b] + 1;
                         A.halfline[b] = hv;
-                        if (hv > kMaxHalvings) {
+                        const double t = A.tline[b];
+                        if (hv > kMaxHalvings || t + 0.5 * dt == t) {   // or a stall
                             dn = 0.0;
                             if (A.status) atomicOr(A.status, sbad);
                         } else {
@@ -1598,7 +1605,7 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
                             A.halfline[b] = 0;
                             A.badline[b] = 0u;
                         }
-                        if (A.dtrule == PP_DT_PP) {
+                        if (pprule) {
                             dn = A.t_end - t;
                         } else {
                             dn = A.cfl * h / S;
@@ -1997,7 +2004,9 @@ __global__ void __launch_bounds__(2 * NC * 64 * W) run1d_kernel(RunArgs R) {
                 break;
             }
             if (threadIdx.x == 0) {
-                if (attempt >= kMaxHalvings) {
+                // last attempt after kMaxHalvings halvings, or once half the
+                // step no longer moves t in FP64 (a stall)
+                if (attempt >= kMaxHalvings || s->t + 0.5 * s->dt == s->t) {
                     s->status |= bad;
                     s->active = 0;
                     s->dt = 0.0;
