@@ -36,7 +36,8 @@ class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("weno_eps", ctypes.c_double),
                 ("eps_cap", ctypes.c_double), ("gl_w1", ctypes.c_double),
                 ("linear", ctypes.c_int), ("first_order", ctypes.c_int),
-                ("limiter", ctypes.c_int), ("flux", ctypes.c_int), ("recon", ctypes.c_int)]
+                ("limiter", ctypes.c_int), ("flux", ctypes.c_int), ("recon", ctypes.c_int),
+                ("fv", ctypes.c_int)]
 
 
 class LineDbg(ctypes.Structure):
@@ -45,14 +46,17 @@ class LineDbg(ctypes.Structure):
 
 
 def params(gamma=1.4, weno_eps=1e-13, eps_cap=1e-13, gl_w1=1.0 / 12.0, linear=False,
-           first_order=False, limiter=True, flux=0, recon=0) -> Params:
+           first_order=False, limiter=True, flux=0, recon=0, fv=0) -> Params:
     """flux: 0 HLLC (eq. (HLLC)), 1 local Lax-Friedrichs (the alternative the
     paper names for Example 3.6).  recon: 0 the compact reconstruction
     (Sec. 2.2), 1 explicit WENO-JS, 2 explicit WENO-Z (the non-compact
     schemes the paper compares against in Sec. 3), 3 the compact
-    reconstruction along characteristic fields (Sec. 2.3; 1D)."""
+    reconstruction along characteristic fields (Sec. 2.3; 1D).  fv (2D):
+    0 one state pair per face (dimension by dimension), 1 three Gauss nodes
+    per face from a transverse reconstruction (a multi-dimensional reading
+    beyond the paper, which leaves that to future work in Sec. 4)."""
     return Params(gamma, weno_eps, eps_cap, gl_w1, int(linear), int(first_order), int(limiter),
-                  int(flux), int(recon))
+                  int(flux), int(recon), int(fv))
 
 
 _lib = None
@@ -106,6 +110,10 @@ def lib():
             "orc_char_eigen": (None, [_DBL, _D, _D, _D, _D, _D]),
             "orc_block_solve": (_I, [_I, _I, _D, _D, _D, _D, _D]),
             "orc_recon_char": (_I, [_I, _I, _D, _P, _D, _D]),
+            "orc_gauss_nodes": (_I, [_D, _D]),
+            "orc_limit_nodes": (_I, [_I, _DBL, _DBL, _DBL, _D, _D, _D]),
+            "orc_gauss_dir": (_L, [_I, _I, _D, _I, _I, _I, _I, _I, _I, _DBL, _P, _DBL, _DBL,
+                                   _D]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -365,6 +373,50 @@ def run_batch(ens, t_end=None, cfl=1.0 / 12.0, p=None, rule=0, viol_out=None):
                                     ens.t_end if t_end is None else t_end, cfl, rule, U.shape[1],
                                     _d(steps), _d(viol)), "run_batch")
     return U, steps
+
+
+def gauss_nodes(v5):
+    """Values at the three Gauss-Legendre nodes of the middle cell of the
+    quartic whose averages over five unit cells are v5 (transverse step of
+    the Gauss-node 2D operator)."""
+    v = _f64(v5).copy()
+    assert v.shape == (5,)
+    out = np.empty(3)
+    _check(lib().orc_gauss_nodes(_d(v), _d(out)), "gauss_nodes")
+    return out
+
+
+def limit_nodes(Ub, Nm, Np, eps_rho, eps_e, w1=1.0 / 12.0):
+    """Node limiter of the Gauss-node 2D operator on one cell: Nm, Np are
+    [3][ncomp] (right-face and left-face nodes).  Returns (Nm, Np, active)."""
+    Ub = _f64(Ub)
+    nc = Ub.shape[0]
+    a = np.zeros((3, 4)); b = np.zeros((3, 4))
+    a[:, :nc] = Nm; b[:, :nc] = Np
+    r = lib().orc_limit_nodes(nc, w1, eps_rho, eps_e, _d(Ub), _d(a), _d(b))
+    return a[:, :nc].copy(), b[:, :nc].copy(), r
+
+
+def gauss_dir_x(U, bc, dx, eps_rho, eps_e, p=None):
+    """The x-direction part of the Gauss-node operator for a [4][ny][nx]
+    state (x-lines closed by bc[0:2], the set of lines by bc[2:4])."""
+    p = p or params(fv=1)
+    U = _f64(U)
+    _, ny, nx = U.shape
+    L = np.empty_like(U)
+    _check(lib().orc_gauss_dir(nx, ny, _d(U), 1, 2, bc[0], bc[1], bc[2], bc[3], dx,
+                               ctypes.byref(p), eps_rho, eps_e, _d(L)), "gauss_dir")
+    return L
+
+
+def rhs_2d_count(U, bc, dx, dy, p=None):
+    """rhs_2d that also returns the number of limited cells."""
+    p = p or params()
+    U = _f64(U)
+    _, ny, nx = U.shape
+    L = np.empty_like(U)
+    r = _check(lib().orc_rhs_2d(nx, ny, _d(U), _bc4(bc), dx, dy, ctypes.byref(p), _d(L)), "rhs_2d")
+    return L, r
 
 
 def weights(v6, eps=1e-13):

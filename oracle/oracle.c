@@ -38,6 +38,9 @@ typedef struct {
     int recon;        /* 0: compact (FVCW, Sec 2.2); 1: explicit WENO-JS; 2: explicit
                        * WENO-Z (the non-compact schemes of Sec 3, see weno5_explicit);
                        * 3: compact, characteristic-wise (Sec 2.3; 1D only) */
+    int fv;           /* 2D face fluxes: 0 one state pair per face (dimension by
+                       * dimension); 1 three Gauss-Legendre nodes per face from a
+                       * transverse reconstruction (see orc_rhs_2d_gauss) */
 } orc_params;
 
 /* Optional per-line intermediate results for tests (any pointer may be NULL). */
@@ -1212,6 +1215,311 @@ int orc_run_1d(int n, double *U, int bc_lo, int bc_hi, double h, const orc_param
     return rc;
 }
 
+/* ------------------------------------------------------- 2D, Gauss nodes
+ * Reading (the paper leaves genuinely multi-dimensional schemes to future
+ * work, Sec. 4): a 2D finite-volume operator whose face fluxes are averages
+ * over the face by three-point Gauss-Legendre quadrature.
+ *  1. Along each x-line the compact reconstruction of Sec. 2.2 turns the
+ *     cell averages into face values that are averages over the cell's
+ *     y-extent (taken before the limiter);
+ *  2. across the lines, at every x-face and side, the quartic whose averages
+ *     over the five cells j-2..j+2 equal those face values gives the values
+ *     at the face's three Gauss nodes (a linear fifth-order step; no WENO
+ *     weights across the lines);
+ *  3. per cell, the limiter steps of Sec. 2.4 act on its six node values
+ *     (three on each x-face) against the cell average, with the middle state
+ *     from Ubar = w1 sum_k g_k (U-_k + U+_k) + (1 - 2 w1) U_mid (g_k the
+ *     Gauss weights), the 2D form of the decomposition behind the theorem;
+ *  4. each face flux is the g_k-weighted sum of the numerical flux at its
+ *     nodes, and L_x = -(F_{i+1/2} - F_{i-1/2}) / dx.
+ * The y-direction is the same with x and y exchanged; L = L_x + L_y.
+ * Ghost lines across the lines follow the ghost-cell reading: periodic wrap,
+ * transmissive copy of the edge line, reflective mirror with the transverse
+ * momentum negated. */
+
+static const double GL_W[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+
+/* Values at the Gauss nodes -sqrt(15)/10, 0, sqrt(15)/10 (in cell widths
+ * from the centre of cell 2) of the quartic whose averages over cells 0..4
+ * (cell m spans [m - 2.5, m - 1.5]) are v[0..4].  The quartic's monomial
+ * coefficients come from the 5x5 system of monomial cell averages. */
+int orc_gauss_nodes(const double *v, double *out)
+{
+    double M[25], a[5];
+    for (int m = 0; m < 5; ++m)
+        for (int p = 0; p < 5; ++p) {
+            double hi = (m - 2) + 0.5, lo = (m - 2) - 0.5;
+            M[m * 5 + p] = (pow(hi, p + 1) - pow(lo, p + 1)) / (p + 1);
+        }
+    int s = orc_dense_solve(5, M, v, a);
+    if (s) return s;
+    double xi[3] = {-sqrt(15.0) / 10.0, 0.0, sqrt(15.0) / 10.0};
+    for (int k = 0; k < 3; ++k) {
+        double q = 0.0, x = 1.0;
+        for (int p = 0; p < 5; ++p) {
+            q += a[p] * x;
+            x *= xi[k];
+        }
+        out[k] = q;
+    }
+    return 0;
+}
+
+/* middle state of the decomposition in step 3 above */
+static void node_mid(int ncomp, double w1, const double *Ub, double Nm[3][4], double Np[3][4],
+                     double *mid)
+{
+    for (int c = 0; c < ncomp; ++c) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) s += GL_W[k] * (Nm[k][c] + Np[k][c]);
+        mid[c] = (Ub[c] - w1 * s) / (1.0 - 2.0 * w1);
+    }
+}
+
+/* Limiter steps 2-4 of Sec. 2.4 on the node states of one cell: Nm[k] the
+ * nodes of its right face (U-), Np[k] those of its left face (U+), modified
+ * in place.  Returns 1 if anything changed. */
+static int pp_limit_nodes(int ncomp, double w1, double eps_rho, double eps_e, const double *Ub,
+                          double Nm[3][4], double Np[3][4])
+{
+    int active = 0;
+    double mid[4];
+    /* step 2: theta1 from the smallest density of the seven states */
+    node_mid(ncomp, w1, Ub, Nm, Np, mid);
+    double rmin = mid[0];
+    for (int k = 0; k < 3; ++k) rmin = fmin(rmin, fmin(Nm[k][0], Np[k][0]));
+    double th1 = 1.0;
+    if (rmin < eps_rho) th1 = fmin((Ub[0] - eps_rho) / (Ub[0] - rmin), 1.0);
+    /* step 3 */
+    if (th1 < 1.0) {
+        for (int k = 0; k < 3; ++k) {
+            Nm[k][0] = th1 * (Nm[k][0] - Ub[0]) + Ub[0];
+            Np[k][0] = th1 * (Np[k][0] - Ub[0]) + Ub[0];
+        }
+        active = 1;
+    }
+    /* step 4: theta2 over the six nodes and the new middle state */
+    node_mid(ncomp, w1, Ub, Nm, Np, mid);
+    double th2 = 1.0;
+    for (int al = 0; al < 7; ++al) {
+        const double *W = al < 3 ? Nm[al] : (al < 6 ? Np[al - 3] : mid);
+        if (!(W[0] > 0.0) || spec_e(ncomp, W) < eps_e) {
+            double t = pp_root(ncomp, eps_e, Ub, W);
+            if (t < th2) th2 = t;
+        }
+    }
+    if (th2 < 1.0) {
+        for (int k = 0; k < 3; ++k)
+            for (int c = 0; c < ncomp; ++c) {
+                Nm[k][c] = th2 * (Nm[k][c] - Ub[c]) + Ub[c];
+                Np[k][c] = th2 * (Np[k][c] - Ub[c]) + Ub[c];
+            }
+        active = 1;
+    }
+    return active;
+}
+
+/* Exported node limiter for unit tests: Nm, Np are [3][4] row-major (node,
+ * component), modified in place. */
+int orc_limit_nodes(int ncomp, double w1, double eps_rho, double eps_e, const double *Ub,
+                    double *Nm, double *Np)
+{
+    double A[3][4], B[3][4];
+    for (int k = 0; k < 3; ++k)
+        for (int c = 0; c < 4; ++c) {
+            A[k][c] = c < ncomp ? Nm[k * 4 + c] : 0.0;
+            B[k][c] = c < ncomp ? Np[k * 4 + c] : 0.0;
+        }
+    int r = pp_limit_nodes(ncomp, w1, eps_rho, eps_e, Ub, A, B);
+    for (int k = 0; k < 3; ++k)
+        for (int c = 0; c < ncomp; ++c) {
+            Nm[k * 4 + c] = A[k][c];
+            Np[k * 4 + c] = B[k][c];
+        }
+    return r;
+}
+
+/* line index of ghost line j (j < 0 or j >= nl) across the lines; *sign is
+ * -1 where the transverse momentum is negated (reflective mirror) */
+static int ghost_line(int j, int nl, int lo, int hi, int *sign)
+{
+    *sign = 1;
+    if (j >= 0 && j < nl) return j;
+    if (lo == 0) return ((j % nl) + nl) % nl;
+    if (j < 0) {
+        if (lo == 1) return 0;
+        *sign = -1;
+        return -1 - j < nl ? -1 - j : nl - 1;
+    }
+    if (hi == 1) return nl - 1;
+    *sign = -1;
+    return 2 * nl - 1 - j >= 0 ? 2 * nl - 1 - j : 0;
+}
+
+/* One direction of the Gauss-node operator: u and L are [4][nl][n] (nl lines
+ * of n cells); nrm / tnrm index the normal / transverse momentum; bc_lo,
+ * bc_hi close the lines, tb_lo, tb_hi the set of lines.  Returns the number
+ * of limited cells or a negative code; smax (may be NULL) receives the
+ * sup-norm of |u_n| + a over the averages and the limited node states. */
+static long gauss_dir(int n, int nl, const double *u, int nrm, int tnrm, int bc_lo, int bc_hi,
+                      int tb_lo, int tb_hi, double h, const orc_params *P, double er, double ee,
+                      double *L, double *smax)
+{
+    size_t cs = (size_t)n * (size_t)nl;
+    double *Wm = (double *)malloc(sizeof(double) * 4u * cs);   /* [4][nl][n] U-_{i+1/2} */
+    double *Wp = (double *)malloc(sizeof(double) * 4u * cs);   /* [4][nl][n] U+_{i-1/2} */
+    double *Nm = (double *)malloc(sizeof(double) * 12u * cs);  /* [nl][n][3][4] limited */
+    double *Np = (double *)malloc(sizeof(double) * 12u * cs);
+    if (!Wm || !Wp || !Nm || !Np) { free(Wm); free(Wp); free(Nm); free(Np); return -2; }
+    int err = 0;
+    long nlim = 0;
+    double sm = 0.0;
+    int cyclic = bc_lo == 0;
+    /* step 1: face averages of every line */
+#pragma omp parallel
+    {
+        double *line = (double *)malloc(sizeof(double) * 4u * (size_t)n);
+        double *lo = (double *)malloc(sizeof(double) * 4u * (size_t)n);
+        double *um = (double *)malloc(sizeof(double) * 4u * (size_t)n);
+        double *up = (double *)malloc(sizeof(double) * 4u * (size_t)n);
+#pragma omp for schedule(static)
+        for (int l = 0; l < nl; ++l) {
+            for (int k = 0; k < 4; ++k)
+                for (int i = 0; i < n; ++i) line[(size_t)k * n + i] = u[k * cs + (size_t)l * n + i];
+            orc_line_dbg dbg = {um, up, NULL, NULL, NULL};
+            long r = orc_line_op(n, 4, nrm, line, bc_lo, bc_hi, h, P, er, ee, lo, &dbg, NULL);
+            if (r < 0) err = (int)r;
+            for (int k = 0; k < 4; ++k)
+                for (int i = 0; i < n; ++i) {
+                    Wm[k * cs + (size_t)l * n + i] = um[(size_t)k * n + i];
+                    Wp[k * cs + (size_t)l * n + i] = up[(size_t)k * n + i];
+                }
+        }
+        free(line); free(lo); free(um); free(up);
+    }
+    if (err) { free(Wm); free(Wp); free(Nm); free(Np); return err; }
+    /* steps 2 and 3: node values across the lines, limiter per cell */
+#pragma omp parallel for schedule(static) reduction(+ : nlim) reduction(max : sm)
+    for (int l = 0; l < nl; ++l) {
+        for (int i = 0; i < n; ++i) {
+            double A[3][4], B[3][4], Ub[4], v[5], q[3];
+            for (int k = 0; k < 4; ++k) {
+                Ub[k] = u[k * cs + (size_t)l * n + i];
+                for (int side = 0; side < 2; ++side) {
+                    const double *W = side == 0 ? Wm : Wp;
+                    for (int m = 0; m < 5; ++m) {
+                        int sg;
+                        int j = ghost_line(l + m - 2, nl, tb_lo, tb_hi, &sg);
+                        v[m] = (k == tnrm ? sg : 1) * W[k * cs + (size_t)j * n + i];
+                    }
+                    orc_gauss_nodes(v, q);
+                    for (int g = 0; g < 3; ++g) (side == 0 ? A : B)[g][k] = q[g];
+                }
+            }
+            if (P->limiter) nlim += pp_limit_nodes(4, P->gl_w1, er, ee, Ub, A, B);
+            double *dm = Nm + ((size_t)l * n + i) * 12u, *dp = Np + ((size_t)l * n + i) * 12u;
+            for (int g = 0; g < 3; ++g)
+                for (int k = 0; k < 4; ++k) {
+                    dm[g * 4 + k] = A[g][k];
+                    dp[g * 4 + k] = B[g][k];
+                }
+            if (smax) {
+                double s = wave_speed(P->gamma, 4, nrm, Ub);
+                for (int g = 0; g < 3; ++g) {
+                    s = fmax(s, wave_speed(P->gamma, 4, nrm, A[g]));
+                    s = fmax(s, wave_speed(P->gamma, 4, nrm, B[g]));
+                }
+                if (s != s) s = INFINITY;
+                if (s > sm) sm = s;
+            }
+        }
+    }
+    /* step 4: Gauss sums of the node fluxes, flux differences */
+#pragma omp parallel
+    {
+        double *F = (double *)malloc(sizeof(double) * 4u * (size_t)(n + 1));
+#pragma omp for schedule(static)
+        for (int l = 0; l < nl; ++l) {
+            for (int f = 0; f <= n; ++f) {
+                double Fs[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int g = 0; g < 3; ++g) {
+                    double Ul[4], Ur[4], Ff[4];
+                    for (int k = 0; k < 4; ++k) {
+                        if (f > 0 && f < n) {
+                            Ul[k] = Nm[((size_t)l * n + f - 1) * 12u + g * 4 + k];
+                            Ur[k] = Np[((size_t)l * n + f) * 12u + g * 4 + k];
+                        } else if (cyclic) {
+                            Ul[k] = Nm[((size_t)l * n + n - 1) * 12u + g * 4 + k];
+                            Ur[k] = Np[((size_t)l * n) * 12u + g * 4 + k];
+                        } else if (f == 0) {
+                            Ur[k] = Np[((size_t)l * n) * 12u + g * 4 + k];
+                            Ul[k] = (bc_lo == 2 && k == nrm) ? -Ur[k] : Ur[k];
+                        } else {
+                            Ul[k] = Nm[((size_t)l * n + n - 1) * 12u + g * 4 + k];
+                            Ur[k] = (bc_hi == 2 && k == nrm) ? -Ul[k] : Ul[k];
+                        }
+                    }
+                    if (P->flux == 1)
+                        lf(P->gamma, 4, nrm, Ul, Ur, Ff);
+                    else
+                        hllc(P->gamma, 4, nrm, Ul, Ur, Ff);
+                    for (int k = 0; k < 4; ++k) Fs[k] += GL_W[g] * Ff[k];
+                }
+                for (int k = 0; k < 4; ++k) F[(size_t)k * (n + 1) + f] = Fs[k];
+            }
+            for (int k = 0; k < 4; ++k)
+                for (int i = 0; i < n; ++i)
+                    L[k * cs + (size_t)l * n + i] =
+                        -(F[(size_t)k * (n + 1) + i + 1] - F[(size_t)k * (n + 1) + i]) / h;
+        }
+        free(F);
+    }
+    free(Wm); free(Wp); free(Nm); free(Np);
+    if (smax) *smax = sm;
+    return nlim;
+}
+
+/* Exported single direction for tests (the x-direction when u is [4][ny][nx]
+ * with n = nx, nl = ny, nrm = 1, tnrm = 2). */
+long orc_gauss_dir(int n, int nl, const double *u, int nrm, int tnrm, int bc_lo, int bc_hi,
+                   int tb_lo, int tb_hi, double h, const orc_params *P, double er, double ee,
+                   double *L)
+{
+    return gauss_dir(n, nl, u, nrm, tnrm, bc_lo, bc_hi, tb_lo, tb_hi, h, P, er, ee, L, NULL);
+}
+
+/* L = L_x + L_y of the Gauss-node operator for a [4][ny][nx] state; smax (may
+ * be NULL) receives the x and y sup-norms of gauss_dir. */
+long orc_rhs_2d_gauss(int nx, int ny, const double *U, const int *bc, double dx, double dy,
+                      const orc_params *P, double *L, double *smax)
+{
+    long ncell = (long)nx * ny;
+    double er, ee;
+    orc_eps(ncell, 4, U, P->eps_cap, &er, &ee);
+    double *Ut = (double *)malloc(sizeof(double) * 4u * (size_t)ncell);
+    double *Lt = (double *)malloc(sizeof(double) * 4u * (size_t)ncell);
+    if (!Ut || !Lt) { free(Ut); free(Lt); return -2; }
+    double sx = 0.0, sy = 0.0;
+    long r1 = gauss_dir(nx, ny, U, 1, 2, bc[0], bc[1], bc[2], bc[3], dx, P, er, ee, L,
+                        smax ? &sx : NULL);
+    for (int k = 0; k < 4; ++k)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) Ut[k * ncell + (long)x * ny + y] = U[k * ncell + (long)y * nx + x];
+    long r2 = r1 < 0 ? r1
+                     : gauss_dir(ny, nx, Ut, 2, 1, bc[2], bc[3], bc[0], bc[1], dy, P, er, ee, Lt,
+                                 smax ? &sy : NULL);
+    if (r2 >= 0)
+        for (int k = 0; k < 4; ++k)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) L[k * ncell + (long)y * nx + x] += Lt[k * ncell + (long)x * ny + y];
+    free(Ut);
+    free(Lt);
+    if (smax) { smax[0] = sx; smax[1] = sy; }
+    if (r1 < 0) return r1;
+    if (r2 < 0) return r2;
+    return r1 + r2;
+}
+
 /* ------------------------------------------------------------------- 2D
  * Reading (the paper is one-dimensional): dimension by dimension.  Each x-line
  * (row) and y-line (column) is treated as a 1D line of 2D cell averages with
@@ -1220,6 +1528,7 @@ int orc_run_1d(int n, double *U, int bc_lo, int bc_hi, double h, const orc_param
 long orc_rhs_2d_speed(int nx, int ny, const double *U, const int *bc, double dx, double dy,
                       const orc_params *P, double *L, double *smax /* [2] or NULL */)
 {
+    if (P->fv == 1) return orc_rhs_2d_gauss(nx, ny, U, bc, dx, dy, P, L, smax);
     long ncell = (long)nx * ny;
     double er, ee;
     orc_eps(ncell, 4, U, P->eps_cap, &er, &ee);

@@ -69,6 +69,65 @@ def density_wave_2d(nx: int, ny: int, t: float = 0.0, gamma: float = 1.4,
                      1.0 / (gamma - 1.0) + 0.5 * rho * (2.0 * vel * vel)])
 
 
+def _smooth_flow_prim(x, y):
+    rho = 1.0 + 0.2 * np.sin(2.0 * np.pi * x) * np.sin(2.0 * np.pi * y)
+    u = 0.4 + 0.1 * np.cos(2.0 * np.pi * y)
+    v = -0.3 + 0.1 * np.sin(2.0 * np.pi * x)
+    p = 1.0 + 0.1 * np.cos(2.0 * np.pi * (x - y))
+    return rho, u, v, p
+
+
+def smooth_flow_2d(nx: int, ny: int, gamma: float = 1.4, quad: int = 6) -> np.ndarray:
+    """A smooth, genuinely two-dimensional, nonlinear state on periodic [0, 1]^2:
+    rho = 1 + 0.2 sin(2 pi x) sin(2 pi y), u = 0.4 + 0.1 cos(2 pi y),
+    v = -0.3 + 0.1 sin(2 pi x), p = 1 + 0.1 cos(2 pi (x - y)).  Cell averages of
+    the conserved variables by quad x quad Gauss-Legendre points per cell."""
+    xg, wg = np.polynomial.legendre.leggauss(quad)
+    dx, dy = 1.0 / nx, 1.0 / ny
+    xc = cell_centres(0.0, 1.0, nx)[None, :]
+    yc = cell_centres(0.0, 1.0, ny)[:, None]
+    U = np.zeros((4, ny, nx))
+    for a, wa in zip(xg, wg):
+        for b, wb in zip(xg, wg):
+            x = xc + 0.5 * a * dx + 0.0 * yc
+            y = yc + 0.5 * b * dy + 0.0 * xc
+            rho, u, v, p = _smooth_flow_prim(x, y)
+            w = 0.25 * wa * wb
+            U[0] += w * rho
+            U[1] += w * rho * u
+            U[2] += w * rho * v
+            U[3] += w * (p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v))
+    return U
+
+
+def smooth_flow_2d_divergence(nx: int, ny: int, gamma: float = 1.4, quad: int = 6) -> np.ndarray:
+    """Exact cell averages of -(df/dx + dg/dy) for smooth_flow_2d, with f, g the
+    Euler fluxes: the face integrals of the pointwise fluxes (quad Gauss points
+    per face) divided by the cell size."""
+    xg, wg = np.polynomial.legendre.leggauss(quad)
+    dx, dy = 1.0 / nx, 1.0 / ny
+    xc = cell_centres(0.0, 1.0, nx)
+    yc = cell_centres(0.0, 1.0, ny)
+    xf = np.arange(nx + 1) * dx
+    yf = np.arange(ny + 1) * dy
+
+    def fluxes(x, y):
+        rho, u, v, p = _smooth_flow_prim(x, y)
+        E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+        f = np.stack([rho * u, rho * u * u + p, rho * u * v, u * (E + p)])
+        g = np.stack([rho * v, rho * u * v, rho * v * v + p, v * (E + p)])
+        return f, g
+
+    Fx = np.zeros((4, ny, nx + 1))
+    Gy = np.zeros((4, ny + 1, nx))
+    for b, wb in zip(xg, wg):
+        f, _ = fluxes(xf[None, :] + 0.0 * yc[:, None], yc[:, None] + 0.5 * b * dy + 0.0 * xf[None, :])
+        Fx += 0.5 * wb * f
+        _, g = fluxes(xc[None, :] + 0.5 * b * dx + 0.0 * yf[:, None], yf[:, None] + 0.0 * xc[None, :])
+        Gy += 0.5 * wb * g
+    return -(Fx[:, :, 1:] - Fx[:, :, :-1]) / dx - (Gy[:, 1:, :] - Gy[:, :-1, :]) / dy
+
+
 # ----------------------------------------------------------- piecewise data
 def piecewise_1d(a: float, b: float, n: int, pieces, gamma: float = 1.4) -> np.ndarray:
     """Exact cell averages of piecewise-constant primitive data.
