@@ -105,6 +105,21 @@ enum { PP_FLUX_HLLC = 0, PP_FLUX_LF = 1 };
  * schemes run in FP64 without a batch (else PP_EUNSUPPORTED at init). */
 enum { PP_RECON_CWENO = 0, PP_RECON_WENOJS = 1, PP_RECON_WENOZ = 2, PP_RECON_CHAR = 3 };
 
+/* 2D face fluxes.  PP_FV_LINE: one state pair per face from the line's
+ * reconstruction, dimension by dimension (the default; fifth order for the
+ * density wave, second order for general nonlinear 2D flows).
+ * PP_FV_GAUSS: a multi-dimensional finite-volume operator (the paper leaves
+ * multi-D schemes to future work, Sec. 4): each face flux is the average over
+ * the face by three-point Gauss-Legendre quadrature.  The compact
+ * reconstruction along each line gives face values averaged over the cell's
+ * transverse extent; across the lines, the quartic through the averages of
+ * five neighbouring face values gives the values at the Gauss nodes; the
+ * limiter steps of Sec. 2.4 act on each cell's six node states with the
+ * Gauss-weighted middle state; the numerical flux is taken per node.  Fifth
+ * order on nonlinear smooth 2D data.  2D, FP64, PP_RECON_CWENO, unbatched
+ * (else PP_EUNSUPPORTED at init); 8 more doubles per cell of scratch. */
+enum { PP_FV_LINE = 0, PP_FV_GAUSS = 1 };
+
 typedef struct {
     int ndim;            /* 1, or 2 (dimension-by-dimension sweeps)                    */
     int64_t nx, ny;      /* cells (ny = 1 in 1D); nx <= 4096 in 1D, nx, ny <= 2048 in 2D */
@@ -122,9 +137,10 @@ typedef struct {
     const int *bcs;         /* host [nbatch][2] boundary codes (batched; non-periodic)  */
     void *stream;        /* hipStream_t to enqueue on (NULL: the null stream)           */
     int flux;            /* PP_FLUX_HLLC (default) or PP_FLUX_LF                        */
-    int recon;           /* PP_RECON_CWENO (default), PP_RECON_WENOJS or PP_RECON_WENOZ  */
+    int recon;           /* PP_RECON_CWENO (default), _WENOJS, _WENOZ or _CHAR           */
     int batch_rule;      /* time-step rule of the batched driver, per problem:
                             PP_DT_CFL (default), PP_DT_PP or PP_DT_RESTART              */
+    int fv;              /* 2D face fluxes: PP_FV_LINE (default) or PP_FV_GAUSS          */
 } pp_cweno_config;
 
 /* Fill *cfg with defaults: ndim 1, gamma 1.4, epsilons 1e-13, gl_w1 1/12, FP64,

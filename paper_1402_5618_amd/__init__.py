@@ -20,6 +20,7 @@ PP_FP64, PP_MIXED = 0, 1
 PP_DT_CFL, PP_DT_H53, PP_DT_PP, PP_DT_RESTART = 0, 1, 2, 3
 PP_FLUX_HLLC, PP_FLUX_LF = 0, 1
 PP_RECON_CWENO, PP_RECON_WENOJS, PP_RECON_WENOZ, PP_RECON_CHAR = 0, 1, 2, 3
+PP_FV_LINE, PP_FV_GAUSS = 0, 1
 
 EXPORTED = [
     "pp_cweno_config_defaults", "pp_cweno_init", "pp_cweno_rhs", "pp_cweno_stage",
@@ -48,6 +49,7 @@ class Config(ctypes.Structure):
         ("flux", ctypes.c_int),
         ("recon", ctypes.c_int),
         ("batch_rule", ctypes.c_int),
+        ("fv", ctypes.c_int),
     ]
 
 
@@ -152,7 +154,7 @@ class Solver:
     def __init__(self, ndim=1, nx=0, ny=1, dx=0.0, dy=0.0, gamma=1.4, bc=(0, 0, 0, 0),
                  precision=PP_FP64, weno_eps=1e-13, pp_eps_cap=1e-13, gl_w1=1.0 / 12.0,
                  lengths=None, dxs=None, bcs=None, stream=None, flux=None, recon=None,
-                 batch_rule=None):
+                 batch_rule=None, fv=None):
         c = default_config()
         c.ndim, c.nx, c.ny, c.dx, c.dy, c.gamma = ndim, nx, ny, dx, dy, gamma
         for i in range(4):
@@ -164,6 +166,8 @@ class Solver:
             c.recon = int(recon)
         if batch_rule is not None:
             c.batch_rule = int(batch_rule)
+        if fv is not None:
+            c.fv = int(fv)
         self._keep = []
         if lengths is not None:
             nb = len(lengths)

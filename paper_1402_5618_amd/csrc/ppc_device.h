@@ -512,6 +512,64 @@ __device__ __forceinline__ int pp_limit(double w1, double i12, double eps_rho, d
     return active;
 }
 
+// Limiter steps 2-4 over the node states of one cell of the Gauss-node 2D
+// operator: Nm[k] the three nodes of its right face (U-), Np[k] those of its
+// left face (U+), limited in place against the cell average Ub.  The middle
+// state is Ub = w1 sum_k g_k (Nm_k + Np_k) + (1 - 2 w1) mid, the Gauss-weighted
+// form of the 1D decomposition; i12 = 1 / (1 - 2 w1).  Returns 1 if anything
+// changed.
+template <int NC>
+__device__ __forceinline__ int pp_limit_nodes(double w1, double i12, const double (&g)[3],
+                                              double eps_rho, double eps_e,
+                                              const double (&Ub)[NC], double (&Nm)[3][NC],
+                                              double (&Np)[3][NC]) {
+    auto middle = [&](double (&mid)[NC]) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s += g[k] * (Nm[k][c] + Np[k][c]);
+            mid[c] = (Ub[c] - w1 * s) * i12;
+        }
+    };
+    int active = 0;
+    double mid[NC];
+    middle(mid);
+    double rmin = mid[0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rmin = fmin(rmin, fmin(Nm[k][0], Np[k][0]));
+    if (rmin < eps_rho) {
+        const double th1 = fmin((Ub[0] - eps_rho) / (Ub[0] - rmin), 1.0);
+        if (th1 < 1.0) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                Nm[k][0] = th1 * (Nm[k][0] - Ub[0]) + Ub[0];
+                Np[k][0] = th1 * (Np[k][0] - Ub[0]) + Ub[0];
+            }
+            active = 1;
+        }
+    }
+    middle(mid);
+    double th2 = 1.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (below_eps<NC>(eps_e, Nm[k])) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, Nm[k]));
+        if (below_eps<NC>(eps_e, Np[k])) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, Np[k]));
+    }
+    if (below_eps<NC>(eps_e, mid)) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, mid));
+    if (th2 < 1.0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                Nm[k][c] = th2 * (Nm[k][c] - Ub[c]) + Ub[c];
+                Np[k][c] = th2 * (Np[k][c] - Ub[c]) + Ub[c];
+            }
+        active = 1;
+    }
+    return active;
+}
+
 // |u_n| + a of a state, a pressure negative by roundoff counting as 0.
 template <int NC, int NRM>
 __device__ __forceinline__ double wave_speed(double g, const double (&U)[NC]) {

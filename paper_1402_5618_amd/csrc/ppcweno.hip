@@ -965,7 +965,10 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     // only: the 2D sweeps (NC = 4) write L (mode 0), and their kernels carry
     // none of that code
     constexpr bool kEpi = (NC == 3);
-    const int mode = kEpi ? A.mode : 0;
+    // mode 4 (2D, FP64 compact scheme): write the face values before the
+    // limiter for the Gauss-node operator, nothing else
+    constexpr bool kFaces = (NC == 4) && !MIXED && RECON == PP_RECON_CWENO;
+    const int mode = kEpi ? A.mode : ((kFaces && A.mode == 4) ? 4 : 0);
     const bool pprule = kEpi && A.dtrule == PP_DT_PP;
     double dt = 0.0;
     if (mode == 1) dt = batched ? A.dtline[b] : (A.dt_dev ? *A.dt_dev : A.dt_val);
@@ -1375,6 +1378,18 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
             }
         }
         __syncthreads();
+        if (kFaces && mode == 4) {
+            // face values of cells g0 .. g1-1: planes c (U- at the right face)
+            // and NC + c (U+ at the left face) of out
+            for (int q = tid; q < NC * S; q += NT) {
+                const int c = q / S, r = q - c * S;
+                const long long at = base + (long long)c * A.cs + g0 + r;
+                A.out[at] = sRes[(2 * c) * SS + padn<PSH>(r + 1)];
+                A.out[at + (long long)NC * A.cs] = sRes[(2 * c + 1) * SS + padn<PSH>(r + 1)];
+            }
+            __syncthreads();
+            continue;
+        }
         // limiter on slots 0..S+1 (cells g0-1 .. g1); a single segment reads its
         // edge neighbours from slots S and 1 instead (periodic) or not at all
         for (int q = tid + (SEG1 ? 1 : 0); q < S + (SEG1 ? 1 : 2); q += NT) {
@@ -1846,6 +1861,134 @@ __global__ void __launch_bounds__(1024) combine2d_kernel(
     }
 }
 
+// ----------------------------------------------------- Gauss-node 2D operator
+// Face fluxes averaged over each face by three-point Gauss-Legendre quadrature
+// (a multi-dimensional form the paper leaves to future work, Sec. 4).  The
+// line kernel in mode 4 writes every cell's two face values before the
+// limiter (averages over the cell's transverse extent, from the compact
+// reconstruction of Sec. 2.2); this kernel turns the face values of five
+// neighbouring lines into values at the face's Gauss nodes, limits a cell's
+// six node states as the steps of Sec. 2.4 do, and sums the node fluxes.
+
+// value at Gauss node k of a face = sum_m c[k][m] x (face value of line l-2+m);
+// g[k] the Gauss-Legendre weights
+struct GaussCoef {
+    double c[3][5];
+    double g[3];
+};
+
+constexpr int kGX = 62;   // cells per wave whose L is written (64 lanes, one halo cell each side)
+constexpr int kGY = 4;    // lines per workgroup (one wave each)
+
+// line index of the line j across the set of nl lines (ghost lines for j < 0
+// or j >= nl); sg = -1 where the transverse momentum is mirrored
+__device__ __forceinline__ int gauss_line(int j, int nl, int lo, int hi, double& sg) {
+    sg = 1.0;
+    if (j >= 0 && j < nl) return j;
+    if (lo == PP_BC_PERIODIC) return j < 0 ? j + nl : j - nl;   // |offset| <= 2, nl >= 5
+    if (j < 0) {
+        if (lo == PP_BC_TRANSMISSIVE) return 0;
+        sg = -1.0;
+        return min(-1 - j, nl - 1);
+    }
+    if (hi == PP_BC_TRANSMISSIVE) return nl - 1;
+    sg = -1.0;
+    return max(2 * nl - 1 - j, 0);
+}
+
+// One direction: U, L are [4][nl][n] (lines of n cells, plane stride cs) and
+// Wf is [8][nl][n] (planes 0-3: U- at each cell's right face, 4-7: U+ at its
+// left face).  A wave holds cells i0-1 .. i0+62 of one line: every lane forms
+// and limits its cell's nodes, takes the flux of its left face with the
+// right-face nodes of the lane before it, and writes L for cells i0 .. i0+61.
+template <int NRM>
+__global__ void __launch_bounds__(64 * kGY) gauss_dir_kernel(
+    const double* __restrict__ Wf, const double* __restrict__ U, double* __restrict__ L, int n,
+    int nl, long long cs, int bc_lo, int bc_hi, int tb_lo, int tb_hi, double h, double gamma,
+    double w1, double i12, int flux, double eps_cap, const long long* eps_enc, const Scal* scal,
+    GaussCoef G) {
+    constexpr int TN = 3 - NRM;   // transverse momentum component
+    if (scal && !scal->active) return;
+    const int lane = threadIdx.x & 63;
+    const int l = blockIdx.y * kGY + (threadIdx.x >> 6);
+    if (l >= nl) return;   // the whole wave
+    const bool cyclic = bc_lo == PP_BC_PERIODIC;
+    const int i = blockIdx.x * kGX - 1 + lane;   // -1 .. n + 62
+    int ci = i;
+    if (cyclic) ci = i < 0 ? i + n : (i >= n ? i - n : i);
+    const bool has = cyclic ? (i <= n) : (i >= 0 && i < n);   // lane forms nodes of cell ci
+    const double eps_rho = fmin(eps_cap, ord_dec(eps_enc[0]));
+    const double eps_e = fmin(eps_cap, ord_dec(eps_enc[1]));
+    double Nm[3][4], Np[3][4];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Nm[k][c] = Np[k][c] = (c == 0 || c == 3) ? 1.0 : 0.0;
+    if (has) {
+        long long row[5];
+        double sg[5];
+#pragma unroll
+        for (int m = 0; m < 5; ++m)
+            row[m] = (long long)gauss_line(l - 2 + m, nl, tb_lo, tb_hi, sg[m]) * n + ci;
+        double Ub[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            Ub[c] = U[c * cs + (long long)l * n + ci];
+            double vm[5], vp[5];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                const double s = (c == TN) ? sg[m] : 1.0;
+                vm[m] = s * Wf[c * cs + row[m]];
+                vp[m] = s * Wf[(4 + c) * cs + row[m]];
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double am = 0.0, ap = 0.0;
+#pragma unroll
+                for (int m = 0; m < 5; ++m) {
+                    am += G.c[k][m] * vm[m];
+                    ap += G.c[k][m] * vp[m];
+                }
+                Nm[k][c] = am;
+                Np[k][c] = ap;
+            }
+        }
+        pp_limit_nodes<4>(w1, i12, G.g, eps_rho, eps_e, Ub, Nm, Np);
+    }
+    // left face of this lane's cell: the lane before holds the cell to its left
+    double Fl[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double Ul[4], Ur[4], F[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            Ul[c] = __shfl_up(Nm[k][c], 1);
+            Ur[c] = Np[k][c];
+        }
+        if (!cyclic && i == 0) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                Ul[c] = (bc_lo == PP_BC_REFLECTIVE && c == NRM) ? -Ur[c] : Ur[c];
+        }
+        if (!cyclic && i == n) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                Ur[c] = (bc_hi == PP_BC_REFLECTIVE && c == NRM) ? -Ul[c] : Ul[c];
+        }
+        if (flux == PP_FLUX_LF) lf_flux<4, NRM>(gamma, Ul, Ur, F);
+        else hllc_flux<4, NRM>(gamma, Ul, Ur, F);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Fl[c] += G.g[k] * F[c];
+    }
+    double Fr[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Fr[c] = __shfl_down(Fl[c], 1);
+    if (lane >= 1 && lane <= kGX && i < n) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) L[c * cs + (long long)l * n + i] = -(Fr[c] - Fl[c]) / h;
+    }
+}
+
 // Min rho, min e and max wave speeds of a state [NC][ncell] (x-fastest 2D or 1D).
 template <int NC>
 __global__ void __launch_bounds__(256) reduce_state_kernel(const double* __restrict__ U,
@@ -2035,6 +2178,8 @@ struct pp_cweno_ctx {
     double *U1 = nullptr, *U2 = nullptr, *UA = nullptr;        // layout A stage buffers
     double *UB = nullptr, *U1B = nullptr, *U2B = nullptr;      // layout B copies (2D)
     double *Lx = nullptr, *LyB = nullptr;                      // 2D operator halves
+    double* Wf = nullptr;    // Gauss-node operator: face values [8][ncell] of one sweep
+    GaussCoef gcoef{};
     Scal* scal = nullptr;
     // batched
     std::vector<int64_t> lengths;
@@ -2381,18 +2526,35 @@ int launch_run1d(pp_cweno_ctx* ctx, double* U, int rule, double cfl, double t_en
     return mixed ? launch_run1d_p<3, 1, 2, 3, true>(ctx, R) : launch_run1d_p<3, 1, 2, 3, false>(ctx, R);
 }
 
+// Gauss-node sweep along one direction (lines of n cells, nl lines): face
+// values in ctx->Wf (written by the line kernel in mode 4) to L.
+template <int NRM>
+int launch_gauss(pp_cweno_ctx* ctx, const double* Us, double* L, int n, int nl, int bc_lo,
+                 int bc_hi, int tb_lo, int tb_hi, double h, const long long* eps_enc, bool run) {
+    if (!eps_enc) return fail(ctx, PP_EINVAL, "the Gauss-node operator needs the grid's epsilons");
+    const auto& c = ctx->cfg;
+    const dim3 grid((unsigned)((n + kGX - 1) / kGX), (unsigned)((nl + kGY - 1) / kGY));
+    hipLaunchKernelGGL(gauss_dir_kernel<NRM>, grid, dim3(64 * kGY), 0, ctx->stream, ctx->Wf, Us, L,
+                       n, nl, (long long)c.nx * c.ny, bc_lo, bc_hi, tb_lo, tb_hi, h, c.gamma,
+                       c.gl_w1, 1.0 / (1.0 - 2.0 * c.gl_w1), c.flux, c.pp_eps_cap, eps_enc,
+                       run ? ctx->scal : nullptr, ctx->gcoef);
+    HIPCHK(ctx, hipGetLastError());
+    return PP_OK;
+}
+
 // 2D sweeps of one stage input (Us in layout A and B) into Lx and LyB.
 int sweeps_2d(pp_cweno_ctx* ctx, const double* UsA, const double* UsB, const long long* eps_enc,
               bool run) {
     const auto& c = ctx->cfg;
+    const bool gauss = c.fv == PP_FV_GAUSS;
     LineArgs A = base_args(ctx);
-    A.mode = 0;
+    A.mode = gauss ? 4 : 0;
     A.eps_enc = eps_enc;
     A.scal = run ? ctx->scal : nullptr;
     A.cs = (long long)c.nx * c.ny;
     // x-lines: rows of the [4][ny][nx] state
     A.U = UsA;
-    A.out = ctx->Lx;
+    A.out = gauss ? ctx->Wf : ctx->Lx;
     A.ls = c.nx;
     A.n = (int)c.nx;
     A.nlines = (int)c.ny;
@@ -2401,11 +2563,14 @@ int sweeps_2d(pp_cweno_ctx* ctx, const double* UsA, const double* UsB, const lon
     A.h = c.dx;
     int slot = timed_begin(ctx, 0);
     int r = launch_line<4, 1, 1, 4>(ctx, A, A.n, false, 0);
+    if (!r && gauss)
+        r = launch_gauss<1>(ctx, UsA, ctx->Lx, (int)c.nx, (int)c.ny, c.bc[0], c.bc[1], c.bc[2],
+                            c.bc[3], c.dx, eps_enc, run);
     timed_end(ctx, 0, slot);
     if (r) return r;
     // y-lines: rows of the transposed [4][nx][ny] state
     A.U = UsB;
-    A.out = ctx->LyB;
+    A.out = gauss ? ctx->Wf : ctx->LyB;
     A.ls = c.ny;
     A.n = (int)c.ny;
     A.nlines = (int)c.nx;
@@ -2414,6 +2579,9 @@ int sweeps_2d(pp_cweno_ctx* ctx, const double* UsA, const double* UsB, const lon
     A.h = c.dy;
     slot = timed_begin(ctx, 1);
     r = launch_line<4, 2, 1, 4>(ctx, A, A.n, false, 0);
+    if (!r && gauss)
+        r = launch_gauss<2>(ctx, UsB, ctx->LyB, (int)c.ny, (int)c.nx, c.bc[2], c.bc[3], c.bc[0],
+                            c.bc[1], c.dy, eps_enc, run);
     timed_end(ctx, 1, slot);
     return r;
 }
@@ -2646,6 +2814,39 @@ int static_scratch(int dev, double** out) {
 
 // Host-side validation of a configuration (PP_OK or the failing code, with
 // the message in the init error slot); no device call.
+// Coefficients of the Gauss-node operator.  The quartic q whose averages
+// over five unit cells (cell m = [m - 2.5, m - 1.5], m = 0..4) are v_m is the
+// derivative of the quintic P through the cell edges x_e = e - 2.5 with
+// P(x_e) = v_0 + ... + v_{e-1}; so q(xi) = sum_m v_m sum_{e > m} l_e'(xi) with
+// l_e the Lagrange basis on the edges.  Nodes: the three Gauss-Legendre
+// points of the middle cell; weights 5/18, 8/18, 5/18.
+GaussCoef gauss_coef() {
+    GaussCoef G{};
+    const double xi[3] = {-std::sqrt(15.0) / 10.0, 0.0, std::sqrt(15.0) / 10.0};
+    double xe[6];
+    for (int e = 0; e < 6; ++e) xe[e] = e - 2.5;
+    for (int k = 0; k < 3; ++k) {
+        double dl[6];   // l_e'(xi_k)
+        for (int e = 0; e < 6; ++e) {
+            double le = 1.0, sum = 0.0;
+            for (int j = 0; j < 6; ++j) {
+                if (j == e) continue;
+                le *= (xi[k] - xe[j]) / (xe[e] - xe[j]);
+                sum += 1.0 / (xi[k] - xe[j]);
+            }
+            dl[e] = le * sum;
+        }
+        for (int m = 0; m < 5; ++m) {
+            double a = 0.0;
+            for (int e = m + 1; e < 6; ++e) a += dl[e];
+            G.c[k][m] = a;
+        }
+    }
+    G.g[0] = G.g[2] = 5.0 / 18.0;
+    G.g[1] = 8.0 / 18.0;
+    return G;
+}
+
 int check_config(const pp_cweno_config& c) {
     if (c.ndim != 1 && c.ndim != 2) return fail(nullptr, PP_EINVAL, "ndim must be 1 or 2");
     if (!(c.gamma > 1.0)) return fail(nullptr, PP_EINVAL, "gamma must be > 1");
@@ -2665,6 +2866,12 @@ int check_config(const pp_cweno_config& c) {
         return fail(nullptr, PP_EINVAL, "precision must be PP_FP64 or PP_MIXED");
     if (c.batch_rule != PP_DT_CFL && c.batch_rule != PP_DT_PP && c.batch_rule != PP_DT_RESTART)
         return fail(nullptr, PP_EINVAL, "batch_rule must be PP_DT_CFL, PP_DT_PP or PP_DT_RESTART");
+    if (c.fv != PP_FV_LINE && c.fv != PP_FV_GAUSS)
+        return fail(nullptr, PP_EINVAL, "fv must be PP_FV_LINE or PP_FV_GAUSS");
+    if (c.fv == PP_FV_GAUSS &&
+        (c.ndim != 2 || c.precision != PP_FP64 || c.recon != PP_RECON_CWENO || c.nbatch > 0))
+        return fail(nullptr, PP_EUNSUPPORTED,
+                    "the Gauss-node operator is 2D, FP64 and the compact reconstruction");
     const int naxes = c.ndim == 2 ? 2 : 1;
     for (int a = 0; a < naxes; ++a) {
         if (!bc_ok(c.bc[2 * a]) || !bc_ok(c.bc[2 * a + 1]))
@@ -2813,6 +3020,10 @@ int pp_cweno_init(const pp_cweno_config* cfg, pp_cweno_ctx** out) {
                 !dmalloc((void**)&ctx->U1B, bytes) || !dmalloc((void**)&ctx->U2B, bytes) ||
                 !dmalloc((void**)&ctx->Lx, bytes) || !dmalloc((void**)&ctx->LyB, bytes))
                 return bail(PP_ENOMEM);
+            if (c.fv == PP_FV_GAUSS) {
+                if (!dmalloc((void**)&ctx->Wf, 2 * bytes)) return bail(PP_ENOMEM);
+                ctx->gcoef = gauss_coef();
+            }
         }
     }
     if (reset_scal(ctx)) return bail(PP_EDEVICE);
@@ -3314,7 +3525,7 @@ void pp_cweno_destroy(pp_cweno_ctx* ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
     void* bufs[] = {ctx->U1, ctx->U2, ctx->UA, ctx->UB, ctx->U1B, ctx->U2B, ctx->Lx, ctx->LyB,
-                    ctx->scal, ctx->d_off, ctx->d_n, ctx->d_h, ctx->d_bc, ctx->d_dt, ctx->d_t,
+                    ctx->Wf, ctx->scal, ctx->d_off, ctx->d_n, ctx->d_h, ctx->d_bc, ctx->d_dt, ctx->d_t,
                     ctx->d_steps,
                     ctx->d_order, ctx->d_counter, ctx->d_dtcopy, ctx->d_tune, ctx->d_bad,
                     ctx->d_half, ctx->chs};

@@ -30,7 +30,7 @@ def test_config_defaults():
     c = pp.default_config()
     assert c.ndim == 1 and c.gamma == 1.4 and c.weno_eps == 1e-13 and c.pp_eps_cap == 1e-13
     assert abs(c.gl_w1 - 1.0 / 12.0) < 1e-16 and c.precision == pp.PP_FP64 and c.nbatch == 0
-    assert c.flux == pp.PP_FLUX_HLLC and c.recon == pp.PP_RECON_CWENO
+    assert c.flux == pp.PP_FLUX_HLLC and c.recon == pp.PP_RECON_CWENO and c.fv == pp.PP_FV_LINE
 
 
 def _init(**kw):
@@ -73,6 +73,10 @@ def _init(**kw):
     (dict(nbatch=2), pp.PP_EINVAL),              # batch arrays missing
     (dict(batch_rule=1), pp.PP_EINVAL),          # the h^(5/3) rule is not a batch rule
     (dict(batch_rule=4), pp.PP_EINVAL),
+    (dict(fv=2), pp.PP_EINVAL),
+    (dict(fv=1), pp.PP_EUNSUPPORTED),                                # Gauss nodes: 2D
+    (dict(fv=1, ndim=2, ny=64, dy=0.01, precision=1), pp.PP_EUNSUPPORTED),   # FP64
+    (dict(fv=1, ndim=2, ny=64, dy=0.01, recon=1), pp.PP_EUNSUPPORTED),       # compact scheme
 ])
 def test_invalid_configs_rejected_before_device(kw, code):
     got, msg = _init(**kw)
