@@ -19,6 +19,8 @@ Other workloads (one JSON line each, bounded runs):
                           N = 28..224; and the N = 4000 double rarefaction per step)
   --dt-rule cfl|pp|restart   time-step rule of ensemble / rarefaction1d / blast1d
   --recon cweno|char      reconstruction of wave1d / rarefaction1d / blast1d
+  --workload gauss2d      Gauss-node 2D operator against the line operator: error of L
+                          on a smooth nonlinear flow and cost per step, N = 128..2048
   --workload copy         plain device copy of a known size (counter calibration)
   --workload accuracy     wall time against L1 error, FP64 and mixed, N = 128..2048
 
@@ -54,10 +56,10 @@ FLOPS_PER_SWEEP_CELL = 716.0
 # hash is recorded (profiles/line_kernel_2d_density_wave_2048_fp64.md);
 # otherwise traffic is reported null.
 TRAFFIC_RECORD = {
-    "src_sha256": "ade9d42fbbeb3fcc1b5651f60dad0a31ce3d9a737880a6896e00d03d1839124c",
+    "src_sha256": "7862cce65839b4f4abfdcf1ed23bfdc5d4c15f0aa569d856a49c45983bf54c96",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "x": {"fetch_kib": 66724.2, "write_kib": 184320.0},
-    "y": {"fetch_kib": 67176.2, "write_kib": 184320.0},
+    "x": {"fetch_kib": 66252.1, "write_kib": 163840.0},
+    "y": {"fetch_kib": 66295.5, "write_kib": 163840.0},
 }
 
 
@@ -72,7 +74,7 @@ def parse():
                     help="oracle steps of the full grid for cpu_baseline (about 10 s on 16 threads)")
     ap.add_argument("--workload", default="density2d",
                     choices=["density2d", "sedov2d", "ensemble", "wave1d", "rarefaction1d",
-                             "blast1d", "copy", "accuracy", "char1d"])
+                             "blast1d", "copy", "accuracy", "char1d", "gauss2d"])
     ap.add_argument("--dt-rule", default="cfl", choices=["cfl", "pp", "restart"],
                     help="ensemble / rarefaction1d / blast1d: averages' CFL, interface-state "
                          "bound, or the averages' CFL with a step redone at half dt")
@@ -169,6 +171,54 @@ def other_workload(args):
                            "equal_accuracy": eq,
                            "compact_vs_wenojs": equal_accuracy("wenojs"),
                            "compact_vs_wenoz": equal_accuracy("wenoz")})
+    elif args.workload == "gauss2d":
+        # the Gauss-node operator against the line operator on a smooth,
+        # nonlinear 2D flow: the error of L against the exact cell average of
+        # -div(f, g), and the cost of an SSP-RK3 step (timed over --steps
+        # steps, per-sweep kernel times from HIP events), N = 128..2048
+        rows = []
+        for n in (128, 256, 512, 1024, 2048):
+            U0 = W.smooth_flow_2d(n, n, quad=4)
+            ex = W.smooth_flow_2d_divergence(n, n, quad=4)
+            for fv, name in ((pp.PP_FV_LINE, "line"), (pp.PP_FV_GAUSS, "gauss")):
+                s = pp.Solver(ndim=2, nx=n, ny=n, dx=1.0 / n, dy=1.0 / n, bc=(0, 0, 0, 0), fv=fv)
+                U = torch.tensor(U0, device="cuda")
+                L = torch.empty_like(U)
+                s.rhs(U, L)
+                torch.cuda.synchronize()
+                l1 = float(np.abs(L.cpu().numpy() - ex).mean())
+                s.run(U.clone(), 1e30, 2, 1.0 / 12.0)
+                torch.cuda.synchronize()
+                s.set_timing(True)
+                t0 = time.perf_counter()
+                _, k = s.run(U, 1e30, args.steps, 1.0 / 12.0)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                tm = s.get_timing()
+                s.set_timing(False)
+                s.close()
+                rows.append({"n": n, "operator": name, "l1_L": l1, "steps": k,
+                             "ms_per_step": 1e3 * wall / k, "cell_updates_per_s": n * n * k / wall,
+                             "kernel_ms_per_launch": {q: v[0] / max(v[1], 1) for q, v in tm.items()}})
+                print(f"gauss2d: n={n} {name} L1(L)={l1:.3e} {1e3 * wall / k:.3f} ms/step",
+                      file=sys.stderr, flush=True)
+        # cheapest line-operator grid whose L error is at least as small as
+        # each Gauss-node grid's, and the cost ratio of their steps
+        eq = []
+        for r in rows:
+            if r["operator"] != "gauss":
+                continue
+            c = [m for m in rows if m["operator"] == "line" and m["l1_L"] <= r["l1_L"]]
+            m = min(c, key=lambda m: m["ms_per_step"]) if c else None
+            eq.append({"n_gauss": r["n"], "l1_gauss": r["l1_L"], "n_line": m["n"] if m else None,
+                       "gauss_step_speedup": (m["ms_per_step"] / r["ms_per_step"]) if m else None})
+        g = [r for r in rows if r["operator"] == "gauss" and r["n"] == 2048][0]
+        out.update(metric="cell-updates/s, 2D Gauss-node operator (3 nodes per face), FP64, 2048^2",
+                   value=g["cell_updates_per_s"], steps=g["steps"], ms_per_step=g["ms_per_step"],
+                   config={"workload": "smooth nonlinear 2D flow, periodic [0,1]^2, CFL 1/12, "
+                                       f"{args.steps} steps per grid; N = 128..2048; Gauss-node "
+                                       "and line (dimension-by-dimension) operators, FP64",
+                           "table": rows, "equal_L_error": eq})
     elif args.workload == "sedov2d":
         n = 1024
         dx = 1.1 / n
