@@ -733,6 +733,33 @@ def test_1d_double_rarefaction_4000_run():
     s.close()
 
 
+def test_1d_double_rarefaction_4000_to_t_end():
+    """The same configuration to its end time t = 0.6 (17 281 steps) against
+    the oracle's run stored by tests/golden/make_rarefaction_0p6.py: equal
+    step counts and times, positivity, and per-component relative L1
+    differences within 1e4 times the oracle's own spread under 1e-15 input
+    perturbations (about 2e-13)."""
+    import os
+    pp = gpu()
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "rarefaction_4000_t0p6.npz"))
+    n = 4000
+    h = 2.0 / n
+    U0 = W.double_rarefaction_1d(n)
+    s = pp.Solver(ndim=1, nx=n, dx=h, bc=(1, 1, 0, 0))
+    Ud = dev(U0)
+    t, steps = s.run(Ud, 0.6, 1 << 40)
+    torch.cuda.synchronize()
+    got = Ud.cpu().numpy()
+    U = ref["U"]
+    assert steps == int(ref["steps"]) and abs(t - float(ref["t"])) <= 1e-14
+    d = np.array([np.abs(got[k] - U[k]).sum() / np.abs(U[k]).sum() for k in range(3)])
+    print(f"double rarefaction to t = 0.6: relative L1 differences {d}, oracle spread "
+          f"{ref['spread']}", flush=True)
+    assert np.all(d <= 1e4 * np.maximum(ref["spread"], 1e-16))
+    assert got[0].min() > 0 and W.pressure(got).min() > 0
+    s.close()
+
+
 # --------------------------------------------------------- mixed precision
 TOL_MIXED_STAGE = 1e-6   # per stage output, relative: float weights/rows/HLLC
 
