@@ -277,14 +277,14 @@ __device__ __forceinline__ void hllc_flux(double g, const double (&Ul)[NC], cons
         vr = Ur[TG] * irr;
     }
     const double El = Ul[IE], Er = Ur[IE];
-    const double pl = (g - 1.0) * (El - 0.5 * rl * (ul * ul + vl * vl));
-    const double pr = (g - 1.0) * (Er - 0.5 * rr * (ur * ur + vr * vr));
+    const double pl = (g - 1.0) * (El - 0.5 * rl * fma(ul, ul, vl * vl));
+    const double pr = (g - 1.0) * (Er - 0.5 * rr * fma(ur, ur, vr * vr));
     const double al = sqrt_nn(g * fmax(pl, 0.0) * irl), ar = sqrt_nn(g * fmax(pr, 0.0) * irr);
     const double Hl = (El + pl) * irl, Hr = (Er + pr) * irr;
     const double R = sqrt_nn(rr * irl);
     const double i1R = rcp_t(1.0 + R);
     const double ut = (ul + ur * R) * i1R, vt = (vl + vr * R) * i1R, Ht = (Hl + Hr * R) * i1R;
-    const double at = sqrt_nn(fmax((g - 1.0) * (Ht - 0.5 * (ut * ut + vt * vt)), 0.0));
+    const double at = sqrt_nn(fmax((g - 1.0) * (Ht - 0.5 * fma(ut, ut, vt * vt)), 0.0));
     const double SL = fmin(ul - al, ut - at);
     const double SR = fmax(ur + ar, ut + at);
     const double den = rr * (SR - ur) - rl * (SL - ul);
@@ -342,8 +342,8 @@ __device__ __forceinline__ void lf_flux(double g, const double (&Ul)[NC], const 
         vr = Ur[TG] * irr;
     }
     const double El = Ul[IE], Er = Ur[IE];
-    const double pl = (g - 1.0) * (El - 0.5 * rl * (ul * ul + vl * vl));
-    const double pr = (g - 1.0) * (Er - 0.5 * rr * (ur * ur + vr * vr));
+    const double pl = (g - 1.0) * (El - 0.5 * rl * fma(ul, ul, vl * vl));
+    const double pr = (g - 1.0) * (Er - 0.5 * rr * fma(ur, ur, vr * vr));
     const double al = sqrt_nn(g * fmax(pl, 0.0) * irl), ar = sqrt_nn(g * fmax(pr, 0.0) * irr);
     const double alpha = fmax(fabs(ul) + al, fabs(ur) + ar);
     double Fl[NC], Fr[NC];
@@ -432,41 +432,45 @@ __device__ __forceinline__ void hllc_flux_f32(double gd, const double (&Uld)[NC]
     for (int k = 0; k < NC; ++k) Fd[k] = (double)F[k];
 }
 
+// a . b over the momentum components, the normal one (NRM) first: a sweep
+// along y of a 2D state and a sweep along x of its mirror image (x and y and
+// the two momenta exchanged) then round identically, so the 2D operator keeps
+// a state's diagonal mirror symmetry exactly (the fluxes spell their sums of
+// squared velocities the same way).
+template <int NC, int NRM>
+__device__ __forceinline__ double mom_dot(const double (&a)[NC], const double (&b)[NC]) {
+    // the fused form is spelled out: left to the compiler, which product is
+    // fused may differ between the two instantiations
+    if constexpr (NC == 4) return fma(a[NRM], b[NRM], a[3 - NRM] * b[3 - NRM]);
+    else return a[1] * b[1];
+}
+
 // e = E/rho - |m|^2 / (2 rho^2), the specific internal energy of the set G.
-template <int NC>
+template <int NC, int NRM = 1>
 __device__ __forceinline__ double spec_e(const double (&U)[NC]) {
-    double m2 = 0.0;
-#pragma unroll
-    for (int k = 1; k < NC - 1; ++k) m2 += U[k] * U[k];
+    const double m2 = mom_dot<NC, NRM>(U, U);
     return U[NC - 1] / U[0] - 0.5 * m2 / (U[0] * U[0]);
 }
 
 // Limiter step 4 test "rho <= 0 or e(W) < eps" without divisions:
 // for rho > 0, e < eps  <=>  rho E - |m|^2/2 < eps rho^2.
-template <int NC>
+template <int NC, int NRM = 1>
 __device__ __forceinline__ bool below_eps(double eps, const double (&U)[NC]) {
-    double m2 = 0.0;
-#pragma unroll
-    for (int k = 1; k < NC - 1; ++k) m2 += U[k] * U[k];
+    const double m2 = mom_dot<NC, NRM>(U, U);
     return !(U[0] > 0.0) || (U[0] * U[NC - 1] - 0.5 * m2 < eps * U[0] * U[0]);
 }
 
 // Limiter step 4: root t in [0, 1] of e(Ubar + t (W - Ubar)) = eps via
 // rho E - |m|^2/2 - eps rho^2 = A t^2 + B t + C, t = 2C / (-B + sqrt(B^2 - 4AC)).
-template <int NC>
+template <int NC, int NRM = 1>
 __device__ __forceinline__ double pp_root(double eps, const double (&Ub)[NC],
                                           const double (&W)[NC]) {
     constexpr int IE = NC - 1;
     double D[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) D[k] = W[k] - Ub[k];
-    double dm2 = 0.0, mdm = 0.0, m2 = 0.0;
-#pragma unroll
-    for (int k = 1; k < IE; ++k) {
-        dm2 += D[k] * D[k];
-        mdm += Ub[k] * D[k];
-        m2 += Ub[k] * Ub[k];
-    }
+    const double dm2 = mom_dot<NC, NRM>(D, D), mdm = mom_dot<NC, NRM>(Ub, D);
+    const double m2 = mom_dot<NC, NRM>(Ub, Ub);
     const double A = D[0] * D[IE] - 0.5 * dm2 - eps * D[0] * D[0];
     const double B = Ub[0] * D[IE] + Ub[IE] * D[0] - mdm - 2.0 * eps * Ub[0] * D[0];
     const double C = Ub[0] * Ub[IE] - 0.5 * m2 - eps * Ub[0] * Ub[0];
@@ -479,7 +483,7 @@ __device__ __forceinline__ double pp_root(double eps, const double (&Ub)[NC],
 
 // Positivity-preserving limiter of one cell (Sec 2.4, steps 1-4): Um = U-_{j+1/2},
 // Up = U+_{j-1/2}, limited in place.  Returns 1 if anything changed.
-template <int NC>
+template <int NC, int NRM = 1>
 __device__ __forceinline__ int pp_limit(double w1, double i12, double eps_rho, double eps_e,
                                         const double (&Ub)[NC], double (&Um)[NC],
                                         double (&Up)[NC]) {
@@ -498,9 +502,9 @@ __device__ __forceinline__ int pp_limit(double w1, double i12, double eps_rho, d
 #pragma unroll
     for (int k = 0; k < NC; ++k) W3[k] = (Ub[k] - w1 * Up[k] - w1 * Um[k]) * i12;
     double th2 = 1.0;
-    if (below_eps<NC>(eps_e, Um)) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, Um));
-    if (below_eps<NC>(eps_e, Up)) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, Up));
-    if (below_eps<NC>(eps_e, W3)) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, W3));
+    if (below_eps<NC, NRM>(eps_e, Um)) th2 = fmin(th2, pp_root<NC, NRM>(eps_e, Ub, Um));
+    if (below_eps<NC, NRM>(eps_e, Up)) th2 = fmin(th2, pp_root<NC, NRM>(eps_e, Ub, Up));
+    if (below_eps<NC, NRM>(eps_e, W3)) th2 = fmin(th2, pp_root<NC, NRM>(eps_e, Ub, W3));
     if (th2 < 1.0) {
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
@@ -518,7 +522,7 @@ __device__ __forceinline__ int pp_limit(double w1, double i12, double eps_rho, d
 // state is Ub = w1 sum_k g_k (Nm_k + Np_k) + (1 - 2 w1) mid, the Gauss-weighted
 // form of the 1D decomposition; i12 = 1 / (1 - 2 w1).  Returns 1 if anything
 // changed.
-template <int NC>
+template <int NC, int NRM = 1>
 __device__ __forceinline__ int pp_limit_nodes(double w1, double i12, const double (&g)[3],
                                               double eps_rho, double eps_e,
                                               const double (&Ub)[NC], double (&Nm)[3][NC],
@@ -553,10 +557,10 @@ __device__ __forceinline__ int pp_limit_nodes(double w1, double i12, const doubl
     double th2 = 1.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        if (below_eps<NC>(eps_e, Nm[k])) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, Nm[k]));
-        if (below_eps<NC>(eps_e, Np[k])) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, Np[k]));
+        if (below_eps<NC, NRM>(eps_e, Nm[k])) th2 = fmin(th2, pp_root<NC, NRM>(eps_e, Ub, Nm[k]));
+        if (below_eps<NC, NRM>(eps_e, Np[k])) th2 = fmin(th2, pp_root<NC, NRM>(eps_e, Ub, Np[k]));
     }
-    if (below_eps<NC>(eps_e, mid)) th2 = fmin(th2, pp_root<NC>(eps_e, Ub, mid));
+    if (below_eps<NC, NRM>(eps_e, mid)) th2 = fmin(th2, pp_root<NC, NRM>(eps_e, Ub, mid));
     if (th2 < 1.0) {
 #pragma unroll
         for (int k = 0; k < 3; ++k)
@@ -573,9 +577,7 @@ __device__ __forceinline__ int pp_limit_nodes(double w1, double i12, const doubl
 // |u_n| + a of a state, a pressure negative by roundoff counting as 0.
 template <int NC, int NRM>
 __device__ __forceinline__ double wave_speed(double g, const double (&U)[NC]) {
-    double m2 = 0.0;
-#pragma unroll
-    for (int k = 1; k < NC - 1; ++k) m2 += U[k] * U[k];
+    const double m2 = mom_dot<NC, NRM>(U, U);
     const double ir = rcp_t(U[0]);
     const double p = (g - 1.0) * (U[NC - 1] - 0.5 * m2 * ir);
     return fabs(U[NRM] * ir) + sqrt_nn(g * fmax(p, 0.0) * ir);

@@ -1403,7 +1403,7 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
                 Um[c] = sRes[(2 * c) * SS + pq];
                 Up[c] = sRes[(2 * c + 1) * SS + pq];
             }
-            pp_limit<NC>(A.w1, A.i12, eps_rho, eps_e, Ub, Um, Up);
+            pp_limit<NC, NRM>(A.w1, A.i12, eps_rho, eps_e, Ub, Um, Up);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 sRes[(2 * c) * SS + pq] = Um[c];
@@ -1953,7 +1953,7 @@ __global__ void __launch_bounds__(64 * kGY) gauss_dir_kernel(
                 Np[k][c] = ap;
             }
         }
-        pp_limit_nodes<4>(w1, i12, G.g, eps_rho, eps_e, Ub, Nm, Np);
+        pp_limit_nodes<4, NRM>(w1, i12, G.g, eps_rho, eps_e, Ub, Nm, Np);
     }
     // left face of this lane's cell: the lane before holds the cell to its left
     double Fl[4] = {0.0, 0.0, 0.0, 0.0};
