@@ -9,6 +9,8 @@ combine) over the whole grid.  Prints one JSON line.
 Other workloads (one JSON line each, bounded runs):
   --workload sedov2d      quarter-plane near-vacuum blast, 1024^2, reflective
                           x=0 / y=0, transmissive far sides, mixed precision
+                          (--precision fp64, --fv gauss, --full to t = 1 with
+                          --checkpoint / --resume across runs)
   --workload ensemble     4096 seeded 1D Riemann problems, N in [256, 4096],
                           mixed precision, one persistent launch per stage,
                           hipGraph replay, per-problem dt
@@ -81,8 +83,14 @@ def parse():
     ap.add_argument("--recon", default="cweno", choices=["cweno", "char"],
                     help="wave1d / rarefaction1d / blast1d: component-wise or characteristic-wise")
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--fv", default="line", choices=["line", "gauss"],
+                    help="sedov2d: the 2D operator (one state pair per face, or Gauss nodes)")
     ap.add_argument("--full", action="store_true",
                     help="sedov2d / ensemble: run to the configuration's end time")
+    ap.add_argument("--checkpoint", default=None,
+                    help="sedov2d: write the state, t and step count to this .npz at the end")
+    ap.add_argument("--resume", default=None,
+                    help="sedov2d: continue from a --checkpoint file")
     ap.add_argument("--max-wall", type=float, default=240.0,
                     help="--full runs stop after this many seconds (sedov2d: the near-vacuum "
                          "centre makes t = 1 take ~1e7 steps; the full ensemble takes ~260 s)")
@@ -222,13 +230,22 @@ def other_workload(args):
     elif args.workload == "sedov2d":
         n = 1024
         dx = 1.1 / n
-        U = torch.tensor(W.sedov_corner_2d(n), device="cuda")
-        s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=(2, 1, 2, 1), precision=prec)
+        t_done, steps, flags, min_rho, min_p = 0.0, 0, 0, math.inf, math.inf
+        steps_before, wall_before = 0, 0.0
+        if args.resume:
+            ck = np.load(args.resume)
+            U = torch.tensor(ck["U"], device="cuda")
+            t_done, steps_before = float(ck["t"]), int(ck["steps"])
+            min_rho, min_p, wall_before = float(ck["min_rho"]), float(ck["min_p"]), float(ck["wall"])
+        else:
+            U = torch.tensor(W.sedov_corner_2d(n), device="cuda")
+        fv_id = pp.PP_FV_GAUSS if args.fv == "gauss" else pp.PP_FV_LINE
+        s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=(2, 1, 2, 1), precision=prec, fv=fv_id)
         torch.cuda.synchronize()
         # --full: to t = 1 in chunks of --steps steps (the state advances in
         # place; each chunk restarts the clock at the chunk's start), with the
-        # minima checked after every chunk; otherwise one chunk
-        t_done, steps, flags, min_rho, min_p = 0.0, 0, 0, math.inf, math.inf
+        # status word and the minima checked after every chunk; otherwise one
+        # chunk
         t0 = time.perf_counter()
         while True:
             try:
@@ -242,7 +259,7 @@ def other_workload(args):
             min_rho = min(min_rho, float(Uh[0].min()))
             min_p = min(min_p, float(W.pressure(Uh).min()))
             if args.full:
-                print(f"sedov2d: {steps} steps, t = {t_done:.4f}, min rho {min_rho:.3e}, "
+                print(f"sedov2d: {steps_before + steps} steps, t = {t_done:.4f}, min rho {min_rho:.3e}, "
                       f"min p {min_p:.3e}, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
                       flush=True)
             if not args.full or t_done >= 1.0 - 1e-12 or k == 0 or \
@@ -251,11 +268,15 @@ def other_workload(args):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         Uh = U.cpu().numpy()
+        if args.checkpoint:
+            np.savez(args.checkpoint, U=Uh, t=t_done, steps=steps_before + steps, min_rho=min_rho,
+                     min_p=min_p, wall=wall_before + wall)
         out.update(metric="cell-updates/s, 2D Sedov-type blast 1024^2",
                    value=n * n * steps / wall if steps else None,
                    steps=steps, ms_per_step=1e3 * wall / steps if steps else None,
                    config={"workload": f"quarter-plane blast 1024^2 on [0,1.1]^2, {prec_name}, "
-                                       f"{steps} steps (t = {t_done:.4e} of 1.0)",
+                                       f"{args.fv} operator, {steps} steps (t = {t_done:.4e} of 1.0)",
+                           "steps_total": steps_before + steps, "wall_total_s": wall_before + wall,
                            "min_rho_over_run": min_rho, "min_p_over_run": min_p,
                            "final_min_rho": float(Uh[0].min()),
                            "final_min_p": float(W.pressure(Uh).min()), "status": flags,
