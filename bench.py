@@ -58,10 +58,10 @@ FLOPS_PER_SWEEP_CELL = 716.0
 # hash is recorded (profiles/line_kernel_2d_density_wave_2048_fp64.md);
 # otherwise traffic is reported null.
 TRAFFIC_RECORD = {
-    "src_sha256": "7862cce65839b4f4abfdcf1ed23bfdc5d4c15f0aa569d856a49c45983bf54c96",
+    "src_sha256": "bbceac5659a5c7442b15ee98e66d3d79eeb4e950e5ee283e0cfadce0bf3796f9",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "x": {"fetch_kib": 66252.1, "write_kib": 163840.0},
-    "y": {"fetch_kib": 66295.5, "write_kib": 163840.0},
+    "x": {"fetch_kib": 66150.6, "write_kib": 163840.0},
+    "y": {"fetch_kib": 66254.6, "write_kib": 163840.0},
 }
 
 
