@@ -58,10 +58,10 @@ FLOPS_PER_SWEEP_CELL = 716.0
 # hash is recorded (profiles/line_kernel_2d_density_wave_2048_fp64.md);
 # otherwise traffic is reported null.
 TRAFFIC_RECORD = {
-    "src_sha256": "bbceac5659a5c7442b15ee98e66d3d79eeb4e950e5ee283e0cfadce0bf3796f9",
+    "src_sha256": "37e97b362b5c5e4b9652c57bd37e167861c1bb988a82dab6d61c5ce43f1db122",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "x": {"fetch_kib": 66150.6, "write_kib": 163840.0},
-    "y": {"fetch_kib": 66254.6, "write_kib": 163840.0},
+    "x": {"fetch_kib": 66166.7, "write_kib": 163840.0},
+    "y": {"fetch_kib": 66272.9, "write_kib": 163840.0},
 }
 
 

@@ -442,7 +442,8 @@ __device__ __forceinline__ double mom_dot(const double (&a)[NC], const double (&
     // the fused form is spelled out: left to the compiler, which product is
     // fused may differ between the two instantiations
     if constexpr (NC == 4) return fma(a[NRM], b[NRM], a[3 - NRM] * b[3 - NRM]);
-    else return a[1] * b[1];
+    else return fma(a[1], b[1], 0.0);   // one momentum: rounded once, and not
+                                        // fused into the caller's next operation
 }
 
 // e = E/rho - |m|^2 / (2 rho^2), the specific internal energy of the set G.

@@ -150,15 +150,25 @@ def test_blast_restart_rule_step_parity():
 def test_blast_interface_state_rule_run():
     """The same blast under PP_DT_PP for 300 steps (about t = 1.1e-5; the
     rule's dt then collapses, since the density-limited interface states at
-    the evacuated centre keep their pressure and reach |u|+a ~ 1e8): equal
-    times and states within 1e-9 of the oracle's, in G, and status bit 2 set
-    as the oracle counts stages whose input breaks (CFL-CD) under the step's
-    dt."""
+    the evacuated centre keep their pressure and reach |u|+a ~ 1e8): in G,
+    status bit 2 set as the oracle counts stages whose input breaks (CFL-CD)
+    under the step's dt, and the time reached and the state within 4x the
+    oracle's own change under 1e-15 input perturbations (at least 1e-9): the
+    dt is set by |u|+a of interface states whose pressure is a
+    roundoff-sized difference, so the oracle's own runs from last-bit
+    perturbed data differ by up to ~1e-9 after 300 steps."""
     pp = gpu()
     n, h = 4000, 2.0 / 4000
     U0 = W.vacuum_blast_1d(n)
     ref, info = oracle.run_1d(U0, (1, 1), h, 1e-3, rule=oracle.DT_PP, max_steps=300)
     assert info["steps"] == 300 and info["viol"] > 0 and in_G(ref)
+    rng = np.random.default_rng(1402)
+    d_alt = t_alt = 0.0
+    for _ in range(3):
+        alt, ialt = oracle.run_1d(U0 * (1.0 + 1e-15 * rng.standard_normal(U0.shape)), (1, 1), h,
+                                  1e-3, rule=oracle.DT_PP, max_steps=300)
+        d_alt = max(d_alt, rel_l1(alt, ref))
+        t_alt = max(t_alt, abs(ialt["t"] / info["t"] - 1))
     s = pp.Solver(ndim=1, nx=n, dx=h, bc=(1, 1, 0, 0))
     Ud = dev(U0)
     t, steps = s.run(Ud, 1e-3, 300, 1.0 / 12.0, pp.PP_DT_PP)
@@ -166,14 +176,12 @@ def test_blast_interface_state_rule_run():
     got = Ud.cpu().numpy()
     d = rel_l1(got, ref)
     print(f"blast, interface-state rule: t {t:.6e} / {info['t']:.6e}, flags {flags}, "
-          f"relative L1 difference {d:.3e}", flush=True)
-    # dt is set by |u|+a of interface states whose pressure is a
-    # roundoff-sized difference (density limited onto eps), so the time
-    # reached carries that conditioning: 1.4e-10 relative after 300 steps
-    assert steps == 300 and abs(t / info["t"] - 1) <= 1e-9
+          f"relative L1 difference {d:.3e} (perturbed oracle: {d_alt:.3e}, time {t_alt:.3e})",
+          flush=True)
+    assert steps == 300 and abs(t / info["t"] - 1) <= max(1e-9, 4 * t_alt)
     assert code == pp.PP_OK and flags == 4
     assert in_G(got)
-    assert d <= 1e-9
+    assert d <= max(1e-9, 4 * d_alt)
     s.close()
 
 
