@@ -600,10 +600,12 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            # what the counters show for this kernel: VALUBusy ~46 %, one
-            # workgroup (2 waves per SIMD) per CU, so issue latency rather
-            # than VALU throughput limits it
-            "counters": "VALU issue latency: VALUBusy ~46 %, one workgroup per CU",
+            # what the counters show for this kernel: VALUBusy ~48 %, one
+            # workgroup (2 waves per SIMD) per CU, 5.81e7 VALU wave
+            # instructions per launch (a 95 us issue floor), so issue latency
+            # rather than VALU throughput or HBM limits it
+            "counters": "VALU issue latency: VALUBusy ~48 %, one workgroup per CU, "
+                        "issue floor 95 us per launch",
             "kernel": {"x": "line_kernel x-lines", "y": "line_kernel y-lines"}[dom],
             "achieved": achieved_tflops,
             "peak": FP64_PEAK_TFLOPS,
