@@ -278,3 +278,30 @@ def test_batched_rules_on_the_problems_that_leave_G(rule, nsteps):
         # carries that conditioning into the time step: 4.6e-9 after 150
         # steps on problem 1162
         assert worst <= 1e-8
+
+
+def test_restart_rule_stops_a_stalled_problem():
+    """Ensemble problem 3354 (N = 3495; left state rho 9.43, right 0.0169,
+    moving apart) under PP_DT_RESTART, as a single line: near t = 1.49e-3
+    every step needs 50-60 halvings and the accepted dt stops moving t in
+    FP64.  The run must end by itself with PP_ESTATE (the stall test) rather
+    than redo steps that advance nothing; a run without the test redid 1.7 M
+    steps in 700 s at that t."""
+    pp = gpu()
+    ens = W.riemann_ensemble()
+    i = 3354
+    sl = slice(ens.offsets[i], ens.offsets[i + 1])
+    n, h = int(ens.lengths[i]), float(ens.dx[i])
+    s = pp.Solver(ndim=1, nx=n, dx=h, bc=(1, 1, 0, 0))
+    Ud = dev(ens.U[:, sl])
+    with pytest.raises(pp.PPError) as e:
+        # (the batched run of the same problem stalled at step 33 177; the
+        # cap keeps a run that did not stall from taking long)
+        s.run(Ud, ens.t_end, 36000, 1.0 / 12.0, pp.PP_DT_RESTART)
+    restarts = s.restarts()
+    got = Ud.cpu().numpy()
+    print(f"problem {i}: {e.value}; restarts {restarts}", flush=True)
+    assert e.value.code == pp.PP_ESTATE
+    assert restarts > 0
+    assert np.all(np.isfinite(got)) and got[0].min() > 0 and W.pressure(got).min() > 0
+    s.close()
