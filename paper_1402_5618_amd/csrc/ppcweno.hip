@@ -64,6 +64,8 @@ struct Scal {
     unsigned status;
     unsigned stepbad;      // restart rule: status bits of the step being tried
     long long restarts;    // restart rule: steps redone with half the dt
+    long long spdif[2];    // 2D interface-state rule: encoded max |u|+a, |v|+a over the
+                           // averages and limited interface states of a stage input
 };
 
 // Steps redone with half the dt before a run gives up (restart rule).
@@ -101,6 +103,8 @@ struct LineArgs {
     double* dbg_um;
     double* dbg_up;
     double* dbg_flux;
+    long long* spd_if;      // 2D sweeps under the interface-state rule: encoded max of
+                            // |u_n|+a over the averages and limited interface states
     int dtrule;             // PP_DT_*: PP_DT_PP reduces |u|+a over the limited interface
                             // states; PP_DT_RESTART commits stage 3 only if the step stayed in G
     unsigned* badline;      // batched, restart rule: status bits of each problem's step
@@ -940,8 +944,10 @@ __device__ __forceinline__ void rows_from_w(float w0, float w2, float& a, float&
 // RECON: the reconstruction, PP_RECON_CWENO (the compact scheme) or one of the
 // explicit comparison schemes (FP64 only; phase 1 then evaluates every face
 // value from its own five averages and solves nothing).
+// IFS (2D sweeps, FP64): reduce |u_n|+a over the averages and the limited
+// interface states of the line into A.spd_if (the 2D interface-state rule).
 template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED, bool LOOPED = false,
-          int RECON = PP_RECON_CWENO>
+          int RECON = PP_RECON_CWENO, bool IFS = false>
 __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) {
     static_assert(RECON == PP_RECON_CWENO || !MIXED, "explicit schemes run in FP64");
     constexpr int NS = 2 * NC;
@@ -969,7 +975,7 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     // limiter for the Gauss-node operator, nothing else
     constexpr bool kFaces = (NC == 4) && !MIXED && RECON == PP_RECON_CWENO;
     const int mode = kEpi ? A.mode : ((kFaces && A.mode == 4) ? 4 : 0);
-    const bool pprule = kEpi && A.dtrule == PP_DT_PP;
+    const bool pprule = (kEpi && A.dtrule == PP_DT_PP) || (NC == 4 && IFS);
     double dt = 0.0;
     if (mode == 1) dt = batched ? A.dtline[b] : (A.dt_dev ? *A.dt_dev : A.dt_val);
     // mode 2 (stage 1 under the interface-state rule): dtline holds the time
@@ -1514,6 +1520,10 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
         }
         __syncthreads();
     }
+    if constexpr (NC == 4 && IFS) {
+        const double S = block_max<NT>(smax_if, red);
+        if (tid == 0) atomicMax(A.spd_if, ord_enc(S));
+    }
     if (mode == 2) {
         // stage 1 under the interface-state rule: the step's dt from the
         // sup-norm over this stage input, then U1 = U + dt L over the L just
@@ -1641,11 +1651,12 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     }
 }
 
-template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED, int RECON = PP_RECON_CWENO>
+template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED, int RECON = PP_RECON_CWENO,
+          bool IFS = false>
 __global__ void __launch_bounds__(2 * NC * 64 * W) line_kernel(LineArgs A) {
     extern __shared__ double smem[];
     if (A.scal && !A.scal->active) return;
-    line_op<NC, NRM, W, CPT, SEG1, MIXED, false, RECON>(A, blockIdx.x, smem);
+    line_op<NC, NRM, W, CPT, SEG1, MIXED, false, RECON, IFS>(A, blockIdx.x, smem);
 }
 
 // Batched ensemble: one persistent launch per stage; workgroups pop problem
@@ -1906,7 +1917,7 @@ __global__ void __launch_bounds__(64 * kGY) gauss_dir_kernel(
     const double* __restrict__ Wf, const double* __restrict__ U, double* __restrict__ L, int n,
     int nl, long long cs, int bc_lo, int bc_hi, int tb_lo, int tb_hi, double h, double gamma,
     double w1, double i12, int flux, double eps_cap, const long long* eps_enc, const Scal* scal,
-    GaussCoef G) {
+    GaussCoef G, long long* spd_if) {
     constexpr int TN = 3 - NRM;   // transverse momentum component
     if (scal && !scal->active) return;
     const int lane = threadIdx.x & 63;
@@ -1920,6 +1931,7 @@ __global__ void __launch_bounds__(64 * kGY) gauss_dir_kernel(
     const double eps_rho = fmin(eps_cap, ord_dec(eps_enc[0]));
     const double eps_e = fmin(eps_cap, ord_dec(eps_enc[1]));
     double Nm[3][4], Np[3][4];
+    double sif = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -1954,6 +1966,20 @@ __global__ void __launch_bounds__(64 * kGY) gauss_dir_kernel(
             }
         }
         pp_limit_nodes<4, NRM>(w1, i12, G.g, eps_rho, eps_e, Ub, Nm, Np);
+        if (spd_if) {
+            // interface-state rule: |u_n|+a over the average and the six
+            // limited node states of the cell
+            double sp = wave_speed<4, NRM>(gamma, Ub);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                sp = fmax(sp, fmax(wave_speed<4, NRM>(gamma, Nm[k]), wave_speed<4, NRM>(gamma, Np[k])));
+            sif = isfinite(sp) ? sp : INFINITY;
+        }
+    }
+    if (spd_if) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sif = fmax(sif, __shfl_xor(sif, o));
+        if (lane == 0) atomicMax(spd_if, ord_enc(sif));
     }
     // left face of this lane's cell: the lane before holds the cell to its left
     double Fl[4] = {0.0, 0.0, 0.0, 0.0};
@@ -2043,6 +2069,7 @@ __global__ void init_scal_kernel(Scal* s) {
     s->status = 0u;
     s->stepbad = 0u;
     s->restarts = 0;
+    s->spdif[0] = s->spdif[1] = kEncZero;
 }
 
 // Start of a step: advance t by the previous dt, pick the new dt from the
@@ -2079,6 +2106,32 @@ __device__ __forceinline__ void dt_update(Scal* s, int ndim, int rule, double cf
 __global__ void dt_kernel(Scal* s, int ndim, int rule, double cfl, double dx, double dy,
                           double t_end, long long steps_max) {
     dt_update(s, ndim, rule, cfl, dx, dy, t_end, steps_max);
+}
+
+// 2D interface-state rule, after the sweeps of stage `stage` (the speeds in
+// spdif, which are cleared here for the next stage): stage 1 picks the
+// step's dt = cfl / (Sx/dx + Sy/dy), clipped to t_end; stages 2 and 3 set
+// status bit 2 when dt (Sx/dx + Sy/dy) > w1 (condition (CFL-CD) broken by
+// that stage's input).  A dt that is not usable retires the run.
+__global__ void dt_pp2d_kernel(Scal* s, int stage, double cfl, double dx, double dy,
+                               double t_end, double w1) {
+    if (!s->active) return;
+    const double sx = ord_dec(s->spdif[0]), sy = ord_dec(s->spdif[1]);
+    s->spdif[0] = s->spdif[1] = kEncZero;
+    const double rate = sx / dx + sy / dy;
+    if (stage == 1) {
+        double dt = cfl / rate;
+        if (!(dt > 0.0) || !isfinite(dt)) {
+            s->status |= 1u;
+            s->active = 0;
+            s->dt = 0.0;
+            return;
+        }
+        if (s->t + dt > t_end) dt = t_end - s->t;
+        s->dt = dt;
+    } else if (s->dt * rate > w1) {
+        s->status |= 4u;
+    }
 }
 
 // Whole 1D run of a single line in one workgroup: up to max_steps SSP-RK3
@@ -2179,6 +2232,8 @@ struct pp_cweno_ctx {
     double *UB = nullptr, *U1B = nullptr, *U2B = nullptr;      // layout B copies (2D)
     double *Lx = nullptr, *LyB = nullptr;                      // 2D operator halves
     double* Wf = nullptr;    // Gauss-node operator: face values [8][ncell] of one sweep
+    int rule2d = PP_DT_CFL;  // 2D run in progress: its time-step rule, cfl and t_end
+    double run_cfl = 0.0, run_t_end = 0.0;
     GaussCoef gcoef{};
     Scal* scal = nullptr;
     // batched
@@ -2357,6 +2412,14 @@ int launch_line_p(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int 
                              : (const void*)line_kernel_persistent<NC, NRM, W, CPT, false, MIXED>;
         else
             return fail(ctx, PP_EUNSUPPORTED, "persistent launches serve 1D ensembles only");
+    } else if (A.spd_if) {
+        // 2D sweeps under the interface-state rule (FP64)
+        if constexpr (NC == 4 && !MIXED)
+            fn = seg >= nmax
+                     ? (const void*)line_kernel<NC, NRM, W, CPT, true, false, PP_RECON_CWENO, true>
+                     : (const void*)line_kernel<NC, NRM, W, CPT, false, false, PP_RECON_CWENO, true>;
+        else
+            return fail(ctx, PP_EUNSUPPORTED, "the 2D interface-state rule runs in FP64");
     } else
         fn = seg >= nmax ? (const void*)line_kernel<NC, NRM, W, CPT, true, MIXED>
                          : (const void*)line_kernel<NC, NRM, W, CPT, false, MIXED>;
@@ -2530,25 +2593,30 @@ int launch_run1d(pp_cweno_ctx* ctx, double* U, int rule, double cfl, double t_en
 // values in ctx->Wf (written by the line kernel in mode 4) to L.
 template <int NRM>
 int launch_gauss(pp_cweno_ctx* ctx, const double* Us, double* L, int n, int nl, int bc_lo,
-                 int bc_hi, int tb_lo, int tb_hi, double h, const long long* eps_enc, bool run) {
+                 int bc_hi, int tb_lo, int tb_hi, double h, const long long* eps_enc, bool run,
+                 long long* spd_if) {
     if (!eps_enc) return fail(ctx, PP_EINVAL, "the Gauss-node operator needs the grid's epsilons");
     const auto& c = ctx->cfg;
     const dim3 grid((unsigned)((n + kGX - 1) / kGX), (unsigned)((nl + kGY - 1) / kGY));
     hipLaunchKernelGGL(gauss_dir_kernel<NRM>, grid, dim3(64 * kGY), 0, ctx->stream, ctx->Wf, Us, L,
                        n, nl, (long long)c.nx * c.ny, bc_lo, bc_hi, tb_lo, tb_hi, h, c.gamma,
                        c.gl_w1, 1.0 / (1.0 - 2.0 * c.gl_w1), c.flux, c.pp_eps_cap, eps_enc,
-                       run ? ctx->scal : nullptr, ctx->gcoef);
+                       run ? ctx->scal : nullptr, ctx->gcoef, spd_if);
     HIPCHK(ctx, hipGetLastError());
     return PP_OK;
 }
 
 // 2D sweeps of one stage input (Us in layout A and B) into Lx and LyB.
+// spd_if (may be NULL): [2] accumulators of the interface-state rule, x and y.
 int sweeps_2d(pp_cweno_ctx* ctx, const double* UsA, const double* UsB, const long long* eps_enc,
-              bool run) {
+              bool run, long long* spd_if = nullptr) {
     const auto& c = ctx->cfg;
     const bool gauss = c.fv == PP_FV_GAUSS;
     LineArgs A = base_args(ctx);
     A.mode = gauss ? 4 : 0;
+    // the line kernel reduces the interface speeds itself; under the
+    // Gauss-node operator the node kernel does
+    A.spd_if = (spd_if && !gauss) ? spd_if : nullptr;
     A.eps_enc = eps_enc;
     A.scal = run ? ctx->scal : nullptr;
     A.cs = (long long)c.nx * c.ny;
@@ -2565,7 +2633,7 @@ int sweeps_2d(pp_cweno_ctx* ctx, const double* UsA, const double* UsB, const lon
     int r = launch_line<4, 1, 1, 4>(ctx, A, A.n, false, 0);
     if (!r && gauss)
         r = launch_gauss<1>(ctx, UsA, ctx->Lx, (int)c.nx, (int)c.ny, c.bc[0], c.bc[1], c.bc[2],
-                            c.bc[3], c.dx, eps_enc, run);
+                            c.bc[3], c.dx, eps_enc, run, spd_if);
     timed_end(ctx, 0, slot);
     if (r) return r;
     // y-lines: rows of the transposed [4][nx][ny] state
@@ -2577,11 +2645,12 @@ int sweeps_2d(pp_cweno_ctx* ctx, const double* UsA, const double* UsB, const lon
     A.bc_lo = c.bc[2];
     A.bc_hi = c.bc[3];
     A.h = c.dy;
+    if (A.spd_if) A.spd_if = spd_if + 1;
     slot = timed_begin(ctx, 1);
     r = launch_line<4, 2, 1, 4>(ctx, A, A.n, false, 0);
     if (!r && gauss)
         r = launch_gauss<2>(ctx, UsB, ctx->LyB, (int)c.ny, (int)c.nx, c.bc[2], c.bc[3], c.bc[0],
-                            c.bc[1], c.dy, eps_enc, run);
+                            c.bc[1], c.dy, eps_enc, run, spd_if ? spd_if + 1 : nullptr);
     timed_end(ctx, 1, slot);
     return r;
 }
@@ -2658,8 +2727,14 @@ int step_single(pp_cweno_ctx* ctx, double* U, const double* dt_dev, double dt_va
     for (int st = 1; st <= 3; ++st) {
         const int in_slot = (st + 1) % 3;
         const int out_slot = st - 1;
-        r = sweeps_2d(ctx, inA[st - 1], inB[st - 1], s->eps[in_slot], run);
+        const bool ifs = run && ctx->rule2d == PP_DT_PP;
+        r = sweeps_2d(ctx, inA[st - 1], inB[st - 1], s->eps[in_slot], run, ifs ? s->spdif : nullptr);
         if (r) return r;
+        if (ifs) {
+            hipLaunchKernelGGL(dt_pp2d_kernel, dim3(1), dim3(1), 0, ctx->stream, s, st,
+                               ctx->run_cfl, c.dx, c.dy, ctx->run_t_end, c.gl_w1);
+            HIPCHK(ctx, hipGetLastError());
+        }
         r = combine_2d(ctx, inA[st - 1], U, outA[st - 1], outB[st - 1], 1, kRK[st][0], kRK[st][1],
                        dt_dev, dt_val, s->eps[out_slot], st == 3 ? s->spd : nullptr,
                        st == 1 ? s->eps[2] : nullptr, run);
@@ -3135,10 +3210,12 @@ int pp_cweno_run(pp_cweno_ctx* ctx, double* U, double t_end, int64_t nsteps_max,
         return fail(ctx, PP_EINVAL, "unknown dt rule");
     if (rule == PP_DT_H53 && ctx->cfg.ndim != 1) return fail(ctx, PP_EINVAL, "h^(5/3) rule is 1D");
     if (ctx->cfg.nbatch > 0) return fail(ctx, PP_EINVAL, "use pp_cweno_batch_run for ensembles");
-    if ((rule == PP_DT_PP || rule == PP_DT_RESTART) &&
-        (ctx->cfg.ndim != 1 || ctx->cfg.recon != PP_RECON_CWENO))
-        return fail(ctx, PP_EUNSUPPORTED,
-                    "the interface-state and restart rules run the 1D compact scheme only");
+    if ((rule == PP_DT_PP || rule == PP_DT_RESTART) && ctx->cfg.recon != PP_RECON_CWENO)
+        return fail(ctx, PP_EUNSUPPORTED, "the interface-state and restart rules run the compact scheme");
+    if (rule == PP_DT_RESTART && ctx->cfg.ndim != 1)
+        return fail(ctx, PP_EUNSUPPORTED, "the restart rule runs in 1D");
+    if (rule == PP_DT_PP && ctx->cfg.ndim == 2 && ctx->cfg.precision != PP_FP64)
+        return fail(ctx, PP_EUNSUPPORTED, "the 2D interface-state rule runs in FP64");
     const auto& c = ctx->cfg;
     Scal* s = ctx->scal;
     int r = reset_scal(ctx);
@@ -3166,6 +3243,16 @@ int pp_cweno_run(pp_cweno_ctx* ctx, double* U, double t_end, int64_t nsteps_max,
     // are launched in batches; the dt kernel
     // retires the run at t_end or after nsteps_max steps (later launches
     // return at once), and each batch ends with a host check of the scalars.
+    // Under the 2D interface-state rule each stage's sweeps also reduce the
+    // interface speeds and a small kernel picks (stage 1) or checks (stages
+    // 2 and 3) the dt before the stage's combine.
+    struct RunRule {
+        pp_cweno_ctx* ctx;
+        ~RunRule() { ctx->rule2d = PP_DT_CFL; }
+    } run_rule{ctx};
+    ctx->rule2d = rule;
+    ctx->run_cfl = cfl;
+    ctx->run_t_end = t_end;
     int64_t launched = 0;
     for (;;) {
         const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(64, nsteps_max - launched + 1));

@@ -305,3 +305,91 @@ def test_restart_rule_stops_a_stalled_problem():
     assert restarts > 0
     assert np.all(np.isfinite(got)) and got[0].min() > 0 and W.pressure(got).min() > 0
     s.close()
+
+
+def _mixed_2d(nx, ny, seed):
+    rng = np.random.default_rng(seed)
+    x = W.cell_centres(0, 1, nx)[None, :]
+    y = W.cell_centres(0, 1, ny)[:, None]
+    rho = 1 + 0.3 * np.sin(2 * np.pi * (x + 2 * y)) + 0.5 * ((x - 0.5) ** 2 + (y - 0.4) ** 2 < 0.06)
+    u = 0.3 * np.cos(2 * np.pi * y) + 0 * x
+    v = -0.2 * np.sin(2 * np.pi * x) + 0 * y
+    p = 1 + 0.5 * (x > 0.6) + 0.1 * rng.normal(size=(ny, nx)) ** 2
+    return np.stack([rho, rho * u, rho * v, p / 0.4 + 0.5 * rho * (u * u + v * v)])
+
+
+@pytest.mark.parametrize("fv,bc", [(0, (1, 2, 2, 1)), (1, (0, 0, 0, 0)), (0, (0, 0, 1, 1))])
+def test_2d_interface_state_rule_run(fv, bc):
+    """PP_DT_PP in 2D (both operators): each step's dt = cfl / (Sx/dx + Sy/dy)
+    with S over the averages and the limited interface (or Gauss-node) states
+    of the stage-1 input, stages 2 and 3 checked against it; 25 steps against
+    the oracle's run of the same rule: equal step counts and times, states
+    within 1e-11, and status bit 2 exactly when the oracle counts a broken
+    (CFL-CD)."""
+    pp = gpu()
+    nx, ny = 40, 24
+    dx, dy = 1.0 / nx, 1.0 / ny
+    U0 = _mixed_2d(nx, ny, 3)
+    P = oracle.params(fv=fv)
+    ref, info = oracle.run_2d(U0, bc, dx, dy, 1.0, p=P, max_steps=25, rule=oracle.DT_PP)
+    s = pp.Solver(ndim=2, nx=nx, ny=ny, dx=dx, dy=dy, bc=bc, fv=fv)
+    Ud = dev(U0)
+    t, steps = s.run(Ud, 1.0, 25, 1.0 / 12.0, pp.PP_DT_PP)
+    code, flags = s.status()
+    got = Ud.cpu().numpy()
+    err = max(float(np.abs(got[k] - ref[k]).max() / np.abs(ref[k]).max()) for k in range(4))
+    print(f"2D interface-state rule fv={fv} bc={bc}: t {t:.6e} / {info['t']:.6e}, flags {flags}, "
+          f"oracle violations {info['viol']}, state {err:.2e}", flush=True)
+    assert steps == info["steps"] == 25
+    assert abs(t / info["t"] - 1) <= 1e-12
+    assert err <= 1e-11
+    assert code == pp.PP_OK and bool(flags & 4) == (info["viol"] > 0)
+    s.close()
+
+
+def test_2d_interface_state_rule_near_vacuum():
+    """The corner blast into a 1e-10 background (48^2, walls at x = 0 and
+    y = 0) for 40 steps under PP_DT_PP: in G, and the time reached and the
+    state within 4x the oracle's own change under 1e-15 input perturbations
+    (at least 1e-10): the rule's dt comes from |u|+a of limited interface
+    states whose pressure near vacuum is a roundoff-sized difference."""
+    pp = gpu()
+    n = 48
+    dx = 1.1 / n
+    bc = (2, 1, 2, 1)
+    U0 = W.sedov_corner_2d(n)
+    ref, info = oracle.run_2d(U0, bc, dx, dx, 1.0, max_steps=40, rule=oracle.DT_PP)
+    assert info["steps"] == 40 and in_G(ref)
+    rng = np.random.default_rng(1402)
+    alt, ialt = oracle.run_2d(U0 * (1.0 + 1e-15 * rng.standard_normal(U0.shape)), bc, dx, dx, 1.0,
+                              max_steps=40, rule=oracle.DT_PP)
+    d_alt = rel_l1(alt, ref)
+    t_alt = abs(ialt["t"] / info["t"] - 1)
+    s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=bc)
+    Ud = dev(U0)
+    t, steps = s.run(Ud, 1.0, 40, 1.0 / 12.0, pp.PP_DT_PP)
+    code, flags = s.status()
+    got = Ud.cpu().numpy()
+    d = rel_l1(got, ref)
+    print(f"2D blast, interface-state rule: t {t:.6e} / {info['t']:.6e} (perturbed {t_alt:.2e}), "
+          f"flags {flags}, relative L1 {d:.3e} (perturbed oracle {d_alt:.3e})", flush=True)
+    assert steps == 40 and code == pp.PP_OK and in_G(got)
+    assert abs(t / info["t"] - 1) <= max(1e-10, 4 * t_alt)
+    assert d <= max(1e-10, 4 * d_alt)
+    s.close()
+
+
+def test_2d_rule_limits():
+    """The restart rule is 1D; the 2D interface-state rule runs in FP64."""
+    pp = gpu()
+    U0 = _mixed_2d(16, 16, 1)
+    s = pp.Solver(ndim=2, nx=16, ny=16, dx=1 / 16, dy=1 / 16, bc=(0, 0, 0, 0))
+    with pytest.raises(pp.PPError) as e:
+        s.run(dev(U0), 0.1, 5, 1.0 / 12.0, pp.PP_DT_RESTART)
+    assert e.value.code == pp.PP_EUNSUPPORTED
+    s.close()
+    s = pp.Solver(ndim=2, nx=16, ny=16, dx=1 / 16, dy=1 / 16, bc=(0, 0, 0, 0), precision=pp.PP_MIXED)
+    with pytest.raises(pp.PPError) as e:
+        s.run(dev(U0), 0.1, 5, 1.0 / 12.0, pp.PP_DT_PP)
+    assert e.value.code == pp.PP_EUNSUPPORTED
+    s.close()

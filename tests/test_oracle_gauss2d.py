@@ -251,3 +251,4 @@ def test_transverse_ghost_lines(ybc):
     L = oracle.gauss_dir_x(U, (0, 0) + ybc, 1.0 / nx, er, ee)
     Le = oracle.gauss_dir_x(ext, (0, 0, 0, 0), 1.0 / nx, er, ee)
     np.testing.assert_array_equal(L, Le[:, 2:ny + 2])
+
