@@ -65,14 +65,17 @@ enum { PP_FP64 = 0, PP_MIXED = 1 };
  *                  S = max(|u|+a) over the cell averages at the start of
  *                  each step.
  *  PP_DT_H53     : dt = cfl * h^(5/3) / S  (Example 3.1, Table 1; 1D only).
- *  PP_DT_PP      : dt = cfl * h / S with S over the cell averages AND the
- *                  limited interface states of the step's input, the states
- *                  the theorem's proof advances by first-order HLLC steps.
- *                  The inputs of stages 2 and 3 are checked against
- *                  dt * S_s / h <= gl_w1 with the same dt; a stage that breaks
- *                  it sets status bit 2 (informative: not PP_ESTATE).  Near
+ *  PP_DT_PP      : dt = cfl * h / S (1D), cfl / (Sx/dx + Sy/dy) (2D) with S
+ *                  over the cell averages AND the limited interface states
+ *                  (2D Gauss-node operator: the limited node states) of the
+ *                  step's input, the states the theorem's proof advances by
+ *                  first-order HLLC steps.  The inputs of stages 2 and 3 are
+ *                  checked against dt * S_s / h <= gl_w1 (2D: dt (Sx_s/dx +
+ *                  Sy_s/dy) <= gl_w1) with the same dt; a stage that breaks it
+ *                  sets status bit 2 (informative: not PP_ESTATE).  Near
  *                  vacuum the density-limited interface states keep their
- *                  pressure, so S can become huge and dt tiny.  1D only.
+ *                  pressure, so S can become huge and dt tiny.  The compact
+ *                  scheme; 2D in FP64.
  *  PP_DT_RESTART : PP_DT_CFL's dt; a step in which any stage output leaves
  *                  the admissible set (rho <= 0, p <= 0 or not finite) is
  *                  discarded and redone from U^n with half the dt, up to 60
