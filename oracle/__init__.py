@@ -51,7 +51,8 @@ def params(gamma=1.4, weno_eps=1e-13, eps_cap=1e-13, gl_w1=1.0 / 12.0, linear=Fa
     paper names for Example 3.6).  recon: 0 the compact reconstruction
     (Sec. 2.2), 1 explicit WENO-JS, 2 explicit WENO-Z (the non-compact
     schemes the paper compares against in Sec. 3), 3 the compact
-    reconstruction along characteristic fields (Sec. 2.3; 1D).  fv (2D):
+    reconstruction along characteristic fields (Sec. 2.3; in 2D along the
+    direction of each line).  fv (2D):
     0 one state pair per face (dimension by dimension), 1 three Gauss nodes
     per face from a transverse reconstruction (a multi-dimensional reading
     beyond the paper, which leaves that to future work in Sec. 4)."""
@@ -110,6 +111,9 @@ def lib():
             "orc_char_eigen": (None, [_DBL, _D, _D, _D, _D, _D]),
             "orc_block_solve": (_I, [_I, _I, _D, _D, _D, _D, _D]),
             "orc_recon_char": (_I, [_I, _I, _D, _P, _D, _D]),
+            "orc_char_eigen2": (None, [_DBL, _I, _D, _D, _D, _D, _D]),
+            "orc_block_solve_nb": (_I, [_I, _I, _I, _D, _D, _D, _D, _D]),
+            "orc_recon_char2": (_I, [_I, _I, _I, _D, _P, _D, _D]),
             "orc_gauss_nodes": (_I, [_D, _D]),
             "orc_limit_nodes": (_I, [_I, _DBL, _DBL, _DBL, _D, _D, _D]),
             "orc_gauss_dir": (_L, [_I, _I, _D, _I, _I, _I, _I, _I, _I, _DBL, _P, _DBL, _DBL,
@@ -436,13 +440,23 @@ def char_eigen(Ua, Ub, gamma=1.4):
     return L.reshape(3, 3), R.reshape(3, 3), lam
 
 
+def char_eigen2(Ua, Ub, nrm, gamma=1.4):
+    """The 2D form of char_eigen: 4x4 eigenvectors of the flux Jacobian along
+    a line whose normal momentum is component ``nrm`` (1: x, 2: y)."""
+    Ua, Ub = _f64(Ua), _f64(Ub)
+    L, R, lam = np.empty(16), np.empty(16), np.empty(4)
+    lib().orc_char_eigen2(gamma, int(nrm), _d(Ua), _d(Ub), _d(L), _d(R), _d(lam))
+    return L.reshape(4, 4), R.reshape(4, 4), lam
+
+
 def block_solve(A, B, C, Y, cyclic=False):
     """Block chasing solve of A_i X_{i-1} + B_i X_i + C_i X_{i+1} = Y_i
-    (3x3 blocks; cyclic: indices mod n)."""
+    (3x3 or 4x4 blocks; cyclic: indices mod n)."""
     A, B, C, Y = (_f64(v) for v in (A, B, C, Y))
-    n = Y.shape[0]
+    n, nb = Y.shape
     X = np.empty_like(Y)
-    _check(lib().orc_block_solve(n, int(cyclic), _d(A), _d(B), _d(C), _d(Y), _d(X)), "block")
+    _check(lib().orc_block_solve_nb(nb, n, int(cyclic), _d(A), _d(B), _d(C), _d(Y), _d(X)),
+           "block")
     return X
 
 
@@ -455,6 +469,18 @@ def recon_char(ue, cyclic_line, p=None):
     um, up = np.empty((3, n)), np.empty((3, n))
     _check(lib().orc_recon_char(n, int(cyclic_line), _d(ue), ctypes.byref(p), _d(um), _d(up)),
            "recon_char")
+    return um, up
+
+
+def recon_char2(ue, cyclic_line, nrm, p=None):
+    """The 2D form of recon_char: a line of ``ue`` ([4][n+6]) whose normal
+    momentum is component ``nrm`` (1: x line, 2: y line)."""
+    p = p or params()
+    ue = _f64(ue)
+    n = ue.shape[1] - 6
+    um, up = np.empty((4, n)), np.empty((4, n))
+    _check(lib().orc_recon_char2(int(nrm), n, int(cyclic_line), _d(ue), ctypes.byref(p),
+                                 _d(um), _d(up)), "recon_char2")
     return um, up
 
 

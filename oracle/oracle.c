@@ -37,7 +37,8 @@ typedef struct {
     int flux;         /* 0: HLLC, eq. (HLLC); 1: local Lax-Friedrichs (see lf below) */
     int recon;        /* 0: compact (FVCW, Sec 2.2); 1: explicit WENO-JS; 2: explicit
                        * WENO-Z (the non-compact schemes of Sec 3, see weno5_explicit);
-                       * 3: compact, characteristic-wise (Sec 2.3; 1D only) */
+                       * 3: compact, characteristic-wise (Sec 2.3; in 2D along
+                       * each line's direction) */
     int fv;           /* 2D face fluxes: 0 one state pair per face (dimension by
                        * dimension); 1 three Gauss-Legendre nodes per face from a
                        * transverse reconstruction (see orc_rhs_2d_gauss) */
@@ -366,7 +367,9 @@ static int recon_scalar(int n, int cyclic, const double *ue, const orc_params *P
  * characteristic field from the characteristic variables l^(k) . Ubar of the
  * Roe average at that node, and stacked into the 3x3 block tridiagonal
  * system (1DEuler-FVC) in the conserved nodal values, solved by block
- * chasing. */
+ * chasing.  The 2D operator applies the same construction line by line
+ * (dimension by dimension), with the eigenvectors of the flux Jacobian
+ * along the line: 4x4 blocks. */
 
 /* Roe average of the states Ua, Ub (rho, rho u, E) and, there, the left
  * eigenvectors l^(k) (rows of L, eq. (leigenv)), the right eigenvectors
@@ -412,85 +415,155 @@ void orc_char_eigen(double gamma, const double *Ua, const double *Ub, double *Lo
         for (int j = 0; j < 3; ++j) { Lo[3 * i + j] = L[i][j]; Ro[3 * i + j] = R[i][j]; }
 }
 
-/* Solve M X = Y for a 3x3 M and k right-hand columns (Y, X row-major 3 x k),
- * Gaussian elimination with partial pivoting.  Returns 0 or -1 if singular. */
-static int solve3(const double M[3][3], int k, const double *Y, double *X)
+/* The 2D form, for a line of the dimension-by-dimension extension: Roe
+ * average of Ua, Ub (rho, rho u, rho v, E) and the eigenvectors of the flux
+ * Jacobian along the line, whose normal momentum is component nrm (1: x,
+ * 2: y; t = 3 - nrm is the tangential one).  With q^2 = u_n^2 + u_t^2,
+ * b1 = (gamma-1)/a^2 and b2 = b1 q^2 / 2 the fields are, in this order, the
+ * acoustic wave u_n - a, the entropy wave u_n, the shear wave u_n (which
+ * carries u_t) and the acoustic wave u_n + a:
+ *   l0 = ( b2 + u_n/a, -b1 u_n - 1/a, -b1 u_t, b1 ) / 2   r0 = (1, u_n - a, u_t, H - u_n a)
+ *   l1 = ( 1 - b2,      b1 u_n,        b1 u_t, -b1 )      r1 = (1, u_n,     u_t, q^2/2)
+ *   l2 = ( -u_t,        0,             1,       0  )      r2 = (0, 0,       1,   u_t)
+ *   l3 = ( b2 - u_n/a, -b1 u_n + 1/a, -b1 u_t, b1 ) / 2   r3 = (1, u_n + a, u_t, H + u_n a)
+ * (entries listed in the order rho, normal momentum, tangential momentum,
+ * E).  With u_t = 0 the acoustic and entropy fields are those of the 1D
+ * system and the shear field is the tangential momentum itself.  The same
+ * reading as in 1D for a Roe sound speed that is not positive. */
+static void roe_eigen2(double g, int nrm, const double *Ua, const double *Ub, double L[4][4],
+                       double R[4][4], double lam[4])
 {
-    double T[3][3 + 8];
-    for (int i = 0; i < 3; ++i) {
-        for (int j = 0; j < 3; ++j) T[i][j] = M[i][j];
-        for (int j = 0; j < k; ++j) T[i][3 + j] = Y[i * k + j];
+    int t = 3 - nrm;
+    double ra = Ua[0], rb = Ub[0];
+    double una = Ua[nrm] / ra, unb = Ub[nrm] / rb;
+    double uta = Ua[t] / ra, utb = Ub[t] / rb;
+    double pa = (g - 1.0) * (Ua[3] - 0.5 * ra * (una * una + uta * uta));
+    double pb = (g - 1.0) * (Ub[3] - 0.5 * rb * (unb * unb + utb * utb));
+    double Ha = (Ua[3] + pa) / ra, Hb = (Ub[3] + pb) / rb;
+    double sa = sqrt(ra), sb = sqrt(rb);
+    double un = (sa * una + sb * unb) / (sa + sb);
+    double ut = (sa * uta + sb * utb) / (sa + sb);
+    double H = (sa * Ha + sb * Hb) / (sa + sb);
+    double q2 = un * un + ut * ut;
+    double a2 = (g - 1.0) * (H - 0.5 * q2);
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) L[i][j] = R[i][j] = 0.0;
+    if (!(a2 > 0.0)) {
+        for (int i = 0; i < 4; ++i) { L[i][i] = R[i][i] = 1.0; lam[i] = un; }
+        return;
     }
-    for (int c = 0; c < 3; ++c) {
+    double a = sqrt(a2);
+    double b1 = (g - 1.0) / a2, b2 = 0.5 * q2 * b1;
+    L[0][0] = 0.5 * (b2 + un / a); L[0][nrm] = 0.5 * (-b1 * un - 1.0 / a);
+    L[0][t] = -0.5 * b1 * ut;      L[0][3] = 0.5 * b1;
+    L[1][0] = 1.0 - b2;            L[1][nrm] = b1 * un;
+    L[1][t] = b1 * ut;             L[1][3] = -b1;
+    L[2][0] = -ut;                 L[2][t] = 1.0;
+    L[3][0] = 0.5 * (b2 - un / a); L[3][nrm] = 0.5 * (-b1 * un + 1.0 / a);
+    L[3][t] = -0.5 * b1 * ut;      L[3][3] = 0.5 * b1;
+    R[0][0] = 1.0; R[nrm][0] = un - a; R[t][0] = ut; R[3][0] = H - un * a;
+    R[0][1] = 1.0; R[nrm][1] = un;     R[t][1] = ut; R[3][1] = 0.5 * q2;
+    R[t][2] = 1.0; R[3][2] = ut;
+    R[0][3] = 1.0; R[nrm][3] = un + a; R[t][3] = ut; R[3][3] = H + un * a;
+    lam[0] = un - a; lam[1] = un; lam[2] = un; lam[3] = un + a;
+}
+
+/* Exported for unit tests: L and R row-major [4][4]. */
+void orc_char_eigen2(double gamma, int nrm, const double *Ua, const double *Ub, double *Lo,
+                     double *Ro, double *lam)
+{
+    double L[4][4], R[4][4];
+    roe_eigen2(gamma, nrm, Ua, Ub, L, R, lam);
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) { Lo[4 * i + j] = L[i][j]; Ro[4 * i + j] = R[i][j]; }
+}
+
+/* Blocks of nb x nb (nb = 3 in 1D, 4 in 2D), row-major and flat. */
+#define NBMAX 4
+
+/* Solve M X = Y for an nb x nb M and k right-hand columns (Y, X row-major
+ * nb x k, k <= 2 nb + 1), Gaussian elimination with partial pivoting.
+ * Returns 0 or -1 if singular. */
+static int solve_nb(int nb, const double *M, int k, const double *Y, double *X)
+{
+    double T[NBMAX][3 * NBMAX + 1];
+    for (int i = 0; i < nb; ++i) {
+        for (int j = 0; j < nb; ++j) T[i][j] = M[i * nb + j];
+        for (int j = 0; j < k; ++j) T[i][nb + j] = Y[i * k + j];
+    }
+    for (int c = 0; c < nb; ++c) {
         int piv = c;
-        for (int i = c + 1; i < 3; ++i)
+        for (int i = c + 1; i < nb; ++i)
             if (fabs(T[i][c]) > fabs(T[piv][c])) piv = i;
         if (T[piv][c] == 0.0) return -1;
         if (piv != c)
-            for (int j = 0; j < 3 + k; ++j) { double t = T[c][j]; T[c][j] = T[piv][j]; T[piv][j] = t; }
-        for (int i = c + 1; i < 3; ++i) {
+            for (int j = 0; j < nb + k; ++j) { double t = T[c][j]; T[c][j] = T[piv][j]; T[piv][j] = t; }
+        for (int i = c + 1; i < nb; ++i) {
             double f = T[i][c] / T[c][c];
-            for (int j = c; j < 3 + k; ++j) T[i][j] -= f * T[c][j];
+            for (int j = c; j < nb + k; ++j) T[i][j] -= f * T[c][j];
         }
     }
     for (int j = 0; j < k; ++j)
-        for (int i = 2; i >= 0; --i) {
-            double v = T[i][3 + j];
-            for (int l = i + 1; l < 3; ++l) v -= T[i][l] * X[l * k + j];
+        for (int i = nb - 1; i >= 0; --i) {
+            double v = T[i][nb + j];
+            for (int l = i + 1; l < nb; ++l) v -= T[i][l] * X[l * k + j];
             X[i * k + j] = v / T[i][i];
         }
     return 0;
 }
 
-/* Y -= M X for 3x3 M and X, Y of k columns (row-major 3 x k). */
-static void sub_mul3(const double M[3][3], int k, const double *X, double *Y)
+/* Y -= M X for an nb x nb M and X, Y of k columns (row-major nb x k). */
+static void sub_mul_nb(int nb, const double *M, int k, const double *X, double *Y)
 {
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < nb; ++i)
         for (int j = 0; j < k; ++j)
-            for (int l = 0; l < 3; ++l) Y[i * k + j] -= M[i][l] * X[l * k + j];
+            for (int l = 0; l < nb; ++l) Y[i * k + j] -= M[i * nb + l] * X[l * k + j];
 }
 
 /* Block chasing (the paper's method for (1DEuler-FVC)):
- * A_i X_{i-1} + B_i X_i + C_i X_{i+1} = Y_i, i = 0..n-1, 3x3 blocks (A_0 and
- * C_{n-1} ignored), Y_i and X_i of k <= 4 columns ([n][3][k]).  Block LU
- * without pivoting between blocks; each pivot block solved with partial
- * pivoting.  Returns 0, -1 on a singular pivot block, -2 on no memory. */
-static int blk_thomas(int n, int k, const double (*A)[3][3], const double (*B)[3][3],
-                      const double (*C)[3][3], const double *Y, double *X)
+ * A_i X_{i-1} + B_i X_i + C_i X_{i+1} = Y_i, i = 0..n-1, nb x nb blocks
+ * ([n][nb][nb]; A_0 and C_{n-1} ignored), Y_i and X_i of k <= nb + 1 columns
+ * ([n][nb][k]).  Block LU without pivoting between blocks; each pivot block
+ * solved with partial pivoting.  Returns 0, -1 on a singular pivot block,
+ * -2 on no memory. */
+static int blk_thomas(int nb, int n, int k, const double *A, const double *B, const double *C,
+                      const double *Y, double *X)
 {
-    double (*Cp)[3][3] = (double (*)[3][3])malloc(sizeof(double) * 9u * (size_t)n);
-    double *Dp = (double *)malloc(sizeof(double) * 3u * (size_t)k * (size_t)n);
+    size_t bb = (size_t)nb * (size_t)nb, bk = (size_t)nb * (size_t)k;
+    double *Cp = (double *)malloc(sizeof(double) * bb * (size_t)n);
+    double *Dp = (double *)malloc(sizeof(double) * bk * (size_t)n);
     if (!Cp || !Dp) { free(Cp); free(Dp); return -2; }
-    int rc = 0;
+    int rc = 0, w = nb + k;
     for (int i = 0; i < n && rc == 0; ++i) {
-        double M[3][3], rhs[3 * 7], sol[3 * 7];
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) M[r][c] = B[i][r][c];
-        for (int r = 0; r < 3; ++r) {
-            for (int c = 0; c < 3; ++c) rhs[r * (3 + k) + c] = (i < n - 1) ? C[i][r][c] : 0.0;
-            for (int c = 0; c < k; ++c) rhs[r * (3 + k) + 3 + c] = Y[(size_t)i * 3 * k + r * k + c];
+        double M[NBMAX * NBMAX], rhs[NBMAX * (2 * NBMAX + 1)], sol[NBMAX * (2 * NBMAX + 1)];
+        const double *Ai = A + (size_t)i * bb, *Bi = B + (size_t)i * bb, *Ci = C + (size_t)i * bb;
+        for (int r = 0; r < nb; ++r)
+            for (int c = 0; c < nb; ++c) M[r * nb + c] = Bi[r * nb + c];
+        for (int r = 0; r < nb; ++r) {
+            for (int c = 0; c < nb; ++c) rhs[r * w + c] = (i < n - 1) ? Ci[r * nb + c] : 0.0;
+            for (int c = 0; c < k; ++c) rhs[r * w + nb + c] = Y[(size_t)i * bk + r * k + c];
         }
         if (i > 0) {
             /* M = B_i - A_i Cp_{i-1};  rhs(Y part) -= A_i Dp_{i-1} */
-            for (int r = 0; r < 3; ++r)
-                for (int c = 0; c < 3; ++c)
-                    for (int l = 0; l < 3; ++l) M[r][c] -= A[i][r][l] * Cp[i - 1][l][c];
-            for (int r = 0; r < 3; ++r)
+            const double *Cq = Cp + (size_t)(i - 1) * bb, *Dq = Dp + (size_t)(i - 1) * bk;
+            for (int r = 0; r < nb; ++r)
+                for (int c = 0; c < nb; ++c)
+                    for (int l = 0; l < nb; ++l) M[r * nb + c] -= Ai[r * nb + l] * Cq[l * nb + c];
+            for (int r = 0; r < nb; ++r)
                 for (int c = 0; c < k; ++c)
-                    for (int l = 0; l < 3; ++l)
-                        rhs[r * (3 + k) + 3 + c] -= A[i][r][l] * Dp[(size_t)(i - 1) * 3 * k + l * k + c];
+                    for (int l = 0; l < nb; ++l) rhs[r * w + nb + c] -= Ai[r * nb + l] * Dq[l * k + c];
         }
-        rc = solve3(M, 3 + k, rhs, sol);
-        for (int r = 0; r < 3; ++r) {
-            for (int c = 0; c < 3; ++c) Cp[i][r][c] = sol[r * (3 + k) + c];
-            for (int c = 0; c < k; ++c) Dp[(size_t)i * 3 * k + r * k + c] = sol[r * (3 + k) + 3 + c];
+        rc = solve_nb(nb, M, w, rhs, sol);
+        for (int r = 0; r < nb; ++r) {
+            for (int c = 0; c < nb; ++c) Cp[(size_t)i * bb + r * nb + c] = sol[r * w + c];
+            for (int c = 0; c < k; ++c) Dp[(size_t)i * bk + r * k + c] = sol[r * w + nb + c];
         }
     }
     if (rc == 0) {
-        for (int j = 0; j < 3 * k; ++j) X[(size_t)(n - 1) * 3 * k + j] = Dp[(size_t)(n - 1) * 3 * k + j];
+        for (size_t j = 0; j < bk; ++j) X[(size_t)(n - 1) * bk + j] = Dp[(size_t)(n - 1) * bk + j];
         for (int i = n - 2; i >= 0; --i) {
-            for (int j = 0; j < 3 * k; ++j) X[(size_t)i * 3 * k + j] = Dp[(size_t)i * 3 * k + j];
-            sub_mul3(Cp[i], k, &X[(size_t)(i + 1) * 3 * k], &X[(size_t)i * 3 * k]);
+            for (size_t j = 0; j < bk; ++j) X[(size_t)i * bk + j] = Dp[(size_t)i * bk + j];
+            sub_mul_nb(nb, Cp + (size_t)i * bb, k, &X[(size_t)(i + 1) * bk], &X[(size_t)i * bk]);
         }
     }
     free(Cp);
@@ -502,44 +575,47 @@ static int blk_thomas(int n, int k, const double (*A)[3][3], const double (*B)[3
  * last unknown is kept as a parameter, X_i = P_i + Q_i X_{n-1} from the
  * leading (n-1) block rows (right-hand columns Y and the two coupling
  * blocks), then the last block row gives X_{n-1}. */
-static int blk_cyclic(int n, const double (*A)[3][3], const double (*B)[3][3],
-                      const double (*C)[3][3], const double *Y, double *X)
+static int blk_cyclic(int nb, int n, const double *A, const double *B, const double *C,
+                      const double *Y, double *X)
 {
-    int m = n - 1;
-    double *Y4 = (double *)calloc((size_t)m * 12u, sizeof(double));
-    double *S4 = (double *)malloc(sizeof(double) * (size_t)m * 12u);
+    int m = n - 1, K = nb + 1;
+    size_t bb = (size_t)nb * (size_t)nb, bK = (size_t)nb * (size_t)K;
+    double *Y4 = (double *)calloc((size_t)m * bK, sizeof(double));
+    double *S4 = (double *)malloc(sizeof(double) * (size_t)m * bK);
     if (!Y4 || !S4) { free(Y4); free(S4); return -2; }
     for (int i = 0; i < m; ++i)
-        for (int r = 0; r < 3; ++r) Y4[(size_t)i * 12 + r * 4] = Y[3 * i + r];
-    for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c) {
-            Y4[r * 4 + 1 + c] -= A[0][r][c];                       /* row 0 couples X_{n-1} */
-            Y4[(size_t)(m - 1) * 12 + r * 4 + 1 + c] -= C[m - 1][r][c];  /* row n-2 too */
+        for (int r = 0; r < nb; ++r) Y4[(size_t)i * bK + r * K] = Y[nb * i + r];
+    for (int r = 0; r < nb; ++r)
+        for (int c = 0; c < nb; ++c) {
+            Y4[r * K + 1 + c] -= A[r * nb + c];                                   /* row 0 couples X_{n-1} */
+            Y4[(size_t)(m - 1) * bK + r * K + 1 + c] -= C[(size_t)(m - 1) * bb + r * nb + c];  /* row n-2 too */
         }
-    int rc = blk_thomas(m, 4, A, B, C, Y4, S4);
+    int rc = blk_thomas(nb, m, K, A, B, C, Y4, S4);
     if (rc == 0) {
         /* (B_{n-1} + A_{n-1} Q_{n-2} + C_{n-1} Q_0) X_{n-1} = Y_{n-1} - A_{n-1} P_{n-2} - C_{n-1} P_0 */
-        double M[3][3], rhs[3], xl[3];
-        const double *Sl = &S4[(size_t)(m - 1) * 12], *S0 = &S4[0];
-        for (int r = 0; r < 3; ++r) {
-            rhs[r] = Y[3 * (n - 1) + r];
-            for (int c = 0; c < 3; ++c) {
-                M[r][c] = B[n - 1][r][c];
-                for (int l = 0; l < 3; ++l)
-                    M[r][c] += A[n - 1][r][l] * Sl[l * 4 + 1 + c] + C[n - 1][r][l] * S0[l * 4 + 1 + c];
+        double M[NBMAX * NBMAX], rhs[NBMAX], xl[NBMAX];
+        const double *Sl = &S4[(size_t)(m - 1) * bK], *S0 = &S4[0];
+        const double *Al = A + (size_t)(n - 1) * bb, *Bl = B + (size_t)(n - 1) * bb,
+                     *Cl = C + (size_t)(n - 1) * bb;
+        for (int r = 0; r < nb; ++r) {
+            rhs[r] = Y[nb * (n - 1) + r];
+            for (int c = 0; c < nb; ++c) {
+                M[r * nb + c] = Bl[r * nb + c];
+                for (int l = 0; l < nb; ++l)
+                    M[r * nb + c] += Al[r * nb + l] * Sl[l * K + 1 + c] + Cl[r * nb + l] * S0[l * K + 1 + c];
             }
-            for (int l = 0; l < 3; ++l)
-                rhs[r] -= A[n - 1][r][l] * Sl[l * 4] + C[n - 1][r][l] * S0[l * 4];
+            for (int l = 0; l < nb; ++l)
+                rhs[r] -= Al[r * nb + l] * Sl[l * K] + Cl[r * nb + l] * S0[l * K];
         }
-        rc = solve3(M, 1, rhs, xl);
+        rc = solve_nb(nb, M, 1, rhs, xl);
         if (rc == 0) {
             for (int i = 0; i < m; ++i)
-                for (int r = 0; r < 3; ++r) {
-                    double v = S4[(size_t)i * 12 + r * 4];
-                    for (int c = 0; c < 3; ++c) v += S4[(size_t)i * 12 + r * 4 + 1 + c] * xl[c];
-                    X[3 * i + r] = v;
+                for (int r = 0; r < nb; ++r) {
+                    double v = S4[(size_t)i * bK + r * K];
+                    for (int c = 0; c < nb; ++c) v += S4[(size_t)i * bK + r * K + 1 + c] * xl[c];
+                    X[nb * i + r] = v;
                 }
-            for (int r = 0; r < 3; ++r) X[3 * (n - 1) + r] = xl[r];
+            for (int r = 0; r < nb; ++r) X[nb * (n - 1) + r] = xl[r];
         }
     }
     free(Y4);
@@ -547,47 +623,63 @@ static int blk_cyclic(int n, const double (*A)[3][3], const double (*B)[3][3],
     return rc;
 }
 
-/* Exported for unit tests: A, B, C [n][3][3], Y, X [n][3]. */
+/* Exported for unit tests: A, B, C [n][nb][nb], Y, X [n][nb], nb = 3 or 4. */
+int orc_block_solve_nb(int nb, int n, int cyclic, const double *A, const double *B,
+                       const double *C, const double *Y, double *X)
+{
+    if (nb < 1 || nb > NBMAX) return -3;
+    if (cyclic) {
+        if (n < 3) return -3;
+        return blk_cyclic(nb, n, A, B, C, Y, X);
+    }
+    return blk_thomas(nb, n, 1, A, B, C, Y, X);
+}
+
+/* The 3x3 form (1D). */
 int orc_block_solve(int n, int cyclic, const double *A, const double *B, const double *C,
                     const double *Y, double *X)
 {
-    if (cyclic) {
-        if (n < 3) return -3;
-        return blk_cyclic(n, (const double (*)[3][3])A, (const double (*)[3][3])B,
-                          (const double (*)[3][3])C, Y, X);
-    }
-    return blk_thomas(n, 1, (const double (*)[3][3])A, (const double (*)[3][3])B,
-                      (const double (*)[3][3])C, Y, X);
+    return orc_block_solve_nb(3, n, cyclic, A, B, C, Y, X);
 }
 
-/* The characteristic-wise reconstruction of one 1D line: ue [3][n+6] holds
- * the ghost-extended averages (cell i at ue[c][i+3]).  um[c][i] = U-_{i+1/2},
+/* The characteristic-wise reconstruction of one line of nb = 3 (1D) or 4
+ * (2D, normal momentum component nrm) components: ue [nb][n+6] holds the
+ * ghost-extended averages (cell i at ue[c][i+3]).  um[c][i] = U-_{i+1/2},
  * up[c][i] = U+_{i-1/2}.  Rows of the "-" system sit at node i+1/2 with the
  * eigenvectors of Roe(Ubar_i, Ubar_{i+1}); rows of the "+" system at node
  * i-1/2 with those of Roe(Ubar_{i-1}, Ubar_i), the mirrored rows of Sec. 2.2,
  * chased from the right end.  Non-periodic lines are closed as the
  * component-wise ones (reading R10). */
-static int recon_char(int n, int cyclic, const double *ue, const orc_params *P, double *um,
-                      double *up)
+static int recon_char(int nb, int nrm, int n, int cyclic, const double *ue, const orc_params *P,
+                      double *um, double *up)
 {
     int ne = n + 2 * NG;
-    double (*A)[3][3] = (double (*)[3][3])malloc(sizeof(double) * 27u * (size_t)n);
-    double (*Bm)[3][3] = A ? A + n : NULL, (*Cm)[3][3] = A ? A + 2 * n : NULL;
-    double *Y = (double *)malloc(sizeof(double) * 6u * (size_t)n);
-    double *X = Y ? Y + 3 * n : NULL;
+    size_t bb = (size_t)nb * (size_t)nb;
+    double *A = (double *)malloc(sizeof(double) * 3u * bb * (size_t)n);
+    double *Bm = A ? A + bb * (size_t)n : NULL, *Cm = A ? A + 2 * bb * (size_t)n : NULL;
+    double *Y = (double *)malloc(sizeof(double) * 2u * (size_t)nb * (size_t)n);
+    double *X = Y ? Y + (size_t)nb * n : NULL;
     if (!A || !Y) { free(A); free(Y); return -2; }
 #define UE(c, m) ue[(size_t)(c) * ne + (m) + NG]
     for (int side = 0; side < 2; ++side) {
         for (int i = 0; i < n; ++i) {
-            double Ua[3], Ub[3], L[3][3], R[3][3], lam[3];
+            double Ua[NBMAX], Ub[NBMAX], L[NBMAX][NBMAX];
             int ca = side == 0 ? i : i - 1;   /* Roe pair of the row's node */
-            for (int c = 0; c < 3; ++c) { Ua[c] = UE(c, ca); Ub[c] = UE(c, ca + 1); }
-            roe_eigen(P->gamma, Ua, Ub, L, R, lam);
-            for (int k = 0; k < 3; ++k) {
+            for (int c = 0; c < nb; ++c) { Ua[c] = UE(c, ca); Ub[c] = UE(c, ca + 1); }
+            if (nb == 3) {
+                double L3[3][3], R3[3][3], lam[3];
+                roe_eigen(P->gamma, Ua, Ub, L3, R3, lam);
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) L[r][c] = L3[r][c];
+            } else {
+                double R4[4][4], lam[4];
+                roe_eigen2(P->gamma, nrm, Ua, Ub, L, R4, lam);
+            }
+            for (int k = 0; k < nb; ++k) {
                 double v[5], beta[3], w[3], a, b, c, r;
                 for (int m = 0; m < 5; ++m) {
                     v[m] = 0.0;
-                    for (int q = 0; q < 3; ++q) v[m] += L[k][q] * UE(q, i - 2 + m);
+                    for (int q = 0; q < nb; ++q) v[m] += L[k][q] * UE(q, i - 2 + m);
                 }
                 if (side == 0) {
                     beta_minus(v, beta);
@@ -598,76 +690,72 @@ static int recon_char(int n, int cyclic, const double *ue, const orc_params *P, 
                     side_weights(beta, P, w);
                     row_plus(w, v[1], v[2], v[3], &a, &b, &c, &r);
                 }
-                for (int q = 0; q < 3; ++q) {
-                    A[i][k][q] = a * L[k][q];
-                    Bm[i][k][q] = b * L[k][q];
-                    Cm[i][k][q] = c * L[k][q];
+                for (int q = 0; q < nb; ++q) {
+                    A[(size_t)i * bb + k * nb + q] = a * L[k][q];
+                    Bm[(size_t)i * bb + k * nb + q] = b * L[k][q];
+                    Cm[(size_t)i * bb + k * nb + q] = c * L[k][q];
                 }
-                Y[3 * i + k] = r;
+                Y[(size_t)nb * i + k] = r;
             }
         }
         int s;
+        const double *A0 = A, *Cl = Cm + (size_t)(n - 1) * bb;
         if (side == 0) {
             if (cyclic) {
-                s = blk_cyclic(n, (const double (*)[3][3])A, (const double (*)[3][3])Bm,
-                               (const double (*)[3][3])Cm, Y, X);
+                s = blk_cyclic(nb, n, A, Bm, Cm, Y, X);
             } else {
                 /* closure values U-_{-1/2} (cell -1) and U-_{n+1/2} (cell n) */
-                double xl[3], xr[3];
-                for (int c = 0; c < 3; ++c) {
+                double xl[NBMAX], xr[NBMAX];
+                for (int c = 0; c < nb; ++c) {
                     xl[c] = weno5z_minus(&ue[(size_t)c * ne + 0], P);
                     xr[c] = weno5z_minus(&ue[(size_t)c * ne + n + 1], P);
                 }
-                for (int k = 0; k < 3; ++k)
-                    for (int q = 0; q < 3; ++q) {
-                        Y[k] -= A[0][k][q] * xl[q];
-                        Y[3 * (n - 1) + k] -= Cm[n - 1][k][q] * xr[q];
+                for (int k = 0; k < nb; ++k)
+                    for (int q = 0; q < nb; ++q) {
+                        Y[k] -= A0[k * nb + q] * xl[q];
+                        Y[(size_t)nb * (n - 1) + k] -= Cl[k * nb + q] * xr[q];
                     }
-                s = blk_thomas(n, 1, (const double (*)[3][3])A, (const double (*)[3][3])Bm,
-                               (const double (*)[3][3])Cm, Y, X);
+                s = blk_thomas(nb, n, 1, A, Bm, Cm, Y, X);
             }
             for (int i = 0; i < n && s == 0; ++i)
-                for (int c = 0; c < 3; ++c) um[(size_t)c * n + i] = X[3 * i + c];
+                for (int c = 0; c < nb; ++c) um[(size_t)c * n + i] = X[(size_t)nb * i + c];
         } else {
             if (!cyclic) {
                 /* closure values U+ at the left faces of cells -1 and n */
-                double xl[3], xr[3], mv[5];
-                for (int c = 0; c < 3; ++c) {
+                double xl[NBMAX], xr[NBMAX], mv[5];
+                for (int c = 0; c < nb; ++c) {
                     for (int k = 0; k < 5; ++k) mv[k] = ue[(size_t)c * ne + 4 - k];
                     xl[c] = weno5z_minus(mv, P);
                     for (int k = 0; k < 5; ++k) mv[k] = ue[(size_t)c * ne + n + 5 - k];
                     xr[c] = weno5z_minus(mv, P);
                 }
-                for (int k = 0; k < 3; ++k)
-                    for (int q = 0; q < 3; ++q) {
-                        Y[k] -= A[0][k][q] * xl[q];
-                        Y[3 * (n - 1) + k] -= Cm[n - 1][k][q] * xr[q];
+                for (int k = 0; k < nb; ++k)
+                    for (int q = 0; q < nb; ++q) {
+                        Y[k] -= A0[k * nb + q] * xl[q];
+                        Y[(size_t)nb * (n - 1) + k] -= Cl[k * nb + q] * xr[q];
                     }
             }
             /* chased from the right end: the reversed system, A and C exchanged */
-            double (*rA)[3][3] = (double (*)[3][3])malloc(sizeof(double) * 27u * (size_t)n);
-            double *rY = (double *)malloc(sizeof(double) * 6u * (size_t)n);
+            double *rA = (double *)malloc(sizeof(double) * 3u * bb * (size_t)n);
+            double *rY = (double *)malloc(sizeof(double) * 2u * (size_t)nb * (size_t)n);
             if (!rA || !rY) { free(rA); free(rY); s = -2; }
             else {
-                double (*rB)[3][3] = rA + n, (*rC)[3][3] = rA + 2 * n;
-                double *rX = rY + 3 * n;
+                double *rB = rA + bb * (size_t)n, *rC = rA + 2 * bb * (size_t)n;
+                double *rX = rY + (size_t)nb * n;
                 for (int i = 0; i < n; ++i) {
                     int j = n - 1 - i;
-                    for (int k = 0; k < 3; ++k) {
-                        for (int q = 0; q < 3; ++q) {
-                            rA[i][k][q] = Cm[j][k][q];
-                            rB[i][k][q] = Bm[j][k][q];
-                            rC[i][k][q] = A[j][k][q];
-                        }
-                        rY[3 * i + k] = Y[3 * j + k];
+                    for (size_t q = 0; q < bb; ++q) {
+                        rA[(size_t)i * bb + q] = Cm[(size_t)j * bb + q];
+                        rB[(size_t)i * bb + q] = Bm[(size_t)j * bb + q];
+                        rC[(size_t)i * bb + q] = A[(size_t)j * bb + q];
                     }
+                    for (int k = 0; k < nb; ++k) rY[(size_t)nb * i + k] = Y[(size_t)nb * j + k];
                 }
-                s = cyclic ? blk_cyclic(n, (const double (*)[3][3])rA, (const double (*)[3][3])rB,
-                                        (const double (*)[3][3])rC, rY, rX)
-                           : blk_thomas(n, 1, (const double (*)[3][3])rA, (const double (*)[3][3])rB,
-                                        (const double (*)[3][3])rC, rY, rX);
+                s = cyclic ? blk_cyclic(nb, n, rA, rB, rC, rY, rX)
+                           : blk_thomas(nb, n, 1, rA, rB, rC, rY, rX);
                 for (int i = 0; i < n && s == 0; ++i)
-                    for (int c = 0; c < 3; ++c) up[(size_t)c * n + (n - 1 - i)] = rX[3 * i + c];
+                    for (int c = 0; c < nb; ++c)
+                        up[(size_t)c * n + (n - 1 - i)] = rX[(size_t)nb * i + c];
                 free(rA);
                 free(rY);
             }
@@ -680,10 +768,18 @@ static int recon_char(int n, int cyclic, const double *ue, const orc_params *P, 
     return 0;
 }
 
-/* Exported for unit tests: ue [3][n+6] ghost-extended averages. */
+/* Exported for unit tests: ue [3][n+6] ghost-extended averages (1D). */
 int orc_recon_char(int n, int cyclic, const double *ue, const orc_params *P, double *um, double *up)
 {
-    return recon_char(n, cyclic, ue, P, um, up);
+    return recon_char(3, 1, n, cyclic, ue, P, um, up);
+}
+
+/* The 2D form: ue [4][n+6], a line whose normal momentum is component nrm. */
+int orc_recon_char2(int nrm, int n, int cyclic, const double *ue, const orc_params *P,
+                    double *um, double *up)
+{
+    if (nrm != 1 && nrm != 2) return -3;
+    return recon_char(4, nrm, n, cyclic, ue, P, um, up);
 }
 
 /* ----------------------------------------------------------------- Sec 2.4
@@ -940,8 +1036,9 @@ long orc_line_op(int n, int ncomp, int nrm, const double *u, int bc_lo, int bc_h
     }
 
     if (P->recon == 3 && !P->first_order) {
-        /* characteristic-wise (Sec. 2.3): all components at once; 1D only */
-        int s = ncomp == 3 ? recon_char(n, cyclic, ue, P, um, up) : -3;
+        /* characteristic-wise (Sec. 2.3): all components at once, with the
+         * eigenvectors of the flux Jacobian along the line */
+        int s = (ncomp == 3 || ncomp == 4) ? recon_char(ncomp, nrm, n, cyclic, ue, P, um, up) : -3;
         if (s) { free(mem); return -10 + s; }
     } else
     /* reconstruction, component by component (conservative variables) */
