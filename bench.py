@@ -19,6 +19,8 @@ Other workloads (one JSON line each, bounded runs):
   --workload char1d       cost of the characteristic-wise against the component-wise
                           reconstruction (Tables 2-3: density wave, CFL 0.16, t = 2,
                           N = 28..224; and the N = 4000 double rarefaction per step)
+  --workload char2d       the same on the 2D density wave (4x4 blocks per line):
+                          ms per step of both reconstructions, N = 256..2048
   --dt-rule cfl|pp|restart   time-step rule of ensemble / rarefaction1d / blast1d
   --recon cweno|char      reconstruction of wave1d / rarefaction1d / blast1d
   --workload gauss2d      Gauss-node 2D operator against the line operator: error of L
@@ -76,7 +78,7 @@ def parse():
                     help="oracle steps of the full grid for cpu_baseline (about 10 s on 16 threads)")
     ap.add_argument("--workload", default="density2d",
                     choices=["density2d", "sedov2d", "ensemble", "wave1d", "rarefaction1d",
-                             "blast1d", "copy", "accuracy", "char1d", "gauss2d"])
+                             "blast1d", "copy", "accuracy", "char1d", "char2d", "gauss2d"])
     ap.add_argument("--dt-rule", default="cfl", choices=["cfl", "pp", "restart"],
                     help="ensemble / rarefaction1d / blast1d: averages' CFL, interface-state "
                          "bound, or the averages' CFL with a step redone at half dt")
@@ -393,6 +395,37 @@ def other_workload(args):
                            "table": rows, "char_over_component_wall": ratio,
                            "us_per_step_n4000": per_step,
                            "paper_char_over_component_cpu_n224": 29.22 / 8.86})
+    elif args.workload == "char2d":
+        # cost per step of the characteristic-wise against the component-wise
+        # reconstruction on the 2D density wave (CFL 1/12), and their L1
+        # after the timed steps (equal to roundoff: three fields are constant)
+        rows = []
+        for n in (256, 1024, 2048):
+            h = 2.0 / n
+            for name, rc in (("component-wise", pp.PP_RECON_CWENO), ("characteristic", pp.PP_RECON_CHAR)):
+                s = pp.Solver(ndim=2, nx=n, ny=n, dx=h, dy=h, bc=(0, 0, 0, 0), recon=rc)
+                U = torch.tensor(W.density_wave_2d(n, n), device="cuda")
+                s.run(U.clone(), 10.0, 2, 1.0 / 12.0)
+                torch.cuda.synchronize()
+                k = 10
+                t0 = time.perf_counter()
+                t, k = s.run(U, 10.0, k, 1.0 / 12.0)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                s.close()
+                Uh = U.cpu().numpy()
+                l1 = float(np.abs(Uh[0] - W.density_wave_2d(n, n, t=t)[0]).mean())
+                rows.append({"n": n, "recon": name, "steps": k, "ms_per_step": 1e3 * wall / k,
+                             "l1_rho": l1})
+                print(f"char2d: n={n} {name} {1e3 * wall / k:.3f} ms/step L1={l1:.3e}",
+                      file=sys.stderr, flush=True)
+        ratio = [r2["ms_per_step"] / r1["ms_per_step"] for r1, r2 in zip(rows[0::2], rows[1::2])]
+        out.update(metric="ms per SSP-RK3 step of the characteristic against the component-wise "
+                          "reconstruction, 2D density wave",
+                   value=None, steps=None,
+                   config={"workload": "2D density wave, periodic [0,2]^2, CFL 1/12, 10 steps, "
+                                       "N = 256, 1024, 2048, FP64",
+                           "table": rows, "char_over_component": ratio})
     else:
         if args.workload == "wave1d":
             n, h, U0, bc, T, rule = 200, 0.01, W.density_wave_1d(200), (0, 0), 2.0, pp.PP_DT_H53

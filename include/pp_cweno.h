@@ -99,8 +99,13 @@ enum { PP_FLUX_HLLC = 0, PP_FLUX_LF = 1 };
  * PP_RECON_CHAR: the compact scheme along characteristic fields (Sec. 2.3,
  * eqs. (cha-1), (1DEuler-FVC)): per node the rows of each field from the
  * characteristic variables of the Roe average's left eigenvectors, a 3x3
- * block tridiagonal system in the conserved nodal values per side; 1D,
- * FP64, unbatched (the paper's choice for discontinuous problems).  PP_RECON_WENOJS / PP_RECON_WENOZ:
+ * block tridiagonal system in the conserved nodal values per side (the
+ * paper's choice for discontinuous problems).  In 2D each line takes the
+ * eigenvectors of the flux Jacobian along it: 4x4 blocks (acoustic,
+ * entropy, shear and acoustic fields).  FP64, unbatched, the line operator
+ * (PP_FV_LINE); the 2D form keeps the block rows of every line of a sweep
+ * in device scratch allocated at init (about 1.35 MB per 2048-cell line).
+ * PP_RECON_WENOJS / PP_RECON_WENOZ:
  * the classical explicit fifth-order finite-volume WENO the paper compares
  * against, with Jiang-Shu weights (eps 1e-6, a reading; the paper gives
  * none) or WENO-Z weights (weno_eps), each face value from its own five

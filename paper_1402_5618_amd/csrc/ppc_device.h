@@ -258,6 +258,118 @@ __device__ __forceinline__ void roe_left(double g, const double (&Ua)[3], const 
     L[8] = 0.5 * c1;
 }
 
+// Blocks of NB x NB (NB = 3 on 1D lines, 4 on the lines of the 2D
+// operator), row-major in registers.  The NB = 3 forms are the ones above.
+template <int NB>
+__device__ __forceinline__ double dotN(const double* a, int sa, const double* b, int sb) {
+    double s = a[(NB - 1) * sa] * b[(NB - 1) * sb];
+#pragma unroll
+    for (int q = NB - 2; q >= 0; --q) s = fma(a[q * sa], b[q * sb], s);
+    return s;
+}
+template <int NB>
+__device__ __forceinline__ void mmN(const double (&A)[NB * NB], const double (&B)[NB * NB],
+                                    double (&C)[NB * NB]) {
+    if constexpr (NB == 3) {
+        mm3(A, B, C);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) C[NB * i + j] = dotN<NB>(&A[NB * i], 1, &B[j], NB);
+    }
+}
+template <int NB>
+__device__ __forceinline__ void mvN(const double (&A)[NB * NB], const double (&x)[NB],
+                                    double (&y)[NB]) {
+    if constexpr (NB == 3) {
+        mv3(A, x, y);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) y[i] = dotN<NB>(&A[NB * i], 1, x, 1);
+    }
+}
+// 4x4 inverse by cofactors, from the twelve 2x2 minors of the top and the
+// bottom row pairs (Laplace expansion along those pairs).
+__device__ __forceinline__ void inv4(const double (&M)[16], double (&I)[16]) {
+    const double s0 = M[0] * M[5] - M[4] * M[1], s1 = M[0] * M[6] - M[4] * M[2];
+    const double s2 = M[0] * M[7] - M[4] * M[3], s3 = M[1] * M[6] - M[5] * M[2];
+    const double s4 = M[1] * M[7] - M[5] * M[3], s5 = M[2] * M[7] - M[6] * M[3];
+    const double c5 = M[10] * M[15] - M[14] * M[11], c4 = M[9] * M[15] - M[13] * M[11];
+    const double c3 = M[9] * M[14] - M[13] * M[10], c2 = M[8] * M[15] - M[12] * M[11];
+    const double c1 = M[8] * M[14] - M[12] * M[10], c0 = M[8] * M[13] - M[12] * M[9];
+    const double id = rcp_t(s0 * c5 - s1 * c4 + s2 * c3 + s3 * c2 - s4 * c1 + s5 * c0);
+    I[0] = (M[5] * c5 - M[6] * c4 + M[7] * c3) * id;
+    I[1] = (-M[1] * c5 + M[2] * c4 - M[3] * c3) * id;
+    I[2] = (M[13] * s5 - M[14] * s4 + M[15] * s3) * id;
+    I[3] = (-M[9] * s5 + M[10] * s4 - M[11] * s3) * id;
+    I[4] = (-M[4] * c5 + M[6] * c2 - M[7] * c1) * id;
+    I[5] = (M[0] * c5 - M[2] * c2 + M[3] * c1) * id;
+    I[6] = (-M[12] * s5 + M[14] * s2 - M[15] * s1) * id;
+    I[7] = (M[8] * s5 - M[10] * s2 + M[11] * s1) * id;
+    I[8] = (M[4] * c4 - M[5] * c2 + M[7] * c0) * id;
+    I[9] = (-M[0] * c4 + M[1] * c2 - M[3] * c0) * id;
+    I[10] = (M[12] * s4 - M[13] * s2 + M[15] * s0) * id;
+    I[11] = (-M[8] * s4 + M[9] * s2 - M[11] * s0) * id;
+    I[12] = (-M[4] * c3 + M[5] * c1 - M[6] * c0) * id;
+    I[13] = (M[0] * c3 - M[1] * c1 + M[2] * c0) * id;
+    I[14] = (-M[12] * s3 + M[13] * s1 - M[14] * s0) * id;
+    I[15] = (M[8] * s3 - M[9] * s1 + M[10] * s0) * id;
+}
+template <int NB>
+__device__ __forceinline__ void invN(const double (&M)[NB * NB], double (&I)[NB * NB]) {
+    if constexpr (NB == 3) inv3(M, I);
+    else inv4(M, I);
+}
+
+// Left eigenvectors for a line of the 2D operator, in the line's own
+// component order (rho, normal momentum, tangential momentum, E): the Roe
+// average of Ua and Ub and, there, the rows for the fields u_n - a, u_n
+// (entropy), u_n (shear, carrying u_t) and u_n + a.  With q^2 = u_n^2 +
+// u_t^2, b1 = (gamma - 1) / a^2 and b2 = b1 q^2 / 2 the rows are
+// ((b2 + u_n/a)/2, -(b1 u_n + 1/a)/2, -b1 u_t/2, b1/2), (1 - b2, b1 u_n,
+// b1 u_t, -b1), (-u_t, 0, 1, 0) and ((b2 - u_n/a)/2, (1/a - b1 u_n)/2,
+// -b1 u_t/2, b1/2).  A Roe sound speed that is not positive leaves the
+// node component-wise (L = I).
+__device__ __forceinline__ void roe_left4(double g, const double (&Ua)[4], const double (&Ub)[4],
+                                          double (&L)[16]) {
+    const double ira = rcp_t(Ua[0]), irb = rcp_t(Ub[0]);
+    const double una = Ua[1] * ira, unb = Ub[1] * irb, uta = Ua[2] * ira, utb = Ub[2] * irb;
+    const double pa = (g - 1.0) * (Ua[3] - 0.5 * fma(Ua[1], una, Ua[2] * uta));
+    const double pb = (g - 1.0) * (Ub[3] - 0.5 * fma(Ub[1], unb, Ub[2] * utb));
+    const double Ha = (Ua[3] + pa) * ira, Hb = (Ub[3] + pb) * irb;
+    const double sa = sqrt_nn(Ua[0]), sb = sqrt_nn(Ub[0]);
+    const double iw = rcp_t(sa + sb);
+    const double un = (sa * una + sb * unb) * iw, ut = (sa * uta + sb * utb) * iw;
+    const double H = (sa * Ha + sb * Hb) * iw;
+    const double q2 = fma(un, un, ut * ut);
+    const double a2 = (g - 1.0) * (H - 0.5 * q2);
+    if (!(a2 > 0.0)) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) L[i] = (i % 5 == 0) ? 1.0 : 0.0;
+        return;
+    }
+    const double ia2 = rcp_t(a2);
+    const double ia = sqrt_nn(a2) * ia2;   // 1/a
+    const double b1 = (g - 1.0) * ia2, b2 = 0.5 * q2 * b1;
+    L[0] = 0.5 * (b2 + un * ia);
+    L[1] = 0.5 * (-b1 * un - ia);
+    L[2] = -0.5 * b1 * ut;
+    L[3] = 0.5 * b1;
+    L[4] = 1.0 - b2;
+    L[5] = b1 * un;
+    L[6] = b1 * ut;
+    L[7] = -b1;
+    L[8] = -ut;
+    L[9] = 0.0;
+    L[10] = 1.0;
+    L[11] = 0.0;
+    L[12] = 0.5 * (b2 - un * ia);
+    L[13] = 0.5 * (-b1 * un + ia);
+    L[14] = -0.5 * b1 * ut;
+    L[15] = 0.5 * b1;
+}
+
 // ------------------------------------------------------------- Sec 2.4
 // HLLC flux across a face with normal momentum component NRM (1: x, 2: y).
 // Contact speed with rho_r in its right term, S_R = max of its candidates,

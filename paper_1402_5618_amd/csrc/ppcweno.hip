@@ -112,6 +112,8 @@ struct LineArgs {
     double* commit;         // batched, restart rule: state the stage-3 output is copied into
     unsigned long long* restart_count;   // batched, restart rule: redone steps (all problems)
     double* chs;            // characteristic reconstruction: scratch of the block solves
+    long long chs_side;     //   doubles of one side's row scratch
+    long long chs_line;     //   doubles of one line's scratch (0: one line)
 };
 
 template <int NT>
@@ -600,40 +602,48 @@ __global__ void __launch_bounds__(64 * W) tridiag_debug_kernel(const double* __r
 }
 
 // ------------------------------------------------ Sec 2.3, characteristic
-// Scratch of the characteristic block solve of one line: per side, per row j
-// of a lane's chunk (at most kCharCH rows), kCharRec doubles per lane,
-// lane-minor so a wave's accesses are coalesced; then the nodal values
-// [side][3][n].
-constexpr int kCharCH = 64;
-constexpr int kCharRec = 21;   // a 3x3 block, a 3-vector and a 3x3 block
-constexpr long long kCharSide = (long long)kCharCH * kCharRec * 64;
-constexpr long long kCharScratch = 2 * kCharSide + 6LL * 4096;
+// Scratch of the characteristic block solves of one line: per side, per row
+// j of a lane's chunk, kCharRec(NB) doubles per lane, lane-minor so a
+// wave's accesses are coalesced; then the nodal values [side][NB][n].  The
+// 2D sweeps give every line of a launch its own scratch.
+constexpr int kCharRec(int nb) { return 2 * nb * nb + nb; }   // two blocks and a vector
+constexpr int kCharRows(int n) { return (n + 63) / 64 + 1; }  // >= the rows of any lane's chunk
+constexpr long long char_side_len(int nb, int n) { return (long long)kCharRows(n) * kCharRec(nb) * 64; }
+constexpr long long char_line_len(int nb, int n) { return 2 * char_side_len(nb, n) + 2LL * nb * n; }
 
-__device__ __forceinline__ void shfl9(const double (&v)[9], int src, double (&o)[9]) {
+template <int NB>
+__device__ __forceinline__ void shflN(const double (&v)[NB], int src, double (&o)[NB]) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) o[i] = __shfl(v[i], src);
+    for (int i = 0; i < NB; ++i) o[i] = __shfl(v[i], src);
 }
-__device__ __forceinline__ void shfl3(const double (&v)[3], int src, double (&o)[3]) {
+template <int NB>
+__device__ __forceinline__ void set_identity(double (&M)[NB * NB]) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) o[i] = __shfl(v[i], src);
+    for (int i = 0; i < NB * NB; ++i) M[i] = (i % (NB + 1) == 0) ? 1.0 : 0.0;
 }
 
-// One side of the characteristic-wise reconstruction of a 1D line, by one
-// wave (lane k): the 3x3 block tridiagonal system (1DEuler-FVC) whose row j
-// sits at node j+1/2 of the line (the "+" side runs on the reversed line, as
-// the scalar path does), A_j x_{j-1} + B_j x_j + C_j x_{j+1} = r_j with
-// A_j = diag(a^(k)) L_j etc., L_j the left eigenvectors at the Roe average of
-// cells j and j+1, a^(k)... the rows of eq. (CWENO-FV) built from the
-// characteristic variables l^(k) . Ubar of the stencil.  Each lane chases
-// its chunk of rows with the left separator kept symbolic, reduces its last
-// row onto the separators, the separator system is solved by block parallel
-// cyclic reduction across the wave, and each lane recovers its rows.
-// sU: the line in LDS ([3][LP], ghosts included); xs: the nodal values
-// [3][n] of this side (reversed order for the "+" side).
-template <int PSH>
+// One side of the characteristic-wise reconstruction of a line, by one wave
+// (lane k): the NB x NB block tridiagonal system (1DEuler-FVC) whose row j
+// sits at node j+1/2 of the line (the "+" side runs on the reversed line,
+// as the scalar path does), A_j x_{j-1} + B_j x_j + C_j x_{j+1} = r_j with
+// A_j = diag(a^(k)) L_j etc., L_j the left eigenvectors at the Roe average
+// of cells j and j+1, a^(k)... the rows of eq. (CWENO-FV) built from the
+// characteristic variables l^(k) . Ubar of the stencil.  NB = 3: a 1D line
+// (rho, rho u, E); NB = 4: a line of the 2D operator whose normal momentum
+// is component NRM, worked in the line's own order (rho, normal momentum,
+// tangential momentum, E) so that x and y lines run the same arithmetic.
+// Each lane chases its chunk of rows with the left separator kept
+// symbolic, reduces its last row onto the separators, the separator system
+// is solved by block parallel cyclic reduction across the wave, and each
+// lane recovers its rows.  sU: the line in LDS ([NB][LP], ghosts included);
+// scr: this side's row scratch; xs: the nodal values [NB][n] of this side
+// (reversed order for the "+" side), components in the grid's order.
+template <int NB, int NRM, int PSH>
 __device__ void char_side(const double* __restrict__ sU, int LP, int n, bool cyclic, bool rev,
                           int k, double gam, double weps, double* __restrict__ scr,
                           double* __restrict__ xs) {
+    constexpr int BB = NB * NB;
+    constexpr int REC = kCharRec(NB);
     int P = 64, lgP = 6;
     while (P > n) {
         P >>= 1;
@@ -643,168 +653,175 @@ __device__ void char_side(const double* __restrict__ sU, int LP, int n, bool cyc
     const int r0 = act ? (int)(((unsigned)k * (unsigned)n) >> lgP) : 0;
     const int r1 = act ? (int)(((unsigned)(k + 1) * (unsigned)n) >> lgP) : 0;
     const int len = r1 - r0;
+    // the line's component c (own order) in the grid's order
+    auto gcomp = [](int c) -> int {
+        if constexpr (NB == 4) return c == 1 ? NRM : (c == 2 ? 3 - NRM : c);
+        else return c;
+    };
     auto cell = [&](int c, int m) -> double {
         const int o = rev ? (n - 1 - m) : m;
-        return sU[c * LP + padn<PSH>(o + kNG)];
+        return sU[gcomp(c) * LP + padn<PSH>(o + kNG)];
     };
-    auto rec = [&](int j, int q) -> double& { return scr[((long long)j * kCharRec + q) * 64 + k]; };
+    auto rec = [&](int j, int q) -> double& { return scr[((long long)j * REC + q) * 64 + k]; };
     // closure values just outside a non-periodic line (explicit WENO5-Z per
     // component, as the component-wise path)
-    double xlo[3] = {0.0, 0.0, 0.0}, xhi[3] = {0.0, 0.0, 0.0};
+    double xlo[NB], xhi[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) xlo[c] = xhi[c] = 0.0;
     if (act && !cyclic && r0 == 0) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < NB; ++c)
             xlo[c] = weno5z_value(cell(c, -3), cell(c, -2), cell(c, -1), cell(c, 0), cell(c, 1), weps);
     }
     if (act && !cyclic && r1 == n) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < NB; ++c)
             xhi[c] = weno5z_value(cell(c, n - 2), cell(c, n - 1), cell(c, n), cell(c, n + 1),
                                   cell(c, n + 2), weps);
     }
-    auto rows = [&](int gg, double (&A)[9], double (&B)[9], double (&C)[9], double (&r)[3]) {
-        double Ua[3], Ub[3], L[9], u5[5][3];
+    auto rows = [&](int gg, double (&A)[BB], double (&B)[BB], double (&C)[BB], double (&r)[NB]) {
+        double Ua[NB], Ub[NB], L[BB], u5[5][NB];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < NB; ++c) {
             Ua[c] = cell(c, gg);
             Ub[c] = cell(c, gg + 1);
         }
-        roe_left(gam, Ua, Ub, L);
+        if constexpr (NB == 3) roe_left(gam, Ua, Ub, L);
+        else roe_left4(gam, Ua, Ub, L);
 #pragma unroll
         for (int m = 0; m < 5; ++m)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) u5[m][c] = cell(c, gg - 2 + m);
+            for (int c = 0; c < NB; ++c) u5[m][c] = cell(c, gg - 2 + m);
 #pragma unroll
-        for (int f = 0; f < 3; ++f) {
+        for (int f = 0; f < NB; ++f) {
             double v[5];
 #pragma unroll
-            for (int m = 0; m < 5; ++m)
-                v[m] = fma(L[3 * f], u5[m][0], fma(L[3 * f + 1], u5[m][1], L[3 * f + 2] * u5[m][2]));
+            for (int m = 0; m < 5; ++m) v[m] = dotN<NB>(&L[NB * f], 1, u5[m], 1);
             double w0, w1, w2, a, b, cc, rr;
             wenoz_weights<double>(v[0], v[1], v[2], v[3], v[4], weps, w0, w1, w2);
             cweno_row<double>(w0, w1, w2, v[1], v[2], v[3], a, b, cc, rr);
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                A[3 * f + q] = a * L[3 * f + q];
-                B[3 * f + q] = b * L[3 * f + q];
-                C[3 * f + q] = cc * L[3 * f + q];
+            for (int q = 0; q < NB; ++q) {
+                A[NB * f + q] = a * L[NB * f + q];
+                B[NB * f + q] = b * L[NB * f + q];
+                C[NB * f + q] = cc * L[NB * f + q];
             }
             r[f] = rr;
         }
         if (!cyclic) {   // the known closure values move to the right side
             if (gg == 0) {
-                double t[3];
-                mv3(A, xlo, t);
+                double t[NB];
+                mvN<NB>(A, xlo, t);
 #pragma unroll
-                for (int i = 0; i < 3; ++i) r[i] -= t[i];
+                for (int i = 0; i < NB; ++i) r[i] -= t[i];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) A[i] = 0.0;
+                for (int i = 0; i < BB; ++i) A[i] = 0.0;
             }
             if (gg == n - 1) {
-                double t[3];
-                mv3(C, xhi, t);
+                double t[NB];
+                mvN<NB>(C, xhi, t);
 #pragma unroll
-                for (int i = 0; i < 3; ++i) r[i] -= t[i];
+                for (int i = 0; i < NB; ++i) r[i] -= t[i];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) C[i] = 0.0;
+                for (int i = 0; i < BB; ++i) C[i] = 0.0;
             }
         }
     };
     // forward chase: x_j = p_j + Q_j Lsep - Cp_j x_{j+1}
-    double cp[9], pp[3], qq[9];
+    double cp[BB], pp[NB], qq[BB];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        cp[i] = 0.0;
-        qq[i] = (i % 4 == 0) ? 1.0 : 0.0;
-    }
-    pp[0] = pp[1] = pp[2] = 0.0;
-    double Ak[9], Bk[9], Ck[9], Dk[3];   // this lane's separator row
-    double FP[3] = {0.0, 0.0, 0.0}, FQ[9], FS[9];   // first row: x_{r0} = FP + FQ Lsep + FS Rsep
+    for (int i = 0; i < BB; ++i) cp[i] = 0.0;
+    set_identity<NB>(qq);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < NB; ++i) pp[i] = 0.0;
+    double Ak[BB], Bk[BB], Ck[BB], Dk[NB];   // this lane's separator row
+    double FP[NB], FQ[BB], FS[BB];   // first row: x_{r0} = FP + FQ Lsep + FS Rsep
+#pragma unroll
+    for (int i = 0; i < BB; ++i) {
         FQ[i] = 0.0;
-        FS[i] = (i % 4 == 0) ? 1.0 : 0.0;
         Ak[i] = 0.0;
         Ck[i] = 0.0;
-        Bk[i] = (i % 4 == 0) ? 1.0 : 0.0;
     }
-    Dk[0] = Dk[1] = Dk[2] = 0.0;
-    double CX[9];   // the separator row's coupling to the next chunk's first row
+    set_identity<NB>(FS);
+    set_identity<NB>(Bk);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) CX[i] = 0.0;
+    for (int i = 0; i < NB; ++i) Dk[i] = FP[i] = 0.0;
+    double CX[BB];   // the separator row's coupling to the next chunk's first row
+#pragma unroll
+    for (int i = 0; i < BB; ++i) CX[i] = 0.0;
     if (act) {
         for (int j = 0; j < len - 1; ++j) {
-            double A[9], B[9], C[9], r[3], M[9], T[9], Mi[9], t3[3];
+            double A[BB], B[BB], C[BB], r[NB], M[BB], T[BB], Mi[BB], t3[NB];
             rows(r0 + j, A, B, C, r);
-            mm3(A, cp, T);
+            mmN<NB>(A, cp, T);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) M[i] = B[i] - T[i];
-            mv3(A, pp, t3);
+            for (int i = 0; i < BB; ++i) M[i] = B[i] - T[i];
+            mvN<NB>(A, pp, t3);
 #pragma unroll
-            for (int i = 0; i < 3; ++i) t3[i] = r[i] - t3[i];
-            mm3(A, qq, T);
+            for (int i = 0; i < NB; ++i) t3[i] = r[i] - t3[i];
+            mmN<NB>(A, qq, T);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) T[i] = -T[i];
-            inv3(M, Mi);
-            mm3(Mi, C, cp);
-            mv3(Mi, t3, pp);
-            mm3(Mi, T, qq);
+            for (int i = 0; i < BB; ++i) T[i] = -T[i];
+            invN<NB>(M, Mi);
+            mmN<NB>(Mi, C, cp);
+            mvN<NB>(Mi, t3, pp);
+            mmN<NB>(Mi, T, qq);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
+            for (int i = 0; i < BB; ++i) {
                 rec(j, i) = cp[i];
-                rec(j, 12 + i) = qq[i];
+                rec(j, BB + NB + i) = qq[i];
             }
 #pragma unroll
-            for (int i = 0; i < 3; ++i) rec(j, 9 + i) = pp[i];
+            for (int i = 0; i < NB; ++i) rec(j, BB + i) = pp[i];
         }
-        double A[9], B[9], r[3], T[9], t3[3];
+        double A[BB], B[BB], r[NB], T[BB], t3[NB];
         rows(r1 - 1, A, B, CX, r);
-        mm3(A, qq, Ak);
-        mm3(A, cp, T);
+        mmN<NB>(A, qq, Ak);
+        mmN<NB>(A, cp, T);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) Bk[i] = B[i] - T[i];
-        mv3(A, pp, t3);
+        for (int i = 0; i < BB; ++i) Bk[i] = B[i] - T[i];
+        mvN<NB>(A, pp, t3);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) Dk[i] = r[i] - t3[i];
+        for (int i = 0; i < NB; ++i) Dk[i] = r[i] - t3[i];
         // symbolic back substitution: x_j = P_j + Qb_j Lsep + S_j Rsep
         for (int j = len - 2; j >= 0; --j) {
-            double cj[9], pj[3], qj[9], Pn[3], Qn[9], Sn[9], T2[9];
+            double cj[BB], pj[NB], qj[BB], Pn[NB], Qn[BB], Sn[BB], T2[BB];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
+            for (int i = 0; i < BB; ++i) {
                 cj[i] = rec(j, i);
-                qj[i] = rec(j, 12 + i);
+                qj[i] = rec(j, BB + NB + i);
             }
 #pragma unroll
-            for (int i = 0; i < 3; ++i) pj[i] = rec(j, 9 + i);
+            for (int i = 0; i < NB; ++i) pj[i] = rec(j, BB + i);
             if (j == len - 2) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
+                for (int i = 0; i < BB; ++i) {
                     Qn[i] = qj[i];
                     Sn[i] = -cj[i];
                 }
 #pragma unroll
-                for (int i = 0; i < 3; ++i) Pn[i] = pj[i];
+                for (int i = 0; i < NB; ++i) Pn[i] = pj[i];
             } else {
-                mv3(cj, FP, t3);
+                mvN<NB>(cj, FP, t3);
 #pragma unroll
-                for (int i = 0; i < 3; ++i) Pn[i] = pj[i] - t3[i];
-                mm3(cj, FQ, T2);
+                for (int i = 0; i < NB; ++i) Pn[i] = pj[i] - t3[i];
+                mmN<NB>(cj, FQ, T2);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) Qn[i] = qj[i] - T2[i];
-                mm3(cj, FS, T2);
+                for (int i = 0; i < BB; ++i) Qn[i] = qj[i] - T2[i];
+                mmN<NB>(cj, FS, T2);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) Sn[i] = -T2[i];
+                for (int i = 0; i < BB; ++i) Sn[i] = -T2[i];
             }
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
+            for (int i = 0; i < BB; ++i) {
                 rec(j, i) = Qn[i];
-                rec(j, 9 + i) = Sn[i];
+                rec(j, BB + i) = Sn[i];
                 FQ[i] = Qn[i];
                 FS[i] = Sn[i];
             }
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                rec(j, 18 + i) = Pn[i];
+            for (int i = 0; i < NB; ++i) {
+                rec(j, 2 * BB + i) = Pn[i];
                 FP[i] = Pn[i];
             }
         }
@@ -812,109 +829,114 @@ __device__ void char_side(const double* __restrict__ sU, int LP, int n, bool cyc
     // the next chunk's first-row relation (x_{r1} = FP' + FQ' Rsep + FS' Rsep')
     {
         const int kn = (k + 1) & (P - 1);
-        double nP[3], nQ[9], nS[9], T[9], t3[3];
-        shfl3(FP, kn, nP);
-        shfl9(FQ, kn, nQ);
-        shfl9(FS, kn, nS);
-        mm3(CX, nQ, T);
+        double nP[NB], nQ[BB], nS[BB], T[BB], t3[NB];
+        shflN<NB>(FP, kn, nP);
+        shflN<BB>(FQ, kn, nQ);
+        shflN<BB>(FS, kn, nS);
+        mmN<NB>(CX, nQ, T);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) Bk[i] += T[i];
-        mm3(CX, nS, Ck);
-        mv3(CX, nP, t3);
+        for (int i = 0; i < BB; ++i) Bk[i] += T[i];
+        mmN<NB>(CX, nS, Ck);
+        mvN<NB>(CX, nP, t3);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) Dk[i] -= t3[i];
+        for (int i = 0; i < NB; ++i) Dk[i] -= t3[i];
     }
     // block parallel cyclic reduction of the separator system over the wave
     for (int st = 1; st < P; st <<= 1) {
         const int km = (k - st) & (P - 1), kp = (k + st) & (P - 1);
-        double Am[9], Bm[9], Cm[9], Dm[3], Ap[9], Bp[9], Cp[9], Dp[3];
-        shfl9(Ak, km, Am);
-        shfl9(Bk, km, Bm);
-        shfl9(Ck, km, Cm);
-        shfl3(Dk, km, Dm);
-        shfl9(Ak, kp, Ap);
-        shfl9(Bk, kp, Bp);
-        shfl9(Ck, kp, Cp);
-        shfl3(Dk, kp, Dp);
+        double Am[BB], Bm[BB], Cm[BB], Dm[NB], Ap[BB], Bp[BB], Cp[BB], Dp[NB];
+        shflN<BB>(Ak, km, Am);
+        shflN<BB>(Bk, km, Bm);
+        shflN<BB>(Ck, km, Cm);
+        shflN<NB>(Dk, km, Dm);
+        shflN<BB>(Ak, kp, Ap);
+        shflN<BB>(Bk, kp, Bp);
+        shflN<BB>(Ck, kp, Cp);
+        shflN<NB>(Dk, kp, Dp);
         if (!cyclic) {
             if (k - st < 0) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
+                for (int i = 0; i < BB; ++i) {
                     Am[i] = 0.0;
                     Cm[i] = 0.0;
-                    Bm[i] = (i % 4 == 0) ? 1.0 : 0.0;
                 }
-                Dm[0] = Dm[1] = Dm[2] = 0.0;
+                set_identity<NB>(Bm);
+#pragma unroll
+                for (int i = 0; i < NB; ++i) Dm[i] = 0.0;
             }
             if (k + st >= P) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
+                for (int i = 0; i < BB; ++i) {
                     Ap[i] = 0.0;
                     Cp[i] = 0.0;
-                    Bp[i] = (i % 4 == 0) ? 1.0 : 0.0;
                 }
-                Dp[0] = Dp[1] = Dp[2] = 0.0;
+                set_identity<NB>(Bp);
+#pragma unroll
+                for (int i = 0; i < NB; ++i) Dp[i] = 0.0;
             }
         }
-        double iBm[9], iBp[9], al[9], bt[9], T[9], t3[3];
-        inv3(Bm, iBm);
-        inv3(Bp, iBp);
-        mm3(Ak, iBm, al);
-        mm3(Ck, iBp, bt);
+        double iBm[BB], iBp[BB], al[BB], bt[BB], T[BB], t3[NB];
+        invN<NB>(Bm, iBm);
+        invN<NB>(Bp, iBp);
+        mmN<NB>(Ak, iBm, al);
+        mmN<NB>(Ck, iBp, bt);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
+        for (int i = 0; i < BB; ++i) {
             al[i] = -al[i];
             bt[i] = -bt[i];
         }
-        double nB[9], nD[3];
-        mm3(al, Cm, T);
+        double nB[BB], nD[NB];
+        mmN<NB>(al, Cm, T);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) nB[i] = Bk[i] + T[i];
-        mm3(bt, Ap, T);
+        for (int i = 0; i < BB; ++i) nB[i] = Bk[i] + T[i];
+        mmN<NB>(bt, Ap, T);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) nB[i] += T[i];
-        mv3(al, Dm, t3);
+        for (int i = 0; i < BB; ++i) nB[i] += T[i];
+        mvN<NB>(al, Dm, t3);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) nD[i] = Dk[i] + t3[i];
-        mv3(bt, Dp, t3);
+        for (int i = 0; i < NB; ++i) nD[i] = Dk[i] + t3[i];
+        mvN<NB>(bt, Dp, t3);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) nD[i] += t3[i];
-        mm3(al, Am, Ak);
-        mm3(bt, Cp, Ck);
+        for (int i = 0; i < NB; ++i) nD[i] += t3[i];
+        mmN<NB>(al, Am, Ak);
+        mmN<NB>(bt, Cp, Ck);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) Bk[i] = nB[i];
+        for (int i = 0; i < BB; ++i) Bk[i] = nB[i];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) Dk[i] = nD[i];
+        for (int i = 0; i < NB; ++i) Dk[i] = nD[i];
     }
-    double Rs[3], Ls[3];
+    double Rs[NB], Ls[NB];
     {
-        double M[9], Mi[9];
+        double M[BB], Mi[BB];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) M[i] = cyclic ? Ak[i] + Bk[i] + Ck[i] : Bk[i];
-        inv3(M, Mi);
-        mv3(Mi, Dk, Rs);
-        shfl3(Rs, (k - 1) & (P - 1), Ls);
-        if (!cyclic && k == 0) Ls[0] = Ls[1] = Ls[2] = 0.0;
+        for (int i = 0; i < BB; ++i) M[i] = cyclic ? Ak[i] + Bk[i] + Ck[i] : Bk[i];
+        invN<NB>(M, Mi);
+        mvN<NB>(Mi, Dk, Rs);
+        shflN<NB>(Rs, (k - 1) & (P - 1), Ls);
+        if (!cyclic && k == 0) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i) Ls[i] = 0.0;
+        }
     }
     if (act) {
         for (int j = 0; j < len - 1; ++j) {
-            double Qb[9], S[9], x[3], t3[3];
+            double Qb[BB], S[BB], x[NB], t3[NB];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
+            for (int i = 0; i < BB; ++i) {
                 Qb[i] = rec(j, i);
-                S[i] = rec(j, 9 + i);
+                S[i] = rec(j, BB + i);
             }
 #pragma unroll
-            for (int i = 0; i < 3; ++i) x[i] = rec(j, 18 + i);
-            mv3(Qb, Ls, t3);
+            for (int i = 0; i < NB; ++i) x[i] = rec(j, 2 * BB + i);
+            mvN<NB>(Qb, Ls, t3);
 #pragma unroll
-            for (int i = 0; i < 3; ++i) x[i] += t3[i];
-            mv3(S, Rs, t3);
+            for (int i = 0; i < NB; ++i) x[i] += t3[i];
+            mvN<NB>(S, Rs, t3);
 #pragma unroll
-            for (int i = 0; i < 3; ++i) xs[(long long)i * n + r0 + j] = x[i] + t3[i];
+            for (int i = 0; i < NB; ++i) xs[(long long)gcomp(i) * n + r0 + j] = x[i] + t3[i];
         }
 #pragma unroll
-        for (int i = 0; i < 3; ++i) xs[(long long)i * n + r1 - 1] = Rs[i];
+        for (int i = 0; i < NB; ++i) xs[(long long)gcomp(i) * n + r1 - 1] = Rs[i];
     }
 }
 
@@ -1094,19 +1116,20 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
             paired_solve<false>(sUc, n, k, P, cyclic, A.weno_eps, sxc, red + 4 * comp, r0, len, E0,
                                 E1, E2, F0, F1, F2);
     } else if constexpr (RECON == PP_RECON_CHAR) {
-        // characteristic-wise (1D, FP64): waves 0 and 1 solve the block
-        // systems of the "-" side and of the "+" side (the reversed line);
-        // every (component, side) lane then takes its chunk of nodal values
-        static_assert(NC == 3 && !MIXED, "characteristic reconstruction: 1D, FP64");
-        double* const xsb = A.chs + 2 * kCharSide;   // [side][3][n]
+        // characteristic-wise (FP64): waves 0 and 1 solve the block systems
+        // of the "-" side and of the "+" side (the reversed line); every
+        // (component, side) lane then takes its chunk of nodal values
+        static_assert(!MIXED, "characteristic reconstruction runs in FP64");
+        double* const chl = A.chs + (long long)b * A.chs_line;   // this line's scratch
+        double* const xsb = chl + 2 * A.chs_side;                  // [side][NC][n]
         if (tid < 128) {
             const int side = tid >> 6;
-            char_side<PSH>(sU, LP, n, cyclic, side == 1, tid & 63, A.gamma, A.weno_eps,
-                           A.chs + side * kCharSide, xsb + (long long)side * 3 * n);
+            char_side<NC, NRM, PSH>(sU, LP, n, cyclic, side == 1, tid & 63, A.gamma, A.weno_eps,
+                                    chl + side * A.chs_side, xsb + (long long)side * NC * n);
         }
         __syncthreads();
         if (act) {
-            const double* xsrc = xsb + (long long)(rev ? 1 : 0) * 3 * n + (long long)comp * n;
+            const double* xsrc = xsb + (long long)(rev ? 1 : 0) * NC * n + (long long)comp * n;
 #pragma unroll
             for (int j = 0; j < kCH; ++j)
                 if (j < len) E0[j] = xsrc[r0 + j];
@@ -2459,12 +2482,11 @@ int launch_line(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int gr
         // init admits the other reconstructions only in FP64 and without a batch
         if (persistent) return fail(ctx, PP_EUNSUPPORTED, "explicit schemes are not batched");
         if (ctx->cfg.recon == PP_RECON_CHAR) {
-            if constexpr (NC == 3) {
-                A.chs = ctx->chs;
-                return launch_line_explicit<NC, NRM, W, CPT, PP_RECON_CHAR>(ctx, A, nmax);
-            } else {
-                return fail(ctx, PP_EUNSUPPORTED, "characteristic reconstruction runs in 1D");
-            }
+            // every line of the launch has its own scratch (init sized it)
+            A.chs = ctx->chs;
+            A.chs_side = char_side_len(NC, A.n);
+            A.chs_line = char_line_len(NC, A.n);
+            return launch_line_explicit<NC, NRM, W, CPT, PP_RECON_CHAR>(ctx, A, nmax);
         }
         return ctx->cfg.recon == PP_RECON_WENOJS
                    ? launch_line_explicit<NC, NRM, W, CPT, PP_RECON_WENOJS>(ctx, A, nmax)
@@ -2931,8 +2953,6 @@ int check_config(const pp_cweno_config& c) {
     if (c.recon != PP_RECON_CWENO && c.recon != PP_RECON_WENOJS && c.recon != PP_RECON_WENOZ &&
         c.recon != PP_RECON_CHAR)
         return fail(nullptr, PP_EINVAL, "recon must be PP_RECON_CWENO, _WENOJS, _WENOZ or _CHAR");
-    if (c.recon == PP_RECON_CHAR && c.ndim != 1)
-        return fail(nullptr, PP_EUNSUPPORTED, "characteristic reconstruction runs in 1D");
     if (c.recon != PP_RECON_CWENO && (c.precision != PP_FP64 || c.nbatch > 0))
         return fail(nullptr, PP_EUNSUPPORTED, "explicit schemes run in FP64 and unbatched");
     if (!(c.weno_eps > 0.0) || !(c.pp_eps_cap > 0.0))
@@ -3088,8 +3108,15 @@ int pp_cweno_init(const pp_cweno_config* cfg, pp_cweno_ctx** out) {
         const size_t bytes = sizeof(double) * ctx->nc * ctx->ncell;
         if (!dmalloc((void**)&ctx->U1, bytes) || !dmalloc((void**)&ctx->U2, bytes))
             return bail(PP_ENOMEM);
-        if (c.recon == PP_RECON_CHAR && !dmalloc((void**)&ctx->chs, sizeof(double) * kCharScratch))
-            return bail(PP_ENOMEM);
+        if (c.recon == PP_RECON_CHAR) {
+            // the block-solve scratch of every line of a sweep (2D: the
+            // larger of the x sweep's ny lines and the y sweep's nx lines)
+            const long long len = c.ndim == 2
+                                      ? std::max((long long)c.ny * char_line_len(4, (int)c.nx),
+                                                 (long long)c.nx * char_line_len(4, (int)c.ny))
+                                      : char_line_len(3, (int)c.nx);
+            if (!dmalloc((void**)&ctx->chs, sizeof(double) * (size_t)len)) return bail(PP_ENOMEM);
+        }
         if (c.ndim == 2) {
             if (!dmalloc((void**)&ctx->UA, bytes) || !dmalloc((void**)&ctx->UB, bytes) ||
                 !dmalloc((void**)&ctx->U1B, bytes) || !dmalloc((void**)&ctx->U2B, bytes) ||

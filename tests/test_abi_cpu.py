@@ -61,8 +61,9 @@ def _init(**kw):
     (dict(flux=2), pp.PP_EINVAL),
     (dict(flux=-1), pp.PP_EINVAL),
     (dict(recon=4), pp.PP_EINVAL),
-    (dict(recon=3, ndim=2, ny=64, dy=0.01), pp.PP_EUNSUPPORTED),   # characteristic: 1D
-    (dict(recon=3, precision=1), pp.PP_EUNSUPPORTED),             # and FP64
+    (dict(recon=3, precision=1), pp.PP_EUNSUPPORTED),             # characteristic: FP64
+    (dict(recon=3, ndim=2, ny=64, dy=0.01, precision=1), pp.PP_EUNSUPPORTED),   # also in 2D
+    (dict(recon=3, nbatch=2), pp.PP_EUNSUPPORTED),                # and not batched
     (dict(recon=-1), pp.PP_EINVAL),
     (dict(recon=1, precision=1), pp.PP_EUNSUPPORTED),   # explicit schemes: FP64 only
     (dict(recon=2, nbatch=2), pp.PP_EUNSUPPORTED),      # and not batched
@@ -77,6 +78,7 @@ def _init(**kw):
     (dict(fv=1), pp.PP_EUNSUPPORTED),                                # Gauss nodes: 2D
     (dict(fv=1, ndim=2, ny=64, dy=0.01, precision=1), pp.PP_EUNSUPPORTED),   # FP64
     (dict(fv=1, ndim=2, ny=64, dy=0.01, recon=1), pp.PP_EUNSUPPORTED),       # compact scheme
+    (dict(fv=1, ndim=2, ny=64, dy=0.01, recon=3), pp.PP_EUNSUPPORTED),       # component-wise
 ])
 def test_invalid_configs_rejected_before_device(kw, code):
     got, msg = _init(**kw)

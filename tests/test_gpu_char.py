@@ -132,3 +132,255 @@ def test_char_density_wave_equals_componentwise_on_gpu():
     eh = W.error_norms(Uh[0], ex[0], h)[0]
     print(f"L1 component-wise {ec:.6e}, characteristic {eh:.6e}", flush=True)
     assert abs(eh / ec - 1) < 1e-8
+
+
+# ------------------------------------------------------- lines of the 2D operator
+def field_2d(nx, ny, seed=0):
+    """Smooth flow with a dense bubble, a pressure jump and pressure noise."""
+    rng = np.random.default_rng(seed)
+    x = W.cell_centres(0, 1, nx)[None, :]
+    y = W.cell_centres(0, 1, ny)[:, None]
+    rho = 1 + 0.3 * np.sin(2 * np.pi * (x + 2 * y)) + 0.5 * ((x - 0.5) ** 2 + (y - 0.4) ** 2 < 0.06)
+    u = 0.3 * np.cos(2 * np.pi * y) + 0 * x
+    v = -0.2 * np.sin(2 * np.pi * x) + 0 * y
+    p = 1 + 0.5 * (x > 0.6) + 0.1 * rng.normal(size=(ny, nx)) ** 2
+    return np.stack([rho, rho * u, rho * v, p / 0.4 + 0.5 * rho * (u * u + v * v)])
+
+
+def stage_tolerance_2d(U0, Us, st, dt, bc, dx, dy, ref, k=3):
+    """1e-12, or 4x the oracle's own change under 1e-15 input perturbations
+    when larger."""
+    rng = np.random.default_rng(1500 + st)
+    P = oracle.params(**P_CHAR)
+    sens = 0.0
+    for _ in range(k):
+        V = oracle.stage_2d(U0 * (1.0 + 1e-15 * rng.standard_normal(U0.shape)),
+                            Us * (1.0 + 1e-15 * rng.standard_normal(Us.shape)), st, dt, bc,
+                            dx, dy, P)
+        sens = max(sens, comp_rel(V, ref))
+    return max(TOL_STAGE, 4.0 * sens)
+
+
+CASES_2D = [(40, 24, (0, 0, 0, 0)), (33, 17, (1, 2, 2, 1)), (64, 64, (0, 0, 1, 1)),
+            (130, 71, (1, 1, 2, 2)), (2048, 6, (0, 0, 1, 2)), (300, 257, (2, 2, 0, 0))]
+
+
+@pytest.mark.parametrize("nx,ny,bc", CASES_2D)
+def test_char_2d_stage_parity(nx, ny, bc):
+    """The 2D operator with characteristic lines (4x4 block systems along x
+    and along y): L and the three stages against the oracle, on grids with
+    one-chunk, ragged multi-chunk and 2048-cell lines and every boundary
+    kind."""
+    pp = gpu()
+    print(f"char 2d case {nx}x{ny} bc={bc}", flush=True)
+    U = field_2d(nx, ny, seed=nx + ny)
+    dx, dy = 1.0 / nx, 1.0 / ny
+    s_x, s_y = oracle.max_speed_2d(U)
+    dt = (1.0 / 12.0) / (s_x / dx + s_y / dy)
+    P = oracle.params(**P_CHAR)
+    s = pp.Solver(ndim=2, nx=nx, ny=ny, dx=dx, dy=dy, bc=bc, recon=pp.PP_RECON_CHAR)
+    Ud = dev(U)
+    L = torch.empty_like(Ud)
+    s.rhs(Ud, L)
+    Lref = oracle.rhs_2d(U, bc, dx, dy, P)
+    U1 = oracle.stage_2d(U, U, 1, dt, bc, dx, dy, P)
+    U2 = oracle.stage_2d(U, U1, 2, dt, bc, dx, dy, P)
+    U3 = oracle.stage_2d(U, U2, 3, dt, bc, dx, dy, P)
+    o1, o2, o3 = (torch.empty_like(Ud) for _ in range(3))
+    s.stage(Ud, Ud, o1, 1, dt)
+    s.stage(Ud, dev(U1), o2, 2, dt)
+    s.stage(Ud, dev(U2), o3, 3, dt)
+    torch.cuda.synchronize()
+    s.close()
+    # L: relative to max|L| per component, with the flux-difference roundoff
+    # scale of the component (as for the component-wise operator)
+    Lg = L.cpu().numpy()
+    for k in range(4):
+        Fs = np.abs(Lref[k]).max()
+        err = float(np.abs(Lg[k] - Lref[k]).max() / Fs)
+        print(f"  L component {k}: {err:.2e}", flush=True)
+        assert err <= 1e-11
+    for st, (got, ref, Us) in enumerate(((o1, U1, U), (o2, U2, U1), (o3, U3, U2)), start=1):
+        err = comp_rel(got.cpu().numpy(), ref)
+        print(f"  stage {st}: relative difference {err:.2e}", flush=True)
+        if err > TOL_STAGE:
+            tol = stage_tolerance_2d(U, Us, st, dt, bc, dx, dy, ref)
+            print(f"  stage {st}: conditioning bound {tol:.2e}", flush=True)
+            assert err <= tol
+    # a different scheme from the component-wise one on this grid
+    assert comp_rel(oracle.stage_2d(U, U, 1, dt, bc, dx, dy), U1) > 1e-10
+
+
+def mirror(U):
+    """Diagonal mirror of a 2D state: x and y exchanged, with the momenta."""
+    return np.ascontiguousarray(U[[0, 2, 1, 3]].transpose(0, 2, 1))
+
+
+@pytest.mark.parametrize("bc", [(2, 1, 2, 1), (0, 0, 0, 0)])
+def test_char_2d_mirror_symmetry_is_exact(bc):
+    """Characteristic lines run in the line's own component order (rho,
+    normal momentum, tangential momentum, E), so the x-sweep of a row and the
+    y-sweep of the mirrored column perform the same arithmetic: a state
+    symmetric under the diagonal mirror stays bitwise symmetric through 30
+    steps (a blast centred on the diagonal, with a symmetrised
+    perturbation)."""
+    pp = gpu()
+    n = 80
+    dx = 1.0 / n
+    x = W.cell_centres(0, 1, n)[None, :]
+    y = W.cell_centres(0, 1, n)[:, None]
+    r2 = (x - 0.4) ** 2 + (y - 0.4) ** 2
+    rng = np.random.default_rng(12)
+    rho = (1.0 + 0.5 * (r2 < 0.05)) * (1.0 + 0.05 * rng.random((n, n)))
+    p = 0.1 + 2.0 * (r2 < 0.03) + 0 * x
+    U = np.stack([rho, 0 * rho, 0 * rho, p / 0.4])
+    U = 0.5 * (U + mirror(U))
+    assert np.array_equal(U, mirror(U))
+    s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=bc, recon=pp.PP_RECON_CHAR)
+    Ud = dev(U)
+    try:
+        s.run(Ud, 1e30, 30)
+    except pp.PPError as e:   # a stage left G: symmetry still applies to what ran
+        print(f"run stopped: {e}", flush=True)
+    torch.cuda.synchronize()
+    s.close()
+    got = Ud.cpu().numpy()
+    assert np.all(np.isfinite(got))
+    diff = np.abs(got - mirror(got)).max()
+    print(f"bc={bc}: max |U - mirror(U)| = {diff:.3e}", flush=True)
+    assert diff == 0.0
+
+
+def test_char_2d_density_wave_equals_componentwise():
+    """On the 2D density wave (u, v, p constant) three characteristic fields
+    are constant along every line and the characteristic run equals the
+    component-wise run to roundoff (Table 3 against Table 2, in 2D)."""
+    pp = gpu()
+    n = 32
+    U0 = W.density_wave_2d(n, n)
+    out = []
+    for recon in (pp.PP_RECON_CWENO, pp.PP_RECON_CHAR):
+        s = pp.Solver(ndim=2, nx=n, ny=n, dx=2.0 / n, dy=2.0 / n, bc=(0, 0, 0, 0), recon=recon)
+        Ud = dev(U0)
+        t, steps = s.run(Ud, 0.1, 1 << 40, 1.0 / 12.0)
+        s.close()
+        out.append((Ud.cpu().numpy(), t, steps))
+    (Uc, tc, sc), (Uh, th, sh) = out
+    assert sc == sh and tc == th
+    d = comp_rel(Uh, Uc)
+    print(f"characteristic against component-wise after {sc} steps: {d:.2e}", flush=True)
+    assert d < 1e-12
+
+
+def _oracle_run_perturbed(U0, bc, dx, dy, T, P, delta, rng):
+    """The oracle's run of the CFL rule, step by step, with every step's
+    output multiplied by 1 + delta N(0, 1) cell by cell (delta = 0: the plain
+    run)."""
+    U, t, k = U0.copy(), 0.0, 0
+    while t < T:
+        s_x, s_y = oracle.max_speed_2d(U)
+        dt = min((1.0 / 12.0) / (s_x / dx + s_y / dy), T - t)
+        U1 = oracle.stage_2d(U, U, 1, dt, bc, dx, dy, P)
+        U2 = oracle.stage_2d(U, U1, 2, dt, bc, dx, dy, P)
+        U = oracle.stage_2d(U, U2, 3, dt, bc, dx, dy, P)
+        if delta:
+            U = U * (1.0 + delta * rng.standard_normal(U.shape))
+        t += dt
+        k += 1
+    return U, t, k
+
+
+def test_char_2d_smooth_run_matches_oracle():
+    """A whole run of the smooth nonlinear 2D flow (periodic, CFL rule, t =
+    0.05): the same steps and end time as the oracle's characteristic run
+    and the states within 1e-11 (the oracle itself moves by 7e-15 under 1e-15
+    perturbations of the initial data here)."""
+    pp = gpu()
+    nx, ny = 48, 40
+    U0 = W.smooth_flow_2d(nx, ny)
+    bc, dx, dy, T = (0, 0, 0, 0), 1.0 / nx, 1.0 / ny, 0.05
+    ref, t_ref, k_ref = _oracle_run_perturbed(U0, bc, dx, dy, T, oracle.params(**P_CHAR), 0.0, None)
+    s = pp.Solver(ndim=2, nx=nx, ny=ny, dx=dx, dy=dy, bc=bc, recon=pp.PP_RECON_CHAR)
+    Ud = dev(U0)
+    t, steps = s.run(Ud, T, 1 << 40, 1.0 / 12.0)
+    s.close()
+    d = comp_rel(Ud.cpu().numpy(), ref)
+    print(f"steps {steps} (oracle {k_ref}), t {t}, difference {d:.2e}", flush=True)
+    assert steps == k_ref and abs(t - t_ref) <= 1e-14
+    assert d <= 1e-11
+
+
+def test_char_2d_blast_run_matches_oracle():
+    """A whole run of a 2D blast with transmissive and reflective walls (CFL
+    rule, t = 0.05), checked step by step along the GPU's own trajectory:
+    every GPU step equals the oracle's step from the same state to 1e-13,
+    or, where it differs more, to 4x the conditioning of the oracle's own
+    reconstruction at that step: the largest relative change of any line's
+    interface values (before the limiter) under 1e-15 perturbations of a
+    stage input.  The characteristic reconstruction is ill-conditioned at
+    isolated steps of this flow (at one of them a y line's interface values
+    move by 3e-11 under such perturbations), which the step output inherits
+    scaled by about dt |u|+a / h.  The run itself takes the oracle's step
+    count and end time and stays in G."""
+    pp = gpu()
+    nx, ny = 48, 40
+    x = W.cell_centres(0, 1, nx)[None, :]
+    y = W.cell_centres(0, 1, ny)[:, None]
+    r2 = (x - 0.45) ** 2 + (y - 0.55) ** 2
+    rho = 1.0 + 0.5 * (r2 < 0.06) + 0 * x
+    p = 0.4 + 2.0 * (r2 < 0.04) + 0 * y
+    u = 0.3 * np.sin(2 * np.pi * y) + 0 * x
+    v = -0.2 * np.cos(2 * np.pi * x) + 0 * y
+    U0 = np.stack([rho, rho * u, rho * v, p / 0.4 + 0.5 * rho * (u * u + v * v)])
+    bc, dx, dy, T = (1, 2, 2, 1), 1.0 / nx, 1.0 / ny, 0.05
+    P = oracle.params(**P_CHAR)
+    rng = np.random.default_rng(9)
+    s = pp.Solver(ndim=2, nx=nx, ny=ny, dx=dx, dy=dy, bc=bc, recon=pp.PP_RECON_CHAR)
+
+    def oracle_step(V, dt):
+        V1 = oracle.stage_2d(V, V, 1, dt, bc, dx, dy, P)
+        V2 = oracle.stage_2d(V, V1, 2, dt, bc, dx, dy, P)
+        return oracle.stage_2d(V, V2, 3, dt, bc, dx, dy, P), (V, V1, V2)
+
+    def recon_sensitivity(V):
+        worst = 0.0
+        for nrm, lo, hi, h, lines in ((1, bc[0], bc[1], dx, [V[:, j, :] for j in range(ny)]),
+                                      (2, bc[2], bc[3], dy, [V[:, :, i] for i in range(nx)])):
+            for line in lines:
+                line = np.ascontiguousarray(line)
+                _, d0 = oracle.line_op(line, lo, hi, h, p=P, nrm=nrm, debug=True)
+                for _ in range(2):
+                    _, d1 = oracle.line_op(line * (1.0 + 1e-15 * rng.standard_normal(line.shape)),
+                                           lo, hi, h, p=P, nrm=nrm, debug=True)
+                    worst = max(worst, comp_rel(d1["um"], d0["um"]), comp_rel(d1["up"], d0["up"]))
+        return worst
+
+    U, t, k, worst, n_cond = U0.copy(), 0.0, 0, 0.0, 0
+    while t < T:
+        s_x, s_y = oracle.max_speed_2d(U)
+        dt = min((1.0 / 12.0) / (s_x / dx + s_y / dy), T - t)
+        ref, stage_inputs = oracle_step(U, dt)
+        Ud = dev(U)
+        s.step(Ud, dt)
+        got = Ud.cpu().numpy()
+        d = comp_rel(got, ref)
+        if d > 1e-13:
+            sens = max(recon_sensitivity(V) for V in stage_inputs)
+            print(f"  step {k}: one-step difference {d:.2e}, reconstruction conditioning {sens:.2e}",
+                  flush=True)
+            assert d <= 4.0 * sens
+            n_cond += 1
+        worst = max(worst, d)
+        U, t, k = got, t + dt, k + 1
+    print(f"{k} steps: largest one-step difference {worst:.2e}, {n_cond} steps above 1e-13",
+          flush=True)
+    # the whole run through the run driver
+    ref, t_ref, k_ref = _oracle_run_perturbed(U0, bc, dx, dy, T, P, 0.0, None)
+    Ud = dev(U0)
+    t, steps = s.run(Ud, T, 1 << 40, 1.0 / 12.0)
+    s.close()
+    got = Ud.cpu().numpy()
+    print(f"run: steps {steps} (oracle {k_ref}), t {t}, difference {comp_rel(got, ref):.2e}",
+          flush=True)
+    assert steps == k_ref and abs(t - t_ref) <= 1e-14
+    assert got[0].min() > 0 and W.pressure(got).min() > 0
