@@ -74,14 +74,15 @@ enum { PP_FP64 = 0, PP_MIXED = 1 };
  *                  Sy_s/dy) <= gl_w1) with the same dt; a stage that breaks it
  *                  sets status bit 2 (informative: not PP_ESTATE).  Near
  *                  vacuum the density-limited interface states keep their
- *                  pressure, so S can become huge and dt tiny.  The compact
- *                  scheme; 2D in FP64.
+ *                  pressure, so S can become huge and dt tiny.  Every
+ *                  reconstruction; 2D in FP64.
  *  PP_DT_RESTART : PP_DT_CFL's dt; a step in which any stage output leaves
  *                  the admissible set (rho <= 0, p <= 0 or not finite) is
  *                  discarded and redone from U^n with half the dt, up to 60
  *                  times; the run stops with PP_ESTATE after that, or as soon
  *                  as half the dt no longer changes t in FP64 (a stall).  The
- *                  next step starts again from the averages' dt.  1D only. */
+ *                  next step starts again from the averages' dt.  1D, the
+ *                  compact reconstruction. */
 enum { PP_DT_CFL = 0, PP_DT_H53 = 1, PP_DT_PP = 2, PP_DT_RESTART = 3 };
 
 /* Numerical flux at the faces.  PP_FLUX_HLLC: eq. (HLLC) with the acoustic

@@ -997,7 +997,12 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
     // limiter for the Gauss-node operator, nothing else
     constexpr bool kFaces = (NC == 4) && !MIXED && RECON == PP_RECON_CWENO;
     const int mode = kEpi ? A.mode : ((kFaces && A.mode == 4) ? 4 : 0);
-    const bool pprule = (kEpi && A.dtrule == PP_DT_PP) || (NC == 4 && IFS);
+    // 2D interface-state rule: a separate instantiation of the compact
+    // scheme's kernels (IFS), a run-time switch (A.spd_if) in the kernels of
+    // the explicit and characteristic reconstructions
+    constexpr bool kIfsRt = (NC == 4) && RECON != PP_RECON_CWENO;
+    const bool ifs = IFS || (kIfsRt && A.spd_if != nullptr);
+    const bool pprule = (kEpi && A.dtrule == PP_DT_PP) || (NC == 4 && ifs);
     double dt = 0.0;
     if (mode == 1) dt = batched ? A.dtline[b] : (A.dt_dev ? *A.dt_dev : A.dt_val);
     // mode 2 (stage 1 under the interface-state rule): dtline holds the time
@@ -1543,9 +1548,11 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
         }
         __syncthreads();
     }
-    if constexpr (NC == 4 && IFS) {
-        const double S = block_max<NT>(smax_if, red);
-        if (tid == 0) atomicMax(A.spd_if, ord_enc(S));
+    if constexpr (NC == 4 && (IFS || kIfsRt)) {
+        if (ifs) {   // uniform over the block
+            const double S = block_max<NT>(smax_if, red);
+            if (tid == 0) atomicMax(A.spd_if, ord_enc(S));
+        }
     }
     if (mode == 2) {
         // stage 1 under the interface-state rule: the step's dt from the
@@ -2255,7 +2262,7 @@ struct pp_cweno_ctx {
     double *UB = nullptr, *U1B = nullptr, *U2B = nullptr;      // layout B copies (2D)
     double *Lx = nullptr, *LyB = nullptr;                      // 2D operator halves
     double* Wf = nullptr;    // Gauss-node operator: face values [8][ncell] of one sweep
-    int rule2d = PP_DT_CFL;  // 2D run in progress: its time-step rule, cfl and t_end
+    int run_rule = PP_DT_CFL;  // run in progress (host-driven steps): its time-step rule, cfl, t_end
     double run_cfl = 0.0, run_t_end = 0.0;
     GaussCoef gcoef{};
     Scal* scal = nullptr;
@@ -2533,6 +2540,11 @@ int launch_1d(pp_cweno_ctx* ctx, const double* Us, const double* U0, double* out
     A.dt_dev = dt_dev;
     A.dt_val = dt_val;
     A.scal = run ? ctx->scal : nullptr;
+    if (run) {   // the run's time-step rule (stage checks, mode 2)
+        A.dtrule = ctx->run_rule;
+        A.cfl = ctx->run_cfl;
+        A.t_end = ctx->run_t_end;
+    }
     A.dbg_um = dbg_um;
     A.dbg_up = dbg_up;
     A.dbg_flux = dbg_flux;
@@ -2728,11 +2740,16 @@ int step_single(pp_cweno_ctx* ctx, double* U, const double* dt_dev, double dt_va
     Scal* s = ctx->scal;
     int r;
     if (c.ndim == 1) {
+        // a run under the interface-state rule (the explicit and the
+        // characteristic reconstructions; the compact one runs in
+        // run1d_kernel): stage 1 picks the step's dt (mode 2), stages 2 and 3
+        // check their inputs against it
+        const bool pp = run && ctx->run_rule == PP_DT_PP;
         const double* Uin[3] = {U, ctx->U1, ctx->U2};
         double* Uout[3] = {ctx->U1, ctx->U2, U};
         for (int st = 1; st <= 3; ++st) {
-            r = launch_1d(ctx, Uin[st - 1], U, Uout[st - 1], 1, st, kRK[st][0], kRK[st][1],
-                          dt_dev, dt_val, run);
+            r = launch_1d(ctx, Uin[st - 1], U, Uout[st - 1], (pp && st == 1) ? 2 : 1, st,
+                          kRK[st][0], kRK[st][1], dt_dev, dt_val, run);
             if (r) return r;
         }
         return PP_OK;
@@ -2749,7 +2766,7 @@ int step_single(pp_cweno_ctx* ctx, double* U, const double* dt_dev, double dt_va
     for (int st = 1; st <= 3; ++st) {
         const int in_slot = (st + 1) % 3;
         const int out_slot = st - 1;
-        const bool ifs = run && ctx->rule2d == PP_DT_PP;
+        const bool ifs = run && ctx->run_rule == PP_DT_PP;
         r = sweeps_2d(ctx, inA[st - 1], inB[st - 1], s->eps[in_slot], run, ifs ? s->spdif : nullptr);
         if (r) return r;
         if (ifs) {
@@ -3237,8 +3254,8 @@ int pp_cweno_run(pp_cweno_ctx* ctx, double* U, double t_end, int64_t nsteps_max,
         return fail(ctx, PP_EINVAL, "unknown dt rule");
     if (rule == PP_DT_H53 && ctx->cfg.ndim != 1) return fail(ctx, PP_EINVAL, "h^(5/3) rule is 1D");
     if (ctx->cfg.nbatch > 0) return fail(ctx, PP_EINVAL, "use pp_cweno_batch_run for ensembles");
-    if ((rule == PP_DT_PP || rule == PP_DT_RESTART) && ctx->cfg.recon != PP_RECON_CWENO)
-        return fail(ctx, PP_EUNSUPPORTED, "the interface-state and restart rules run the compact scheme");
+    if (rule == PP_DT_RESTART && ctx->cfg.recon != PP_RECON_CWENO)
+        return fail(ctx, PP_EUNSUPPORTED, "the restart rule runs the compact scheme");
     if (rule == PP_DT_RESTART && ctx->cfg.ndim != 1)
         return fail(ctx, PP_EUNSUPPORTED, "the restart rule runs in 1D");
     if (rule == PP_DT_PP && ctx->cfg.ndim == 2 && ctx->cfg.precision != PP_FP64)
@@ -3275,24 +3292,89 @@ int pp_cweno_run(pp_cweno_ctx* ctx, double* U, double t_end, int64_t nsteps_max,
     // 2 and 3) the dt before the stage's combine.
     struct RunRule {
         pp_cweno_ctx* ctx;
-        ~RunRule() { ctx->rule2d = PP_DT_CFL; }
-    } run_rule{ctx};
-    ctx->rule2d = rule;
+        ~RunRule() { ctx->run_rule = PP_DT_CFL; }
+    } rule_guard{ctx};
+    ctx->run_rule = rule;
     ctx->run_cfl = cfl;
     ctx->run_t_end = t_end;
-    int64_t launched = 0;
-    for (;;) {
-        const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(64, nsteps_max - launched + 1));
-        for (int64_t i = 0; i < batch; ++i, ++launched) {
+    auto launch_group = [&](int64_t count) -> int {
+        for (int64_t i = 0; i < count; ++i) {
             hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(1), 0, ctx->stream, s, c.ndim, rule, cfl,
                                c.dx, c.dy, t_end, (long long)nsteps_max);
             HIPCHK(ctx, hipGetLastError());
-            r = step_single(ctx, U, &s->dt, 0.0, true);
-            if (r) return r;
+            const int rs = step_single(ctx, U, &s->dt, 0.0, true);
+            if (rs) return rs;
         }
-        HIPCHK(ctx, hipMemcpyAsync(&host, s, sizeof(Scal), hipMemcpyDeviceToHost, ctx->stream));
-        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-        if (!host.active) break;
+        return PP_OK;
+    };
+    auto check = [&](hipStream_t st) -> int {
+        HIPCHK(ctx, hipMemcpyAsync(&host, s, sizeof(Scal), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        return PP_OK;
+    };
+    // The first group runs eagerly (it also sets the kernels' LDS limits).
+    // Later groups replay one captured group: a hipGraph of kRunGroup
+    // (dt kernel, step) pairs on a private stream ordered after the
+    // caller's, so a long run of small grids is not bound by launch
+    // overhead.  With kernel timing on, every group is launched eagerly.
+    constexpr int64_t kRunGroup = 16;
+    int64_t launched = std::max<int64_t>(1, std::min<int64_t>(kRunGroup, nsteps_max + 1));
+    r = launch_group(launched);
+    if (!r) r = check(ctx->stream);
+    if (r) return r;
+    if (host.active && ctx->timing) {
+        for (;;) {
+            const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(64, nsteps_max - launched + 1));
+            r = launch_group(batch);
+            if (!r) r = check(ctx->stream);
+            if (r) return r;
+            launched += batch;
+            if (!host.active) break;
+        }
+    } else if (host.active) {
+        hipStream_t user = ctx->stream, gs = nullptr;
+        hipEvent_t ev = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        auto cleanup = [&]() {
+            ctx->stream = user;
+            if (gs) (void)hipStreamSynchronize(gs);
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (ev) (void)hipEventDestroy(ev);
+            if (gs) (void)hipStreamDestroy(gs);
+        };
+        hipError_t e = hipStreamCreateWithFlags(&gs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(ev, user);
+        if (e == hipSuccess) e = hipStreamWaitEvent(gs, ev, 0);
+        if (e == hipSuccess) e = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            cleanup();
+            return hip_fail(ctx, e, "run graph capture");
+        }
+        ctx->stream = gs;
+        r = launch_group(kRunGroup);
+        e = hipStreamEndCapture(gs, &graph);
+        ctx->stream = user;
+        if (!r && e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (r || e != hipSuccess) {
+            cleanup();
+            return r ? r : hip_fail(ctx, e, "run graph capture");
+        }
+        // the dt kernel retires the run at t_end or nsteps_max; the pairs of a
+        // replay after that return at once
+        for (;;) {
+            e = hipGraphLaunch(exec, gs);
+            if (e == hipSuccess) e = hipMemcpyAsync(&host, s, sizeof(Scal), hipMemcpyDeviceToHost, gs);
+            if (e == hipSuccess) e = hipStreamSynchronize(gs);
+            if (e != hipSuccess) {
+                cleanup();
+                return hip_fail(ctx, e, "run graph replay");
+            }
+            if (!host.active) break;
+        }
+        cleanup();
     }
     if (t_out) *t_out = host.t;
     if (steps_out) *steps_out = host.steps;

@@ -393,3 +393,76 @@ def test_2d_rule_limits():
         s.run(dev(U0), 0.1, 5, 1.0 / 12.0, pp.PP_DT_PP)
     assert e.value.code == pp.PP_EUNSUPPORTED
     s.close()
+
+
+def test_restart_rule_limits_reconstructions():
+    """The restart rule runs the compact reconstruction only."""
+    pp = gpu()
+    U0 = W.lax_1d(64)
+    s = pp.Solver(ndim=1, nx=64, dx=10.0 / 64, bc=(1, 1, 0, 0), recon=pp.PP_RECON_CHAR)
+    with pytest.raises(pp.PPError) as e:
+        s.run(dev(U0), 0.1, 5, 1.0 / 12.0, pp.PP_DT_RESTART)
+    assert e.value.code == pp.PP_EUNSUPPORTED
+    s.close()
+
+
+def _spread(run, U0, k=2):
+    """The oracle run's largest relative change under 1e-15 perturbations of
+    its initial data."""
+    ref = run(U0)[0]
+    rng = np.random.default_rng(77)
+    return max(max(float(np.abs(V[c] - ref[c]).max() / np.abs(ref[c]).max())
+                   for c in range(ref.shape[0]))
+               for V in (run(U0 * (1.0 + 1e-15 * rng.standard_normal(U0.shape)))[0]
+                         for _ in range(k)))
+
+
+@pytest.mark.parametrize("ndim,recon", [(1, 1), (1, 3), (2, 1), (2, 3)])
+def test_interface_state_rule_other_reconstructions(ndim, recon):
+    """PP_DT_PP with the explicit WENO-JS and the characteristic-wise
+    reconstruction: the rule's reduction runs in their line kernels as in the
+    compact one's.  1D: the Lax tube (N = 200, transmissive), 300 steps;
+    2D: 25 steps of the mixed field (WENO-JS, walls) or of the smooth flow
+    (characteristic, periodic).  Equal step counts and times as the
+    oracle's run of the same rule and reconstruction, states within 1e-11
+    (or 4x the oracle's own change under 1e-15 perturbations of the initial
+    data), status bit 2 exactly when the oracle counts a broken (CFL-CD)."""
+    pp = gpu()
+    P = oracle.params(recon=recon)
+    rc = {1: pp.PP_RECON_WENOJS, 3: pp.PP_RECON_CHAR}[recon]
+    if ndim == 1:
+        n, h, nsteps = 200, 10.0 / 200, 300
+        U0 = W.lax_1d(n)
+
+        def run(U):
+            return oracle.run_1d(U, (1, 1), h, 1.4, rule=oracle.DT_PP, p=P, max_steps=nsteps)
+        s = pp.Solver(ndim=1, nx=n, dx=h, bc=(1, 1, 0, 0), recon=rc)
+    else:
+        nx, ny, nsteps = 48, 40, 25
+        dx, dy = 1.0 / nx, 1.0 / ny
+        if recon == 1:
+            U0, bc = _mixed_2d(nx, ny, 5), (1, 2, 2, 1)
+        else:
+            U0, bc = W.smooth_flow_2d(nx, ny), (0, 0, 0, 0)
+
+        def run(U):
+            return oracle.run_2d(U, bc, dx, dy, 1.0, p=P, max_steps=nsteps, rule=oracle.DT_PP)
+        s = pp.Solver(ndim=2, nx=nx, ny=ny, dx=dx, dy=dy, bc=bc, recon=rc)
+    ref, info = run(U0)
+    Ud = dev(U0)
+    t, steps = s.run(Ud, 1.4 if ndim == 1 else 1.0, nsteps, 1.0 / 12.0, pp.PP_DT_PP)
+    code, flags = s.status()
+    s.close()
+    got = Ud.cpu().numpy()
+    err = max(float(np.abs(got[k] - ref[k]).max() / np.abs(ref[k]).max())
+              for k in range(ref.shape[0]))
+    bar = 1e-11
+    if err > bar:
+        bar = max(bar, 4.0 * _spread(run, U0))
+    print(f"interface-state rule, {ndim}D recon {recon}: t {t:.6e} / {info['t']:.6e}, steps "
+          f"{steps}, flags {flags}, oracle violations {info['viol']}, state {err:.2e} "
+          f"(bar {bar:.1e})", flush=True)
+    assert steps == info["steps"] == nsteps
+    assert abs(t / info["t"] - 1) <= 1e-12
+    assert err <= bar
+    assert code == pp.PP_OK and bool(flags & 4) == (info["viol"] > 0)
