@@ -60,10 +60,10 @@ FLOPS_PER_SWEEP_CELL = 716.0
 # hash is recorded (profiles/line_kernel_2d_density_wave_2048_fp64.md);
 # otherwise traffic is reported null.
 TRAFFIC_RECORD = {
-    "src_sha256": "37e97b362b5c5e4b9652c57bd37e167861c1bb988a82dab6d61c5ce43f1db122",
+    "src_sha256": "85bacf1399aa378487c89342fe24c241f54392c1f343ba4784697bff79315f81",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "x": {"fetch_kib": 66166.7, "write_kib": 163840.0},
-    "y": {"fetch_kib": 66272.9, "write_kib": 163840.0},
+    "x": {"fetch_kib": 66450.3, "write_kib": 163840.0},
+    "y": {"fetch_kib": 66364.2, "write_kib": 163840.0},
 }
 
 
