@@ -75,7 +75,7 @@ int main(void)
     {
         static double V[4 * 12 * 10];
         const int bc2[4] = {1, 2, 2, 1};
-        for (int recon = 0; recon < 3; ++recon) {
+        for (int recon = 0; recon < 4; ++recon) {   /* 3: characteristic lines (4x4) */
             for (int j = 0; j < 10; ++j)
                 for (int i = 0; i < 12; ++i) {
                     int c = j * 12 + i;
@@ -87,7 +87,7 @@ int main(void)
                 }
             orc_params P = params(recon, 0);
             int rc = orc_run_2d_rule(12, 10, V, bc2, 1.0 / 12, 1.0 / 10, &P, 0.02, 1.0 / 12.0,
-                                     recon == 1 ? 2 : 0, 10, out);
+                                     recon == 1 || recon == 3 ? 2 : 0, 10, out);
             if (rc != 0) { printf("2D run recon=%d: rc %d\n", recon, rc); ++failures; }
         }
     }
