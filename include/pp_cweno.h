@@ -81,8 +81,10 @@ enum { PP_FP64 = 0, PP_MIXED = 1 };
  *                  discarded and redone from U^n with half the dt, up to 60
  *                  times; the run stops with PP_ESTATE after that, or as soon
  *                  as half the dt no longer changes t in FP64 (a stall).  The
- *                  next step starts again from the averages' dt.  1D, the
- *                  compact reconstruction. */
+ *                  next step starts again from the averages' dt.  1D and 2D,
+ *                  every reconstruction (in 2D and for the explicit and
+ *                  characteristic schemes the step tried is kept in the
+ *                  stage-1 buffers and copied to U when it stands). */
 enum { PP_DT_CFL = 0, PP_DT_H53 = 1, PP_DT_PP = 2, PP_DT_RESTART = 3 };
 
 /* Numerical flux at the faces.  PP_FLUX_HLLC: eq. (HLLC) with the acoustic

@@ -353,11 +353,11 @@ def max_speed_2d(U, gamma=1.4):
 def run_2d(U, bc, dx, dy, t_end, cfl=1.0 / 12.0, p=None, max_steps=1 << 40, rule=0):
     p = p or params()
     U = _f64(U).copy()
-    out = np.zeros(6)
+    out = np.zeros(8)
     _check(lib().orc_run_2d_rule(U.shape[2], U.shape[1], _d(U), _bc4(bc), dx, dy, ctypes.byref(p),
                                  t_end, cfl, rule, max_steps, _d(out)), "run_2d")
     return U, dict(t=out[0], steps=int(out[1]), limited=int(out[2]), min_rho=out[3],
-                   min_p=out[4], viol=int(out[5]))
+                   min_p=out[4], viol=int(out[5]), restarts=int(out[6]), out_of_G=int(out[7]))
 
 
 # ----------------------------------------------------------------- batched

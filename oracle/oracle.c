@@ -1226,6 +1226,16 @@ static int in_G_1d(int n, const double *U, double g)
     return 1;
 }
 
+/* The same for a 2D state [4][nc] (nc cells). */
+static int in_G_2d(long nc, const double *U, double g)
+{
+    for (long i = 0; i < nc; ++i) {
+        double r = U[i], mx = U[nc + i], my = U[2 * nc + i], E = U[3 * nc + i];
+        if (!(r > 0.0) || !((g - 1.0) * (E - 0.5 * (mx * mx + my * my) / r) > 0.0)) return 0;
+    }
+    return 1;
+}
+
 /* Advance U ([3][n], in place) to t_end (or max_steps).  out[0] = t reached,
  * out[1] = steps, out[2] = total limited cells, out[3] = min rho, out[4] = min p
  * over all step outputs, out[5] = stages whose input broke (CFL-CD) under the
@@ -1708,7 +1718,11 @@ void orc_max_speed_2d(int nx, int ny, const double *U, double gamma, double *out
  * and |v|+a: over the cell averages at the start of the step (rule 0), or
  * over the averages and the limited interface states of the x- and y-lines
  * of the step's input (rule 2, ORC_DT_PP, with the stage-2 and stage-3 inputs
- * checked against dt (Sx_s/dx + Sy_s/dy) <= w^_1, out[5]); last step clipped. */
+ * checked against dt (Sx_s/dx + Sy_s/dy) <= w^_1, out[5]); last step clipped.
+ * Rule 3 (ORC_DT_RESTART): rule 0's dt, and a step with a stage output
+ * outside G is redone from U^n with half the dt, with the 1D rule's bounds
+ * (out[6] = steps redone, out[7] = stage outputs outside G of the attempts
+ * kept; -4 when the bounds end the run). */
 int orc_run_2d_rule(int nx, int ny, double *U, const int *bc, double dx, double dy,
                     const orc_params *P, double t_end, double cfl, int rule, long max_steps,
                     double *out)
@@ -1718,7 +1732,7 @@ int orc_run_2d_rule(int nx, int ny, double *U, const int *bc, double dx, double 
     double *L = (double *)malloc(sizeof(double) * m);
     if (!U1 || !U2 || !L) { free(U1); free(U2); free(L); return -2; }
     double t = 0.0, minr = INFINITY, minp = INFINITY, s[2];
-    long steps = 0, lim = 0, viol = 0;
+    long steps = 0, lim = 0, viol = 0, restarts = 0, outG = 0;
     int rc = 0;
     while (t < t_end && steps < max_steps) {
         long r1, r2, r3;
@@ -1746,9 +1760,23 @@ int orc_run_2d_rule(int nx, int ny, double *U, const int *bc, double dx, double 
             dt = cfl / (s[0] / dx + s[1] / dy);
             if (!(dt > 0.0) || dt == INFINITY) { rc = -4; break; }
             if (t + dt > t_end) dt = t_end - t;
-            r1 = orc_stage_2d(nx, ny, U, U, U1, 1, dt, bc, dx, dy, P);
-            r2 = r1 >= 0 ? orc_stage_2d(nx, ny, U, U1, U2, 2, dt, bc, dx, dy, P) : r1;
-            r3 = r2 >= 0 ? orc_stage_2d(nx, ny, U, U2, U1, 3, dt, bc, dx, dy, P) : r2;
+            for (int halvings = 0;; ++halvings) {
+                long bad = 0;   /* stage outputs of this attempt outside G */
+                r1 = orc_stage_2d(nx, ny, U, U, U1, 1, dt, bc, dx, dy, P);
+                bad += r1 >= 0 && !in_G_2d(nx * (long)ny, U1, P->gamma);
+                r2 = r1 >= 0 ? orc_stage_2d(nx, ny, U, U1, U2, 2, dt, bc, dx, dy, P) : r1;
+                bad += r2 >= 0 && !in_G_2d(nx * (long)ny, U2, P->gamma);
+                r3 = r2 >= 0 ? orc_stage_2d(nx, ny, U, U2, U1, 3, dt, bc, dx, dy, P) : r2;
+                bad += r3 >= 0 && !in_G_2d(nx * (long)ny, U1, P->gamma);
+                if (rule != ORC_DT_RESTART || bad == 0 || r3 < 0) {
+                    outG += bad;
+                    break;
+                }
+                /* the 1D rule's bounds: ORC_MAX_HALVINGS halvings, or a stall */
+                if (halvings == ORC_MAX_HALVINGS || t + 0.5 * dt == t) { r3 = -4; break; }
+                dt *= 0.5;   /* redo the step from U^n with half the step */
+                ++restarts;
+            }
         }
         if (r3 < 0) { rc = (int)r3; break; }
         lim += r1 + r2 + r3;
@@ -1765,6 +1793,8 @@ int orc_run_2d_rule(int nx, int ny, double *U, const int *bc, double dx, double 
     }
     out[0] = t; out[1] = (double)steps; out[2] = (double)lim; out[3] = minr; out[4] = minp;
     out[5] = (double)viol;
+    out[6] = (double)restarts;
+    out[7] = (double)outG;
     free(U1); free(U2); free(L);
     return rc;
 }

@@ -66,6 +66,9 @@ struct Scal {
     long long restarts;    // restart rule: steps redone with half the dt
     long long spdif[2];    // 2D interface-state rule: encoded max |u|+a, |v|+a over the
                            // averages and limited interface states of a stage input
+    long long eps3[2];     // restart rule, 2D: epsilons of the stage-3 output being tried
+    int redo;              // restart rule, host-driven runs: the next step is a retry
+    int halvings;          //   halvings of the step being tried
 };
 
 // Steps redone with half the dt before a run gives up (restart rule).
@@ -2100,6 +2103,9 @@ __global__ void init_scal_kernel(Scal* s) {
     s->stepbad = 0u;
     s->restarts = 0;
     s->spdif[0] = s->spdif[1] = kEncZero;
+    s->eps3[0] = s->eps3[1] = kEncPosInf;
+    s->redo = 0;
+    s->halvings = 0;
 }
 
 // Start of a step: advance t by the previous dt, pick the new dt from the
@@ -2108,24 +2114,30 @@ __global__ void init_scal_kernel(Scal* s) {
 __device__ __forceinline__ void dt_update(Scal* s, int ndim, int rule, double cfl, double dx,
                                           double dy, double t_end, long long steps_max) {
     if (!s->active) return;   // retired run: later calls change nothing
-    if (s->dt > 0.0) {
-        s->t += s->dt;
-        s->steps += 1;
-    }
-    const double sx = ord_dec(s->spd[0]), sy = ord_dec(s->spd[1]);
-    double dt = 0.0;
-    bool go = s->t < t_end && s->steps < steps_max;
-    if (rule != PP_DT_PP) {   // (the interface-state rule picks dt in stage 1)
-        if (ndim == 1) dt = (rule == PP_DT_H53 ? cfl * pow(dx, 5.0 / 3.0) : cfl * dx) / sx;
-        else dt = cfl / (sx / dx + sy / dy);
-        if (go && !(dt > 0.0 && isfinite(dt))) {
-            s->status |= 1u;   // no usable wave speed: stop the run
-            go = false;
+    if (s->redo) {
+        // restart rule: the step is tried again from the same state with the
+        // dt the verdict halved; t and the step count stay
+        s->redo = 0;
+    } else {
+        if (s->dt > 0.0) {
+            s->t += s->dt;
+            s->steps += 1;
         }
-        if (go && s->t + dt > t_end) dt = t_end - s->t;
+        const double sx = ord_dec(s->spd[0]), sy = ord_dec(s->spd[1]);
+        double dt = 0.0;
+        bool go = s->t < t_end && s->steps < steps_max;
+        if (rule != PP_DT_PP) {   // (the interface-state rule picks dt in stage 1)
+            if (ndim == 1) dt = (rule == PP_DT_H53 ? cfl * pow(dx, 5.0 / 3.0) : cfl * dx) / sx;
+            else dt = cfl / (sx / dx + sy / dy);
+            if (go && !(dt > 0.0 && isfinite(dt))) {
+                s->status |= 1u;   // no usable wave speed: stop the run
+                go = false;
+            }
+            if (go && s->t + dt > t_end) dt = t_end - s->t;
+        }
+        s->active = go ? 1 : 0;
+        s->dt = go ? dt : 0.0;
     }
-    s->active = go ? 1 : 0;
-    s->dt = go ? dt : 0.0;
     s->spd[0] = s->spd[1] = kEncZero;
     s->eps[0][0] = s->eps[0][1] = kEncPosInf;
     s->eps[1][0] = s->eps[1][1] = kEncPosInf;
@@ -2162,6 +2174,50 @@ __global__ void dt_pp2d_kernel(Scal* s, int stage, double cfl, double dx, double
     } else if (s->dt * rate > w1) {
         s->status |= 4u;
     }
+}
+
+// Restart rule on the host-driven path (2D, and the explicit and
+// characteristic reconstructions in 1D).  The stage-3 output of the step
+// being tried sits in the stage-1 buffers (both layouts in 2D); it becomes
+// the state when no stage output of the step left G.
+__global__ void restart_commit_kernel(const Scal* s, const double* __restrict__ srcA,
+                                      double* __restrict__ dstA, const double* __restrict__ srcB,
+                                      double* __restrict__ dstB, long long m) {
+    if (!s->active || s->stepbad != 0u) return;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        dstA[i] = srcA[i];
+        if (dstB) dstB[i] = srcB[i];
+    }
+}
+
+// ... and the verdict on the step, after the commit: kept (2D: the stage-3
+// output's epsilons become those of the next stage-1 input), or redone from
+// the same state with half the dt, or, after kMaxHalvings halvings or once
+// half the dt no longer moves t (a stall), the run stops with the step's
+// status bits.
+__global__ void restart_verdict_kernel(Scal* s, int ndim) {
+    if (!s->active) return;
+    const unsigned bad = s->stepbad;
+    s->stepbad = 0u;
+    if (bad == 0u) {
+        if (ndim == 2) {
+            s->eps[2][0] = s->eps3[0];
+            s->eps[2][1] = s->eps3[1];
+        }
+        s->halvings = 0;
+        return;
+    }
+    if (s->halvings >= kMaxHalvings || s->t + 0.5 * s->dt == s->t) {
+        s->status |= bad;
+        s->active = 0;
+        s->dt = 0.0;
+        return;
+    }
+    s->dt *= 0.5;
+    s->restarts += 1;
+    s->halvings += 1;
+    s->redo = 1;
 }
 
 // Whole 1D run of a single line in one workgroup: up to max_steps SSP-RK3
@@ -2544,6 +2600,8 @@ int launch_1d(pp_cweno_ctx* ctx, const double* Us, const double* U0, double* out
         A.dtrule = ctx->run_rule;
         A.cfl = ctx->run_cfl;
         A.t_end = ctx->run_t_end;
+        // restart rule: a stage output's status bits belong to the step tried
+        if (ctx->run_rule == PP_DT_RESTART) A.status = &ctx->scal->stepbad;
     }
     A.dbg_um = dbg_um;
     A.dbg_up = dbg_up;
@@ -2695,10 +2753,13 @@ int combine_2d(pp_cweno_ctx* ctx, const double* UsA, const double* Un, double* O
     const auto& c = ctx->cfg;
     dim3 grid((unsigned)((c.nx + TC - 1) / TC), (unsigned)((c.ny + TC - 1) / TC));
     const int slot = timed_begin(ctx, 2);
+    // restart rule: a stage output's status bits belong to the step tried
+    unsigned* const stat =
+        !ctx->scal ? nullptr
+                   : (run && ctx->run_rule == PP_DT_RESTART ? &ctx->scal->stepbad : &ctx->scal->status);
     hipLaunchKernelGGL(combine2d_kernel, grid, dim3(1024), 0, ctx->stream, ctx->Lx, ctx->LyB, UsA,
                        Un, Out, OutB, (int)c.nx, (int)c.ny, mode, ra, rb, dt_dev, dt_val, c.gamma,
-                       eps_out, spd_out, eps_reset, run ? ctx->scal : nullptr,
-                       ctx->scal ? &ctx->scal->status : nullptr);
+                       eps_out, spd_out, eps_reset, run ? ctx->scal : nullptr, stat);
     timed_end(ctx, 2, slot);
     HIPCHK(ctx, hipGetLastError());
     return PP_OK;
@@ -2735,6 +2796,20 @@ int reset_scal(pp_cweno_ctx* ctx) {
 // One full SSP-RK3 step on a single grid (U in/out, layout A; for 2D the
 // B copy of U must be current in ctx->UB).  run = take dt and the epsilon
 // reductions from the device scalars.
+// Restart rule, host-driven runs: commit the step tried (U1 -> U, and
+// U1B -> UB in 2D) if no stage output left G, then the verdict kernel.
+int restart_end(pp_cweno_ctx* ctx, double* U, double* UB) {
+    const long long m = (long long)ctx->nc * ctx->ncell;
+    const int grid = (int)std::min<long long>((m + 255) / 256, 2048);
+    hipLaunchKernelGGL(restart_commit_kernel, dim3(grid), dim3(256), 0, ctx->stream, ctx->scal,
+                       ctx->U1, U, UB ? ctx->U1B : nullptr, UB, m);
+    HIPCHK(ctx, hipGetLastError());
+    hipLaunchKernelGGL(restart_verdict_kernel, dim3(1), dim3(1), 0, ctx->stream, ctx->scal,
+                       ctx->cfg.ndim);
+    HIPCHK(ctx, hipGetLastError());
+    return PP_OK;
+}
+
 int step_single(pp_cweno_ctx* ctx, double* U, const double* dt_dev, double dt_val, bool run) {
     const auto& c = ctx->cfg;
     Scal* s = ctx->scal;
@@ -2745,23 +2820,31 @@ int step_single(pp_cweno_ctx* ctx, double* U, const double* dt_dev, double dt_va
         // run1d_kernel): stage 1 picks the step's dt (mode 2), stages 2 and 3
         // check their inputs against it
         const bool pp = run && ctx->run_rule == PP_DT_PP;
+        // restart rule: the stage-3 output goes to U1 (free by then) and is
+        // committed to U if the step stands
+        const bool rs = run && ctx->run_rule == PP_DT_RESTART;
         const double* Uin[3] = {U, ctx->U1, ctx->U2};
-        double* Uout[3] = {ctx->U1, ctx->U2, U};
+        double* Uout[3] = {ctx->U1, ctx->U2, rs ? ctx->U1 : U};
         for (int st = 1; st <= 3; ++st) {
             r = launch_1d(ctx, Uin[st - 1], U, Uout[st - 1], (pp && st == 1) ? 2 : 1, st,
                           kRK[st][0], kRK[st][1], dt_dev, dt_val, run);
             if (r) return r;
         }
+        if (rs) return restart_end(ctx, U, nullptr);
         return PP_OK;
     }
     // 2D: stage inputs in both layouts.  Epsilon slots: 2 = stage-1 input
     // (written by the previous stage 3 or the initial reduction), 0 = U1,
     // 1 = U2.  Stage 3 combines in place into U (each element is read and
     // written by the same thread only).
+    // Restart rule: stage 3 writes U1 (both layouts; free by then) and its
+    // epsilons to eps3, stage 1 clears eps3 instead of slot 2 (slot 2 stays
+    // the epsilon of U^n for a retry); the verdict then commits or retries.
+    const bool rs = run && ctx->run_rule == PP_DT_RESTART;
     const double* inA[3] = {U, ctx->U1, ctx->U2};
     const double* inB[3] = {ctx->UB, ctx->U1B, ctx->U2B};
-    double* outA[3] = {ctx->U1, ctx->U2, U};
-    double* outB[3] = {ctx->U1B, ctx->U2B, ctx->UB};
+    double* outA[3] = {ctx->U1, ctx->U2, rs ? ctx->U1 : U};
+    double* outB[3] = {ctx->U1B, ctx->U2B, rs ? ctx->U1B : ctx->UB};
     TimedChain chain(ctx);   // x, y, combine of each stage: nine launches in a row
     for (int st = 1; st <= 3; ++st) {
         const int in_slot = (st + 1) % 3;
@@ -2774,11 +2857,13 @@ int step_single(pp_cweno_ctx* ctx, double* U, const double* dt_dev, double dt_va
                                ctx->run_cfl, c.dx, c.dy, ctx->run_t_end, c.gl_w1);
             HIPCHK(ctx, hipGetLastError());
         }
+        long long* const eps_out = (rs && st == 3) ? s->eps3 : s->eps[out_slot];
+        long long* const eps_reset = st == 1 ? (rs ? s->eps3 : s->eps[2]) : nullptr;
         r = combine_2d(ctx, inA[st - 1], U, outA[st - 1], outB[st - 1], 1, kRK[st][0], kRK[st][1],
-                       dt_dev, dt_val, s->eps[out_slot], st == 3 ? s->spd : nullptr,
-                       st == 1 ? s->eps[2] : nullptr, run);
+                       dt_dev, dt_val, eps_out, st == 3 ? s->spd : nullptr, eps_reset, run);
         if (r) return r;
     }
+    if (rs) return restart_end(ctx, U, ctx->UB);
     return PP_OK;
 }
 
@@ -3254,10 +3339,6 @@ int pp_cweno_run(pp_cweno_ctx* ctx, double* U, double t_end, int64_t nsteps_max,
         return fail(ctx, PP_EINVAL, "unknown dt rule");
     if (rule == PP_DT_H53 && ctx->cfg.ndim != 1) return fail(ctx, PP_EINVAL, "h^(5/3) rule is 1D");
     if (ctx->cfg.nbatch > 0) return fail(ctx, PP_EINVAL, "use pp_cweno_batch_run for ensembles");
-    if (rule == PP_DT_RESTART && ctx->cfg.recon != PP_RECON_CWENO)
-        return fail(ctx, PP_EUNSUPPORTED, "the restart rule runs the compact scheme");
-    if (rule == PP_DT_RESTART && ctx->cfg.ndim != 1)
-        return fail(ctx, PP_EUNSUPPORTED, "the restart rule runs in 1D");
     if (rule == PP_DT_PP && ctx->cfg.ndim == 2 && ctx->cfg.precision != PP_FP64)
         return fail(ctx, PP_EUNSUPPORTED, "the 2D interface-state rule runs in FP64");
     const auto& c = ctx->cfg;
