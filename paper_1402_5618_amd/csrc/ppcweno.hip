@@ -730,7 +730,11 @@ __device__ void char_side(const double* __restrict__ sU, int LP, int n, bool cyc
             }
         }
     };
-    // forward chase: x_j = p_j + Q_j Lsep - Cp_j x_{j+1}
+    // forward chase: x_j = p_j + Q_j Lsep - Cp_j x_{j+1}.  The chunk's first
+    // row in terms of the separators, x_{r0} = FP + FQ Lsep + FS Rsep, is
+    // accumulated on the way: with M_0 = I and M_{j+1} = -M_j Cp_j,
+    // FP = sum M_j p_j, FQ = sum M_j Q_j and FS = the last M; the rows'
+    // (Cp, p, Q) go to the scratch for the recovery only.
     double cp[BB], pp[NB], qq[BB];
 #pragma unroll
     for (int i = 0; i < BB; ++i) cp[i] = 0.0;
@@ -776,6 +780,16 @@ __device__ void char_side(const double* __restrict__ sU, int LP, int n, bool cyc
             }
 #pragma unroll
             for (int i = 0; i < NB; ++i) rec(j, BB + i) = pp[i];
+            // FS holds M_j: FP += M_j p_j, FQ += M_j Q_j, then M_{j+1} = -M_j Cp_j
+            mvN<NB>(FS, pp, t3);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) FP[i] += t3[i];
+            mmN<NB>(FS, qq, T);
+#pragma unroll
+            for (int i = 0; i < BB; ++i) FQ[i] += T[i];
+            mmN<NB>(FS, cp, T);
+#pragma unroll
+            for (int i = 0; i < BB; ++i) FS[i] = -T[i];
         }
         double A[BB], B[BB], r[NB], T[BB], t3[NB];
         rows(r1 - 1, A, B, CX, r);
@@ -786,48 +800,6 @@ __device__ void char_side(const double* __restrict__ sU, int LP, int n, bool cyc
         mvN<NB>(A, pp, t3);
 #pragma unroll
         for (int i = 0; i < NB; ++i) Dk[i] = r[i] - t3[i];
-        // symbolic back substitution: x_j = P_j + Qb_j Lsep + S_j Rsep
-        for (int j = len - 2; j >= 0; --j) {
-            double cj[BB], pj[NB], qj[BB], Pn[NB], Qn[BB], Sn[BB], T2[BB];
-#pragma unroll
-            for (int i = 0; i < BB; ++i) {
-                cj[i] = rec(j, i);
-                qj[i] = rec(j, BB + NB + i);
-            }
-#pragma unroll
-            for (int i = 0; i < NB; ++i) pj[i] = rec(j, BB + i);
-            if (j == len - 2) {
-#pragma unroll
-                for (int i = 0; i < BB; ++i) {
-                    Qn[i] = qj[i];
-                    Sn[i] = -cj[i];
-                }
-#pragma unroll
-                for (int i = 0; i < NB; ++i) Pn[i] = pj[i];
-            } else {
-                mvN<NB>(cj, FP, t3);
-#pragma unroll
-                for (int i = 0; i < NB; ++i) Pn[i] = pj[i] - t3[i];
-                mmN<NB>(cj, FQ, T2);
-#pragma unroll
-                for (int i = 0; i < BB; ++i) Qn[i] = qj[i] - T2[i];
-                mmN<NB>(cj, FS, T2);
-#pragma unroll
-                for (int i = 0; i < BB; ++i) Sn[i] = -T2[i];
-            }
-#pragma unroll
-            for (int i = 0; i < BB; ++i) {
-                rec(j, i) = Qn[i];
-                rec(j, BB + i) = Sn[i];
-                FQ[i] = Qn[i];
-                FS[i] = Sn[i];
-            }
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                rec(j, 2 * BB + i) = Pn[i];
-                FP[i] = Pn[i];
-            }
-        }
     }
     // the next chunk's first-row relation (x_{r1} = FP' + FQ' Rsep + FS' Rsep')
     {
@@ -922,24 +894,33 @@ __device__ void char_side(const double* __restrict__ sU, int LP, int n, bool cyc
         }
     }
     if (act) {
-        for (int j = 0; j < len - 1; ++j) {
-            double Qb[BB], S[BB], x[NB], t3[NB];
+        // recovery, last row first: x_j = p_j + Q_j Lsep - Cp_j x_{j+1}
+        double xn[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            xn[i] = Rs[i];
+            xs[(long long)gcomp(i) * n + r1 - 1] = Rs[i];
+        }
+        for (int j = len - 2; j >= 0; --j) {
+            double cj[BB], pj[NB], qj[BB], x[NB], t3[NB];
 #pragma unroll
             for (int i = 0; i < BB; ++i) {
-                Qb[i] = rec(j, i);
-                S[i] = rec(j, BB + i);
+                cj[i] = rec(j, i);
+                qj[i] = rec(j, BB + NB + i);
             }
 #pragma unroll
-            for (int i = 0; i < NB; ++i) x[i] = rec(j, 2 * BB + i);
-            mvN<NB>(Qb, Ls, t3);
+            for (int i = 0; i < NB; ++i) pj[i] = rec(j, BB + i);
+            mvN<NB>(qj, Ls, t3);
 #pragma unroll
-            for (int i = 0; i < NB; ++i) x[i] += t3[i];
-            mvN<NB>(S, Rs, t3);
+            for (int i = 0; i < NB; ++i) x[i] = pj[i] + t3[i];
+            mvN<NB>(cj, xn, t3);
 #pragma unroll
-            for (int i = 0; i < NB; ++i) xs[(long long)gcomp(i) * n + r0 + j] = x[i] + t3[i];
+            for (int i = 0; i < NB; ++i) {
+                x[i] -= t3[i];
+                xs[(long long)gcomp(i) * n + r0 + j] = x[i];
+                xn[i] = x[i];
+            }
         }
-#pragma unroll
-        for (int i = 0; i < NB; ++i) xs[(long long)gcomp(i) * n + r1 - 1] = Rs[i];
     }
 }
 

@@ -46,7 +46,7 @@ CASES = {
 }
 
 
-def gpu_run(U0, bc, h, T, gamma, flux=0, recon=0):
+def gpu_run(U0, bc, h, T, gamma, flux=0, recon=0, rule=0):
     import torch
     import paper_1402_5618_amd as pp
 
@@ -56,7 +56,7 @@ def gpu_run(U0, bc, h, T, gamma, flux=0, recon=0):
     U = torch.tensor(U0, device="cuda")
     code = pp.PP_OK
     try:
-        t, steps = s.run(U, T, 1 << 40, 1.0 / 12.0)
+        t, steps = s.run(U, T, 1 << 40, 1.0 / 12.0, rule)
     except pp.PPError as e:
         t, steps, code = None, None, e.code
     torch.cuda.synchronize()
@@ -168,6 +168,9 @@ def test_suite_explicit_schemes_match_oracle(name, recon):
     assert Ug[0].min() > 0 and W.pressure(Ug, gamma).min() > 0
 
 
+ROUNDOFF_DECIDED = {"low_density_123"}
+
+
 @pytest.mark.gpu
 @pytest.mark.parametrize("name", list(CASES))
 def test_suite_characteristic_matches_oracle(name):
@@ -177,11 +180,20 @@ def test_suite_characteristic_matches_oracle(name):
     case's bound, positivity)."""
     make, bc, h, T, gamma, tol = CASES[name]
     U0 = make()
-    print(f"case {name} (characteristic): n={U0.shape[1]} t_end={T}", flush=True)
-    Ug, t, steps, code = gpu_run(U0, bc, h, T, gamma, recon=3)
-    Uo, info = oracle.run_1d(U0, bc, h, T, p=oracle.params(gamma=gamma, recon=3))
+    # Under the CFL rule the 123 problem's characteristic run leaves G or not
+    # by roundoff: the oracle's own runs from initial data perturbed by 1e-15
+    # leave it for 2 of 7 seeds.  That case runs the restart rule (both
+    # sides), which keeps every run in G; its redone steps are again decided
+    # by roundoff, so the step count is compared within 2 %.
+    rule = oracle.DT_RESTART if name in ROUNDOFF_DECIDED else oracle.DT_CFL
+    print(f"case {name} (characteristic): n={U0.shape[1]} t_end={T} rule={rule}", flush=True)
+    Ug, t, steps, code = gpu_run(U0, bc, h, T, gamma, recon=3, rule=rule)
+    Uo, info = oracle.run_1d(U0, bc, h, T, p=oracle.params(gamma=gamma, recon=3), rule=rule)
     assert code == 0, (name, code)
-    assert steps == info["steps"], (steps, info["steps"])
+    if rule == oracle.DT_CFL:
+        assert steps == info["steps"], (steps, info["steps"])
+    else:
+        assert abs(steps / info["steps"] - 1) <= 0.02, (steps, info["steps"])
     assert abs(t - info["t"]) <= 1e-12 * T
     d = max(float(np.abs(Ug[c] - Uo[c]).sum() / np.abs(Uo[c]).sum()) for c in range(3))
     bar = tol
@@ -193,7 +205,7 @@ def test_suite_characteristic_matches_oracle(name):
         # bar is then 4x that sensitivity.
         rng = np.random.default_rng(1402)
         Up, _ = oracle.run_1d(U0 * (1.0 + 1e-15 * rng.standard_normal(U0.shape)), bc, h, T,
-                              p=oracle.params(gamma=gamma, recon=3))
+                              p=oracle.params(gamma=gamma, recon=3), rule=rule)
         sens = max(float(np.abs(Up[c] - Uo[c]).sum() / np.abs(Uo[c]).sum()) for c in range(3))
         bar = max(tol, 4.0 * sens)
     print(f"  relative L1 difference {d:.2e} (bar {bar:.1e})", flush=True)
