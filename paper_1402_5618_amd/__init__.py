@@ -214,6 +214,7 @@ class Solver:
         return self._check(lib().pp_cweno_step(self._ctx, _ptr(U, self._nstate), float(dt)))
 
     def run(self, U, t_end, nsteps_max=1 << 62, cfl=1.0 / 12.0, rule=PP_DT_CFL):
+        """pp_cweno_run: advance U in place; returns (t reached, steps)."""
         t = ctypes.c_double()
         n = ctypes.c_int64()
         self._check(lib().pp_cweno_run(self._ctx, _ptr(U, self._nstate), float(t_end),

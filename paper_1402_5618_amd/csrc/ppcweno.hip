@@ -3345,13 +3345,14 @@ int pp_cweno_run(pp_cweno_ctx* ctx, double* U, double t_end, int64_t nsteps_max,
             return fail(ctx, PP_ESTATE, "a stage left the admissible set or was not finite");
         return PP_OK;
     }
-    // 2D, and the explicit comparison schemes in 1D: (dt kernel, step) pairs
-    // are launched in batches; the dt kernel
-    // retires the run at t_end or after nsteps_max steps (later launches
-    // return at once), and each batch ends with a host check of the scalars.
-    // Under the 2D interface-state rule each stage's sweeps also reduce the
-    // interface speeds and a small kernel picks (stage 1) or checks (stages
-    // 2 and 3) the dt before the stage's combine.
+    // 2D, and the explicit and characteristic schemes in 1D: (dt kernel,
+    // step) pairs, launched in groups (below); the dt kernel retires the run
+    // at t_end or after nsteps_max steps (later launches return at once),
+    // and each group ends with a host check of the scalars.  Under the 2D
+    // interface-state rule each stage's sweeps also reduce the interface
+    // speeds and a small kernel picks (stage 1) or checks (stages 2 and 3)
+    // the dt before the stage's combine; under the restart rule each step
+    // ends with its commit and verdict kernels.
     struct RunRule {
         pp_cweno_ctx* ctx;
         ~RunRule() { ctx->run_rule = PP_DT_CFL; }
