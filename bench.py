@@ -60,10 +60,10 @@ FLOPS_PER_SWEEP_CELL = 716.0
 # hash is recorded (profiles/line_kernel_2d_density_wave_2048_fp64.md);
 # otherwise traffic is reported null.
 TRAFFIC_RECORD = {
-    "src_sha256": "85bacf1399aa378487c89342fe24c241f54392c1f343ba4784697bff79315f81",
+    "src_sha256": "f64fcfe19eb7293948035aa6a531a6dc0b21110d0b38ab8a84469908735c56f3",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "x": {"fetch_kib": 66450.3, "write_kib": 163840.0},
-    "y": {"fetch_kib": 66364.2, "write_kib": 163840.0},
+    "x": {"fetch_kib": 66159.4, "write_kib": 163840.0},
+    "y": {"fetch_kib": 66221.7, "write_kib": 163840.0},
 }
 
 
