@@ -1515,7 +1515,8 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
                     const double u0 = (A.rk_a != 0.0) ? A.U0[at] : 0.0;
                     o[c] = A.rk_a * u0 + A.rk_b * (us + dt * L);
                 }
-                A.out[at] = o[c];
+                if constexpr (NC == 4) __builtin_nontemporal_store(o[c], &A.out[at]);
+                else A.out[at] = o[c];
             }
             if (mode == 1) {
                 // state checks without divisions: rho > 0 and rho E - |m|^2/2 > 0
