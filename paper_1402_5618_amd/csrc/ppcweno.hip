@@ -1515,7 +1515,10 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
                     const double u0 = (A.rk_a != 0.0) ? A.U0[at] : 0.0;
                     o[c] = A.rk_a * u0 + A.rk_b * (us + dt * L);
                 }
-                if constexpr (NC == 4) __builtin_nontemporal_store(o[c], &A.out[at]);
+                // 2D x-sweep: L_x goes out past the caches (the y-sweep
+                // streams the whole state before the combine reads it);
+                // L_y stays cacheable for the combine that follows at once
+                if constexpr (NC == 4 && NRM == 1) __builtin_nontemporal_store(o[c], &A.out[at]);
                 else A.out[at] = o[c];
             }
             if (mode == 1) {
