@@ -60,10 +60,10 @@ FLOPS_PER_SWEEP_CELL = 716.0
 # hash is recorded (profiles/line_kernel_2d_density_wave_2048_fp64.md);
 # otherwise traffic is reported null.
 TRAFFIC_RECORD = {
-    "src_sha256": "f64fcfe19eb7293948035aa6a531a6dc0b21110d0b38ab8a84469908735c56f3",
+    "src_sha256": "ae673ede4b4cd2628d9470afc6815e3b78d974d93baf04d6a6b5f029ca6003d4",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "x": {"fetch_kib": 66159.4, "write_kib": 163840.0},
-    "y": {"fetch_kib": 66221.7, "write_kib": 163840.0},
+    "x": {"fetch_kib": 66020.6, "write_kib": 163928.0},
+    "y": {"fetch_kib": 66448.3, "write_kib": 163840.0},
 }
 
 
