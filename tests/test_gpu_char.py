@@ -162,7 +162,8 @@ def stage_tolerance_2d(U0, Us, st, dt, bc, dx, dy, ref, k=3):
 
 
 CASES_2D = [(40, 24, (0, 0, 0, 0)), (33, 17, (1, 2, 2, 1)), (64, 64, (0, 0, 1, 1)),
-            (130, 71, (1, 1, 2, 2)), (2048, 6, (0, 0, 1, 2)), (300, 257, (2, 2, 0, 0))]
+            (130, 71, (1, 1, 2, 2)), (2048, 6, (0, 0, 1, 2)), (300, 257, (2, 2, 0, 0)),
+            (7, 3, (0, 0, 1, 2)), (3, 9, (1, 2, 2, 1)), (5, 5, (2, 1, 0, 0))]
 
 
 @pytest.mark.parametrize("nx,ny,bc", CASES_2D)
@@ -170,7 +171,7 @@ def test_char_2d_stage_parity(nx, ny, bc):
     """The 2D operator with characteristic lines (4x4 block systems along x
     and along y): L and the three stages against the oracle, on grids with
     one-chunk, ragged multi-chunk and 2048-cell lines and every boundary
-    kind."""
+    kind, down to 3-cell lines."""
     pp = gpu()
     print(f"char 2d case {nx}x{ny} bc={bc}", flush=True)
     U = field_2d(nx, ny, seed=nx + ny)
