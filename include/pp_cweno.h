@@ -198,8 +198,11 @@ int pp_cweno_step_static(const pp_cweno_config *cfg, double *U, double dt);
 /* Advance U (in place) from t = 0 until t_end or nsteps_max steps, whichever
  * comes first, with the time-step rule `rule` (PP_DT_*) and factor cfl; dt is
  * computed on the device every step.  Writes the time reached and the number
- * of steps taken to *t_out, *steps_out (host; either may be NULL).
- * Synchronises; returns PP_ESTATE if a stage left the admissible set. */
+ * of steps taken to *t_out, *steps_out (host; either may be NULL).  A 1D run
+ * of the compact scheme loops inside one kernel; the other runs replay a
+ * captured hipGraph of 16 steps on a private stream ordered after the
+ * config's stream (kernel timing on: launched directly).  Synchronises;
+ * returns PP_ESTATE if a stage left the admissible set. */
 int pp_cweno_run(pp_cweno_ctx *ctx, double *U, double t_end, int64_t nsteps_max, double cfl,
                  int rule, double *t_out, int64_t *steps_out);
 
