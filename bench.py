@@ -22,7 +22,7 @@ Other workloads (one JSON line each, bounded runs):
   --workload char2d       the same on the 2D density wave (4x4 blocks per line):
                           ms per step of both reconstructions, N = 256..2048
   --dt-rule cfl|pp|restart   time-step rule of ensemble / rarefaction1d / blast1d
-  --recon cweno|char      reconstruction of wave1d / rarefaction1d / blast1d
+  --recon cweno|char      reconstruction of ensemble (FP64) / wave1d / rarefaction1d / blast1d
   --workload gauss2d      Gauss-node 2D operator against the line operator: error of L
                           on a smooth nonlinear flow and cost per step, N = 128..2048
   --workload copy         plain device copy of a known size (counter calibration)
@@ -290,7 +290,7 @@ def other_workload(args):
         nb = len(ens.lengths)
         U = torch.tensor(ens.U, device="cuda")
         s = pp.Solver(ndim=1, lengths=ens.lengths, dxs=ens.dx, bcs=[1] * (2 * nb), precision=prec,
-                      batch_rule=rule_id)
+                      batch_rule=rule_id, recon=recon_id)
         plan, plan_ms = s.batch_tune(U, 1.0 / 12.0)       # launch plan (length classes)
         s.batch_run(U.clone(), ens.t_end, 2, 1.0 / 12.0)   # warm-up (graph, kernels)
         torch.cuda.synchronize()
@@ -335,7 +335,8 @@ def other_workload(args):
         out.update(metric="cell-updates/s, 4096-problem 1D Riemann ensemble",
                    value=cu / wall, steps=int(max(steps)), ms_per_step=1e3 * wall / max(steps),
                    config={"workload": f"{nb} Riemann problems, N in [256,4096] (sum "
-                                       f"{int(ens.lengths.sum())} cells), {prec_name}, " +
+                                       f"{int(ens.lengths.sum())} cells), {prec_name}, "
+                                       f"{args.recon} reconstruction, " +
                                        (f"to t_end {ens.t_end} (problems at t_end: "
                                         f"{sum(1 for t in ts if t >= ens.t_end)}; slowest at "
                                         f"t = {t_min})" if args.full else

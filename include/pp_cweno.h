@@ -105,15 +105,17 @@ enum { PP_FLUX_HLLC = 0, PP_FLUX_LF = 1 };
  * block tridiagonal system in the conserved nodal values per side (the
  * paper's choice for discontinuous problems).  In 2D each line takes the
  * eigenvectors of the flux Jacobian along it: 4x4 blocks (acoustic,
- * entropy, shear and acoustic fields).  FP64, unbatched, the line operator
- * (PP_FV_LINE); the 2D form keeps the block rows of every line of a sweep
- * in device scratch allocated at init (about 1.35 MB per 2048-cell line).
+ * entropy, shear and acoustic fields).  FP64, the line operator
+ * (PP_FV_LINE), also for batched 1D ensembles; the block rows live in
+ * device scratch allocated at init: per line of a 2D sweep (about 1.35 MB
+ * per 2048-cell line) or per workgroup of a batched launch (one per CU).
  * PP_RECON_WENOJS / PP_RECON_WENOZ:
  * the classical explicit fifth-order finite-volume WENO the paper compares
  * against, with Jiang-Shu weights (eps 1e-6, a reading; the paper gives
  * none) or WENO-Z weights (weno_eps), each face value from its own five
  * averages.  The limiter, flux and stage update are shared.  The explicit
- * schemes run in FP64 without a batch (else PP_EUNSUPPORTED at init). */
+ * schemes run in FP64 without a batch, the characteristic one in FP64
+ * (else PP_EUNSUPPORTED at init). */
 enum { PP_RECON_CWENO = 0, PP_RECON_WENOJS = 1, PP_RECON_WENOZ = 2, PP_RECON_CHAR = 3 };
 
 /* 2D face fluxes.  PP_FV_LINE: one state pair per face from the line's

@@ -1109,7 +1109,9 @@ __device__ __forceinline__ void line_op(const LineArgs& A, int b, double* smem) 
         // of the "-" side and of the "+" side (the reversed line); every
         // (component, side) lane then takes its chunk of nodal values
         static_assert(!MIXED, "characteristic reconstruction runs in FP64");
-        double* const chl = A.chs + (long long)b * A.chs_line;   // this line's scratch
+        // this line's scratch: per line of a sweep, or per workgroup of a
+        // persistent launch (each works one problem at a time)
+        double* const chl = A.chs + (LOOPED ? (long long)blockIdx.x : (long long)b) * A.chs_line;
         double* const xsb = chl + 2 * A.chs_side;                  // [side][NC][n]
         if (tid < 128) {
             const int side = tid >> 6;
@@ -1679,7 +1681,7 @@ __global__ void __launch_bounds__(2 * NC * 64 * W) line_kernel(LineArgs A) {
 
 // Batched ensemble: one persistent launch per stage; workgroups pop problem
 // ids (longest first) from a counter until the queue is empty.
-template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED>
+template <int NC, int NRM, int W, int CPT, bool SEG1, bool MIXED, int RECON = PP_RECON_CWENO>
 __global__ void __launch_bounds__(2 * NC * 64 * W) line_kernel_persistent(LineArgs A) {
     extern __shared__ double smem[];
     __shared__ int next;
@@ -1696,7 +1698,7 @@ __global__ void __launch_bounds__(2 * NC * 64 * W) line_kernel_persistent(LineAr
         const int q = next;
         __syncthreads();
         if (q >= Ai.nlines) break;
-        line_op<NC, NRM, W, CPT, SEG1, MIXED, true>(Ai, Ai.order[q], smem);
+        line_op<NC, NRM, W, CPT, SEG1, MIXED, true, RECON>(Ai, Ai.order[q], smem);
         __syncthreads();
     }
 }
@@ -2524,18 +2526,47 @@ int launch_line_explicit(pp_cweno_ctx* ctx, LineArgs A, int nmax) {
     return PP_OK;
 }
 
+// Persistent launch of the characteristic-wise line kernel (batched 1D
+// ensembles, FP64): grid workgroups, each with its own row scratch.
+template <int NC, int NRM, int W, int CPT>
+int launch_char_persistent(pp_cweno_ctx* ctx, LineArgs A, int nmax, int grid) {
+    constexpr int NT = 2 * NC * 64 * W;
+    const int seg = pick_segment<NC, W, CPT, false, PP_RECON_CHAR>(nmax);
+    A.seg_max = seg;
+    const size_t lds = line_lds_bytes<NC, W, false, PP_RECON_CHAR>(nmax, seg);
+    if (lds > kLdsBudget || (seg + NT - 1) / NT > CPT)
+        return fail(ctx, PP_EUNSUPPORTED, "line too long for the on-chip line kernel");
+    if (grid > ctx->n_sm) return fail(ctx, PP_EINVAL, "persistent grid above the scratch slots");
+    const void* fn =
+        seg >= nmax ? (const void*)line_kernel_persistent<NC, NRM, W, CPT, true, false, PP_RECON_CHAR>
+                    : (const void*)line_kernel_persistent<NC, NRM, W, CPT, false, false, PP_RECON_CHAR>;
+    {
+        const int rg = grant_lds(ctx, fn, lds);
+        if (rg) return rg;
+    }
+    void* args[] = {&A};
+    HIPCHK(ctx, hipLaunchKernel(fn, dim3(grid), dim3(NT), args, lds, ctx->stream));
+    return PP_OK;
+}
+
 template <int NC, int NRM, int W, int CPT>
 int launch_line(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int grid) {
     if (ctx->cfg.recon != PP_RECON_CWENO) {
-        // init admits the other reconstructions only in FP64 and without a batch
-        if (persistent) return fail(ctx, PP_EUNSUPPORTED, "explicit schemes are not batched");
+        // init admits the other reconstructions only in FP64 (batched: the
+        // characteristic one)
         if (ctx->cfg.recon == PP_RECON_CHAR) {
-            // every line of the launch has its own scratch (init sized it)
+            // every line of a sweep, or every workgroup of a persistent
+            // launch, has its own scratch (init sized it for nmax cells)
             A.chs = ctx->chs;
-            A.chs_side = char_side_len(NC, A.n);
-            A.chs_line = char_line_len(NC, A.n);
+            A.chs_side = char_side_len(NC, nmax);
+            A.chs_line = char_line_len(NC, nmax);
+            if (persistent) {
+                if constexpr (NC == 3) return launch_char_persistent<NC, NRM, W, CPT>(ctx, A, nmax, grid);
+                else return fail(ctx, PP_EUNSUPPORTED, "persistent launches serve 1D ensembles only");
+            }
             return launch_line_explicit<NC, NRM, W, CPT, PP_RECON_CHAR>(ctx, A, nmax);
         }
+        if (persistent) return fail(ctx, PP_EUNSUPPORTED, "explicit schemes are not batched");
         return ctx->cfg.recon == PP_RECON_WENOJS
                    ? launch_line_explicit<NC, NRM, W, CPT, PP_RECON_WENOJS>(ctx, A, nmax)
                    : launch_line_explicit<NC, NRM, W, CPT, PP_RECON_WENOZ>(ctx, A, nmax);
@@ -3040,8 +3071,10 @@ int check_config(const pp_cweno_config& c) {
     if (c.recon != PP_RECON_CWENO && c.recon != PP_RECON_WENOJS && c.recon != PP_RECON_WENOZ &&
         c.recon != PP_RECON_CHAR)
         return fail(nullptr, PP_EINVAL, "recon must be PP_RECON_CWENO, _WENOJS, _WENOZ or _CHAR");
-    if (c.recon != PP_RECON_CWENO && (c.precision != PP_FP64 || c.nbatch > 0))
-        return fail(nullptr, PP_EUNSUPPORTED, "explicit schemes run in FP64 and unbatched");
+    if (c.recon != PP_RECON_CWENO && c.precision != PP_FP64)
+        return fail(nullptr, PP_EUNSUPPORTED, "the explicit and characteristic schemes run in FP64");
+    if (c.recon != PP_RECON_CWENO && c.recon != PP_RECON_CHAR && c.nbatch > 0)
+        return fail(nullptr, PP_EUNSUPPORTED, "the explicit schemes are not batched");
     if (!(c.weno_eps > 0.0) || !(c.pp_eps_cap > 0.0))
         return fail(nullptr, PP_EINVAL, "epsilons must be > 0");
     if (c.precision != PP_FP64 && c.precision != PP_MIXED)
@@ -3156,6 +3189,11 @@ int pp_cweno_init(const pp_cweno_config* cfg, pp_cweno_ctx** out) {
         }
         ctx->total = off[nb];
         ctx->ncell = ctx->total;
+        // characteristic reconstruction: row scratch per workgroup slot of the
+        // persistent launches (at most one workgroup per CU per launch)
+        if (c.recon == PP_RECON_CHAR &&
+            !dmalloc((void**)&ctx->chs, sizeof(double) * (size_t)ctx->n_sm * (size_t)char_line_len(3, ctx->maxn)))
+            return bail(PP_ENOMEM);
         std::vector<int> order(nb), ln(nb);
         for (int64_t i = 0; i < nb; ++i) {
             order[i] = (int)i;

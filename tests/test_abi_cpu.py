@@ -63,7 +63,7 @@ def _init(**kw):
     (dict(recon=4), pp.PP_EINVAL),
     (dict(recon=3, precision=1), pp.PP_EUNSUPPORTED),             # characteristic: FP64
     (dict(recon=3, ndim=2, ny=64, dy=0.01, precision=1), pp.PP_EUNSUPPORTED),   # also in 2D
-    (dict(recon=3, nbatch=2), pp.PP_EUNSUPPORTED),                # and not batched
+    (dict(recon=3, nbatch=2, precision=1), pp.PP_EUNSUPPORTED),   # batched: FP64 too
     (dict(recon=-1), pp.PP_EINVAL),
     (dict(recon=1, precision=1), pp.PP_EUNSUPPORTED),   # explicit schemes: FP64 only
     (dict(recon=2, nbatch=2), pp.PP_EUNSUPPORTED),      # and not batched

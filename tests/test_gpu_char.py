@@ -385,3 +385,105 @@ def test_char_2d_blast_run_matches_oracle():
           flush=True)
     assert steps == k_ref and abs(t - t_ref) <= 1e-14
     assert got[0].min() > 0 and W.pressure(got).min() > 0
+
+
+# ----------------------------------------------------------- batched ensembles
+def _step_sensitivity_1d(U, dt, bc, h, ref, P, k=3):
+    """The oracle's own change of one SSP-RK3 step under k seeded relative
+    input perturbations of 1e-15 (relative to each component's maximum)."""
+    rng = np.random.default_rng(1402)
+    sens = 0.0
+    for _ in range(k):
+        V0 = U * (1.0 + 1e-15 * rng.standard_normal(U.shape))
+        V1 = oracle.stage_1d(V0, V0, 1, dt, bc, h, P)
+        V2 = oracle.stage_1d(V0, V1, 2, dt, bc, h, P)
+        sens = max(sens, comp_rel(oracle.stage_1d(V0, V2, 3, dt, bc, h, P), ref))
+    return sens
+
+
+@pytest.mark.parametrize("n_lo,n_hi,plan", [(8, 40, 0), (256, 4096, 1), (8, 40, 3),
+                                             (256, 4096, 4)])
+def test_char_batch_step_parity(n_lo, n_hi, plan):
+    """Batched ensembles with the characteristic-wise reconstruction: one
+    SSP-RK3 step of every problem (persistent launches, one row scratch per
+    workgroup) against the oracle's characteristic stages, each problem with
+    its own dt, under launch plans with one and two waves per system and one
+    or two length classes; one problem inactive.  Bar: 1e-12, or 4x the
+    oracle's own change under 1e-15 input perturbations where larger."""
+    pp = gpu()
+    ens = W.riemann_ensemble(nprob=16, seed=1402, n_lo=n_lo, n_hi=n_hi)
+    print(f"char batch n in [{n_lo},{n_hi}] plan={plan}", flush=True)
+    nb = len(ens.lengths)
+    P = oracle.params(**P_CHAR)
+    dts = np.array([(1.0 / 12.0) * ens.dx[i] /
+                    oracle.max_speed_1d(ens.U[:, ens.offsets[i]:ens.offsets[i + 1]])
+                    for i in range(nb)])
+    dts[3] = 0.0
+    s = pp.Solver(ndim=1, lengths=ens.lengths, dxs=ens.dx, bcs=[1] * (2 * nb),
+                  recon=pp.PP_RECON_CHAR)
+    assert s.batch_tune(force_plan=plan)[0] == plan
+    Ud = dev(ens.U)
+    s.batch_step(Ud, dev(dts))
+    torch.cuda.synchronize()
+    got = Ud.cpu().numpy()
+    s.close()
+    worst = 0.0
+    for i in range(nb):
+        sl = slice(ens.offsets[i], ens.offsets[i + 1])
+        U = ens.U[:, sl]
+        if dts[i] == 0.0:
+            assert np.array_equal(got[:, sl], U)
+            continue
+        h = ens.dx[i]
+        U1 = oracle.stage_1d(U, U, 1, dts[i], (1, 1), h, P)
+        U2 = oracle.stage_1d(U, U1, 2, dts[i], (1, 1), h, P)
+        U3 = oracle.stage_1d(U, U2, 3, dts[i], (1, 1), h, P)
+        err = comp_rel(got[:, sl], U3)
+        if err > TOL_STAGE:
+            bar = max(TOL_STAGE, 4.0 * _step_sensitivity_1d(U, dts[i], (1, 1), h, U3, P, k=6))
+            print(f"  problem {i} (n={ens.lengths[i]}): {err:.2e}, conditioning bound {bar:.1e}",
+                  flush=True)
+            assert err <= bar, i
+        worst = max(worst, err)
+    print(f"  largest difference {worst:.2e}", flush=True)
+
+
+def test_char_batch_run_matches_oracle():
+    """The graph-replayed batched driver with the characteristic-wise
+    reconstruction to t = 0.03 (12 problems, 32..160 cells) against the
+    oracle's per-problem runs: problem 10 (rho 9.69 | 0.015) leaves G on both
+    sides, so the run reports PP_ESTATE; every other problem takes the
+    oracle's step count and lands within 1e-10, or 4x the oracle's own change
+    under 1e-15 perturbations of its initial data where larger."""
+    pp = gpu()
+    ens = W.riemann_ensemble(nprob=12, seed=7, n_lo=32, n_hi=160)
+    nb = len(ens.lengths)
+    P = oracle.params(**P_CHAR)
+    s = pp.Solver(ndim=1, lengths=ens.lengths, dxs=ens.dx, bcs=[1] * (2 * nb),
+                  recon=pp.PP_RECON_CHAR)
+    Ud = dev(ens.U)
+    with pytest.raises(pp.PPError) as e:
+        s.batch_run(Ud, 0.03, 10 ** 6, 1.0 / 12.0)
+    assert e.value.code == pp.PP_ESTATE
+    steps = s.last_batch_steps()
+    got = Ud.cpu().numpy()
+    s.close()
+    rng = np.random.default_rng(3)
+    compared = 0
+    for i in range(nb):
+        sl = slice(ens.offsets[i], ens.offsets[i + 1])
+        U0 = ens.U[:, sl]
+        ref, info = oracle.run_1d(U0, (1, 1), ens.dx[i], 0.03, p=P)
+        if info["out_of_G"] > 0:
+            assert i == 10
+            continue
+        alt, _ = oracle.run_1d(U0 * (1.0 + 1e-15 * rng.standard_normal(U0.shape)), (1, 1),
+                               ens.dx[i], 0.03, p=P)
+        bar = max(1e-10, 4.0 * comp_rel(alt, ref))
+        d = comp_rel(got[:, sl], ref)
+        print(f"  problem {i}: steps {steps[i]} / {info['steps']}, difference {d:.2e} "
+              f"(bar {bar:.1e})", flush=True)
+        assert steps[i] == info["steps"], i
+        assert d <= bar, i
+        compared += 1
+    assert compared == nb - 1
