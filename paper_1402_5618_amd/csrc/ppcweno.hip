@@ -642,7 +642,7 @@ __device__ __forceinline__ void set_identity(double (&M)[NB * NB]) {
 // scr: this side's row scratch; xs: the nodal values [NB][n] of this side
 // (reversed order for the "+" side), components in the grid's order.
 template <int NB, int NRM, int PSH>
-__device__ void char_side(const double* __restrict__ sU, int LP, int n, bool cyclic, bool rev,
+__device__ __forceinline__ void char_side(const double* __restrict__ sU, int LP, int n, bool cyclic, bool rev,
                           int k, double gam, double weps, double* __restrict__ scr,
                           double* __restrict__ xs) {
     constexpr int BB = NB * NB;
@@ -682,7 +682,8 @@ __device__ void char_side(const double* __restrict__ sU, int LP, int n, bool cyc
             xhi[c] = weno5z_value(cell(c, n - 2), cell(c, n - 1), cell(c, n), cell(c, n + 1),
                                   cell(c, n + 2), weps);
     }
-    auto rows = [&](int gg, double (&A)[BB], double (&B)[BB], double (&C)[BB], double (&r)[NB]) {
+    auto rows = [&](int gg, double (&A)[BB], double (&B)[BB], double (&C)[BB],
+                    double (&r)[NB]) __attribute__((always_inline)) {
         double Ua[NB], Ub[NB], L[BB], u5[5][NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
@@ -816,20 +817,20 @@ __device__ void char_side(const double* __restrict__ sU, int LP, int n, bool cyc
 #pragma unroll
         for (int i = 0; i < NB; ++i) Dk[i] -= t3[i];
     }
-    // block parallel cyclic reduction of the separator system over the wave
+    // block parallel cyclic reduction of the separator system over the wave;
+    // the lower neighbour's blocks are used up before the upper one's are
+    // fetched (the same arithmetic, fewer blocks live at once)
     for (int st = 1; st < P; st <<= 1) {
         const int km = (k - st) & (P - 1), kp = (k + st) & (P - 1);
-        double Am[BB], Bm[BB], Cm[BB], Dm[NB], Ap[BB], Bp[BB], Cp[BB], Dp[NB];
-        shflN<BB>(Ak, km, Am);
-        shflN<BB>(Bk, km, Bm);
-        shflN<BB>(Ck, km, Cm);
-        shflN<NB>(Dk, km, Dm);
-        shflN<BB>(Ak, kp, Ap);
-        shflN<BB>(Bk, kp, Bp);
-        shflN<BB>(Ck, kp, Cp);
-        shflN<NB>(Dk, kp, Dp);
-        if (!cyclic) {
-            if (k - st < 0) {
+        const bool lo_out = !cyclic && k - st < 0, hi_out = !cyclic && k + st >= P;
+        double nA[BB], nB[BB], nD[NB], al[BB];
+        {
+            double Am[BB], Bm[BB], Cm[BB], Dm[NB], iBm[BB], T[BB], t3[NB];
+            shflN<BB>(Ak, km, Am);
+            shflN<BB>(Bk, km, Bm);
+            shflN<BB>(Ck, km, Cm);
+            shflN<NB>(Dk, km, Dm);
+            if (lo_out) {
 #pragma unroll
                 for (int i = 0; i < BB; ++i) {
                     Am[i] = 0.0;
@@ -839,7 +840,25 @@ __device__ void char_side(const double* __restrict__ sU, int LP, int n, bool cyc
 #pragma unroll
                 for (int i = 0; i < NB; ++i) Dm[i] = 0.0;
             }
-            if (k + st >= P) {
+            invN<NB>(Bm, iBm);
+            mmN<NB>(Ak, iBm, al);
+#pragma unroll
+            for (int i = 0; i < BB; ++i) al[i] = -al[i];
+            mmN<NB>(al, Cm, T);
+#pragma unroll
+            for (int i = 0; i < BB; ++i) nB[i] = Bk[i] + T[i];
+            mvN<NB>(al, Dm, t3);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) nD[i] = Dk[i] + t3[i];
+            mmN<NB>(al, Am, nA);
+        }
+        {
+            double Ap[BB], Bp[BB], Cp[BB], Dp[NB], iBp[BB], bt[BB], T[BB], t3[NB];
+            shflN<BB>(Ak, kp, Ap);
+            shflN<BB>(Bk, kp, Bp);
+            shflN<BB>(Ck, kp, Cp);
+            shflN<NB>(Dk, kp, Dp);
+            if (hi_out) {
 #pragma unroll
                 for (int i = 0; i < BB; ++i) {
                     Ap[i] = 0.0;
@@ -849,34 +868,23 @@ __device__ void char_side(const double* __restrict__ sU, int LP, int n, bool cyc
 #pragma unroll
                 for (int i = 0; i < NB; ++i) Dp[i] = 0.0;
             }
+            invN<NB>(Bp, iBp);
+            mmN<NB>(Ck, iBp, bt);
+#pragma unroll
+            for (int i = 0; i < BB; ++i) bt[i] = -bt[i];
+            mmN<NB>(bt, Ap, T);
+#pragma unroll
+            for (int i = 0; i < BB; ++i) nB[i] += T[i];
+            mvN<NB>(bt, Dp, t3);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) nD[i] += t3[i];
+            mmN<NB>(bt, Cp, Ck);
         }
-        double iBm[BB], iBp[BB], al[BB], bt[BB], T[BB], t3[NB];
-        invN<NB>(Bm, iBm);
-        invN<NB>(Bp, iBp);
-        mmN<NB>(Ak, iBm, al);
-        mmN<NB>(Ck, iBp, bt);
 #pragma unroll
         for (int i = 0; i < BB; ++i) {
-            al[i] = -al[i];
-            bt[i] = -bt[i];
+            Ak[i] = nA[i];
+            Bk[i] = nB[i];
         }
-        double nB[BB], nD[NB];
-        mmN<NB>(al, Cm, T);
-#pragma unroll
-        for (int i = 0; i < BB; ++i) nB[i] = Bk[i] + T[i];
-        mmN<NB>(bt, Ap, T);
-#pragma unroll
-        for (int i = 0; i < BB; ++i) nB[i] += T[i];
-        mvN<NB>(al, Dm, t3);
-#pragma unroll
-        for (int i = 0; i < NB; ++i) nD[i] = Dk[i] + t3[i];
-        mvN<NB>(bt, Dp, t3);
-#pragma unroll
-        for (int i = 0; i < NB; ++i) nD[i] += t3[i];
-        mmN<NB>(al, Am, Ak);
-        mmN<NB>(bt, Cp, Ck);
-#pragma unroll
-        for (int i = 0; i < BB; ++i) Bk[i] = nB[i];
 #pragma unroll
         for (int i = 0; i < NB; ++i) Dk[i] = nD[i];
     }
