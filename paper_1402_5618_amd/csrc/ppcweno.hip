@@ -682,9 +682,14 @@ __device__ __forceinline__ void char_side(const double* __restrict__ sU, int LP,
             xhi[c] = weno5z_value(cell(c, n - 2), cell(c, n - 1), cell(c, n), cell(c, n + 1),
                                   cell(c, n + 2), weps);
     }
-    auto rows = [&](int gg, double (&A)[BB], double (&B)[BB], double (&C)[BB],
+    // Row gg of the block system in factored form: A = diag(ra) L,
+    // B = diag(rb) L, C = diag(rc) L with L the left eigenvectors of the
+    // node and (ra, rb, rc, rr) the scalar rows of eq. (CWENO-FV) of each
+    // field; the closure values of a non-periodic line move to the right
+    // side (ra or rc then 0).
+    auto rows = [&](int gg, double (&L)[BB], double (&ra)[NB], double (&rb)[NB], double (&rc)[NB],
                     double (&r)[NB]) __attribute__((always_inline)) {
-        double Ua[NB], Ub[NB], L[BB], u5[5][NB];
+        double Ua[NB], Ub[NB], u5[5][NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
             Ua[c] = cell(c, gg);
@@ -701,33 +706,28 @@ __device__ __forceinline__ void char_side(const double* __restrict__ sU, int LP,
             double v[5];
 #pragma unroll
             for (int m = 0; m < 5; ++m) v[m] = dotN<NB>(&L[NB * f], 1, u5[m], 1);
-            double w0, w1, w2, a, b, cc, rr;
+            double w0, w1, w2;
             wenoz_weights<double>(v[0], v[1], v[2], v[3], v[4], weps, w0, w1, w2);
-            cweno_row<double>(w0, w1, w2, v[1], v[2], v[3], a, b, cc, rr);
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                A[NB * f + q] = a * L[NB * f + q];
-                B[NB * f + q] = b * L[NB * f + q];
-                C[NB * f + q] = cc * L[NB * f + q];
-            }
-            r[f] = rr;
+            cweno_row<double>(w0, w1, w2, v[1], v[2], v[3], ra[f], rb[f], rc[f], r[f]);
         }
         if (!cyclic) {   // the known closure values move to the right side
             if (gg == 0) {
                 double t[NB];
-                mvN<NB>(A, xlo, t);
+                mvN<NB>(L, xlo, t);
 #pragma unroll
-                for (int i = 0; i < NB; ++i) r[i] -= t[i];
-#pragma unroll
-                for (int i = 0; i < BB; ++i) A[i] = 0.0;
+                for (int i = 0; i < NB; ++i) {
+                    r[i] -= ra[i] * t[i];
+                    ra[i] = 0.0;
+                }
             }
             if (gg == n - 1) {
                 double t[NB];
-                mvN<NB>(C, xhi, t);
+                mvN<NB>(L, xhi, t);
 #pragma unroll
-                for (int i = 0; i < NB; ++i) r[i] -= t[i];
-#pragma unroll
-                for (int i = 0; i < BB; ++i) C[i] = 0.0;
+                for (int i = 0; i < NB; ++i) {
+                    r[i] -= rc[i] * t[i];
+                    rc[i] = 0.0;
+                }
             }
         }
     };
@@ -759,20 +759,32 @@ __device__ __forceinline__ void char_side(const double* __restrict__ sU, int LP,
     for (int i = 0; i < BB; ++i) CX[i] = 0.0;
     if (act) {
         for (int j = 0; j < len - 1; ++j) {
-            double A[BB], B[BB], C[BB], r[NB], M[BB], T[BB], Mi[BB], t3[NB];
-            rows(r0 + j, A, B, C, r);
-            mmN<NB>(A, cp, T);
+            double L[BB], ra[NB], rb[NB], rc[NB], r[NB], M[BB], T[BB], Mi[BB], t3[NB];
+            rows(r0 + j, L, ra, rb, rc, r);
+            // M = B - A Cp = diag(rb) L - diag(ra) (L Cp)
+            mmN<NB>(L, cp, T);
 #pragma unroll
-            for (int i = 0; i < BB; ++i) M[i] = B[i] - T[i];
-            mvN<NB>(A, pp, t3);
+            for (int f = 0; f < NB; ++f)
 #pragma unroll
-            for (int i = 0; i < NB; ++i) t3[i] = r[i] - t3[i];
-            mmN<NB>(A, qq, T);
+                for (int q = 0; q < NB; ++q) M[NB * f + q] = rb[f] * L[NB * f + q] - ra[f] * T[NB * f + q];
+            // r - A p
+            mvN<NB>(L, pp, t3);
 #pragma unroll
-            for (int i = 0; i < BB; ++i) T[i] = -T[i];
+            for (int f = 0; f < NB; ++f) t3[f] = r[f] - ra[f] * t3[f];
             invN<NB>(M, Mi);
-            mmN<NB>(Mi, C, cp);
+            // Cp = M^-1 C with C = diag(rc) L
+#pragma unroll
+            for (int f = 0; f < NB; ++f)
+#pragma unroll
+                for (int q = 0; q < NB; ++q) M[NB * f + q] = rc[f] * L[NB * f + q];
+            mmN<NB>(Mi, M, cp);
             mvN<NB>(Mi, t3, pp);
+            // Q = -M^-1 A Q_prev with A = diag(ra) L
+            mmN<NB>(L, qq, T);
+#pragma unroll
+            for (int f = 0; f < NB; ++f)
+#pragma unroll
+                for (int q = 0; q < NB; ++q) T[NB * f + q] = -ra[f] * T[NB * f + q];
             mmN<NB>(Mi, T, qq);
 #pragma unroll
             for (int i = 0; i < BB; ++i) {
@@ -792,15 +804,25 @@ __device__ __forceinline__ void char_side(const double* __restrict__ sU, int LP,
 #pragma unroll
             for (int i = 0; i < BB; ++i) FS[i] = -T[i];
         }
-        double A[BB], B[BB], r[NB], T[BB], t3[NB];
-        rows(r1 - 1, A, B, CX, r);
-        mmN<NB>(A, qq, Ak);
-        mmN<NB>(A, cp, T);
+        // the chunk's last row, reduced onto the separators
+        double L[BB], ra[NB], rb[NB], rc[NB], r[NB], T[BB], t3[NB];
+        rows(r1 - 1, L, ra, rb, rc, r);
+        mmN<NB>(L, qq, T);
 #pragma unroll
-        for (int i = 0; i < BB; ++i) Bk[i] = B[i] - T[i];
-        mvN<NB>(A, pp, t3);
+        for (int f = 0; f < NB; ++f)
 #pragma unroll
-        for (int i = 0; i < NB; ++i) Dk[i] = r[i] - t3[i];
+            for (int q = 0; q < NB; ++q) Ak[NB * f + q] = ra[f] * T[NB * f + q];
+        mmN<NB>(L, cp, T);
+#pragma unroll
+        for (int f = 0; f < NB; ++f)
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                Bk[NB * f + q] = rb[f] * L[NB * f + q] - ra[f] * T[NB * f + q];
+                CX[NB * f + q] = rc[f] * L[NB * f + q];
+            }
+        mvN<NB>(L, pp, t3);
+#pragma unroll
+        for (int f = 0; f < NB; ++f) Dk[f] = r[f] - ra[f] * t3[f];
     }
     // the next chunk's first-row relation (x_{r1} = FP' + FQ' Rsep + FS' Rsep')
     {
