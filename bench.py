@@ -60,10 +60,10 @@ FLOPS_PER_SWEEP_CELL = 716.0
 # hash is recorded (profiles/line_kernel_2d_density_wave_2048_fp64.md);
 # otherwise traffic is reported null.
 TRAFFIC_RECORD = {
-    "src_sha256": "f9ee5690f100124dfe42e3051782eb0e174c87bd0d3357fe2f2be3b97249a6a8",
+    "src_sha256": "0e8e86411f4acac62f74114a67a5893785101d4fe9e13dead2de1a8554bf77bb",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "x": {"fetch_kib": 65845.5, "write_kib": 163930.0},
-    "y": {"fetch_kib": 66235.1, "write_kib": 163840.0},
+    "x": {"fetch_kib": 66005.0, "write_kib": 163971.0},
+    "y": {"fetch_kib": 65996.2, "write_kib": 163840.0},
 }
 
 
