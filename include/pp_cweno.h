@@ -114,8 +114,8 @@ enum { PP_FLUX_HLLC = 0, PP_FLUX_LF = 1 };
  * against, with Jiang-Shu weights (eps 1e-6, a reading; the paper gives
  * none) or WENO-Z weights (weno_eps), each face value from its own five
  * averages.  The limiter, flux and stage update are shared.  The explicit
- * schemes run in FP64 without a batch, the characteristic one in FP64
- * (else PP_EUNSUPPORTED at init). */
+ * and characteristic schemes run in FP64 (else PP_EUNSUPPORTED at init),
+ * single lines, 2D grids and batched ensembles alike. */
 enum { PP_RECON_CWENO = 0, PP_RECON_WENOJS = 1, PP_RECON_WENOZ = 2, PP_RECON_CHAR = 3 };
 
 /* 2D face fluxes.  PP_FV_LINE: one state pair per face from the line's

@@ -2556,20 +2556,21 @@ int launch_line_explicit(pp_cweno_ctx* ctx, LineArgs A, int nmax) {
     return PP_OK;
 }
 
-// Persistent launch of the characteristic-wise line kernel (batched 1D
-// ensembles, FP64): grid workgroups, each with its own row scratch.
-template <int NC, int NRM, int W, int CPT>
-int launch_char_persistent(pp_cweno_ctx* ctx, LineArgs A, int nmax, int grid) {
+// Persistent launch of the characteristic-wise or an explicit line kernel
+// (batched 1D ensembles, FP64): grid workgroups, each (characteristic) with
+// its own row scratch.
+template <int NC, int NRM, int W, int CPT, int RECON>
+int launch_recon_persistent(pp_cweno_ctx* ctx, LineArgs A, int nmax, int grid) {
     constexpr int NT = 2 * NC * 64 * W;
-    const int seg = pick_segment<NC, W, CPT, false, PP_RECON_CHAR>(nmax);
+    const int seg = pick_segment<NC, W, CPT, false, RECON>(nmax);
     A.seg_max = seg;
-    const size_t lds = line_lds_bytes<NC, W, false, PP_RECON_CHAR>(nmax, seg);
+    const size_t lds = line_lds_bytes<NC, W, false, RECON>(nmax, seg);
     if (lds > kLdsBudget || (seg + NT - 1) / NT > CPT)
         return fail(ctx, PP_EUNSUPPORTED, "line too long for the on-chip line kernel");
     if (grid > ctx->n_sm) return fail(ctx, PP_EINVAL, "persistent grid above the scratch slots");
     const void* fn =
-        seg >= nmax ? (const void*)line_kernel_persistent<NC, NRM, W, CPT, true, false, PP_RECON_CHAR>
-                    : (const void*)line_kernel_persistent<NC, NRM, W, CPT, false, false, PP_RECON_CHAR>;
+        seg >= nmax ? (const void*)line_kernel_persistent<NC, NRM, W, CPT, true, false, RECON>
+                    : (const void*)line_kernel_persistent<NC, NRM, W, CPT, false, false, RECON>;
     {
         const int rg = grant_lds(ctx, fn, lds);
         if (rg) return rg;
@@ -2582,8 +2583,7 @@ int launch_char_persistent(pp_cweno_ctx* ctx, LineArgs A, int nmax, int grid) {
 template <int NC, int NRM, int W, int CPT>
 int launch_line(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int grid) {
     if (ctx->cfg.recon != PP_RECON_CWENO) {
-        // init admits the other reconstructions only in FP64 (batched: the
-        // characteristic one)
+        // init admits the other reconstructions only in FP64
         if (ctx->cfg.recon == PP_RECON_CHAR) {
             // every line of a sweep, or every workgroup of a persistent
             // launch, has its own scratch (init sized it for nmax cells)
@@ -2591,12 +2591,20 @@ int launch_line(pp_cweno_ctx* ctx, LineArgs A, int nmax, bool persistent, int gr
             A.chs_side = char_side_len(NC, nmax);
             A.chs_line = char_line_len(NC, nmax);
             if (persistent) {
-                if constexpr (NC == 3) return launch_char_persistent<NC, NRM, W, CPT>(ctx, A, nmax, grid);
+                if constexpr (NC == 3)
+                    return launch_recon_persistent<NC, NRM, W, CPT, PP_RECON_CHAR>(ctx, A, nmax, grid);
                 else return fail(ctx, PP_EUNSUPPORTED, "persistent launches serve 1D ensembles only");
             }
             return launch_line_explicit<NC, NRM, W, CPT, PP_RECON_CHAR>(ctx, A, nmax);
         }
-        if (persistent) return fail(ctx, PP_EUNSUPPORTED, "explicit schemes are not batched");
+        if (persistent) {
+            if constexpr (NC == 3)
+                return ctx->cfg.recon == PP_RECON_WENOJS
+                           ? launch_recon_persistent<NC, NRM, W, CPT, PP_RECON_WENOJS>(ctx, A, nmax, grid)
+                           : launch_recon_persistent<NC, NRM, W, CPT, PP_RECON_WENOZ>(ctx, A, nmax, grid);
+            else
+                return fail(ctx, PP_EUNSUPPORTED, "persistent launches serve 1D ensembles only");
+        }
         return ctx->cfg.recon == PP_RECON_WENOJS
                    ? launch_line_explicit<NC, NRM, W, CPT, PP_RECON_WENOJS>(ctx, A, nmax)
                    : launch_line_explicit<NC, NRM, W, CPT, PP_RECON_WENOZ>(ctx, A, nmax);
@@ -3103,8 +3111,6 @@ int check_config(const pp_cweno_config& c) {
         return fail(nullptr, PP_EINVAL, "recon must be PP_RECON_CWENO, _WENOJS, _WENOZ or _CHAR");
     if (c.recon != PP_RECON_CWENO && c.precision != PP_FP64)
         return fail(nullptr, PP_EUNSUPPORTED, "the explicit and characteristic schemes run in FP64");
-    if (c.recon != PP_RECON_CWENO && c.recon != PP_RECON_CHAR && c.nbatch > 0)
-        return fail(nullptr, PP_EUNSUPPORTED, "the explicit schemes are not batched");
     if (!(c.weno_eps > 0.0) || !(c.pp_eps_cap > 0.0))
         return fail(nullptr, PP_EINVAL, "epsilons must be > 0");
     if (c.precision != PP_FP64 && c.precision != PP_MIXED)

@@ -66,7 +66,7 @@ def _init(**kw):
     (dict(recon=3, nbatch=2, precision=1), pp.PP_EUNSUPPORTED),   # batched: FP64 too
     (dict(recon=-1), pp.PP_EINVAL),
     (dict(recon=1, precision=1), pp.PP_EUNSUPPORTED),   # explicit schemes: FP64 only
-    (dict(recon=2, nbatch=2), pp.PP_EUNSUPPORTED),      # and not batched
+    (dict(recon=2, nbatch=2, precision=1), pp.PP_EUNSUPPORTED),   # batched: FP64 too
     (dict(nx=5000), pp.PP_EUNSUPPORTED),
     (dict(ndim=2, ny=3000, dy=0.1, nx=64), pp.PP_EUNSUPPORTED),
     (dict(ndim=2, ny=64, dy=0.0), pp.PP_EINVAL),

@@ -351,6 +351,54 @@ def test_batch_step_parity(n_lo, n_hi, plan):
     s.close()
 
 
+@pytest.mark.parametrize("recon", [1, 2])
+@pytest.mark.parametrize("n_lo,n_hi,plan", [(8, 40, 0), (256, 4096, 1), (8, 40, 3),
+                                             (256, 4096, 4)])
+def test_batch_step_parity_explicit_schemes(recon, n_lo, n_hi, plan):
+    """Batched ensembles with the explicit WENO-JS / WENO-Z reconstructions
+    (persistent launches templated on the reconstruction): one step of every
+    problem against the oracle's stages of the same scheme, one problem
+    inactive, under plans with one and two waves per system."""
+    pp = gpu()
+    ens = ensemble(16, n_lo, n_hi)
+    print(f"case batch recon={recon} n in [{n_lo},{n_hi}] plan={plan}", flush=True)
+    nb = len(ens.lengths)
+    P = oracle.params(recon=recon)
+    dts = np.array([(1.0 / 12.0) * ens.dx[i] /
+                    oracle.max_speed_1d(ens.U[:, ens.offsets[i]:ens.offsets[i + 1]])
+                    for i in range(nb)])
+    dts[2] = 0.0
+    rc = pp.PP_RECON_WENOJS if recon == 1 else pp.PP_RECON_WENOZ
+    s = pp.Solver(ndim=1, lengths=ens.lengths, dxs=ens.dx, bcs=[1] * (2 * nb), recon=rc)
+    assert s.batch_tune(force_plan=plan)[0] == plan
+    Ud = dev(ens.U)
+    s.batch_step(Ud, dev(dts))
+    torch.cuda.synchronize()
+    got = Ud.cpu().numpy()
+    s.close()
+    for i in range(nb):
+        sl = slice(ens.offsets[i], ens.offsets[i + 1])
+        U = ens.U[:, sl]
+        if dts[i] == 0.0:
+            assert np.array_equal(got[:, sl], U)
+            continue
+        h = ens.dx[i]
+        U1 = oracle.stage_1d(U, U, 1, dts[i], (1, 1), h, P)
+        U2 = oracle.stage_1d(U, U1, 2, dts[i], (1, 1), h, P)
+        U3 = oracle.stage_1d(U, U2, 3, dts[i], (1, 1), h, P)
+        err = comp_rel(got[:, sl], U3)
+        if err > TOL_STAGE:
+            rng = np.random.default_rng(1402)
+            sens = 0.0
+            for _ in range(4):
+                V0 = U * (1.0 + 1e-15 * rng.standard_normal(U.shape))
+                V1 = oracle.stage_1d(V0, V0, 1, dts[i], (1, 1), h, P)
+                V2 = oracle.stage_1d(V0, V1, 2, dts[i], (1, 1), h, P)
+                sens = max(sens, comp_rel(oracle.stage_1d(V0, V2, 3, dts[i], (1, 1), h, P), U3))
+            print(f"  problem {i}: {err:.2e}, conditioning bound {4 * sens:.1e}", flush=True)
+            assert err <= max(TOL_STAGE, 4.0 * sens), i
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_full_ensemble_step_sampled_parity(precision):
     """The benchmarked ensemble at full size (4096 seeded Riemann problems,
