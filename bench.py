@@ -60,10 +60,10 @@ FLOPS_PER_SWEEP_CELL = 716.0
 # hash is recorded (profiles/line_kernel_2d_density_wave_2048_fp64.md);
 # otherwise traffic is reported null.
 TRAFFIC_RECORD = {
-    "src_sha256": "0e8e86411f4acac62f74114a67a5893785101d4fe9e13dead2de1a8554bf77bb",
+    "src_sha256": "c799dec158d8fbb4dbb4399ae5a1334a007458ef6a59c4d3a16c401b26ee4f43",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "x": {"fetch_kib": 66005.0, "write_kib": 163971.0},
-    "y": {"fetch_kib": 65996.2, "write_kib": 163840.0},
+    "x": {"fetch_kib": 66010.0, "write_kib": 163970.0},
+    "y": {"fetch_kib": 66310.9, "write_kib": 163840.0},
 }
 
 
