@@ -287,3 +287,13 @@ def test_rhs_2d_char_one_axis_equals_1d():
     for j in range(ny):
         np.testing.assert_allclose(L2[[0, 1, 3], j], L1, atol=1e-12 * scale)
     assert np.abs(L2[2]).max() < 1e-13 * scale
+
+
+def test_rhs_2d_char_conserves_on_periodic_grids():
+    """The characteristic lines change the face values, not the flux form:
+    on a periodic grid the flux differences telescope, so the sum of L over
+    the cells vanishes to roundoff in every component."""
+    U = _blast_2d(24, 20)
+    L = oracle.rhs_2d(U, (0, 0, 0, 0), 1 / 24, 1 / 20, oracle.params(recon=3))
+    for k in range(4):
+        assert abs(L[k].sum()) <= 1e-12 * np.abs(L[k]).sum(), k
