@@ -552,3 +552,58 @@ def test_char_2d_run_conserves_mass_and_energy():
         drift = abs(got[k].sum() - U0[k].sum()) / np.abs(U0[k]).sum()
         print(f"component {k}: relative drift {drift:.2e}", flush=True)
         assert drift <= 1e-13, k
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0, 0), (1, 2, 2, 1)])
+def test_char_2d_2048_stage_sampled_parity(bc):
+    """The 2048^2 grid the characteristic 2D benchmark times, one stage in
+    the same launch shape (2048-cell x- and y-lines of 4x4 block systems);
+    the oracle evaluates sampled cells one by one from its characteristic
+    row and column operators with the grid-wide limiter epsilon.  Where a
+    sample misses 1e-12, the bar is 4x the oracle's own change at that cell
+    under 1e-15 perturbations of the two lines (the block systems' roundoff
+    conditioning), printed with the cell."""
+    pp = gpu()
+    n = 2048
+    dx = 2.0 / n
+    U = W.density_wave_2d(n, n)
+    yy, xx = np.mgrid[0:n, 0:n]
+    U[0] += 0.3 * (((xx - 700) ** 2 + (yy - 900) ** 2) < 200 ** 2)
+    sx, sy = oracle.max_speed_2d(U)
+    dt = (1.0 / 12.0) / (sx / dx + sy / dx)
+    print(f"char 2048^2 stage parity, bc {bc}", flush=True)
+    s = pp.Solver(ndim=2, nx=n, ny=n, dx=dx, dy=dx, bc=bc, recon=pp.PP_RECON_CHAR)
+    Ud = dev(U)
+    out = torch.empty_like(Ud)
+    s.stage(Ud, Ud, out, 1, dt)
+    torch.cuda.synchronize()
+    s.close()
+    got = out.cpu().numpy()
+    er, ee = oracle.eps(U)
+    P = oracle.params(**P_CHAR)
+    rng = np.random.default_rng(13)
+    pts = [(int(y), int(x)) for y, x in rng.integers(0, n, size=(10, 2))]
+    pts += [(900, 500), (700, 700), (900, 899), (0, 0), (n - 1, n - 1), (1, 2)]
+    scale = np.abs(U).reshape(4, -1).max(axis=1)
+
+    def cell(V, y, x):
+        Lx = oracle.line_op(np.ascontiguousarray(V[:, y, :]), bc[0], bc[1], dx, p=P,
+                            eps_rho=er, eps_e=ee, nrm=1)
+        Ly = oracle.line_op(np.ascontiguousarray(V[:, :, x]), bc[2], bc[3], dx, p=P,
+                            eps_rho=er, eps_e=ee, nrm=2)
+        return V[:, y, x] + dt * (Lx[:, x] + Ly[:, y])
+
+    for (y, x) in pts:
+        ref = cell(U, y, x)
+        err = float(np.max(np.abs(got[:, y, x] - ref) / scale))
+        if err > TOL_STAGE:
+            prng = np.random.default_rng(y * n + x)
+            sens = 0.0
+            for _ in range(3):
+                V = U.copy()
+                V[:, y, :] *= 1.0 + 1e-15 * prng.standard_normal((4, n))
+                V[:, :, x] *= 1.0 + 1e-15 * prng.standard_normal((4, n))
+                sens = max(sens, float(np.max(np.abs(cell(V, y, x) - ref) / scale)))
+            print(f"  cell ({y}, {x}): {err:.2e}, conditioning bound {4.0 * sens:.2e}",
+                  flush=True)
+            assert err <= max(TOL_STAGE, 4.0 * sens), (y, x)
