@@ -95,7 +95,9 @@ def parse():
                     help="sedov2d: continue from a --checkpoint file")
     ap.add_argument("--max-wall", type=float, default=240.0,
                     help="--full runs stop after this many seconds (sedov2d: the near-vacuum "
-                         "centre makes t = 1 take ~1e7 steps; the full ensemble takes ~260 s)")
+                         "centre makes t = 1 take ~1e7 steps; the FP64 ensemble under the "
+                         "restart rule takes ~275 s, and a near-vacuum problem can keep the "
+                         "CFL-rule run stepping past any cap)")
     return ap.parse_args()
 
 
